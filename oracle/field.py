@@ -1,0 +1,40 @@
+"""Exterior field points (oracle; test infrastructure only).
+
+Eq. (BIE_I) with lambda = 1 at a point x outside the body and tau = 1:
+    phi(x) = phi_inc(x) + sum_j ( int_Gj H(x, y) dy - c_j int_Gj G(x, y) dy ) phi_j,
+with v_j = c_j phi_j.  The element integrals use the same quasi-singular and
+regular rules as the collocation rows (Sec. 3.1.3-3.1.4), r~ measured from x.
+
+Pinned by: tests/test_oracle_operator.py (reciprocity of two point sources,
+the analytic sphere field at r = 2).
+"""
+
+import numpy as np
+
+from .integrals import offdiag_integrals
+from .operator import bc_factor
+
+
+def field_matrix(geom, pts, k, beta=None, p=None):
+    """M with p_field = p_inc + M p_surface, shape (n_pts, N)."""
+    pts = np.asarray(pts, dtype=np.float64)
+    N = geom["x"].shape[0]
+    M = np.zeros((pts.shape[0], N), dtype=np.complex128)
+    c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
+    jj = np.arange(N)
+    dummy_n = np.tile(np.array([0.0, 0.0, 1.0]), (N, 1))
+    for f in range(pts.shape[0]):
+        xf = np.tile(pts[f], (N, 1))
+        IG, IH, _, _ = offdiag_integrals(xf, dummy_n, geom["P0"], geom["P1"], geom["P2"],
+                                         geom["n"], geom["A"], k, p)
+        M[f, jj] = IH - c * IG
+    return M
+
+
+def plane_wave(pts, k, d, P0=1.0):
+    return P0 * np.exp(1j * k * (np.asarray(pts) @ np.asarray(d, dtype=np.float64)))
+
+
+def point_source(pts, k, xs, P0=1.0):
+    R = np.linalg.norm(np.asarray(pts) - np.asarray(xs), axis=1)
+    return P0 * np.exp(1j * k * R) / (4.0 * np.pi * R)
