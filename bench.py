@@ -1,0 +1,201 @@
+"""Benchmark: Burton-Miller operator matvec (near field on the fly + FMM far
+field) and GMRES solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1]
+
+A step is one application of the whole operator (near field, FMM far field,
+diagonal) to a seeded complex vector already resident in HBM, in the mixed
+(complex-FP32) path; the FP64 path is timed the same way and reported beside
+it, with one GMRES solve per precision.  Prints one JSON line.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic flops per near-field quadrature point of the fused kernel
+# (point, r, 1/r, exp(ikr), the four kernels combined, complex accumulate;
+# rsqrt, sin and cos counted as one flop each); 91 with admittance terms
+FLOPS_PER_POINT = 74
+FLOPS_PER_POINT_BC = 91
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+WORKLOADS = {
+    # config of the headline metric: 20480-triangle rigid sphere, 6 elements
+    # per wavelength, 3-level FMM with ~32-element leaves
+    "c2": dict(mesh=("icosphere", 5), use_fmm=1, levels=3, leaf_size=32, preset="tight",
+               elems_per_wavelength=6.0),
+    # 1280-triangle rigid sphere, k = 1, every pair by direct quadrature
+    "c1": dict(mesh=("icosphere", 3), use_fmm=0, preset="tight", k=1.0),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(frequency sharding across GPUs is a design note only).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    from paper_2312_00005_amd import bemfmm
+
+    wl = WORKLOADS[args.workload]
+    nodes, tris = synth.icosphere(wl["mesh"][1])
+    N = len(tris)
+    if "k" in wl:
+        k = wl["k"]
+    else:
+        k = 2 * math.pi / (wl["elems_per_wavelength"] * synth.mean_edge_length(nodes, tris))
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    kw = dict(use_fmm=wl["use_fmm"])
+    if wl["use_fmm"]:
+        kw.update(levels=wl["levels"], leaf_size=wl["leaf_size"])
+    mesh = bemfmm.Mesh(nodes, tris, wl["preset"], **kw)
+    t_mesh = time.perf_counter() - t0
+    log(f"mesh N={N} built in {t_mesh:.2f}s: {mesh.stats()}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mesh.set_problem(k)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    stats = mesh.stats()
+    x = torch.from_numpy(synth.complex_normal(N, seed=4)).to("cuda")
+    y = torch.empty_like(x)
+
+    def timed(fn, steps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / steps
+
+    res = {}
+    for prec in ("mixed", "fp64"):
+        for _ in range(args.warmup):
+            mesh.apply(x, prec=prec, out=y)
+        t_full = timed(lambda: mesh.apply(x, prec=prec, out=y), args.steps)
+        t_near = timed(lambda: mesh.apply_part(x, 1, prec=prec, out=y), args.steps)
+        res[prec] = dict(t_full=t_full, t_near=t_near)
+        log(f"{prec}: matvec {t_full * 1e3:.3f} ms, near part {t_near * 1e3:.3f} ms")
+    solves = {}
+    if not args.no_solve:
+        for prec in ("mixed", "fp64"):
+            o = bemfmm.bem_options_default(wl["preset"])
+            o.use_fmm = wl["use_fmm"]
+            if wl["use_fmm"]:
+                o.levels = wl["levels"]
+                o.leaf_size = wl["leaf_size"]
+            o.precision = bemfmm.BEM_PREC_MIXED if prec == "mixed" else bemfmm.BEM_PREC_FP64
+            o.gmres_tol = 1e-6
+            ms = bemfmm.Mesh(nodes, tris, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ms.set_problem(k)
+            rhs = ms.rhs_plane_wave((0.0, 0.0, 1.0))
+            p, _, info = ms.solve(rhs)
+            torch.cuda.synchronize()
+            solves[prec] = dict(seconds=time.perf_counter() - t0, iterations=info["iterations"],
+                                refinements=info["refinements"], rel_residual=info["rel_residual"],
+                                L=info["L"])
+            log(f"{prec}: solve {solves[prec]}")
+            ms.close()
+
+    t_step = res["mixed"]["t_full"]
+    value = N * N / t_step
+    pts = stats["quad_points"]
+    near_flops = pts * FLOPS_PER_POINT
+    achieved = near_flops / res["mixed"]["t_near"] / 1e12
+    out = {
+        "metric": "FMM matvec element-interactions/s and GMRES solve s/frequency, mixed vs FP64",
+        "value": value,
+        "unit": "element-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (fp32 operator; fp64 diagonal, Krylov and refinement)",
+        "data": "synthetic (seeded icosphere mesh and complex-normal vector)",
+        "config": {"workload": f"{args.workload}: rigid sphere N={N}, k={k:.4f}, "
+                   + (f"{wl['levels']}-level FMM leaf~{wl['leaf_size']}" if wl["use_fmm"] else "all pairs direct")
+                   + f", preset {wl['preset']}",
+                   "n_elements": N, "k": k, "preset": wl["preset"]},
+        "fp64": {"value": N * N / res["fp64"]["t_full"], "ms_per_step": res["fp64"]["t_full"] * 1e3},
+        "mixed_speedup_over_fp64": res["fp64"]["t_full"] / t_step,
+        "near_ms": {p: res[p]["t_near"] * 1e3 for p in res},
+        "near_quad_points": pts,
+        "setup_s": {"mesh": t_mesh, "per_frequency": t_setup},
+        "solve_s_per_frequency": {p: solves[p]["seconds"] for p in solves},
+        "solve": solves,
+        "roofline": {"bound": "alu", "kernel": "k_near<float,false>", "achieved": achieved,
+                     "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp32"],
+                     "traffic": None,
+                     "fp64_kernel": {"kernel": "k_near<double,false>",
+                                     "achieved": near_flops / res["fp64"]["t_near"] / 1e12,
+                                     "peak": PEAK_TFLOPS["fp64"],
+                                     "frac": near_flops / res["fp64"]["t_near"] / 1e12 / PEAK_TFLOPS["fp64"]}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(nodes, tris, k, wl["preset"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(nodes, tris, k, pre, budget):
+    """The oracle timed on the host: dense operator rows assembled by direct
+    quadrature and multiplied by the same vector (element-interactions/s)."""
+    import numpy as np
+    import synth
+    from oracle import operator as op
+    from oracle.geometry import element_geometry
+    from oracle.presets import preset
+    g = element_geometry(nodes, tris)
+    N = len(tris)
+    x = synth.complex_normal(N, seed=4)
+    rng = np.random.default_rng(7)
+    t0 = time.perf_counter()
+    op.rows(g, rng.choice(N, 1, replace=False), k, p=preset(pre)) @ x
+    t1 = time.perf_counter() - t0
+    nrows = max(1, min(N, int(budget / max(t1, 1e-6))))
+    rows = rng.choice(N, nrows, replace=False)
+    t0 = time.perf_counter()
+    y = op.rows(g, rows, k, p=preset(pre)) @ x
+    dt = time.perf_counter() - t0
+    return {"value": nrows * N / dt, "unit": "element-interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nrows} random rows of the dense N={N} operator ({pre} preset) assembled by "
+                      f"the numpy oracle and applied to x, {dt:.1f}s on one host core"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * bemfmm.h -- C ABI of the MI355X (gfx950) Burton-Miller BEM / multilevel FMM
+ * library.
+ *
+ * The library solves the exterior Helmholtz problem on a closed surface made
+ * of flat triangles with constant elements and collocation at the centroids
+ * (arXiv 2312.00005, Sec. 2.2-2.3), in the Burton-Miller form of Eq. (SystemI)
+ * with tau = 1 and coupling gamma = i/k (Sec. 2.5):
+ *
+ *   (phi - gamma v)/2 - (H - gamma E) phi + (G - gamma H') v = phi_inc - gamma v_inc
+ *
+ * Per element j the boundary condition is v_j = c_j phi_j with c_j = 0 on a
+ * sound-hard element (the default of the paper's mesh appendix) and
+ * c_j = -i k beta_j for an admittance element, beta = rho c Y (exterior
+ * reading v = -Y p).  The unknown may be read as surface pressure p; all
+ * source amplitudes are pressure amplitudes.
+ *
+ * The operator A is applied as the near field (direct singular,
+ * hypersingular, quasi-singular and regular quadrature, Sec. 3.1, evaluated
+ * on the fly on every application) plus the far field of a multilevel fast
+ * multipole method on the paper's cluster tree (Sec. 3.3): aggregation of
+ * leaf elements to signatures on unit-sphere quadrature points, band-limited
+ * interpolation between levels, diagonal translation by the truncated
+ * expansion of Eq. (FMMBase), anterpolation and disaggregation.
+ *
+ * Conventions (all functions):
+ *   - SI units; k is the wavenumber in rad/m.
+ *   - bem_c128 is layout-compatible with C99 double complex,
+ *     std::complex<double> and a torch.complex128 element.
+ *   - Vectors indexed by element follow the caller's triangle order.
+ *   - "device" pointers are HIP device pointers on the current device
+ *     (e.g. tensor.data_ptr() of a CUDA/HIP tensor); "host" pointers are
+ *     ordinary CPU memory.  Buffers are owned by the caller; the library owns
+ *     only the memory held by a bem_mesh and releases it in bem_mesh_destroy.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work on it and return; bem_mesh_create and bem_solve return only when
+ *     their result is complete.
+ *   - Every function returns a bem_status; on failure bem_last_error() gives a
+ *     thread-local message valid until the next call on the same thread.
+ *     Nothing is thrown across this boundary.
+ *   - A bem_mesh is not thread-safe: use one per host thread / stream.
+ */
+#ifndef BEMFMM_H
+#define BEMFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } bem_c128;
+
+typedef enum {
+  BEM_OK = 0,
+  BEM_E_ARG = 1,     /* invalid argument (NULL pointer, size, NaN, unknown preset) */
+  BEM_E_MESH = 2,    /* degenerate triangle, or more nested subdivisions than
+                        allowed (Sec. 4.1 "subdivision loop" error); see
+                        bem_mesh_bad_element() */
+  BEM_E_NOCONV = 3,  /* iterative solver did not reach the tolerance; the
+                        outputs hold the last iterate */
+  BEM_E_HIP = 4,     /* a HIP runtime call failed */
+  BEM_E_OOM = 5,     /* device or host allocation failed */
+  BEM_E_STATE = 6    /* call out of order (e.g. apply before set_problem) */
+} bem_status;
+
+typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_precision;
+
+/* Operator selector of bem_apply. */
+typedef enum {
+  BEM_OP_A = 0,   /* y = A x                          */
+  BEM_OP_AH = 1   /* y = A^H x (conjugate transpose)  */
+} bem_op;
+
+/* Warning bits of bem_solve_info.warnings (computation continues). */
+#define BEM_WARN_COARSE_MESH 1u  /* fewer than 6 elements per wavelength (Sec. 2.2) */
+#define BEM_WARN_LARGE_L 2u      /* an expansion length above 30 (Sec. 3.4.2)      */
+#define BEM_WARN_NOT_CONVERGED 4u/* iterative solver stopped at its cap (Sec. 3.2) */
+
+typedef struct bem_options {
+  int32_t use_fmm;          /* 0: every pair by direct quadrature (dense
+                               operator applied on the fly); 1: FMM          */
+  int32_t levels;           /* number of tree levels (root = 1) when use_fmm */
+  int32_t leaf_size;        /* target elements per leaf cluster              */
+  double root_box_edge;     /* root sub-box edge; 0 = derived from levels and
+                               leaf_size (Sec. 3.3.4)                        */
+  double admissibility;     /* far if |z_i - z_j| > admissibility (r_i + r_j);
+                               2/sqrt(3) in Eq. (Farfieldcond)               */
+  int32_t l_mode;           /* 0: L from Eq. (FMMTruncation) alone;
+                               1: also an accuracy term (see l_eps)          */
+  double l_factor;          /* 1.8 in Eq. (FMMTruncation)                    */
+  int32_t l_min;            /* lower bound of L (8 in Eq. (FMMTruncation))   */
+  double l_eps;             /* target accuracy of the expansion (l_mode 1)   */
+  int32_t t_order;          /* order of the triangle rule for aggregation    */
+  double quad_eps;          /* a-priori quadrature tolerance (1e-3, Sec. 3.1.4) */
+  int32_t quad_m_max;       /* maximum Gauss order (6, Sec. 3.1.4)           */
+  int32_t quad_split_on_cap;/* 1: split instead of capping the order (Sec. 4.1.2) */
+  double subdiv_ratio;      /* split while r~ < subdiv_ratio (1.3, Sec. 3.1.3) */
+  int32_t max_subdiv;       /* nested split limit (15, Sec. 4.1)             */
+  int32_t self_n;           /* Duffy rule order per direction (4, Sec. 3.1.1) */
+  int32_t edge_parts;       /* parts per edge for E_ii (4, Sec. 3.1.2)        */
+  int32_t edge_gauss;       /* Gauss points per part (3, Sec. 3.1.2)          */
+  bem_precision precision;  /* arithmetic of the inner operator in bem_solve */
+  int32_t gmres_restart;    /* Krylov dimension before restart                */
+  int32_t gmres_maxit;      /* iteration cap (250 as in Sec. 3.2)             */
+  double gmres_tol;         /* relative residual target                       */
+  int32_t refine_maxit;     /* outer refinement steps (mixed precision)      */
+  double inner_tol;         /* inner GMRES tolerance (mixed precision)       */
+} bem_options;
+
+typedef struct bem_solve_info {
+  int32_t iterations;       /* total inner Krylov iterations                 */
+  int32_t refinements;      /* outer refinement steps (mixed)                */
+  int32_t levels;           /* tree levels (0 without FMM)                   */
+  int32_t L[16];            /* expansion length per level, root first        */
+  int32_t clusters[16];     /* clusters per level, root first                */
+  int64_t near_pairs;       /* near element pairs, self pairs included       */
+  int64_t near_items;       /* quadrature items (sub-triangles) per apply    */
+  int64_t quad_points;      /* near-field quadrature points per apply        */
+  double rel_residual;      /* final ||b - A x|| / ||b|| (FP64 operator)      */
+  uint32_t warnings;        /* BEM_WARN_* bits                                */
+} bem_solve_info;
+
+typedef struct bem_mesh bem_mesh;
+
+/* Fill *o with a named preset: "paper" (the paper's defaults), "tight"
+ * (higher-accuracy quadrature and expansion, FP64) or "mixed" ("tight" with
+ * complex-FP32 inner operator and FP64 refinement).  Unknown name: BEM_E_ARG. */
+bem_status bem_options_default(bem_options* o, const char* preset);
+
+/* Build the mesh plan: element geometry, cluster tree (Sec. 3.3.2-3.3.4),
+ * interaction lists, near-field pairs and their frequency-independent
+ * quadrature plan (Sec. 3.1.3-3.1.4), and upload it to the current device.
+ *   xyz : host, double[n_nodes][3]
+ *   tri : host, int32[n_tri][3], 0-based node indices, counter-clockwise seen
+ *         from outside (the paper's mesh appendix)
+ * Blocking.  BEM_E_MESH for a zero-area triangle or a subdivision overflow. */
+bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri,
+                           const int32_t* tri, const bem_options* o,
+                           bem_mesh** out);
+
+/* Element index (caller order) that caused the last BEM_E_MESH, or -1. */
+int64_t bem_mesh_bad_element(const bem_mesh* m);
+
+/* Per-frequency setup: wavenumber k > 0 and per-element normalised
+ * admittance beta (device bem_c128[n_tri], or NULL for sound-hard
+ * everywhere).  Computes the singular self terms, expansion lengths, sphere
+ * grids, interpolation and translation data (Sec. 3.3.1, Sec. 3.4.2). */
+bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta,
+                           void* stream);
+
+/* Right-hand side b = p_inc - gamma dp_inc/dn at the centroids (Sec. 2.4):
+ * plane wave P0 exp(i k d.x) with unit direction d, or point source
+ * P0 exp(i k R)/(4 pi R) at x0.  rhs: device bem_c128[n_tri]. */
+bem_status bem_rhs_plane_wave(bem_mesh* m, const double d[3], bem_c128 P0,
+                              bem_c128* rhs, void* stream);
+bem_status bem_rhs_point_source(bem_mesh* m, const double x0[3], bem_c128 P0,
+                                bem_c128* rhs, void* stream);
+
+/* One operator application y = A x or y = A^H x (device vectors of n_tri),
+ * in FP64 or in the mixed path's complex-FP32 arithmetic (self terms FP64). */
+bem_status bem_apply(bem_mesh* m, bem_op op, bem_precision prec,
+                     const bem_c128* x, bem_c128* y, void* stream);
+
+/* The two parts of one application, for measurement and testing:
+ * part = 1: y = (diagonal + near field) x only; part = 2: y = far field
+ * (FMM) x only (zero without FMM); part = 0 is bem_apply. */
+bem_status bem_apply_part(bem_mesh* m, bem_op op, bem_precision prec, int part,
+                          const bem_c128* x, bem_c128* y, void* stream);
+
+/* Solve A p = rhs by GMRES (FP64 Krylov vectors and residuals; with
+ * precision MIXED an FP64 outer refinement around a complex-FP32 inner
+ * operator).  p_out: device bem_c128[n_tri]; v_out (may be NULL): normal
+ * velocity v = -beta/(rho_c) p.  info: host, may be NULL.  Blocking.
+ * BEM_E_NOCONV if the tolerance was not reached (outputs still written). */
+bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out,
+                     bem_c128* v_out, double rho_c, bem_solve_info* info,
+                     void* stream);
+
+/* Mesh statistics (host outputs; any pointer may be NULL). */
+bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,
+                          int64_t* near_pairs, int64_t* near_items,
+                          int64_t* quad_points);
+
+/* Device bytes held by the mesh plan and the current problem. */
+size_t bem_workspace_bytes(const bem_mesh* m);
+
+void bem_mesh_destroy(bem_mesh* m);
+
+const char* bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEMFMM_H */

@@ -1,0 +1,304 @@
+"""ctypes binding of libbemfmm.so (include/bemfmm.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+module-level ``bem_*`` functions mirror the C entry points one to one (same
+names, same arguments, pointers as Python ints) and raise ``BemError`` on a
+non-zero status.  ``Mesh`` wraps them for torch tensors: device buffers are
+``torch.complex128`` tensors on the current HIP device and streams are
+``torch.cuda.current_stream()``.
+
+Importing this module fails loudly if the library has not been built.
+"""
+
+import ctypes
+import os
+
+# torch ships its own HIP runtime (soname libamdhip64.so.7).  Importing torch
+# first makes the library below bind to that same runtime instead of loading a
+# second copy from /opt/rocm, so both share one device context.
+import torch  # noqa: F401
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbemfmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_00005_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+BEM_OK, BEM_E_ARG, BEM_E_MESH, BEM_E_NOCONV, BEM_E_HIP, BEM_E_OOM, BEM_E_STATE = range(7)
+BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
+BEM_OP_A, BEM_OP_AH = 0, 1
+BEM_WARN_COARSE_MESH, BEM_WARN_LARGE_L, BEM_WARN_NOT_CONVERGED = 1, 2, 4
+
+_STATUS_NAMES = {0: "BEM_OK", 1: "BEM_E_ARG", 2: "BEM_E_MESH", 3: "BEM_E_NOCONV",
+                 4: "BEM_E_HIP", 5: "BEM_E_OOM", 6: "BEM_E_STATE"}
+
+
+class BemError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class bem_c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class bem_options(ctypes.Structure):
+    _fields_ = [
+        ("use_fmm", ctypes.c_int32), ("levels", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+        ("root_box_edge", ctypes.c_double), ("admissibility", ctypes.c_double),
+        ("l_mode", ctypes.c_int32), ("l_factor", ctypes.c_double), ("l_min", ctypes.c_int32),
+        ("l_eps", ctypes.c_double), ("t_order", ctypes.c_int32), ("quad_eps", ctypes.c_double),
+        ("quad_m_max", ctypes.c_int32), ("quad_split_on_cap", ctypes.c_int32),
+        ("subdiv_ratio", ctypes.c_double), ("max_subdiv", ctypes.c_int32),
+        ("self_n", ctypes.c_int32), ("edge_parts", ctypes.c_int32), ("edge_gauss", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
+        ("gmres_maxit", ctypes.c_int32), ("gmres_tol", ctypes.c_double),
+        ("refine_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class bem_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32), ("levels", ctypes.c_int32),
+        ("L", ctypes.c_int32 * 16), ("clusters", ctypes.c_int32 * 16),
+        ("near_pairs", ctypes.c_int64), ("near_items", ctypes.c_int64),
+        ("quad_points", ctypes.c_int64), ("rel_residual", ctypes.c_double),
+        ("warnings", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        nl = self.levels
+        return {"iterations": self.iterations, "refinements": self.refinements, "levels": nl,
+                "L": list(self.L[:nl]), "clusters": list(self.clusters[:nl]),
+                "near_pairs": self.near_pairs, "near_items": self.near_items,
+                "quad_points": self.quad_points, "rel_residual": self.rel_residual,
+                "warnings": self.warnings}
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+
+_SIGS = {
+    "bem_options_default": (_i32, [ctypes.POINTER(bem_options), ctypes.c_char_p]),
+    "bem_mesh_create": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), ctypes.POINTER(_vp)]),
+    "bem_mesh_bad_element": (_i64, [_vp]),
+    "bem_set_problem": (_i32, [_vp, _dbl, _vp, _vp]),
+    "bem_rhs_plane_wave": (_i32, [_vp, _vp, bem_c128, _vp, _vp]),
+    "bem_rhs_point_source": (_i32, [_vp, _vp, bem_c128, _vp, _vp]),
+    "bem_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "bem_apply_part": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "bem_solve": (_i32, [_vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(bem_solve_info), _vp]),
+    "bem_mesh_stats": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "bem_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "bem_mesh_destroy": (None, [_vp]),
+    "bem_last_error": (ctypes.c_char_p, []),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(status):
+    if status != BEM_OK:
+        msg = _lib.bem_last_error()
+        raise BemError(status, msg.decode() if msg else "")
+    return status
+
+
+# ---- one-to-one wrappers of the C entry points -------------------------------
+
+def bem_options_default(preset="paper"):
+    o = bem_options()
+    _check(_lib.bem_options_default(ctypes.byref(o), preset.encode()))
+    return o
+
+
+def bem_mesh_create(n_nodes, xyz_ptr, n_tri, tri_ptr, options):
+    out = _vp()
+    st = _lib.bem_mesh_create(n_nodes, xyz_ptr, n_tri, tri_ptr, ctypes.byref(options), ctypes.byref(out))
+    _check(st)
+    return out.value
+
+
+def bem_mesh_bad_element(mesh):
+    return _lib.bem_mesh_bad_element(mesh)
+
+
+def bem_set_problem(mesh, k, beta_ptr, stream):
+    _check(_lib.bem_set_problem(mesh, k, beta_ptr, stream))
+
+
+def bem_rhs_plane_wave(mesh, d, P0, rhs_ptr, stream):
+    dd = (ctypes.c_double * 3)(*d)
+    _check(_lib.bem_rhs_plane_wave(mesh, dd, bem_c128(P0.real, P0.imag), rhs_ptr, stream))
+
+
+def bem_rhs_point_source(mesh, x0, P0, rhs_ptr, stream):
+    xx = (ctypes.c_double * 3)(*x0)
+    _check(_lib.bem_rhs_point_source(mesh, xx, bem_c128(P0.real, P0.imag), rhs_ptr, stream))
+
+
+def bem_apply(mesh, op, prec, x_ptr, y_ptr, stream):
+    _check(_lib.bem_apply(mesh, op, prec, x_ptr, y_ptr, stream))
+
+
+def bem_apply_part(mesh, op, prec, part, x_ptr, y_ptr, stream):
+    _check(_lib.bem_apply_part(mesh, op, prec, part, x_ptr, y_ptr, stream))
+
+
+def bem_solve(mesh, rhs_ptr, p_ptr, v_ptr, rho_c, stream):
+    info = bem_solve_info()
+    st = _lib.bem_solve(mesh, rhs_ptr, p_ptr, v_ptr, rho_c, ctypes.byref(info), stream)
+    return st, info
+
+
+def bem_mesh_stats(mesh):
+    lv = _i32()
+    cl = (_i32 * 16)()
+    npairs, nitems, npts = _i64(), _i64(), _i64()
+    _check(_lib.bem_mesh_stats(mesh, ctypes.byref(lv), cl, ctypes.byref(npairs), ctypes.byref(nitems),
+                               ctypes.byref(npts)))
+    return {"levels": lv.value, "clusters": list(cl[:lv.value]), "near_pairs": npairs.value,
+            "near_items": nitems.value, "quad_points": npts.value}
+
+
+def bem_workspace_bytes(mesh):
+    return _lib.bem_workspace_bytes(mesh)
+
+
+def bem_mesh_destroy(mesh):
+    _lib.bem_mesh_destroy(mesh)
+
+
+def bem_last_error():
+    m = _lib.bem_last_error()
+    return m.decode() if m else ""
+
+
+# ---- torch convenience layer -------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_c128(t, n, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 device tensor")
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with {n} elements")
+    return t.data_ptr()
+
+
+_PRECS = {"fp64": BEM_PREC_FP64, "mixed": BEM_PREC_MIXED, BEM_PREC_FP64: BEM_PREC_FP64,
+          BEM_PREC_MIXED: BEM_PREC_MIXED}
+_OPS = {"A": BEM_OP_A, "AH": BEM_OP_AH, BEM_OP_A: BEM_OP_A, BEM_OP_AH: BEM_OP_AH}
+
+
+class Mesh:
+    """A bem_mesh with torch-tensor helpers.  Elements keep the caller's order."""
+
+    def __init__(self, nodes, tris, options=None, **overrides):
+        import numpy as np
+        if options is None:
+            options = bem_options_default("paper")
+        elif isinstance(options, str):
+            options = bem_options_default(options)
+        for key, val in overrides.items():
+            setattr(options, key, val)
+        self.options = options
+        self._nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        self._tris = np.ascontiguousarray(tris, dtype=np.int32)
+        self.n = int(self._tris.shape[0])
+        self._h = None
+        self._h = bem_mesh_create(self._nodes.shape[0], self._nodes.ctypes.data, self.n,
+                                  self._tris.ctypes.data, options)
+        self._beta = None
+
+    def close(self):
+        if self._h:
+            bem_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_problem(self, k, beta=None):
+        ptr = None
+        if beta is not None:
+            ptr = _dev_c128(beta, self.n, "beta")
+            self._beta = beta
+        bem_set_problem(self._h, float(k), ptr, _stream())
+
+    def _empty(self, n=None):
+        torch = _torch()
+        return torch.empty(self.n if n is None else n, dtype=torch.complex128, device="cuda")
+
+    def rhs_plane_wave(self, d=(0.0, 0.0, 1.0), P0=1.0):
+        out = self._empty()
+        bem_rhs_plane_wave(self._h, d, complex(P0), out.data_ptr(), _stream())
+        return out
+
+    def rhs_point_source(self, x0, P0=1.0):
+        out = self._empty()
+        bem_rhs_point_source(self._h, x0, complex(P0), out.data_ptr(), _stream())
+        return out
+
+    def apply(self, x, op="A", prec="fp64", out=None):
+        xp = _dev_c128(x, self.n, "x")
+        out = self._empty() if out is None else out
+        bem_apply(self._h, _OPS[op], _PRECS[prec], xp, _dev_c128(out, self.n, "y"), _stream())
+        return out
+
+    def apply_part(self, x, part, op="A", prec="fp64", out=None):
+        """part 1: diagonal + near field only; part 2: far field only."""
+        xp = _dev_c128(x, self.n, "x")
+        out = self._empty() if out is None else out
+        bem_apply_part(self._h, _OPS[op], _PRECS[prec], int(part), xp, _dev_c128(out, self.n, "y"),
+                       _stream())
+        return out
+
+    def solve(self, rhs, rho_c=None, allow_noconv=False):
+        """Returns (p, v or None, info dict)."""
+        rp = _dev_c128(rhs, self.n, "rhs")
+        p = self._empty()
+        v = self._empty() if rho_c is not None else None
+        st, info = bem_solve(self._h, rp, p.data_ptr(), v.data_ptr() if v is not None else None,
+                             float(rho_c) if rho_c is not None else 0.0, _stream())
+        if st != BEM_OK and not (allow_noconv and st == BEM_E_NOCONV):
+            _check(st)
+        return p, v, info.as_dict()
+
+    def stats(self):
+        return bem_mesh_stats(self._h)
+
+    def workspace_bytes(self):
+        return bem_workspace_bytes(self._h)

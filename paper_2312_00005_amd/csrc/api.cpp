@@ -1,0 +1,475 @@
+// C ABI entry points (include/bemfmm.h).  Every entry point catches
+// exceptions and turns them into a status code plus a thread-local message.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "state.h"
+
+using namespace bem;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bem_status fail(bem_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+bem_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(BEM_E_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(BEM_E_ARG, e.what());
+  }
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+void set_paper(bem_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->use_fmm = 1;
+  o->levels = 0;
+  o->leaf_size = 25;
+  o->root_box_edge = 0.0;
+  o->admissibility = 2.0 / std::sqrt(3.0);
+  o->l_mode = 0;
+  o->l_factor = 1.8;
+  o->l_min = 8;
+  o->l_eps = 1e-3;
+  o->t_order = 4;
+  o->quad_eps = 1e-3;
+  o->quad_m_max = 6;
+  o->quad_split_on_cap = 0;
+  o->subdiv_ratio = 1.3;
+  o->max_subdiv = 15;
+  o->self_n = 4;
+  o->edge_parts = 4;
+  o->edge_gauss = 3;
+  o->precision = BEM_PREC_FP64;
+  o->gmres_restart = 100;
+  o->gmres_maxit = 250;
+  o->gmres_tol = 1e-9;
+  o->refine_maxit = 20;
+  o->inner_tol = 1e-3;
+}
+
+void upload_rules() {
+  static bool done = false;
+  if (done) return;
+  double a[kRulePoints], b[kRulePoints], w[kRulePoints];
+  int off[kMaxRuleOrder + 1];
+  int pos = 0;
+  for (int m = 1; m <= kMaxRuleOrder; ++m) {
+    off[m - 1] = pos;
+    std::vector<double> xi, wx, eta, we;
+    gauss_jacobi_xi01(m, xi, wx);
+    gauss_legendre01(m, eta, we);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        a[pos] = xi[i] * (1.0 - eta[j]);
+        b[pos] = xi[i] * eta[j];
+        w[pos] = wx[i] * we[j];
+        ++pos;
+      }
+  }
+  off[kMaxRuleOrder] = pos;
+  upload_rule_tables(a, b, w, off);
+  BEM_HIP(hipGetLastError());
+  done = true;
+}
+
+int default_levels(int64_t N) {
+  // 1 + round(log2(sqrt(N) / 22.5) / 2), at least 1
+  double v = 0.5 * std::log2(std::sqrt(double(N)) / 22.5);
+  return std::max(1, 1 + (int)std::floor(v + 0.5));
+}
+
+void check_options(const bem_options* o) {
+  if (!o) throw Error(BEM_E_ARG, "options is NULL");
+  if (o->quad_m_max < 1 || o->quad_m_max > kMaxRuleOrder) throw Error(BEM_E_ARG, "quad_m_max must be in [1, 8]");
+  if (!(o->quad_eps > 0.0)) throw Error(BEM_E_ARG, "quad_eps must be positive");
+  if (!(o->subdiv_ratio > 0.0)) throw Error(BEM_E_ARG, "subdiv_ratio must be positive");
+  if (o->max_subdiv < 0 || o->max_subdiv > 15) throw Error(BEM_E_ARG, "max_subdiv must be in [0, 15]");
+  if (o->self_n < 1 || o->self_n > 64) throw Error(BEM_E_ARG, "self_n must be in [1, 64]");
+  if (o->edge_parts < 1 || o->edge_gauss < 1 || o->edge_parts * o->edge_gauss > 4096)
+    throw Error(BEM_E_ARG, "invalid edge rule");
+  if (o->gmres_restart < 1 || o->gmres_restart > 200) throw Error(BEM_E_ARG, "gmres_restart must be in [1, 200]");
+  if (o->gmres_maxit < 1) throw Error(BEM_E_ARG, "gmres_maxit must be positive");
+  if (!(o->gmres_tol > 0.0)) throw Error(BEM_E_ARG, "gmres_tol must be positive");
+  if (o->use_fmm) {
+    if (o->levels < 0 || o->levels > 16) throw Error(BEM_E_ARG, "levels must be in [0, 16]");
+    if (o->leaf_size < 1) throw Error(BEM_E_ARG, "leaf_size must be positive");
+    if (!(o->admissibility > 0.0)) throw Error(BEM_E_ARG, "admissibility must be positive");
+    if (o->t_order < 1 || o->t_order > kMaxRuleOrder) throw Error(BEM_E_ARG, "t_order must be in [1, 8]");
+  }
+  if (o->precision != BEM_PREC_FP64 && o->precision != BEM_PREC_MIXED)
+    throw Error(BEM_E_ARG, "unknown precision");
+}
+
+}  // namespace
+
+namespace bem {
+
+void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s) {
+  apply_tree_part(m, op, prec, 0, x, y, s);
+}
+
+void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
+                     hipStream_t s) {
+  if (part == 2) {
+    BEM_HIP(hipMemsetAsync(y, 0, m->N * sizeof(double2), s));
+    if (m->fmm) fmm_apply(m, op, prec, x, y, s);
+    return;
+  }
+  NearLaunch L{};
+  L.N = m->N;
+  L.geom = m->d_geom.p;
+  L.geom32 = m->d_geom32.p;
+  L.cfac = m->have_beta ? m->d_cfac.p : nullptr;
+  L.diag = m->d_diag.p;
+  L.k = m->k;
+  L.gre = m->gre;
+  L.gim = m->gim;
+  if (op == BEM_OP_A) {
+    L.off = m->d_off.p;
+    L.items = m->d_items.p;
+    if (prec == BEM_PREC_FP64) launch_near_f64(L, x, y, s);
+    else launch_near_f32(L, x, y, s);
+  } else {
+    ensure_transposed_plan(m, s);
+    L.off = m->d_off_t.p;
+    L.items = m->d_items_t.p;
+    if (prec == BEM_PREC_FP64) launch_near_adj_f64(L, x, y, s);
+    else launch_near_adj_f32(L, x, y, s);
+  }
+  BEM_HIP(hipGetLastError());
+  if (part == 0 && m->fmm) fmm_apply(m, op, prec, x, y, s);
+}
+
+void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
+  if (m->have_plan_t) return;
+  const NearPlan& P = m->plan;
+  const int64_t N = m->N;
+  NearPlan T;
+  T.off.assign(N + 1, 0);
+  const uint64_t jmask = (uint64_t(1) << 26) - 1;
+  for (uint64_t it : P.items) T.off[(it & jmask) + 1]++;
+  for (int64_t j = 0; j < N; ++j) T.off[j + 1] += T.off[j];
+  T.items.resize(P.items.size());
+  std::vector<int64_t> pos(T.off.begin(), T.off.end() - 1);
+  for (int64_t t = 0; t < N; ++t)
+    for (int64_t q = P.off[t]; q < P.off[t + 1]; ++q) {
+      uint64_t it = P.items[q];
+      int64_t j = (int64_t)(it & jmask);
+      T.items[pos[j]++] = (it & ~jmask) | (uint64_t)t;
+    }
+  // sort each source's list by rule order for uniform wavefront work
+  for (int64_t j = 0; j < N; ++j)
+    std::stable_sort(T.items.begin() + T.off[j], T.items.begin() + T.off[j + 1],
+                     [](uint64_t a, uint64_t b) { return ((a >> 26) & 7) < ((b >> 26) & 7); });
+  T.pairs = P.pairs;
+  T.points = P.points;
+  T.max_m = P.max_m;
+  m->plan_t = std::move(T);
+  m->d_off_t.upload(m->plan_t.off, s);
+  m->d_items_t.upload(m->plan_t.items, s);
+  BEM_HIP(hipStreamSynchronize(s));
+  m->have_plan_t = true;
+}
+
+}  // namespace bem
+
+extern "C" {
+
+const char* bem_last_error(void) { return g_last_error.c_str(); }
+
+bem_status bem_options_default(bem_options* o, const char* preset) {
+  return guarded([&]() -> bem_status {
+    if (!o || !preset) return fail(BEM_E_ARG, "NULL argument");
+    std::string p(preset);
+    set_paper(o);
+    if (p == "paper") return BEM_OK;
+    if (p == "tight" || p == "mixed") {
+      o->leaf_size = 32;
+      o->admissibility = 3.0;
+      o->l_mode = 1;
+      o->l_eps = 1e-7;
+      o->t_order = 6;
+      o->quad_eps = 1e-7;
+      o->quad_split_on_cap = 1;
+      o->self_n = 12;
+      o->edge_parts = 8;
+      o->edge_gauss = 6;
+      o->gmres_tol = 1e-6;
+      if (p == "mixed") o->precision = BEM_PREC_MIXED;
+      return BEM_OK;
+    }
+    return fail(BEM_E_ARG, "unknown preset '" + p + "'");
+  });
+}
+
+bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
+                           const bem_options* o, bem_mesh** out) {
+  return guarded([&]() -> bem_status {
+    if (!out) return fail(BEM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!xyz || !tri || n_nodes < 3 || n_tri < 1) return fail(BEM_E_ARG, "empty or NULL mesh");
+    check_options(o);
+    for (int64_t i = 0; i < 3 * n_nodes; ++i)
+      if (!std::isfinite(xyz[i])) return fail(BEM_E_ARG, "non-finite node coordinate");
+    auto m = std::make_unique<bem_mesh>();
+    m->opt = *o;
+    m->N = n_tri;
+    std::vector<int64_t> ident(n_tri);
+    for (int64_t i = 0; i < n_tri; ++i) ident[i] = i;
+    Geometry gc;
+    try {
+      gc = build_geometry(xyz, n_nodes, tri, n_tri, ident);
+    } catch (const Error& e) {
+      m->bad_element = e.element;
+      throw;
+    }
+    m->fmm = o->use_fmm != 0;
+    std::vector<int64_t> src_off, src_beg, src_end, tgt_group(n_tri, 0);
+    if (m->fmm) {
+      int levels = o->levels > 0 ? o->levels : default_levels(n_tri);
+      m->tree = build_tree(gc, levels, o->root_box_edge, o->leaf_size, o->admissibility);
+      m->g = build_geometry(xyz, n_nodes, tri, n_tri, m->tree.perm);
+      const Level& leaf = m->tree.lv.back();
+      src_off.assign(leaf.nc + 1, 0);
+      for (int64_t c = 0; c < leaf.nc; ++c) {
+        for (int64_t e = leaf.ebeg[c]; e < leaf.eend[c]; ++e) tgt_group[e] = c;
+        for (int64_t q = leaf.nr_off[c]; q < leaf.nr_off[c + 1]; ++q) {
+          int64_t nb = leaf.nr[q];
+          src_beg.push_back(leaf.ebeg[nb]);
+          src_end.push_back(leaf.eend[nb]);
+        }
+        src_off[c + 1] = (int64_t)src_beg.size();
+      }
+    } else {
+      m->tree.perm = ident;
+      m->tree.inv = ident;
+      m->g = std::move(gc);
+      src_off = {0, 1};
+      src_beg = {0};
+      src_end = {n_tri};
+    }
+    QuadParams q{o->quad_eps, o->quad_m_max, o->quad_split_on_cap, o->subdiv_ratio, o->max_subdiv};
+    try {
+      m->plan = build_near_plan(m->g, q, src_off, src_beg, src_end, tgt_group);
+    } catch (const Error& e) {
+      m->bad_element = e.element >= 0 ? m->tree.perm[e.element] : -1;
+      std::string msg = "more than max_subdiv nested subdivisions for element " + std::to_string(m->bad_element);
+      throw Error(e.code, msg, m->bad_element);
+    }
+    upload_rules();
+    hipStream_t s = nullptr;
+    m->d_geom.upload(m->g.f, s);
+    std::vector<float> g32(m->g.f.begin(), m->g.f.end());
+    m->d_geom32.upload(g32, s);
+    m->d_perm.upload(m->tree.perm, s);
+    m->d_off.upload(m->plan.off, s);
+    m->d_items.upload(m->plan.items, s);
+    std::vector<double> u, w;
+    gauss_legendre01(o->self_n, u, w);
+    m->d_duffy_u.upload(u, s);
+    m->d_duffy_w.upload(w, s);
+    std::vector<double> gt, gw, et, ew;
+    gauss_legendre01(o->edge_gauss, gt, gw);
+    for (int p = 0; p < o->edge_parts; ++p)
+      for (int i = 0; i < o->edge_gauss; ++i) {
+        et.push_back((p + gt[i]) / o->edge_parts);
+        ew.push_back(gw[i] / o->edge_parts);
+      }
+    m->d_edge_t.upload(et, s);
+    m->d_edge_w.upload(ew, s);
+    m->d_x.alloc(n_tri);
+    m->d_y.alloc(n_tri);
+    m->d_b.alloc(n_tri);
+    m->d_sol.alloc(n_tri);
+    m->d_cfac.alloc(n_tri);
+    m->d_diag.alloc(n_tri);
+    BEM_HIP(hipStreamSynchronize(s));
+    *out = m.release();
+    return BEM_OK;
+  });
+}
+
+int64_t bem_mesh_bad_element(const bem_mesh* m) { return m ? m->bad_element : -1; }
+
+bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m) return fail(BEM_E_ARG, "mesh is NULL");
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(BEM_E_ARG, "k must be positive and finite");
+    hipStream_t s = as_stream(stream);
+    m->k = k;
+    m->gre = 0.0;
+    m->gim = 1.0 / k;  // gamma = i / k (Sec. 2.5)
+    m->have_beta = beta != nullptr;
+    if (beta) {
+      m->d_beta.alloc(m->N);
+      BEM_HIP(hipMemcpyAsync(m->d_beta.p, beta, m->N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      launch_cfac(m->N, m->d_perm.p, m->d_beta.p, k, m->d_cfac.p, s);
+    }
+    SelfLaunch L{};
+    L.N = m->N;
+    L.geom = m->d_geom.p;
+    L.cfac = m->have_beta ? m->d_cfac.p : nullptr;
+    L.duffy_u = m->d_duffy_u.p;
+    L.duffy_w = m->d_duffy_w.p;
+    L.self_n = m->opt.self_n;
+    L.edge_t = m->d_edge_t.p;
+    L.edge_w = m->d_edge_w.p;
+    L.edge_pts = m->opt.edge_parts * m->opt.edge_gauss;
+    L.k = k;
+    L.gre = m->gre;
+    L.gim = m->gim;
+    launch_self_terms(L, m->d_diag.p, s);
+    BEM_HIP(hipGetLastError());
+    if (m->fmm) fmm_setup_problem(m, s);
+    m->have_problem = true;
+    return BEM_OK;
+  });
+}
+
+bem_status bem_rhs_plane_wave(bem_mesh* m, const double d[3], bem_c128 P0, bem_c128* rhs, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !d || !rhs) return fail(BEM_E_ARG, "NULL argument");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    double n = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(n > 0.0)) return fail(BEM_E_ARG, "direction must be non-zero");
+    double du[3] = {d[0] / n, d[1] / n, d[2] / n};
+    hipStream_t s = as_stream(stream);
+    launch_rhs_plane(m->N, m->d_geom.p, m->k, m->gre, m->gim, du, P0.re, P0.im, m->d_y.p, s);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(rhs), s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_rhs_point_source(bem_mesh* m, const double x0[3], bem_c128 P0, bem_c128* rhs, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !x0 || !rhs) return fail(BEM_E_ARG, "NULL argument");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    launch_rhs_point(m->N, m->d_geom.p, m->k, m->gre, m->gim, x0, P0.re, P0.im, m->d_y.p, s);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(rhs), s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_apply(bem_mesh* m, bem_op op, bem_precision prec, const bem_c128* x, bem_c128* y,
+                     void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !x || !y) return fail(BEM_E_ARG, "NULL argument");
+    if (op != BEM_OP_A && op != BEM_OP_AH) return fail(BEM_E_ARG, "unknown operator");
+    if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return fail(BEM_E_ARG, "unknown precision");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(x), m->d_x.p, s);
+    apply_tree(m, op, prec, m->d_x.p, m->d_y.p, s);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(y), s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_apply_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const bem_c128* x,
+                          bem_c128* y, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !x || !y) return fail(BEM_E_ARG, "NULL argument");
+    if (op != BEM_OP_A && op != BEM_OP_AH) return fail(BEM_E_ARG, "unknown operator");
+    if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return fail(BEM_E_ARG, "unknown precision");
+    if (part < 0 || part > 2) return fail(BEM_E_ARG, "part must be 0, 1 or 2");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(x), m->d_x.p, s);
+    apply_tree_part(m, op, prec, part, m->d_x.p, m->d_y.p, s);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(y), s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out, bem_c128* v_out, double rho_c,
+                     bem_solve_info* info, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !rhs || !p_out) return fail(BEM_E_ARG, "NULL argument");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    if (v_out && !(rho_c > 0.0)) return fail(BEM_E_ARG, "rho_c must be positive when v_out is requested");
+    hipStream_t s = as_stream(stream);
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(rhs), m->d_b.p, s);
+    SolveResult r = solve_tree(m, m->d_b.p, m->d_sol.p, s);
+    launch_scatter(m->N, m->d_perm.p, m->d_sol.p, reinterpret_cast<double2*>(p_out), s);
+    if (v_out)
+      launch_velocity(m->N, m->have_beta ? m->d_beta.p : nullptr, rho_c, reinterpret_cast<double2*>(p_out),
+                      reinterpret_cast<double2*>(v_out), s);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(s));
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->iterations = r.iterations;
+      info->refinements = r.refinements;
+      info->rel_residual = r.rel_residual;
+      info->near_pairs = m->plan.pairs;
+      info->near_items = (int64_t)m->plan.items.size();
+      info->quad_points = m->plan.points;
+      if (m->fmm) {
+        info->levels = (int)m->tree.lv.size();
+        for (int l = 0; l < info->levels && l < 16; ++l) {
+          info->clusters[l] = (int32_t)m->tree.lv[l].nc;
+          info->L[l] = m->fmm_L[l];
+          if (m->fmm_L[l] > 30) info->warnings |= BEM_WARN_LARGE_L;
+        }
+      }
+      if (!r.converged) info->warnings |= BEM_WARN_NOT_CONVERGED;
+      // elements per wavelength from the mean element size sqrt(2 A) (equilateral edge ~ 1.52 sqrt(A))
+      double asum = 0.0;
+      for (int64_t e = 0; e < m->N; ++e) asum += m->g.at(G_AREA, e);
+      double h = std::sqrt(4.0 / std::sqrt(3.0) * asum / double(m->N));
+      double lambda = 2.0 * M_PI / m->k;
+      if (lambda / h < 6.0) info->warnings |= BEM_WARN_COARSE_MESH;
+    }
+    if (!r.converged)
+      return fail(BEM_E_NOCONV, "GMRES stopped at relative residual " + std::to_string(r.rel_residual));
+    return BEM_OK;
+  });
+}
+
+bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters, int64_t* near_pairs,
+                          int64_t* near_items, int64_t* quad_points) {
+  return guarded([&]() -> bem_status {
+    if (!m) return fail(BEM_E_ARG, "mesh is NULL");
+    int nl = m->fmm ? (int)m->tree.lv.size() : 0;
+    if (levels) *levels = nl;
+    if (clusters)
+      for (int l = 0; l < nl; ++l) clusters[l] = (int32_t)m->tree.lv[l].nc;
+    if (near_pairs) *near_pairs = m->plan.pairs;
+    if (near_items) *near_items = (int64_t)m->plan.items.size();
+    if (quad_points) *quad_points = m->plan.points;
+    return BEM_OK;
+  });
+}
+
+size_t bem_workspace_bytes(const bem_mesh* m) {
+  if (!m) return 0;
+  size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_perm.bytes() + m->d_off.bytes() +
+             m->d_items.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
+             m->d_cfac.bytes() + m->d_diag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
+             m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
+             m->d_partial.bytes() + m->d_h.bytes();
+  return b + fmm_bytes(m);
+}
+
+void bem_mesh_destroy(bem_mesh* m) { delete m; }
+
+}  // extern "C"

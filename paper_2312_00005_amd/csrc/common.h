@@ -1,0 +1,138 @@
+// Internal declarations of the bemfmm library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "bemfmm.h"
+
+namespace bem {
+
+struct Error : std::runtime_error {
+  bem_status code;
+  int64_t element;
+  Error(bem_status c, const std::string& m, int64_t e = -1)
+      : std::runtime_error(m), code(c), element(e) {}
+};
+
+#define BEM_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      throw ::bem::Error(e_ == hipErrorOutOfMemory ? BEM_E_OOM : BEM_E_HIP, \
+                         std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Owning device buffer.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    BEM_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+  void upload(const std::vector<T>& h, hipStream_t s = nullptr) {
+    alloc(h.size());
+    if (!h.empty())
+      BEM_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------- rules ---
+// 1-D rules on [0, 1]: Gauss-Legendre, and Gauss for weight xi.
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
+void gauss_jacobi_xi01(int n, std::vector<double>& x, std::vector<double>& w);
+
+// ------------------------------------------------------------- geometry ---
+// Element data in structure-of-arrays form, field f of element e at f*N + e.
+enum GeomField {
+  G_P0X = 0, G_P0Y, G_P0Z, G_P1X, G_P1Y, G_P1Z, G_P2X, G_P2Y, G_P2Z,
+  G_NX, G_NY, G_NZ, G_AREA, G_CX, G_CY, G_CZ, G_NFIELDS
+};
+
+struct Geometry {
+  int64_t N = 0;
+  std::vector<double> f;  // G_NFIELDS * N
+  double& at(int field, int64_t e) { return f[field * N + e]; }
+  double at(int field, int64_t e) const { return f[field * N + e]; }
+};
+
+// Build geometry in the order given by perm (perm[t] = caller index of the
+// element at position t).  Throws BEM_E_MESH on a zero-area triangle.
+Geometry build_geometry(const double* xyz, int64_t n_nodes, const int32_t* tri,
+                        int64_t n_tri, const std::vector<int64_t>& perm);
+
+// ----------------------------------------------------------------- tree ---
+struct Level {
+  int64_t nc = 0;
+  std::vector<double> z;           // 3 * nc
+  std::vector<double> r;           // nc
+  std::vector<int64_t> ebeg, eend; // element range in tree order
+  std::vector<int64_t> parent;     // cluster index on the level above (-1 at root)
+  std::vector<int64_t> cbeg, cend; // children range on the level below
+  std::vector<int64_t> il_off, il; // interaction list (CSR)
+  std::vector<int64_t> nr_off, nr; // near list (CSR)
+};
+
+struct Tree {
+  std::vector<Level> lv;        // lv[0] = root level
+  std::vector<int64_t> perm;    // tree position -> caller element index
+  std::vector<int64_t> inv;     // caller element index -> tree position
+};
+
+// Cluster tree of Sec. 3.3.2-3.3.4 on the caller-ordered geometry gc.
+Tree build_tree(const Geometry& gc, int levels, double root_edge, int leaf_size,
+                double admissibility);
+
+// -------------------------------------------------------- near-field plan ---
+// One quadrature item: a (sub-)triangle of source element j integrated with
+// an order-m conical rule.  Packed in 64 bits:
+//   bits  0..25  j (tree position)
+//   bits 26..28  m - 1
+//   bits 29..32  subdivision depth
+//   bits 33..62  path, two bits per level (child index 0..3), level 0 lowest
+struct NearPlan {
+  std::vector<int64_t> off;     // per target (tree order), size N+1
+  std::vector<uint64_t> items;
+  int64_t pairs = 0;            // near pairs including self pairs
+  int64_t points = 0;           // quadrature points per application
+  int max_m = 1;
+};
+
+struct QuadParams {
+  double eps;
+  int m_max;
+  int split_on_cap;
+  double ratio;
+  int max_subdiv;
+};
+
+// targets: element positions (tree order); for target t the sources are
+// [src_ranges) given by a callback-free CSR: src_off/src_beg/src_end.
+NearPlan build_near_plan(const Geometry& g, const QuadParams& q,
+                         const std::vector<int64_t>& tgt_src_off,
+                         const std::vector<int64_t>& src_beg,
+                         const std::vector<int64_t>& src_end,
+                         const std::vector<int64_t>& tgt_group);
+
+}  // namespace bem

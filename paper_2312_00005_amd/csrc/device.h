@@ -1,0 +1,68 @@
+// Device-side declarations shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bem {
+
+constexpr int kMaxRuleOrder = 8;                       // conical rule orders 1..8
+constexpr int kRulePoints = 204;                       // sum of m*m for m = 1..8
+
+// Launch helpers (host-callable, defined in the .hip files).
+void upload_rule_tables(const double* a, const double* b, const double* w, const int* off);
+
+struct NearLaunch {
+  int64_t N;
+  const double* geom;     // G_NFIELDS * N, tree order
+  const float* geom32;    // same fields in float (mixed path)
+  const int64_t* off;     // N + 1
+  const uint64_t* items;
+  const double2* cfac;    // c_j, tree order (nullptr: sound-hard everywhere)
+  const double2* diag;    // A_ii, tree order
+  double k;
+  double gre, gim;        // coupling gamma
+};
+
+// y = diag x + sum over near items (tree-order vectors); accumulate = 1 adds
+// into y instead of overwriting it.
+void launch_near_f64(const NearLaunch& L, const double2* x, double2* y, hipStream_t s);
+void launch_near_f32(const NearLaunch& L, const double2* x, double2* y, hipStream_t s);
+// conjugate-transpose near field: y = conj(diag) x + sum_i conj(K_ij) x_i
+// over the transposed item lists (items indexed by source).
+void launch_near_adj_f64(const NearLaunch& Lt, const double2* x, double2* y, hipStream_t s);
+void launch_near_adj_f32(const NearLaunch& Lt, const double2* x, double2* y, hipStream_t s);
+
+struct SelfLaunch {
+  int64_t N;
+  const double* geom;
+  const double2* cfac;
+  const double* duffy_u; const double* duffy_w; int self_n;
+  const double* edge_t; const double* edge_w; int edge_pts;
+  double k, gre, gim;
+};
+void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s);
+
+void launch_rhs_plane(int64_t N, const double* geom, double k, double gre, double gim,
+                      const double* d, double p0re, double p0im, double2* out, hipStream_t s);
+void launch_rhs_point(int64_t N, const double* geom, double k, double gre, double gim,
+                      const double* x0, double p0re, double p0im, double2* out, hipStream_t s);
+void launch_gather(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s);
+void launch_scatter(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s);
+void launch_cfac(int64_t N, const int64_t* perm, const double2* beta_caller, double k, double2* cfac,
+                 hipStream_t s);
+void launch_velocity(int64_t N, const double2* beta_caller, double rho_c, const double2* p,
+                     double2* v, hipStream_t s);
+
+// Krylov helpers (FP64)
+void launch_multidot(int64_t N, int nv, const double2* V, int64_t ldv, const double2* w,
+                     double2* partial, int nblk, hipStream_t s);
+void launch_reduce_partials(int nv, int nblk, const double2* partial, double2* h, hipStream_t s);
+void launch_multiaxpy(int64_t N, int nv, const double2* V, int64_t ldv, const double2* h,
+                      double sign, double2* w, hipStream_t s);
+void launch_scale_copy(int64_t N, const double2* w, double2 alpha, double2* out, hipStream_t s);
+void launch_axpby(int64_t N, double2 a, const double2* x, double2 b, const double2* y, double2* out,
+                  hipStream_t s);
+int multidot_blocks(int64_t N);
+
+}  // namespace bem

@@ -1,0 +1,496 @@
+// Near-field part of the Burton-Miller operator, evaluated on the fly.
+//
+// For every target (collocation node x_i, normal n_i) and every quadrature
+// item of its near-field plan -- a (sub-)triangle of source element j with an
+// order-m conical rule -- the kernel forms, at each quadrature point y,
+//
+//   K(x_i, y) = -(H - gamma E) + (G - gamma H') c_j          (Eq. (SystemI))
+//
+// with G = exp(ikr)/(4 pi r), H = dG/dn_y, H' = dG/dn_x, E = d2G/dn_x dn_y
+// (Sec. 2.1, 2.5).  All four share r, 1/r and exp(ikr); with R = y - x_i,
+// a = ik - 1/r and B = 3/r^2 - 3ik/r - k^2 the combination is
+//
+//   K = G [ -a (Rh.n_j) - gamma (B (Rh.n_i)(Rh.n_j) + a (n_i.n_j)/r) ]
+//     + c_j G [ 1 + gamma a (Rh.n_i) ].
+//
+// Work layout: one 64-lane wavefront per target element; lanes stride over
+// the target's items (sorted by rule order, so most wavefront iterations run
+// one rule), each lane integrates its whole item and multiplies by x_j, and
+// a shuffle reduction adds the lanes in a fixed order -- no atomics, so every
+// run is bit-identical.  The singular self term is not an item: it is folded
+// into the per-frequency diagonal A_ii (self-term kernel below).
+#include "device.h"
+
+#include <cmath>
+
+namespace bem {
+
+__constant__ double c_rule_a[kRulePoints];
+__constant__ double c_rule_b[kRulePoints];
+__constant__ double c_rule_w[kRulePoints];
+__constant__ float c_rule_a32[kRulePoints];
+__constant__ float c_rule_b32[kRulePoints];
+__constant__ float c_rule_w32[kRulePoints];
+__constant__ int c_rule_off[kMaxRuleOrder + 1];
+
+void upload_rule_tables(const double* a, const double* b, const double* w, const int* off) {
+  float a32[kRulePoints], b32[kRulePoints], w32[kRulePoints];
+  for (int i = 0; i < kRulePoints; ++i) {
+    a32[i] = (float)a[i];
+    b32[i] = (float)b[i];
+    w32[i] = (float)w[i];
+  }
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a), a, sizeof(double) * kRulePoints);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b), b, sizeof(double) * kRulePoints);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_w), w, sizeof(double) * kRulePoints);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a32), a32, sizeof(float) * kRulePoints);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b32), b32, sizeof(float) * kRulePoints);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_w32), w32, sizeof(float) * kRulePoints);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_off), off, sizeof(int) * (kMaxRuleOrder + 1));
+}
+
+namespace {
+
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+
+// field offsets (match GeomField on the host)
+enum { P0X = 0, P1X = 3, P2X = 6, NX = 9, AREA = 12, CX = 13 };
+
+template <typename T> struct RuleTab;
+template <> struct RuleTab<double> {
+  __device__ static double a(int i) { return c_rule_a[i]; }
+  __device__ static double b(int i) { return c_rule_b[i]; }
+  __device__ static double w(int i) { return c_rule_w[i]; }
+};
+template <> struct RuleTab<float> {
+  __device__ static float a(int i) { return c_rule_a32[i]; }
+  __device__ static float b(int i) { return c_rule_b32[i]; }
+  __device__ static float w(int i) { return c_rule_w32[i]; }
+};
+
+__device__ inline void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ inline void sincos_t(float x, float* s, float* c) { __sincosf(x, s, c); }
+__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
+__device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Load the (sub-)triangle of an item: element vertices, then the recorded
+// sequence of child choices (children of (P0, P1, P2) with edge midpoints
+// M01, M12, M20 are (P0,M01,M20), (P1,M12,M01), (P2,M20,M12), (M01,M12,M20)).
+template <typename T>
+__device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t j, int depth,
+                                     uint64_t path, T v0[3], T v1[3], T v2[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    v0[c] = g[(P0X + c) * N + j];
+    v1[c] = g[(P1X + c) * N + j];
+    v2[c] = g[(P2X + c) * N + j];
+  }
+  for (int d = 0; d < depth; ++d) {
+    int ch = (int)((path >> (2 * d)) & 3u);
+    T m01[3], m12[3], m20[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      m01[c] = T(0.5) * (v0[c] + v1[c]);
+      m12[c] = T(0.5) * (v1[c] + v2[c]);
+      m20[c] = T(0.5) * (v2[c] + v0[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T a0, a1, a2;
+      if (ch == 0) { a0 = v0[c]; a1 = m01[c]; a2 = m20[c]; }
+      else if (ch == 1) { a0 = v1[c]; a1 = m12[c]; a2 = m01[c]; }
+      else if (ch == 2) { a0 = v2[c]; a1 = m20[c]; a2 = m12[c]; }
+      else { a0 = m01[c]; a1 = m12[c]; a2 = m20[c]; }
+      v0[c] = a0; v1[c] = a1; v2[c] = a2;
+    }
+  }
+}
+
+// Integrate one item: returns S1 (c-independent part) and S2 (c_j part),
+// both already multiplied by 2 * area of the (sub-)triangle.
+template <typename T, bool HAS_C>
+__device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64_t item, const T xi[3],
+                                      const T ni[3], T k, T gre, T gim, T& s1r, T& s1i, T& s2r,
+                                      T& s2i, int64_t& jout) {
+  const int64_t j = (int64_t)(item & ((uint64_t(1) << 26) - 1));
+  const int m = (int)((item >> 26) & 7u) + 1;
+  const int depth = (int)((item >> 29) & 15u);
+  const uint64_t path = item >> 33;
+  jout = j;
+  T v0[3], v1[3], v2[3];
+  item_triangle<T>(g, N, j, depth, path, v0, v1, v2);
+  T e1[3], e2[3], nj[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    e1[c] = v1[c] - v0[c];
+    e2[c] = v2[c] - v0[c];
+    nj[c] = g[(NX + c) * N + j];
+  }
+  const T area2 = T(2) * g[AREA * N + j] * (T)ldexp(1.0, -2 * depth);
+  const T nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
+  const int base = c_rule_off[m - 1];
+  const int np = m * m;
+  T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+  for (int q = 0; q < np; ++q) {
+    const T qa = RuleTab<T>::a(base + q), qb = RuleTab<T>::b(base + q), qw = RuleTab<T>::w(base + q);
+    T R[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[c] = (v0[c] + qa * e1[c] + qb * e2[c]) - xi[c];
+    const T r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    const T rinv = rsqrt_t(r2);
+    const T r = r2 * rinv;
+    T sn, cs;
+    sincos_t(k * r, &sn, &cs);
+    const T gs = qw * rinv * T(kInv4Pi);
+    const T Gr = gs * cs, Gi = gs * sn;
+    const T rny = (R[0] * nj[0] + R[1] * nj[1] + R[2] * nj[2]) * rinv;
+    const T rnx = (R[0] * ni[0] + R[1] * ni[1] + R[2] * ni[2]) * rinv;
+    // t1 = B rnx rny + a nn / r with a = (-1/r, k), B = (3/r^2 - k^2, -3k/r)
+    const T p = rnx * rny;
+    const T t1r = (T(3) * rinv * rinv - k * k) * p - nn * rinv * rinv;
+    const T t1i = -T(3) * k * rinv * p + k * nn * rinv;
+    // b1 = -a rny - gamma t1
+    const T b1r = rinv * rny - (gre * t1r - gim * t1i);
+    const T b1i = -k * rny - (gre * t1i + gim * t1r);
+    a1r += Gr * b1r - Gi * b1i;
+    a1i += Gr * b1i + Gi * b1r;
+    if (HAS_C) {
+      // b2 = 1 + gamma a rnx
+      const T b2r = T(1) + (-gre * rinv - gim * k) * rnx;
+      const T b2i = (gre * k - gim * rinv) * rnx;
+      a2r += Gr * b2r - Gi * b2i;
+      a2i += Gr * b2i + Gi * b2r;
+    }
+  }
+  s1r = a1r * area2;
+  s1i = a1i * area2;
+  s2r = a2r * area2;
+  s2i = a2i * area2;
+}
+
+template <typename T, bool HAS_C>
+__global__ __launch_bounds__(256) void k_near(NearLaunch L, const T* __restrict__ g,
+                                              const double2* __restrict__ x, double2* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= L.N) return;  // the whole wavefront leaves together
+  const int64_t N = L.N;
+  T xi[3], ni[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    xi[c] = g[(CX + c) * N + t];
+    ni[c] = g[(NX + c) * N + t];
+  }
+  const T k = (T)L.k, gre = (T)L.gre, gim = (T)L.gim;
+  T accr = 0, acci = 0;
+  const int64_t e = L.off[t + 1];
+  for (int64_t it = L.off[t] + lane; it < e; it += 64) {
+    T s1r, s1i, s2r, s2i;
+    int64_t j;
+    integrate_item<T, HAS_C>(g, N, L.items[it], xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, j);
+    T vr = s1r, vi = s1i;
+    if (HAS_C) {
+      const double2 c = L.cfac[j];
+      const T cr = (T)c.x, ci = (T)c.y;
+      vr += cr * s2r - ci * s2i;
+      vi += cr * s2i + ci * s2r;
+    }
+    const double2 xj = x[j];
+    const T xr = (T)xj.x, xim = (T)xj.y;
+    accr += vr * xr - vi * xim;
+    acci += vr * xim + vi * xr;
+  }
+  double sr = wave_sum((double)accr);
+  double si = wave_sum((double)acci);
+  if (lane == 0) {
+    const double2 d = L.diag[t];
+    const double2 xt = x[t];
+    y[t] = make_double2(d.x * xt.x - d.y * xt.y + sr, d.x * xt.y + d.y * xt.x + si);
+  }
+}
+
+// Conjugate transpose: items are indexed by source j ("targets" of this
+// launch are sources); the item's element field holds the collocation index i.
+// y_j = conj(A_jj) x_j + sum_i conj(K_ij) x_i.
+template <typename T, bool HAS_C>
+__global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restrict__ g,
+                                                  const double2* __restrict__ x, double2* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t jsrc = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (jsrc >= L.N) return;
+  const int64_t N = L.N;
+  const T k = (T)L.k, gre = (T)L.gre, gim = (T)L.gim;
+  T cr = 0, ci = 0;
+  if (HAS_C) {
+    const double2 c = L.cfac[jsrc];
+    cr = (T)c.x;
+    ci = (T)c.y;
+  }
+  T accr = 0, acci = 0;
+  const int64_t e = L.off[jsrc + 1];
+  for (int64_t it = L.off[jsrc] + lane; it < e; it += 64) {
+    const uint64_t raw = L.items[it];
+    const int64_t i = (int64_t)(raw & ((uint64_t(1) << 26) - 1));
+    // rebuild the forward item (source jsrc) and integrate from target i
+    const uint64_t item = (raw & ~((uint64_t(1) << 26) - 1)) | (uint64_t)jsrc;
+    T xi[3], ni[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xi[c] = g[(CX + c) * N + i];
+      ni[c] = g[(NX + c) * N + i];
+    }
+    T s1r, s1i, s2r, s2i;
+    int64_t jj;
+    integrate_item<T, HAS_C>(g, N, item, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, jj);
+    T vr = s1r, vi = s1i;
+    if (HAS_C) {
+      vr += cr * s2r - ci * s2i;
+      vi += cr * s2i + ci * s2r;
+    }
+    const double2 xv = x[i];
+    const T xr = (T)xv.x, xim = (T)xv.y;
+    // conj(v) * x
+    accr += vr * xr + vi * xim;
+    acci += vr * xim - vi * xr;
+  }
+  double sr = wave_sum((double)accr);
+  double si = wave_sum((double)acci);
+  if (lane == 0) {
+    const double2 d = L.diag[jsrc];
+    const double2 xt = x[jsrc];
+    y[jsrc] = make_double2(d.x * xt.x + d.y * xt.y + sr, d.x * xt.y - d.y * xt.x + si);
+  }
+}
+
+template <typename T>
+void near_dispatch(const NearLaunch& L, const T* g, const double2* x, double2* y, hipStream_t s, bool adj) {
+  if (L.N <= 0) return;
+  dim3 grid((unsigned)((L.N + 3) / 4)), block(256);
+  if (!adj) {
+    if (L.cfac) hipLaunchKernelGGL((k_near<T, true>), grid, block, 0, s, L, g, x, y);
+    else hipLaunchKernelGGL((k_near<T, false>), grid, block, 0, s, L, g, x, y);
+  } else {
+    if (L.cfac) hipLaunchKernelGGL((k_near_adj<T, true>), grid, block, 0, s, L, g, x, y);
+    else hipLaunchKernelGGL((k_near_adj<T, false>), grid, block, 0, s, L, g, x, y);
+  }
+}
+
+// ------------------------------------------------------------ self terms ---
+// G_ii by the six-triangle Duffy rule (Sec. 3.1.1); E_ii = sum over the
+// counter-clockwise edges of int (n x grad_y G) . dy plus k^2 G_ii
+// (Sec. 3.1.2); H_ii = H'_ii = 0.  Then
+// A_ii = (1 - gamma c_i)/2 + gamma E_ii + G_ii c_i.
+__global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict__ diag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.N) return;
+  const int64_t N = L.N;
+  const double* g = L.geom;
+  double P[3][3], x[3], n[3];
+  for (int v = 0; v < 3; ++v)
+    for (int c = 0; c < 3; ++c) P[v][c] = g[(P0X + 3 * v + c) * N + t];
+  for (int c = 0; c < 3; ++c) {
+    x[c] = g[(CX + c) * N + t];
+    n[c] = g[(NX + c) * N + t];
+  }
+  const double k = L.k;
+  double M[3][3];
+  for (int c = 0; c < 3; ++c) {
+    M[0][c] = 0.5 * (P[0][c] + P[1][c]);
+    M[1][c] = 0.5 * (P[1][c] + P[2][c]);
+    M[2][c] = 0.5 * (P[2][c] + P[0][c]);
+  }
+  const double* Q1s[6] = {P[0], M[0], P[1], M[1], P[2], M[2]};
+  const double* Q2s[6] = {M[0], P[1], M[1], P[2], M[2], P[0]};
+  double Gr = 0, Gi = 0;
+  for (int sidx = 0; sidx < 6; ++sidx) {
+    const double* Q1 = Q1s[sidx];
+    const double* Q2 = Q2s[sidx];
+    double a[3], b[3], d[3];
+    for (int c = 0; c < 3; ++c) {
+      a[c] = Q1[c] - x[c];
+      b[c] = Q2[c] - x[c];
+      d[c] = Q2[c] - Q1[c];
+    }
+    double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    const double As2 = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    for (int ia = 0; ia < L.self_n; ++ia) {
+      const double u = L.duffy_u[ia], wu = L.duffy_w[ia];
+      for (int ib = 0; ib < L.self_n; ++ib) {
+        const double v = L.duffy_u[ib], wv = L.duffy_w[ib];
+        double R[3];
+        for (int c = 0; c < 3; ++c) R[c] = u * (a[c] + v * d[c]);
+        const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+        double sn, cs;
+        sincos(k * r, &sn, &cs);
+        const double wgt = As2 * u * wu * wv * kInv4Pi / r;
+        Gr += wgt * cs;
+        Gi += wgt * sn;
+      }
+    }
+  }
+  double Er = 0, Ei = 0;
+  for (int e = 0; e < 3; ++e) {
+    const double* Pa = P[e];
+    const double* Pb = P[(e + 1) % 3];
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = Pb[c] - Pa[c];
+    // (n x R) . d
+    for (int q = 0; q < L.edge_pts; ++q) {
+      double R[3];
+      for (int c = 0; c < 3; ++c) R[c] = Pa[c] + L.edge_t[q] * d[c] - x[c];
+      const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+      const double rinv = 1.0 / r;
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      double nxR[3] = {n[1] * R[2] - n[2] * R[1], n[2] * R[0] - n[0] * R[2], n[0] * R[1] - n[1] * R[0]};
+      const double proj = nxR[0] * d[0] + nxR[1] * d[1] + nxR[2] * d[2];
+      // grad_y G = G (ik - 1/r) R / r, G = exp(ikr)/(4 pi r)
+      const double s = L.edge_w[q] * proj * kInv4Pi * rinv * rinv;
+      // exp(ikr) (ik - 1/r) = (cs + i sn)(-1/r + i k)
+      const double fr = -cs * rinv - sn * k;
+      const double fi = cs * k - sn * rinv;
+      Er += s * fr;
+      Ei += s * fi;
+    }
+  }
+  Er += k * k * Gr;
+  Ei += k * k * Gi;
+  double cr = 0, ci = 0;
+  if (L.cfac) {
+    cr = L.cfac[t].x;
+    ci = L.cfac[t].y;
+  }
+  // (1 - gamma c)/2 + gamma E + G c
+  const double gcr = L.gre * cr - L.gim * ci, gci = L.gre * ci + L.gim * cr;
+  double dr = 0.5 * (1.0 - gcr) + (L.gre * Er - L.gim * Ei) + (Gr * cr - Gi * ci);
+  double di = -0.5 * gci + (L.gre * Ei + L.gim * Er) + (Gr * ci + Gi * cr);
+  diag[t] = make_double2(dr, di);
+}
+
+// -------------------------------------------------------- small kernels ---
+__global__ void k_rhs_plane(int64_t N, const double* __restrict__ g, double k, double gre, double gim,
+                            double d0, double d1, double d2, double p0r, double p0i, double2* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double ph = k * (g[CX * N + t] * d0 + g[(CX + 1) * N + t] * d1 + g[(CX + 2) * N + t] * d2);
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  const double pr = p0r * cs - p0i * sn, pi = p0r * sn + p0i * cs;
+  const double dn = k * (g[NX * N + t] * d0 + g[(NX + 1) * N + t] * d1 + g[(NX + 2) * N + t] * d2);
+  // dp/dn = i dn p ; b = p - gamma dp/dn
+  const double qr = -dn * pi, qi = dn * pr;
+  out[t] = make_double2(pr - (gre * qr - gim * qi), pi - (gre * qi + gim * qr));
+}
+
+__global__ void k_rhs_point(int64_t N, const double* __restrict__ g, double k, double gre, double gim,
+                            double s0, double s1, double s2, double p0r, double p0i, double2* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double R0 = g[CX * N + t] - s0, R1 = g[(CX + 1) * N + t] - s1, R2 = g[(CX + 2) * N + t] - s2;
+  const double R = sqrt(R0 * R0 + R1 * R1 + R2 * R2);
+  double sn, cs;
+  sincos(k * R, &sn, &cs);
+  const double sc = kInv4Pi / R;
+  const double pr = sc * (p0r * cs - p0i * sn), pi = sc * (p0r * sn + p0i * cs);
+  const double rn = (R0 * g[NX * N + t] + R1 * g[(NX + 1) * N + t] + R2 * g[(NX + 2) * N + t]) / R;
+  // dp/dn = p (ik - 1/R) rn
+  const double fr = -rn / R, fi = k * rn;
+  const double qr = pr * fr - pi * fi, qi = pr * fi + pi * fr;
+  out[t] = make_double2(pr - (gre * qr - gim * qi), pi - (gre * qi + gim * qr));
+}
+
+__global__ void k_gather(int64_t N, const int64_t* __restrict__ perm, const double2* __restrict__ src,
+                         double2* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) dst[t] = src[perm[t]];
+}
+
+__global__ void k_scatter(int64_t N, const int64_t* __restrict__ perm, const double2* __restrict__ src,
+                          double2* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) dst[perm[t]] = src[t];
+}
+
+__global__ void k_cfac(int64_t N, const int64_t* __restrict__ perm, const double2* __restrict__ beta,
+                       double k, double2* __restrict__ cf) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double2 b = beta[perm[t]];
+  // c = -i k beta
+  cf[t] = make_double2(k * b.y, -k * b.x);
+}
+
+__global__ void k_velocity(int64_t N, const double2* __restrict__ beta, double inv_rc,
+                           const double2* __restrict__ p, double2* __restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double2 b = beta ? beta[t] : make_double2(0.0, 0.0);
+  const double2 q = p[t];
+  v[t] = make_double2(-inv_rc * (b.x * q.x - b.y * q.y), -inv_rc * (b.x * q.y + b.y * q.x));
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_near_f64(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
+  near_dispatch<double>(L, L.geom, x, y, s, false);
+}
+void launch_near_f32(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
+  near_dispatch<float>(L, L.geom32, x, y, s, false);
+}
+void launch_near_adj_f64(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
+  near_dispatch<double>(L, L.geom, x, y, s, true);
+}
+void launch_near_adj_f32(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
+  near_dispatch<float>(L, L.geom32, x, y, s, true);
+}
+
+void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s) {
+  if (L.N <= 0) return;
+  hipLaunchKernelGGL(k_self, dim3(blocks_for(L.N, 256)), dim3(256), 0, s, L, diag);
+}
+
+void launch_rhs_plane(int64_t N, const double* geom, double k, double gre, double gim, const double* d,
+                      double p0re, double p0im, double2* out, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_rhs_plane, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, geom, k, gre, gim,
+                     d[0], d[1], d[2], p0re, p0im, out);
+}
+
+void launch_rhs_point(int64_t N, const double* geom, double k, double gre, double gim, const double* x0,
+                      double p0re, double p0im, double2* out, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_rhs_point, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, geom, k, gre, gim,
+                     x0[0], x0[1], x0[2], p0re, p0im, out);
+}
+
+void launch_gather(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, perm, src, dst);
+}
+
+void launch_scatter(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, perm, src, dst);
+}
+
+void launch_cfac(int64_t N, const int64_t* perm, const double2* beta, double k, double2* cf,
+                 hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_cfac, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, perm, beta, k, cf);
+}
+
+void launch_velocity(int64_t N, const double2* beta, double rho_c, const double2* p, double2* v,
+                     hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_velocity, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, beta, 1.0 / rho_c, p, v);
+}
+
+}  // namespace bem

@@ -1,0 +1,185 @@
+// Krylov driver: restarted GMRES with classical Gram-Schmidt applied twice,
+// FP64 basis vectors and FP64 residuals (Sec. 3.2 uses CGS with a 1e-9
+// tolerance and a 250-iteration cap; GMRES takes its place here).  With the
+// mixed precision option the inner solves run on the complex-FP32 operator
+// inside an FP64 iterative-refinement loop: r = b - A x with the FP64
+// operator, inner GMRES on A d = r, x += d.
+#include <algorithm>
+#include <complex>
+
+#include "state.h"
+
+namespace bem {
+
+namespace {
+
+using cd = std::complex<double>;
+
+struct Work {
+  int64_t N;
+  int restart;
+  int nblk;
+};
+
+double vec_norm(bem_mesh* m, const double2* v, const Work& W, hipStream_t s) {
+  launch_multidot(W.N, 1, v, W.N, v, m->d_partial.p, W.nblk, s);
+  launch_reduce_partials(1, W.nblk, m->d_partial.p, m->d_h.p, s);
+  double2 h;
+  BEM_HIP(hipMemcpyAsync(&h, m->d_h.p, sizeof(double2), hipMemcpyDeviceToHost, s));
+  BEM_HIP(hipStreamSynchronize(s));
+  return std::sqrt(std::max(0.0, h.x));
+}
+
+// One restarted GMRES solve of A x = b with operator precision prec.  x holds
+// the initial guess (x_zero: treat it as zero).  Stops when the residual
+// estimate falls below tol_abs, or after maxit iterations in total.
+int gmres(bem_mesh* m, bem_precision prec, const double2* b, double2* x, bool x_zero, double tol_abs,
+          int maxit, const Work& W, hipStream_t s, bool* converged) {
+  const int64_t N = W.N;
+  const int R = W.restart;
+  double2* V = m->d_V.p;
+  double2* w = m->d_w.p;
+  double2* r = m->d_r.p;
+  double2* dh = m->d_h.p;  // [0, R+1): h1, [R+1, 2R+2): h2, [2R+2]: norm
+  int iters = 0;
+  *converged = false;
+  std::vector<cd> H((R + 1) * R), g(R + 1), cs(R), sn(R);
+  std::vector<double2> hh(2 * (R + 1) + 1);
+  for (;;) {
+    if (x_zero) {
+      BEM_HIP(hipMemcpyAsync(r, b, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
+      x_zero = false;
+    } else {
+      apply_tree(m, BEM_OP_A, prec, x, w, s);
+      launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), w, r, s);
+    }
+    double beta = vec_norm(m, r, W, s);
+    if (beta <= tol_abs) {
+      *converged = true;
+      return iters;
+    }
+    if (iters >= maxit) return iters;
+    launch_scale_copy(N, r, make_double2(1.0 / beta, 0.0), V, s);
+    std::fill(g.begin(), g.end(), cd(0));
+    g[0] = beta;
+    int jend = -1;
+    bool done = false;
+    for (int j = 0; j < R; ++j) {
+      apply_tree(m, BEM_OP_A, prec, V + (int64_t)j * N, w, s);
+      ++iters;
+      // classical Gram-Schmidt, twice
+      launch_multidot(N, j + 1, V, N, w, m->d_partial.p, W.nblk, s);
+      launch_reduce_partials(j + 1, W.nblk, m->d_partial.p, dh, s);
+      launch_multiaxpy(N, j + 1, V, N, dh, -1.0, w, s);
+      launch_multidot(N, j + 1, V, N, w, m->d_partial.p, W.nblk, s);
+      launch_reduce_partials(j + 1, W.nblk, m->d_partial.p, dh + (R + 1), s);
+      launch_multiaxpy(N, j + 1, V, N, dh + (R + 1), -1.0, w, s);
+      launch_multidot(N, 1, w, N, w, m->d_partial.p, W.nblk, s);
+      launch_reduce_partials(1, W.nblk, m->d_partial.p, dh + 2 * (R + 1), s);
+      BEM_HIP(hipMemcpyAsync(hh.data(), dh, hh.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+      BEM_HIP(hipStreamSynchronize(s));
+      const double hn = std::sqrt(std::max(0.0, hh[2 * (R + 1)].x));
+      for (int i = 0; i <= j; ++i) H[i * R + j] = cd(hh[i].x + hh[R + 1 + i].x, hh[i].y + hh[R + 1 + i].y);
+      H[(j + 1) * R + j] = hn;
+      if (hn > 0.0) launch_scale_copy(N, w, make_double2(1.0 / hn, 0.0), V + (int64_t)(j + 1) * N, s);
+      // apply the previous rotations and build the new one
+      for (int i = 0; i < j; ++i) {
+        cd a = H[i * R + j], bb = H[(i + 1) * R + j];
+        H[i * R + j] = std::conj(cs[i]) * a + std::conj(sn[i]) * bb;
+        H[(i + 1) * R + j] = -sn[i] * a + cs[i] * bb;
+      }
+      cd a = H[j * R + j], bb = H[(j + 1) * R + j];
+      double den = std::sqrt(std::norm(a) + std::norm(bb));
+      if (den == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = a / den;
+        sn[j] = bb / den;
+      }
+      H[j * R + j] = std::conj(cs[j]) * a + std::conj(sn[j]) * bb;
+      H[(j + 1) * R + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = std::conj(cs[j]) * g[j];
+      jend = j;
+      const double res = std::abs(g[j + 1]);
+      if (res <= tol_abs || iters >= maxit || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    // back substitution and update x += V y
+    const int nj = jend + 1;
+    std::vector<cd> y(nj);
+    for (int i = nj - 1; i >= 0; --i) {
+      cd acc = g[i];
+      for (int l = i + 1; l < nj; ++l) acc -= H[i * R + l] * y[l];
+      y[i] = acc / H[i * R + i];
+    }
+    std::vector<double2> yh(nj);
+    for (int i = 0; i < nj; ++i) yh[i] = make_double2(y[i].real(), y[i].imag());
+    BEM_HIP(hipMemcpyAsync(dh, yh.data(), nj * sizeof(double2), hipMemcpyHostToDevice, s));
+    launch_multiaxpy(N, nj, V, N, dh, 1.0, x, s);
+    BEM_HIP(hipStreamSynchronize(s));
+    if (done && iters >= maxit) {
+      // recompute the true residual to decide
+      apply_tree(m, BEM_OP_A, prec, x, w, s);
+      launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), w, r, s);
+      *converged = vec_norm(m, r, W, s) <= tol_abs;
+      return iters;
+    }
+  }
+}
+
+}  // namespace
+
+SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s) {
+  const int64_t N = m->N;
+  Work W{N, std::max(1, std::min(m->opt.gmres_restart, 200)), multidot_blocks(N)};
+  m->d_V.alloc((size_t)(W.restart + 1) * N);
+  m->d_w.alloc(N);
+  m->d_r.alloc(N);
+  m->d_tmp.alloc(N);
+  m->d_partial.alloc((size_t)(W.restart + 1) * W.nblk + 8);
+  m->d_h.alloc(2 * (W.restart + 1) + 8);
+  SolveResult out;
+  const double bnorm = vec_norm(m, b, W, s);
+  if (bnorm == 0.0) {
+    BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
+    out.converged = true;
+    return out;
+  }
+  const double tol = m->opt.gmres_tol;
+  if (m->opt.precision == BEM_PREC_FP64) {
+    bool conv = false;
+    out.iterations = gmres(m, BEM_PREC_FP64, b, x, true, tol * bnorm, m->opt.gmres_maxit, W, s, &conv);
+  } else {
+    // FP64 iterative refinement around the complex-FP32 operator
+    BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
+    BEM_HIP(hipMemcpyAsync(m->d_tmp.p, b, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    double2* rr = m->d_tmp.p;
+    double2* d = m->d_y.p;
+    for (int it = 0; it < std::max(1, m->opt.refine_maxit); ++it) {
+      double rn = vec_norm(m, rr, W, s);
+      if (rn <= tol * bnorm) break;
+      bool conv = false;
+      // save rr: gmres uses d_r internally
+      out.iterations += gmres(m, BEM_PREC_MIXED, rr, d, true, m->opt.inner_tol * rn,
+                              m->opt.gmres_maxit, W, s, &conv);
+      ++out.refinements;
+      launch_axpby(N, make_double2(1, 0), x, make_double2(1, 0), d, x, s);
+      apply_tree(m, BEM_OP_A, BEM_PREC_FP64, x, m->d_w.p, s);
+      launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), m->d_w.p, rr, s);
+      if (out.iterations >= m->opt.gmres_maxit) break;
+    }
+  }
+  // true FP64 residual
+  apply_tree(m, BEM_OP_A, BEM_PREC_FP64, x, m->d_w.p, s);
+  launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), m->d_w.p, m->d_r.p, s);
+  out.rel_residual = vec_norm(m, m->d_r.p, W, s) / bnorm;
+  out.converged = out.rel_residual <= tol * (1.0 + 1e-6);
+  return out;
+}
+
+}  // namespace bem

@@ -1,0 +1,75 @@
+// The opaque bem_mesh object and internal entry points shared by api.cpp,
+// solver.cpp and the FMM files.
+#pragma once
+
+#include <memory>
+
+#include "common.h"
+#include "device.h"
+
+namespace bem {
+struct FmmState;                                     // fmm_setup.cpp
+void fmm_destroy(FmmState* f);
+}  // namespace bem
+
+struct bem_mesh {
+  bem_options opt{};
+  int64_t N = 0;
+  bool fmm = false;
+  bem::Tree tree;
+  bem::Geometry g;                 // tree order
+  bem::NearPlan plan;              // items by target
+  bool have_plan_t = false;
+  bem::NearPlan plan_t;            // items by source (conjugate transpose)
+  int64_t bad_element = -1;
+
+  bem::DevBuf<double> d_geom;
+  bem::DevBuf<float> d_geom32;
+  bem::DevBuf<int64_t> d_perm;
+  bem::DevBuf<int64_t> d_off, d_off_t;
+  bem::DevBuf<uint64_t> d_items, d_items_t;
+  bem::DevBuf<double> d_duffy_u, d_duffy_w, d_edge_t, d_edge_w;
+
+  // per-problem state
+  bool have_problem = false;
+  double k = 0.0;
+  double gre = 0.0, gim = 0.0;     // coupling gamma
+  bool have_beta = false;
+  bem::DevBuf<double2> d_beta;     // caller order
+  bem::DevBuf<double2> d_cfac;     // tree order, c_j = -i k beta_j
+  bem::DevBuf<double2> d_diag;     // tree order, A_ii
+
+  // work vectors (tree order)
+  bem::DevBuf<double2> d_x, d_y, d_r, d_b, d_sol, d_tmp;
+  bem::DevBuf<double2> d_V, d_w, d_partial, d_h;
+
+  bem::FmmState* fmm_state = nullptr;
+  int fmm_L[16] = {0};
+
+  ~bem_mesh() { bem::fmm_destroy(fmm_state); }
+};
+
+namespace bem {
+
+// tree-order operator application (x_t, y_t device, length N)
+void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s);
+// part 0: whole operator; 1: diagonal + near field; 2: far field only
+void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
+                     hipStream_t s);
+
+// FMM far field: y += far(x), tree order.  No-op if the mesh has no FMM.
+void fmm_setup_problem(bem_mesh* m, hipStream_t s);
+void fmm_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s);
+size_t fmm_bytes(const bem_mesh* m);
+
+struct SolveResult {
+  int iterations = 0;
+  int refinements = 0;
+  double rel_residual = 0.0;
+  bool converged = false;
+};
+SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s);
+
+void ensure_transposed_plan(bem_mesh* m, hipStream_t s);
+
+}  // namespace bem

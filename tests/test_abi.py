@@ -1,0 +1,98 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and rejects invalid arguments before any device work."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if not f.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", f)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(bem_\w+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def bem():
+    from paper_2312_00005_amd import bemfmm
+    return bemfmm
+
+
+def test_every_declared_symbol_is_exported(bem):
+    declared = _declared()
+    assert declared, "no declarations found"
+    import ctypes
+    lib = ctypes.CDLL(bem.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(bem.exported_symbols())
+
+
+def test_presets(bem):
+    p = bem.bem_options_default("paper")
+    assert p.quad_eps == 1e-3 and p.quad_m_max == 6 and p.subdiv_ratio == 1.3
+    assert p.max_subdiv == 15 and p.self_n == 4 and p.edge_parts == 4 and p.edge_gauss == 3
+    assert p.l_factor == 1.8 and p.l_min == 8 and abs(p.admissibility - 2 / 3 ** 0.5) < 1e-15
+    assert p.gmres_maxit == 250
+    t = bem.bem_options_default("tight")
+    assert t.quad_split_on_cap == 1 and t.admissibility == 3.0
+    m = bem.bem_options_default("mixed")
+    assert m.precision == bem.BEM_PREC_MIXED
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_options_default("nope")
+    assert e.value.status == bem.BEM_E_ARG
+
+
+def test_degenerate_triangle_is_a_mesh_error(bem):
+    nodes, tris = synth.icosphere(1)
+    tris = tris.copy()
+    tris[7] = [tris[7][0], tris[7][0], tris[7][1]]
+    with pytest.raises(bem.BemError) as e:
+        bem.Mesh(nodes, tris, "paper", use_fmm=0)
+    assert e.value.status == bem.BEM_E_MESH
+    assert "7" in e.value.message
+
+
+def test_invalid_arguments(bem):
+    nodes, tris = synth.icosphere(1)
+    bad = tris.copy()
+    bad[0, 0] = 10 ** 6
+    with pytest.raises(bem.BemError) as e:
+        bem.Mesh(nodes, bad, "paper", use_fmm=0)
+    assert e.value.status == bem.BEM_E_ARG
+    nn = nodes.copy()
+    nn[0, 0] = np.nan
+    with pytest.raises(bem.BemError) as e:
+        bem.Mesh(nn, tris, "paper", use_fmm=0)
+    assert e.value.status == bem.BEM_E_ARG
+    with pytest.raises(bem.BemError) as e:
+        bem.Mesh(nodes, tris, "paper", use_fmm=0, quad_m_max=9)
+    assert e.value.status == bem.BEM_E_ARG
+    with pytest.raises(bem.BemError) as e:
+        bem.Mesh(nodes, tris, "paper", use_fmm=0, gmres_restart=0)
+    assert e.value.status == bem.BEM_E_ARG
+    with pytest.raises(bem.BemError):
+        bem.bem_mesh_create(3, None, 1, None, bem.bem_options_default("paper"))
+
+
+def test_subdivision_overflow_names_the_element(bem):
+    # two coplanar triangles whose centroids nearly coincide with a vertex of
+    # the other never reach r~ >= 1.3 within two splits
+    nodes = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1e-7, 1e-7, 0.0], [1, 1e-7, 0], [1e-7, 1, 0]],
+                     dtype=np.float64)
+    tris = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    with pytest.raises(bem.BemError) as e:
+        bem.Mesh(nodes, tris, "paper", use_fmm=0, max_subdiv=2)
+    assert e.value.status == bem.BEM_E_MESH

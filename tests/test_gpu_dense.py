@@ -1,0 +1,156 @@
+"""GPU parity of the near-field kernels with every pair in the near field
+(use_fmm = 0, i.e. the dense operator applied on the fly), against the CPU
+oracle's dense matrix, through the C ABI.
+
+Tolerances: FP64 paths agree with the oracle to rounding (1e-12 relative to
+max|y|: the same rules on both sides, only summation order and libm differ);
+the complex-FP32 path to 2e-5 (single-precision kernel evaluation and
+accumulation over ~1e3 terms)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import operator as op
+from oracle import sphere
+from oracle.geometry import element_geometry
+from oracle.presets import preset
+from gpu_util import to_dev, to_host, rel_max, rel_l2, announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bem():
+    from paper_2312_00005_amd import bemfmm
+    return bemfmm
+
+
+def _mesh(name):
+    if name == "ico3":
+        return synth.icosphere(3)
+    if name == "ragged":
+        # an open surface with N = 1277: not a multiple of the 4 targets per
+        # block nor of the 64 lanes per wavefront
+        n, t = synth.icosphere(3)
+        keep = np.ones(len(t), bool)
+        keep[[5, 400, 999]] = False
+        return n, t[keep]
+    if name == "oct":
+        return synth.octahedron()
+    if name == "patch":
+        return synth.flat_patch(0.3)
+    raise KeyError(name)
+
+
+_ORACLE = {}
+
+
+def oracle_case(mesh, pre, k, with_beta):
+    key = (mesh, pre, k, with_beta)
+    if key not in _ORACLE:
+        nodes, tris = _mesh(mesh)
+        g = element_geometry(nodes, tris)
+        beta = None
+        if with_beta:
+            u = synth.uniform01(len(tris), seed=1)
+            beta = (1.0 + 0.5 * u) + 0.25j * u
+        A = op.dense(g, k, beta=beta, p=preset(pre))
+        _ORACLE[key] = (nodes, tris, g, beta, A)
+    return _ORACLE[key]
+
+
+def gpu_mesh(bem, nodes, tris, pre, k, beta):
+    m = bem.Mesh(nodes, tris, pre, use_fmm=0)
+    m.set_problem(k, None if beta is None else to_dev(beta))
+    return m
+
+
+CASES = [("ico3", "paper", 1.0, False), ("ico3", "tight", 4.0, False),
+         ("ragged", "paper", 6.0, True), ("oct", "paper", 2.0, False), ("patch", "tight", 3.0, True)]
+
+
+@pytest.mark.parametrize("mesh,pre,k,with_beta", CASES)
+def test_apply_matches_oracle(bem, mesh, pre, k, with_beta):
+    announce(f"dense apply {mesh} {pre} k={k} beta={with_beta}")
+    nodes, tris, g, beta, A = oracle_case(mesh, pre, k, with_beta)
+    m = gpu_mesh(bem, nodes, tris, pre, k, beta)
+    x = synth.complex_normal(len(tris), seed=4)
+    y = to_host(m.apply(to_dev(x)))
+    assert rel_max(y, A @ x) < 1e-12
+    # conjugate transpose
+    yh = to_host(m.apply(to_dev(x), op="AH"))
+    assert rel_max(yh, A.conj().T @ x) < 1e-12
+    # complex-FP32 arithmetic (self terms stay FP64)
+    y32 = to_host(m.apply(to_dev(x), prec="mixed"))
+    assert rel_max(y32, A @ x) < 2e-5
+    y32h = to_host(m.apply(to_dev(x), op="AH", prec="mixed"))
+    assert rel_max(y32h, A.conj().T @ x) < 2e-5
+
+
+def test_apply_is_bitwise_deterministic(bem):
+    announce("dense determinism")
+    nodes, tris, g, beta, A = oracle_case("ico3", "paper", 1.0, False)
+    m = gpu_mesh(bem, nodes, tris, "paper", 1.0, None)
+    x = to_dev(synth.complex_normal(len(tris), seed=4))
+    a = to_host(m.apply(x))
+    b = to_host(m.apply(x))
+    assert np.array_equal(a, b)
+
+
+def test_rhs_matches_oracle(bem):
+    announce("rhs")
+    nodes, tris = _mesh("ico3")
+    g = element_geometry(nodes, tris)
+    k = 2.5
+    m = gpu_mesh(bem, nodes, tris, "paper", k, None)
+    d = np.array([0.3, -0.4, 0.866])
+    d /= np.linalg.norm(d)
+    b = to_host(m.rhs_plane_wave(tuple(d), 1.5 - 0.5j))
+    assert rel_max(b, op.rhs_plane_wave(g, k, d, P0=1.5 - 0.5j)) < 1e-13
+    xs = (0.2, 1.7, -0.4)
+    b = to_host(m.rhs_point_source(xs, 2.0))
+    assert rel_max(b, op.rhs_point_source(g, k, xs, P0=2.0)) < 1e-13
+
+
+def test_solve_matches_lu_and_analytic(bem):
+    announce("dense solve ico3 paper k=1")
+    nodes, tris, g, beta, A = oracle_case("ico3", "paper", 1.0, False)
+    m = bem.Mesh(nodes, tris, "paper", use_fmm=0, gmres_tol=1e-12)
+    m.set_problem(1.0)
+    rhs = m.rhs_plane_wave((0.0, 0.0, 1.0))
+    p, v, info = m.solve(rhs, rho_c=343.0 * 1.3)
+    p = to_host(p)
+    ref = op.lu_solve(A, op.rhs_plane_wave(g, 1.0, [0, 0, 1]))
+    assert rel_l2(p, ref) < 1e-10
+    assert info["rel_residual"] < 1e-12
+    assert np.all(to_host(v) == 0)
+    an = sphere.pressure(g["x"] / np.linalg.norm(g["x"], axis=1, keepdims=True), 1.0)
+    assert rel_l2(p, an) < 5e-3
+
+
+def test_solve_mixed_refinement(bem):
+    announce("dense mixed solve ragged paper k=6 beta")
+    nodes, tris, g, beta, A = oracle_case("ragged", "paper", 6.0, True)
+    m = bem.Mesh(nodes, tris, "paper", use_fmm=0, precision=bem.BEM_PREC_MIXED, gmres_tol=1e-10,
+                 inner_tol=1e-3)
+    m.set_problem(6.0, to_dev(beta))
+    rhs = m.rhs_plane_wave((1.0, 0.0, 0.0))
+    p, v, info = m.solve(rhs, rho_c=2.0)
+    ref = op.lu_solve(A, op.rhs_plane_wave(g, 6.0, [1, 0, 0]))
+    assert rel_l2(to_host(p), ref) < 1e-8
+    assert info["refinements"] >= 1
+    assert rel_l2(to_host(v), -beta / 2.0 * ref) < 1e-8
+
+
+def test_noconv_status(bem):
+    announce("noconv")
+    nodes, tris = _mesh("ico3")
+    m = bem.Mesh(nodes, tris, "paper", use_fmm=0, gmres_maxit=1, gmres_tol=1e-14)
+    m.set_problem(1.0)
+    rhs = m.rhs_plane_wave((0.0, 0.0, 1.0))
+    with pytest.raises(bem.BemError) as e:
+        m.solve(rhs)
+    assert e.value.status == bem.BEM_E_NOCONV
+    p, _, info = m.solve(rhs, allow_noconv=True)
+    assert info["warnings"] & bem.BEM_WARN_NOT_CONVERGED
