@@ -107,6 +107,9 @@ typedef struct bem_options {
   double gmres_tol;         /* relative residual target                       */
   int32_t refine_maxit;     /* outer refinement steps (mixed precision)      */
   double inner_tol;         /* inner GMRES tolerance (mixed precision)       */
+  double l_eps_mixed;       /* expansion accuracy of the complex-FP32 operator;
+                               its L is also capped so that FP32 rounding times
+                               (2L+1)|h_L(k X_min)| stays below l_eps_mixed/10 */
 } bem_options;
 
 typedef struct bem_solve_info {
@@ -120,6 +123,8 @@ typedef struct bem_solve_info {
   int64_t quad_points;      /* near-field quadrature points per apply        */
   double rel_residual;      /* final ||b - A x|| / ||b|| (FP64 operator)      */
   uint32_t warnings;        /* BEM_WARN_* bits                                */
+  int32_t L_mixed[16];      /* expansion length per level of the complex-FP32
+                               operator (mixed path), root first             */
 } bem_solve_info;
 
 typedef struct bem_mesh bem_mesh;
@@ -187,6 +192,31 @@ bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,
 size_t bem_workspace_bytes(const bem_mesh* m);
 
 void bem_mesh_destroy(bem_mesh* m);
+
+/* ---- host-only inspection of the frequency-independent plan -------------
+ * bem_tree_build runs the same geometry, cluster-tree and near-field-plan
+ * construction as bem_mesh_create but touches no device; it exists so that
+ * the tree and plan can be inspected and tested without a GPU.  Levels are
+ * numbered from the root (0).  Arrays are written by the caller-sized output
+ * pointers (any may be NULL): z[3 nc], r[nc], ebeg/eend/parent[nc] (element
+ * ranges in tree order; parent index on the level above, -1 at the root),
+ * il_off/near_off[nc + 1] and il/near (cluster indices, CSR). */
+typedef struct bem_tree bem_tree;
+bem_status bem_tree_build(int64_t n_nodes, const double* xyz, int64_t n_tri,
+                          const int32_t* tri, const bem_options* o, bem_tree** out);
+int32_t bem_tree_levels(const bem_tree* t);
+bem_status bem_tree_level(const bem_tree* t, int32_t level, int64_t* nc,
+                          int64_t* n_il, int64_t* n_near);
+bem_status bem_tree_level_data(const bem_tree* t, int32_t level, double* z, double* r,
+                               int64_t* ebeg, int64_t* eend, int64_t* parent,
+                               int64_t* il_off, int64_t* il, int64_t* near_off,
+                               int64_t* near);
+/* perm[t] = caller index of the element at tree position t (host int64[n_tri]) */
+bem_status bem_tree_perm(const bem_tree* t, int64_t* perm);
+/* near pairs (self included), quadrature items and points of one application */
+bem_status bem_tree_plan_stats(const bem_tree* t, int64_t* pairs, int64_t* items,
+                               int64_t* points);
+void bem_tree_destroy(bem_tree* t);
 
 const char* bem_last_error(void);
 

@@ -92,6 +92,7 @@ def offdiag_integrals(x, nx, P0, P1, P2, ny, A, k, p, stats=None):
     area = np.asarray(A, dtype=np.float64).copy()
     depth = np.zeros(P, dtype=np.int64)
     n_points = 0
+    n_items = 0
     while idx.size:
         mid = (v0 + v1 + v2) / 3.0
         d = x[idx] - mid
@@ -116,6 +117,7 @@ def offdiag_integrals(x, nx, P0, P1, P2, ny, A, k, p, stats=None):
             vals = _apply_rule(x[ii], nx[ii], v0[sel], v1[sel], v2[sel],
                                ny[ii], area[sel], int(mv), k)
             n_points += sel.size * int(mv) * int(mv)
+            n_items += sel.size
             for q in range(4):
                 np.add.at(out[q], ii, vals[q])
         s = np.nonzero(split)[0]
@@ -131,6 +133,7 @@ def offdiag_integrals(x, nx, P0, P1, P2, ny, A, k, p, stats=None):
         depth = np.tile(depth[s] + 1, 4)
     if stats is not None:
         stats["points"] = stats.get("points", 0) + n_points
+        stats["items"] = stats.get("items", 0) + n_items
     return out
 
 

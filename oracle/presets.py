@@ -6,7 +6,7 @@ order capped, split while r~ < 1.3, at most 15 splits, 4x4 Duffy rule,
 (Farfieldcond) (factor 1.8, minimum expansion length 8, admissibility
 2/sqrt(3)).
 
-``tight``: the same rules with a 1e-7 order tolerance, splitting instead of
+``tight``: the same rules with a 1e-8 order tolerance, splitting instead of
 capping the order (the higher-accuracy variant of Sec. 4.1.2), finer
 singular and edge rules, and a wider admissibility with an accuracy-driven
 expansion length so that the FMM agrees with the dense operator to ~1e-7.
@@ -24,19 +24,19 @@ PRESETS = {
     "paper": dict(quad_eps=1e-3, m_max=6, split_on_cap=False, subdiv_ratio=1.3,
                   max_subdiv=15, self_n=4, edge_parts=4, edge_gauss=3,
                   admissibility=2.0 / math.sqrt(3.0), l_factor=1.8, l_min=8,
-                  l_mode=0, fmm_eps=1e-3, t_order=4),
-    "tight": dict(quad_eps=1e-7, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
+                  l_mode=0, fmm_eps=1e-3, fmm_eps_mixed=1e-3, t_order=4),
+    "tight": dict(quad_eps=1e-8, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
                   max_subdiv=15, self_n=12, edge_parts=8, edge_gauss=6,
                   admissibility=3.0, l_factor=1.8, l_min=8,
-                  l_mode=1, fmm_eps=1e-7, t_order=6),
-    "mixed": dict(quad_eps=1e-7, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
+                  l_mode=1, fmm_eps=1e-7, fmm_eps_mixed=1e-4, t_order=6),
+    "mixed": dict(quad_eps=1e-8, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
                   max_subdiv=15, self_n=12, edge_parts=8, edge_gauss=6,
                   admissibility=3.0, l_factor=1.8, l_min=8,
-                  l_mode=1, fmm_eps=1e-7, t_order=6),
+                  l_mode=1, fmm_eps=1e-7, fmm_eps_mixed=1e-4, t_order=6),
     "reference": dict(quad_eps=1e-12, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
                       max_subdiv=15, self_n=20, edge_parts=16, edge_gauss=10,
                       admissibility=3.0, l_factor=1.8, l_min=8,
-                      l_mode=1, fmm_eps=1e-10, t_order=8),
+                      l_mode=1, fmm_eps=1e-10, fmm_eps_mixed=1e-4, t_order=8),
 }
 
 

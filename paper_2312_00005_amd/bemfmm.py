@@ -58,6 +58,7 @@ class bem_options(ctypes.Structure):
         ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
         ("gmres_maxit", ctypes.c_int32), ("gmres_tol", ctypes.c_double),
         ("refine_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+        ("l_eps_mixed", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -70,13 +71,14 @@ class bem_solve_info(ctypes.Structure):
         ("L", ctypes.c_int32 * 16), ("clusters", ctypes.c_int32 * 16),
         ("near_pairs", ctypes.c_int64), ("near_items", ctypes.c_int64),
         ("quad_points", ctypes.c_int64), ("rel_residual", ctypes.c_double),
-        ("warnings", ctypes.c_uint32),
+        ("warnings", ctypes.c_uint32), ("L_mixed", ctypes.c_int32 * 16),
     ]
 
     def as_dict(self):
         nl = self.levels
         return {"iterations": self.iterations, "refinements": self.refinements, "levels": nl,
-                "L": list(self.L[:nl]), "clusters": list(self.clusters[:nl]),
+                "L": list(self.L[:nl]), "L_mixed": list(self.L_mixed[:nl]),
+                "clusters": list(self.clusters[:nl]),
                 "near_pairs": self.near_pairs, "near_items": self.near_items,
                 "quad_points": self.quad_points, "rel_residual": self.rel_residual,
                 "warnings": self.warnings}
@@ -101,6 +103,13 @@ _SIGS = {
     "bem_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "bem_mesh_destroy": (None, [_vp]),
     "bem_last_error": (ctypes.c_char_p, []),
+    "bem_tree_build": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), ctypes.POINTER(_vp)]),
+    "bem_tree_levels": (_i32, [_vp]),
+    "bem_tree_level": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "bem_tree_level_data": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bem_tree_perm": (_i32, [_vp, _vp]),
+    "bem_tree_plan_stats": (_i32, [_vp, _vp, _vp, _vp]),
+    "bem_tree_destroy": (None, [_vp]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -188,6 +197,88 @@ def bem_mesh_destroy(mesh):
 def bem_last_error():
     m = _lib.bem_last_error()
     return m.decode() if m else ""
+
+
+def bem_tree_build(n_nodes, xyz_ptr, n_tri, tri_ptr, options):
+    out = _vp()
+    _check(_lib.bem_tree_build(n_nodes, xyz_ptr, n_tri, tri_ptr, ctypes.byref(options), ctypes.byref(out)))
+    return out.value
+
+
+def bem_tree_levels(tree):
+    return _lib.bem_tree_levels(tree)
+
+
+def bem_tree_level(tree, level):
+    nc, nil, nnr = _i64(), _i64(), _i64()
+    _check(_lib.bem_tree_level(tree, level, ctypes.byref(nc), ctypes.byref(nil), ctypes.byref(nnr)))
+    return nc.value, nil.value, nnr.value
+
+
+def bem_tree_level_data(tree, level):
+    import numpy as np
+    nc, nil, nnr = bem_tree_level(tree, level)
+    out = {"z": np.zeros((nc, 3)), "r": np.zeros(nc), "ebeg": np.zeros(nc, np.int64),
+           "eend": np.zeros(nc, np.int64), "parent": np.zeros(nc, np.int64),
+           "il_off": np.zeros(nc + 1, np.int64), "il": np.zeros(max(nil, 1), np.int64),
+           "near_off": np.zeros(nc + 1, np.int64), "near": np.zeros(max(nnr, 1), np.int64)}
+    p = {k_: v.ctypes.data for k_, v in out.items()}
+    _check(_lib.bem_tree_level_data(tree, level, p["z"], p["r"], p["ebeg"], p["eend"], p["parent"],
+                                    p["il_off"], p["il"], p["near_off"], p["near"]))
+    out["il"] = out["il"][:nil]
+    out["near"] = out["near"][:nnr]
+    return out
+
+
+def bem_tree_perm(tree, n_tri):
+    import numpy as np
+    perm = np.zeros(n_tri, np.int64)
+    _check(_lib.bem_tree_perm(tree, perm.ctypes.data))
+    return perm
+
+
+def bem_tree_plan_stats(tree):
+    a, b_, c = _i64(), _i64(), _i64()
+    _check(_lib.bem_tree_plan_stats(tree, ctypes.byref(a), ctypes.byref(b_), ctypes.byref(c)))
+    return {"near_pairs": a.value, "near_items": b_.value, "quad_points": c.value}
+
+
+def bem_tree_destroy(tree):
+    _lib.bem_tree_destroy(tree)
+
+
+class HostTree:
+    """Host-only cluster tree and near-field plan (no GPU needed)."""
+
+    def __init__(self, nodes, tris, options=None, **overrides):
+        import numpy as np
+        if options is None or isinstance(options, str):
+            options = bem_options_default(options or "paper")
+        for key, val in overrides.items():
+            setattr(options, key, val)
+        self._nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        self._tris = np.ascontiguousarray(tris, dtype=np.int32)
+        self.n = int(self._tris.shape[0])
+        self._h = None
+        self._h = bem_tree_build(self._nodes.shape[0], self._nodes.ctypes.data, self.n,
+                                 self._tris.ctypes.data, options)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                bem_tree_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def levels(self):
+        return [bem_tree_level_data(self._h, l) for l in range(bem_tree_levels(self._h))]
+
+    def perm(self):
+        return bem_tree_perm(self._h, self.n)
+
+    def plan_stats(self):
+        return bem_tree_plan_stats(self._h)
 
 
 # ---- torch convenience layer -------------------------------------------------

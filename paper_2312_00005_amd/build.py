@@ -17,6 +17,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbemfmm.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("BEM_CXX", "/opt/rocm/llvm/bin/clang++")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
@@ -24,7 +25,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"
 # packed-FP32 instructions are disabled for all device code
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
           "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
-HOST = ["-ffp-contract=off", "-fopenmp"]
+# host-only C++ (tree, plan, driver): no device code, no FP contraction so that
+# the plan's floating-point decisions follow the written expressions exactly
+HOST = ["-ffp-contract=off", "-fopenmp", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 
 
 def sources():
@@ -40,7 +43,7 @@ def _compile(src):
     if src.endswith(".hip"):
         cmd = [HIPCC] + COMMON + DEVICE + ["-c", src, "-o", obj]
     else:
-        cmd = [HIPCC] + COMMON + HOST + ["-c", src, "-o", obj]
+        cmd = [CXX] + COMMON + HOST + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -59,6 +59,7 @@ void set_paper(bem_options* o) {
   o->gmres_tol = 1e-9;
   o->refine_maxit = 20;
   o->inner_tol = 1e-3;
+  o->l_eps_mixed = 1e-3;
 }
 
 void upload_rules() {
@@ -187,6 +188,70 @@ void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
 
 }  // namespace bem
 
+namespace {
+
+// Geometry, cluster tree and near-field plan on the host (no device work).
+void build_host(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri, const bem_options& o,
+                Tree& tree, Geometry& g, NearPlan& plan, int64_t& bad_element) {
+  std::vector<int64_t> ident(n_tri);
+  for (int64_t i = 0; i < n_tri; ++i) ident[i] = i;
+  Geometry gc;
+  try {
+    gc = build_geometry(xyz, n_nodes, tri, n_tri, ident);
+  } catch (const Error& e) {
+    bad_element = e.element;
+    throw;
+  }
+  std::vector<int64_t> src_off, src_beg, src_end, tgt_group(n_tri, 0);
+  if (o.use_fmm) {
+    int levels = o.levels > 0 ? o.levels : default_levels(n_tri);
+    tree = build_tree(gc, levels, o.root_box_edge, o.leaf_size, o.admissibility);
+    g = build_geometry(xyz, n_nodes, tri, n_tri, tree.perm);
+    const Level& leaf = tree.lv.back();
+    src_off.assign(leaf.nc + 1, 0);
+    for (int64_t c = 0; c < leaf.nc; ++c) {
+      for (int64_t e = leaf.ebeg[c]; e < leaf.eend[c]; ++e) tgt_group[e] = c;
+      for (int64_t q = leaf.nr_off[c]; q < leaf.nr_off[c + 1]; ++q) {
+        int64_t nb = leaf.nr[q];
+        src_beg.push_back(leaf.ebeg[nb]);
+        src_end.push_back(leaf.eend[nb]);
+      }
+      src_off[c + 1] = (int64_t)src_beg.size();
+    }
+  } else {
+    tree.perm = ident;
+    tree.inv = ident;
+    g = std::move(gc);
+    src_off = {0, 1};
+    src_beg = {0};
+    src_end = {n_tri};
+  }
+  QuadParams q{o.quad_eps, o.quad_m_max, o.quad_split_on_cap, o.subdiv_ratio, o.max_subdiv};
+  try {
+    plan = build_near_plan(g, q, src_off, src_beg, src_end, tgt_group);
+  } catch (const Error& e) {
+    bad_element = e.element >= 0 ? tree.perm[e.element] : -1;
+    throw Error(e.code, "more than max_subdiv nested subdivisions for element " + std::to_string(bad_element),
+                bad_element);
+  }
+}
+
+void validate_mesh_args(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri) {
+  if (!xyz || !tri || n_nodes < 3 || n_tri < 1) throw Error(BEM_E_ARG, "empty or NULL mesh");
+  for (int64_t i = 0; i < 3 * n_nodes; ++i)
+    if (!std::isfinite(xyz[i])) throw Error(BEM_E_ARG, "non-finite node coordinate");
+}
+
+}  // namespace
+
+struct bem_tree {
+  int64_t N = 0;
+  bool fmm = false;
+  Tree tree;
+  Geometry g;
+  NearPlan plan;
+};
+
 extern "C" {
 
 const char* bem_last_error(void) { return g_last_error.c_str(); }
@@ -203,12 +268,13 @@ bem_status bem_options_default(bem_options* o, const char* preset) {
       o->l_mode = 1;
       o->l_eps = 1e-7;
       o->t_order = 6;
-      o->quad_eps = 1e-7;
+      o->quad_eps = 1e-8;
       o->quad_split_on_cap = 1;
       o->self_n = 12;
       o->edge_parts = 8;
       o->edge_gauss = 6;
       o->gmres_tol = 1e-6;
+      o->l_eps_mixed = 1e-4;
       if (p == "mixed") o->precision = BEM_PREC_MIXED;
       return BEM_OK;
     }
@@ -221,55 +287,13 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
   return guarded([&]() -> bem_status {
     if (!out) return fail(BEM_E_ARG, "out is NULL");
     *out = nullptr;
-    if (!xyz || !tri || n_nodes < 3 || n_tri < 1) return fail(BEM_E_ARG, "empty or NULL mesh");
+    validate_mesh_args(n_nodes, xyz, n_tri, tri);
     check_options(o);
-    for (int64_t i = 0; i < 3 * n_nodes; ++i)
-      if (!std::isfinite(xyz[i])) return fail(BEM_E_ARG, "non-finite node coordinate");
     auto m = std::make_unique<bem_mesh>();
     m->opt = *o;
     m->N = n_tri;
-    std::vector<int64_t> ident(n_tri);
-    for (int64_t i = 0; i < n_tri; ++i) ident[i] = i;
-    Geometry gc;
-    try {
-      gc = build_geometry(xyz, n_nodes, tri, n_tri, ident);
-    } catch (const Error& e) {
-      m->bad_element = e.element;
-      throw;
-    }
     m->fmm = o->use_fmm != 0;
-    std::vector<int64_t> src_off, src_beg, src_end, tgt_group(n_tri, 0);
-    if (m->fmm) {
-      int levels = o->levels > 0 ? o->levels : default_levels(n_tri);
-      m->tree = build_tree(gc, levels, o->root_box_edge, o->leaf_size, o->admissibility);
-      m->g = build_geometry(xyz, n_nodes, tri, n_tri, m->tree.perm);
-      const Level& leaf = m->tree.lv.back();
-      src_off.assign(leaf.nc + 1, 0);
-      for (int64_t c = 0; c < leaf.nc; ++c) {
-        for (int64_t e = leaf.ebeg[c]; e < leaf.eend[c]; ++e) tgt_group[e] = c;
-        for (int64_t q = leaf.nr_off[c]; q < leaf.nr_off[c + 1]; ++q) {
-          int64_t nb = leaf.nr[q];
-          src_beg.push_back(leaf.ebeg[nb]);
-          src_end.push_back(leaf.eend[nb]);
-        }
-        src_off[c + 1] = (int64_t)src_beg.size();
-      }
-    } else {
-      m->tree.perm = ident;
-      m->tree.inv = ident;
-      m->g = std::move(gc);
-      src_off = {0, 1};
-      src_beg = {0};
-      src_end = {n_tri};
-    }
-    QuadParams q{o->quad_eps, o->quad_m_max, o->quad_split_on_cap, o->subdiv_ratio, o->max_subdiv};
-    try {
-      m->plan = build_near_plan(m->g, q, src_off, src_beg, src_end, tgt_group);
-    } catch (const Error& e) {
-      m->bad_element = e.element >= 0 ? m->tree.perm[e.element] : -1;
-      std::string msg = "more than max_subdiv nested subdivisions for element " + std::to_string(m->bad_element);
-      throw Error(e.code, msg, m->bad_element);
-    }
+    build_host(n_nodes, xyz, n_tri, tri, *o, m->tree, m->g, m->plan, m->bad_element);
     upload_rules();
     hipStream_t s = nullptr;
     m->d_geom.upload(m->g.f, s);
@@ -428,6 +452,7 @@ bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out, bem_c128
         for (int l = 0; l < info->levels && l < 16; ++l) {
           info->clusters[l] = (int32_t)m->tree.lv[l].nc;
           info->L[l] = m->fmm_L[l];
+          info->L_mixed[l] = m->fmm_L32[l];
           if (m->fmm_L[l] > 30) info->warnings |= BEM_WARN_LARGE_L;
         }
       }
@@ -469,6 +494,78 @@ size_t bem_workspace_bytes(const bem_mesh* m) {
              m->d_partial.bytes() + m->d_h.bytes();
   return b + fmm_bytes(m);
 }
+
+bem_status bem_tree_build(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
+                          const bem_options* o, bem_tree** out) {
+  return guarded([&]() -> bem_status {
+    if (!out) return fail(BEM_E_ARG, "out is NULL");
+    *out = nullptr;
+    validate_mesh_args(n_nodes, xyz, n_tri, tri);
+    check_options(o);
+    auto t = std::make_unique<bem_tree>();
+    t->N = n_tri;
+    t->fmm = o->use_fmm != 0;
+    int64_t bad = -1;
+    build_host(n_nodes, xyz, n_tri, tri, *o, t->tree, t->g, t->plan, bad);
+    *out = t.release();
+    return BEM_OK;
+  });
+}
+
+int32_t bem_tree_levels(const bem_tree* t) { return (t && t->fmm) ? (int32_t)t->tree.lv.size() : 0; }
+
+bem_status bem_tree_level(const bem_tree* t, int32_t level, int64_t* nc, int64_t* n_il, int64_t* n_near) {
+  return guarded([&]() -> bem_status {
+    if (!t || level < 0 || level >= bem_tree_levels(t)) return fail(BEM_E_ARG, "invalid tree or level");
+    const Level& L = t->tree.lv[level];
+    if (nc) *nc = L.nc;
+    if (n_il) *n_il = (int64_t)L.il.size();
+    if (n_near) *n_near = (int64_t)L.nr.size();
+    return BEM_OK;
+  });
+}
+
+bem_status bem_tree_level_data(const bem_tree* t, int32_t level, double* z, double* r, int64_t* ebeg,
+                               int64_t* eend, int64_t* parent, int64_t* il_off, int64_t* il, int64_t* near_off,
+                               int64_t* near) {
+  return guarded([&]() -> bem_status {
+    if (!t || level < 0 || level >= bem_tree_levels(t)) return fail(BEM_E_ARG, "invalid tree or level");
+    const Level& L = t->tree.lv[level];
+    auto cp = [](auto* dst, const auto& v) {
+      if (dst) std::copy(v.begin(), v.end(), dst);
+    };
+    cp(z, L.z);
+    cp(r, L.r);
+    cp(ebeg, L.ebeg);
+    cp(eend, L.eend);
+    cp(parent, L.parent);
+    cp(il_off, L.il_off);
+    cp(il, L.il);
+    cp(near_off, L.nr_off);
+    cp(near, L.nr);
+    return BEM_OK;
+  });
+}
+
+bem_status bem_tree_perm(const bem_tree* t, int64_t* perm) {
+  return guarded([&]() -> bem_status {
+    if (!t || !perm) return fail(BEM_E_ARG, "NULL argument");
+    std::copy(t->tree.perm.begin(), t->tree.perm.end(), perm);
+    return BEM_OK;
+  });
+}
+
+bem_status bem_tree_plan_stats(const bem_tree* t, int64_t* pairs, int64_t* items, int64_t* points) {
+  return guarded([&]() -> bem_status {
+    if (!t) return fail(BEM_E_ARG, "NULL argument");
+    if (pairs) *pairs = t->plan.pairs;
+    if (items) *items = (int64_t)t->plan.items.size();
+    if (points) *points = t->plan.points;
+    return BEM_OK;
+  });
+}
+
+void bem_tree_destroy(bem_tree* t) { delete t; }
 
 void bem_mesh_destroy(bem_mesh* m) { delete m; }
 

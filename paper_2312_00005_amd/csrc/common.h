@@ -37,6 +37,17 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
@@ -50,10 +61,14 @@ struct DevBuf {
     BEM_HIP(hipMalloc(&p, count * sizeof(T)));
     n = count;
   }
+  // Copy a host vector to the device and wait for the copy (setup paths only:
+  // the caller's vector may be released right after the call).
   void upload(const std::vector<T>& h, hipStream_t s = nullptr) {
     alloc(h.size());
-    if (!h.empty())
+    if (!h.empty()) {
       BEM_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      BEM_HIP(hipStreamSynchronize(s));
+    }
   }
   size_t bytes() const { return n * sizeof(T); }
 };

@@ -1,0 +1,512 @@
+// Multilevel FMM far field on the cluster tree (Sec. 3.3).
+//
+// Per application:
+//   leaf aggregation   Sig_c(nu) = sum_{j in c} T'[j][nu] x_j
+//   upward pass        Sig_p = sum_children shift_c * Interp(Sig_c)
+//   translation        Loc_m(nu) = sum_{n in IL(m)} D[m,n][nu] Sig_n(nu)     (every level)
+//   downward pass      Loc_c += Anterp(conj(shift_c) * Loc_p)
+//   disaggregation     y_i += sum_nu S'[i][nu] Loc_c(i)(nu)
+// with T' (element integral of the outgoing plane wave times the combined
+// source factor c_j + ik s.n_j) and S' (quadrature weight, ik/(16 pi^2) and
+// the target factor 1 - gamma ik s.n_i) precomputed per frequency.
+//
+// Interpolation between a child grid (L_c) and a parent grid (L_p) is the
+// band-limited resampling in spherical harmonics of degree < L_c, factored
+// into an azimuthal DFT, one dense (L_p x L_c) matrix per azimuthal order and
+// an inverse DFT; anterpolation is its weighted transpose.  When the grids
+// coincide only the shift is applied.
+//
+// Every output element has a single owner thread or wavefront and sums in a
+// fixed order (no atomics): results are bit-reproducible.
+#include "fmm.h"
+
+#include <cmath>
+
+namespace bem {
+
+namespace {
+
+constexpr double kInv16Pi2 = 0.0063325739776461107152;  // 1 / (16 pi^2)
+enum { P0X = 0, P1X = 3, P2X = 6, NX = 9, AREA = 12, CX = 13 };
+
+__device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
+__device__ inline float2 mk(float a, float b) { return make_float2(a, b); }
+template <typename V>
+__device__ inline V cmul(V a, V b) { return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// conj(a) * b
+template <typename V>
+__device__ inline V cmulc(V a, V b) { return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+template <typename V>
+__device__ inline V cadd(V a, V b) { return mk(a.x + b.x, a.y + b.y); }
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename V> __device__ inline V from_d2(double2 v);
+template <> __device__ inline double2 from_d2<double2>(double2 v) { return v; }
+template <> __device__ inline float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------ setup ---
+__global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t* __restrict__ ec,
+                         const double* __restrict__ zc, const double* __restrict__ s, int nu,
+                         const double2* __restrict__ cfac, double k, const double* __restrict__ ra,
+                         const double* __restrict__ rb, const double* __restrict__ rw, int nq,
+                         double2* __restrict__ T64, float2* __restrict__ T32) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * nu) return;
+  const int64_t j = idx / nu;
+  const int v = (int)(idx - j * nu);
+  const int64_t c = ec[j];
+  const double sx = s[3 * v], sy = s[3 * v + 1], sz = s[3 * v + 2];
+  double P0[3], e1[3], e2[3];
+  for (int d = 0; d < 3; ++d) {
+    P0[d] = g[(P0X + d) * N + j];
+    e1[d] = g[(P1X + d) * N + j] - P0[d];
+    e2[d] = g[(P2X + d) * N + j] - P0[d];
+  }
+  // exp(ik (z - y).s) = exp(ik (z - P0).s) exp(-ik (a e1 + b e2).s)
+  const double base = k * ((zc[3 * c] - P0[0]) * sx + (zc[3 * c + 1] - P0[1]) * sy + (zc[3 * c + 2] - P0[2]) * sz);
+  const double pe1 = k * (e1[0] * sx + e1[1] * sy + e1[2] * sz);
+  const double pe2 = k * (e2[0] * sx + e2[1] * sy + e2[2] * sz);
+  double ar = 0.0, ai = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    double sn, cs;
+    sincos(base - ra[q] * pe1 - rb[q] * pe2, &sn, &cs);
+    ar += rw[q] * cs;
+    ai += rw[q] * sn;
+  }
+  const double a2 = 2.0 * g[AREA * N + j];
+  ar *= a2;
+  ai *= a2;
+  // factor c_j + ik s.n_j
+  const double sn_ = sx * g[NX * N + j] + sy * g[(NX + 1) * N + j] + sz * g[(NX + 2) * N + j];
+  double fr = 0.0, fi = k * sn_;
+  if (cfac) {
+    fr += cfac[j].x;
+    fi += cfac[j].y;
+  }
+  const double tr = ar * fr - ai * fi, ti = ar * fi + ai * fr;
+  if (T64) T64[idx] = make_double2(tr, ti);
+  if (T32) T32[idx] = make_float2((float)tr, (float)ti);
+}
+
+__global__ void k_leaf_S(int64_t N, const double* __restrict__ g, const int64_t* __restrict__ ec,
+                         const double* __restrict__ zc, const double* __restrict__ s,
+                         const double* __restrict__ w, int nu, double k, double gre, double gim,
+                         double2* __restrict__ S64, float2* __restrict__ S32) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * nu) return;
+  const int64_t i = idx / nu;
+  const int v = (int)(idx - i * nu);
+  const int64_t c = ec[i];
+  const double sx = s[3 * v], sy = s[3 * v + 1], sz = s[3 * v + 2];
+  const double ph = k * ((g[CX * N + i] - zc[3 * c]) * sx + (g[(CX + 1) * N + i] - zc[3 * c + 1]) * sy +
+                         (g[(CX + 2) * N + i] - zc[3 * c + 2]) * sz);
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  const double sdn = sx * g[NX * N + i] + sy * g[(NX + 1) * N + i] + sz * g[(NX + 2) * N + i];
+  // (1 - gamma ik s.n): gamma ik = -k gim + i k gre
+  const double fr = 1.0 + k * gim * sdn, fi = -k * gre * sdn;
+  // prefactor ik w / (16 pi^2)
+  const double pre = k * w[v] * kInv16Pi2;
+  // i pre (fr + i fi)(cs + i sn)
+  const double ur = fr * cs - fi * sn, ui = fr * sn + fi * cs;
+  const double r = -pre * ui, im = pre * ur;
+  if (S64) S64[idx] = make_double2(r, im);
+  if (S32) S32[idx] = make_float2((float)r, (float)im);
+}
+
+// one block per interaction pair; h_l by upward recurrence in shared memory
+__global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64_t* __restrict__ pm,
+                                                     const int64_t* __restrict__ pn,
+                                                     const double* __restrict__ z,
+                                                     const double* __restrict__ s, int nu, int L, double k,
+                                                     double2* __restrict__ D64, float2* __restrict__ D32) {
+  extern __shared__ double2 coef[];  // L + 1 values i^l (2l+1) h_l(k|X|)
+  const int64_t q = blockIdx.x;
+  if (q >= npairs) return;
+  const int64_t a = pm[q], b = pn[q];
+  const double X0 = z[3 * a] - z[3 * b], X1 = z[3 * a + 1] - z[3 * b + 1], X2 = z[3 * a + 2] - z[3 * b + 2];
+  const double r = sqrt(X0 * X0 + X1 * X1 + X2 * X2);
+  if (threadIdx.x == 0) {
+    const double x = k * r;
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    double h0r = sn / x, h0i = -cs / x;
+    double h1r = (sn - x * cs) / (x * x), h1i = -(cs + x * sn) / (x * x);
+    for (int l = 0; l <= L; ++l) {
+      double hr, hi;
+      if (l == 0) { hr = h0r; hi = h0i; }
+      else if (l == 1) { hr = h1r; hi = h1i; }
+      else {
+        const double f = (2.0 * (l - 1) + 1.0) / x;
+        hr = f * h1r - h0r;
+        hi = f * h1i - h0i;
+        h0r = h1r; h0i = h1i;
+        h1r = hr; h1i = hi;
+      }
+      // i^l
+      double cr, ci;
+      switch (l & 3) {
+        case 0: cr = hr; ci = hi; break;
+        case 1: cr = -hi; ci = hr; break;
+        case 2: cr = -hr; ci = -hi; break;
+        default: cr = hi; ci = -hr; break;
+      }
+      coef[l] = make_double2((2.0 * l + 1.0) * cr, (2.0 * l + 1.0) * ci);
+    }
+  }
+  __syncthreads();
+  const double u0 = X0 / r, u1 = X1 / r, u2 = X2 / r;
+  for (int v = threadIdx.x; v < nu; v += blockDim.x) {
+    const double ct = s[3 * v] * u0 + s[3 * v + 1] * u1 + s[3 * v + 2] * u2;
+    double pm1 = 1.0, p = ct;
+    double dr = coef[0].x, di = coef[0].y;
+    if (L >= 1) {
+      dr += coef[1].x * ct;
+      di += coef[1].y * ct;
+    }
+    for (int l = 1; l < L; ++l) {
+      const double pn1 = ((2.0 * l + 1.0) * ct * p - l * pm1) / (l + 1.0);
+      pm1 = p;
+      p = pn1;
+      dr += coef[l + 1].x * p;
+      di += coef[l + 1].y * p;
+    }
+    if (D64) D64[q * nu + v] = make_double2(dr, di);
+    if (D32) D32[q * nu + v] = make_float2((float)dr, (float)di);
+  }
+}
+
+__global__ void k_shift(int64_t nchild, const int64_t* __restrict__ parent, const double* __restrict__ zp,
+                        const double* __restrict__ zc, const double* __restrict__ s, int nu, double k,
+                        double2* __restrict__ S64, float2* __restrict__ S32) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nchild * nu) return;
+  const int64_t c = idx / nu;
+  const int v = (int)(idx - c * nu);
+  const int64_t p = parent[c];
+  const double ph = k * ((zp[3 * p] - zc[3 * c]) * s[3 * v] + (zp[3 * p + 1] - zc[3 * c + 1]) * s[3 * v + 1] +
+                         (zp[3 * p + 2] - zc[3 * c + 2]) * s[3 * v + 2]);
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  if (S64) S64[idx] = make_double2(cs, sn);
+  if (S32) S32[idx] = make_float2((float)cs, (float)sn);
+}
+
+// ------------------------------------------------------------ apply ---
+// CONJ: use conj(Tm) (the conjugate transpose of disaggregation)
+template <typename T, typename V, bool CONJ>
+__global__ __launch_bounds__(256) void k_aggregate(const int64_t* __restrict__ ebeg,
+                                                   const int64_t* __restrict__ eend, int nu,
+                                                   const V* __restrict__ Tm, const double2* __restrict__ x,
+                                                   V* __restrict__ sig) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (v >= nu) return;
+  V acc = mk(T(0), T(0));
+  for (int64_t j = ebeg[c]; j < eend[c]; ++j) {
+    const V t = Tm[j * nu + v];
+    acc = cadd(acc, CONJ ? cmulc(t, from_d2<V>(x[j])) : cmul(t, from_d2<V>(x[j])));
+  }
+  sig[c * nu + v] = acc;
+}
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// CONJ: use conj(Sm) (the conjugate transpose of aggregation)
+template <typename T, typename V, bool CONJ>
+__global__ __launch_bounds__(256) void k_disaggregate(int64_t N, const int64_t* __restrict__ ec, int nu,
+                                                      const V* __restrict__ Sm, const V* __restrict__ loc,
+                                                      double2* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= N) return;
+  const int64_t c = ec[i];
+  T ar = 0, ai = 0;
+  for (int v = lane; v < nu; v += 64) {
+    const V a = Sm[i * nu + v], b = loc[c * nu + v];
+    const T ay = CONJ ? -a.y : a.y;
+    ar += a.x * b.x - ay * b.y;
+    ai += a.x * b.y + ay * b.x;
+  }
+  const double sr = wsum((double)ar), si = wsum((double)ai);
+  if (lane == 0) {
+    double2 o = y[i];
+    y[i] = make_double2(o.x + sr, o.y + si);
+  }
+}
+
+// tpos == NULL: loc_m = sum_q D[q] sig_il[q] over m's pairs q;
+// tpos != NULL: conjugate transpose, loc_m = sum_q conj(D[tpos[q]]) sig_il[q]
+// where tpos[q] is the position of the reversed pair (il[q], m).
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_translate(const int64_t* __restrict__ il_off,
+                                                   const int64_t* __restrict__ il,
+                                                   const int64_t* __restrict__ tpos, int nu,
+                                                   const V* __restrict__ D, const V* __restrict__ sig,
+                                                   V* __restrict__ loc) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = blockIdx.y;
+  if (v >= nu) return;
+  V acc = mk(T(0), T(0));
+  if (!tpos) {
+    for (int64_t q = il_off[m]; q < il_off[m + 1]; ++q) acc = cadd(acc, cmul(D[q * nu + v], sig[il[q] * nu + v]));
+  } else {
+    for (int64_t q = il_off[m]; q < il_off[m + 1]; ++q)
+      acc = cadd(acc, cmulc(D[tpos[q] * nu + v], sig[il[q] * nu + v]));
+  }
+  loc[m * nu + v] = acc;
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_up_equal(const int64_t* __restrict__ cbeg,
+                                                  const int64_t* __restrict__ cend, int nu,
+                                                  const V* __restrict__ shift, const V* __restrict__ sigc,
+                                                  V* __restrict__ sigp) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = blockIdx.y;
+  if (v >= nu) return;
+  V acc = mk(T(0), T(0));
+  for (int64_t c = cbeg[p]; c < cend[p]; ++c) acc = cadd(acc, cmul(shift[c * nu + v], sigc[c * nu + v]));
+  sigp[p * nu + v] = acc;
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_down_equal(const int64_t* __restrict__ parent, int nu,
+                                                    const V* __restrict__ shift, const V* __restrict__ locp,
+                                                    V* __restrict__ locc) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (v >= nu) return;
+  const V add = cmulc(shift[c * nu + v], locp[parent[c] * nu + v]);
+  locc[c * nu + v] = cadd(locc[c * nu + v], add);
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_dft(int64_t total, int nt, int nj, int nm, const V* __restrict__ in,
+                                             const V* __restrict__ shift, const int64_t* __restrict__ parent,
+                                             int mode, const V* __restrict__ E, V* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int mi = (int)(idx % nm);
+  const int64_t ct = idx / nm;
+  const int t = (int)(ct % nt);
+  const int64_t c = ct / nt;
+  V acc = mk(T(0), T(0));
+  const int64_t row = (int64_t)t * nj;
+  if (mode == 0) {
+    const V* src = in + c * (int64_t)nt * nj + row;
+    for (int j = 0; j < nj; ++j) acc = cadd(acc, cmul(src[j], E[(int64_t)mi * nj + j]));
+  } else {
+    const V* src = in + parent[c] * (int64_t)nt * nj + row;
+    const V* sh = shift + c * (int64_t)nt * nj + row;
+    for (int j = 0; j < nj; ++j) acc = cadd(acc, cmul(cmulc(sh[j], src[j]), E[(int64_t)mi * nj + j]));
+  }
+  out[idx] = acc;
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_theta(int64_t total, int nto, int nti, int nm, int mhalf,
+                                               const T* __restrict__ M, const V* __restrict__ in,
+                                               V* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int mi = (int)(idx % nm);
+  const int64_t ct = idx / nm;
+  const int to = (int)(ct % nto);
+  const int64_t c = ct / nto;
+  int am = mi - mhalf;
+  if (am < 0) am = -am;
+  const T* Mr = M + ((int64_t)am * nto + to) * nti;
+  const V* src = in + c * (int64_t)nti * nm + mi;
+  V acc = mk(T(0), T(0));
+  for (int ti = 0; ti < nti; ++ti) {
+    const V a = src[(int64_t)ti * nm];
+    acc = mk(acc.x + Mr[ti] * a.x, acc.y + Mr[ti] * a.y);
+  }
+  out[idx] = acc;
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_up_idft(int64_t total, const int64_t* __restrict__ cbeg,
+                                                 const int64_t* __restrict__ cend, int nt, int nj, int nm,
+                                                 const V* __restrict__ G, const V* __restrict__ E,
+                                                 const V* __restrict__ shift, V* __restrict__ sigp) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int j = (int)(idx % nj);
+  const int64_t pt = idx / nj;
+  const int t = (int)(pt % nt);
+  const int64_t p = pt / nt;
+  V acc = mk(T(0), T(0));
+  for (int64_t c = cbeg[p]; c < cend[p]; ++c) {
+    const V* g = G + (c * nt + t) * (int64_t)nm;
+    V s = mk(T(0), T(0));
+    for (int mi = 0; mi < nm; ++mi) s = cadd(s, cmul(g[mi], E[(int64_t)mi * nj + j]));
+    acc = cadd(acc, cmul(shift[(c * nt + t) * (int64_t)nj + j], s));
+  }
+  sigp[idx] = acc;
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_down_idft(int64_t total, int nt, int nj, int nm,
+                                                   const V* __restrict__ K, const V* __restrict__ E,
+                                                   V* __restrict__ locc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int j = (int)(idx % nj);
+  const int64_t ct = idx / nj;
+  const V* kk = K + ct * (int64_t)nm;
+  V s = mk(T(0), T(0));
+  for (int mi = 0; mi < nm; ++mi) s = cadd(s, cmul(kk[mi], E[(int64_t)mi * nj + j]));
+  locc[idx] = cadd(locc[idx], s);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers ---
+void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
+                       int nu, const double2* cfac, double k, const double* ra, const double* rb,
+                       const double* rw, int nq, double2* T64, float2* T32, hipStream_t st) {
+  const int64_t tot = N * nu;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_leaf_T, dim3(nblk(tot, 256)), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac, k, ra, rb,
+                     rw, nq, T64, T32);
+}
+
+void launch_fmm_leaf_S(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
+                       const double* w, int nu, double k, double gre, double gim, double2* S64, float2* S32,
+                       hipStream_t st) {
+  const int64_t tot = N * nu;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_leaf_S, dim3(nblk(tot, 256)), dim3(256), 0, st, N, geom, ec, zc, s, w, nu, k, gre, gim,
+                     S64, S32);
+}
+
+void launch_fmm_translation(int64_t npairs, const int64_t* pm, const int64_t* pn, const double* z,
+                            const double* s, int nu, int L, double k, double2* D64, float2* D32,
+                            hipStream_t st) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_translation, dim3((unsigned)npairs), dim3(256), (L + 1) * sizeof(double2), st, npairs,
+                     pm, pn, z, s, nu, L, k, D64, D32);
+}
+
+void launch_fmm_shift(int64_t nchild, const int64_t* parent, const double* zp, const double* zc,
+                      const double* s, int nu, double k, double2* S64, float2* S32, hipStream_t st) {
+  const int64_t tot = nchild * nu;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_shift, dim3(nblk(tot, 256)), dim3(256), 0, st, nchild, parent, zp, zc, s, nu, k, S64,
+                     S32);
+}
+
+template <typename T, typename V>
+void launch_fmm_aggregate(int64_t nclust, const int64_t* ebeg, const int64_t* eend, int nu, const V* Tm,
+                          const double2* x, V* sig, bool conj_rows, hipStream_t st) {
+  if (nclust <= 0) return;
+  if (conj_rows)
+    hipLaunchKernelGGL((k_aggregate<T, V, true>), dim3(nblk(nu, 256), (unsigned)nclust), dim3(256), 0, st, ebeg,
+                       eend, nu, Tm, x, sig);
+  else
+    hipLaunchKernelGGL((k_aggregate<T, V, false>), dim3(nblk(nu, 256), (unsigned)nclust), dim3(256), 0, st, ebeg,
+                       eend, nu, Tm, x, sig);
+}
+
+template <typename T, typename V>
+void launch_fmm_disaggregate(int64_t N, const int64_t* ec, int nu, const V* Sm, const V* loc, double2* y,
+                             bool conj_rows, hipStream_t st) {
+  if (N <= 0) return;
+  if (conj_rows)
+    hipLaunchKernelGGL((k_disaggregate<T, V, true>), dim3(nblk(N, 4)), dim3(256), 0, st, N, ec, nu, Sm, loc, y);
+  else
+    hipLaunchKernelGGL((k_disaggregate<T, V, false>), dim3(nblk(N, 4)), dim3(256), 0, st, N, ec, nu, Sm, loc, y);
+}
+
+template <typename T, typename V>
+void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* tpos, int nu,
+                          const V* D, const V* sig, V* loc, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL((k_translate<T, V>), dim3(nblk(nu, 256), (unsigned)nc), dim3(256), 0, st, il_off, il, tpos,
+                     nu, D, sig, loc);
+}
+
+template <typename T, typename V>
+void launch_fmm_up_equal(int64_t np, const int64_t* cbeg, const int64_t* cend, int nu, const V* shift,
+                         const V* sigc, V* sigp, hipStream_t st) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL((k_up_equal<T, V>), dim3(nblk(nu, 256), (unsigned)np), dim3(256), 0, st, cbeg, cend, nu,
+                     shift, sigc, sigp);
+}
+
+template <typename T, typename V>
+void launch_fmm_down_equal(int64_t nchild, const int64_t* parent, int nu, const V* shift, const V* locp,
+                           V* locc, hipStream_t st) {
+  if (nchild <= 0) return;
+  hipLaunchKernelGGL((k_down_equal<T, V>), dim3(nblk(nu, 256), (unsigned)nchild), dim3(256), 0, st, parent, nu,
+                     shift, locp, locc);
+}
+
+template <typename T, typename V>
+void launch_fmm_dft(int64_t nc, int nt, int nj, int nm, const V* in, const V* shift, const int64_t* parent,
+                    int mode, const V* E, V* out, hipStream_t st) {
+  const int64_t tot = nc * nt * (int64_t)nm;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL((k_dft<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, nt, nj, nm, in, shift, parent,
+                     mode, E, out);
+}
+
+template <typename T, typename V>
+void launch_fmm_theta(int64_t nc, int nto, int nti, int nm, int mhalf, const T* M, const V* in, V* out,
+                      hipStream_t st) {
+  const int64_t tot = nc * nto * (int64_t)nm;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL((k_theta<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, nto, nti, nm, mhalf, M, in,
+                     out);
+}
+
+template <typename T, typename V>
+void launch_fmm_up_idft(int64_t np, const int64_t* cbeg, const int64_t* cend, int nt, int nj, int nm,
+                        const V* G, const V* E, const V* shift, V* sigp, hipStream_t st) {
+  const int64_t tot = np * nt * (int64_t)nj;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL((k_up_idft<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, cbeg, cend, nt, nj, nm, G,
+                     E, shift, sigp);
+}
+
+template <typename T, typename V>
+void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const V* E, V* locc,
+                          hipStream_t st) {
+  const int64_t tot = nc * nt * (int64_t)nj;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL((k_down_idft<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, nt, nj, nm, K, E, locc);
+}
+
+#define BEM_FMM_INST(T, V)                                                                                    \
+  template void launch_fmm_aggregate<T, V>(int64_t, const int64_t*, const int64_t*, int, const V*,            \
+                                           const double2*, V*, bool, hipStream_t);                            \
+  template void launch_fmm_disaggregate<T, V>(int64_t, const int64_t*, int, const V*, const V*, double2*,     \
+                                              bool, hipStream_t);                                             \
+  template void launch_fmm_translate<T, V>(int64_t, const int64_t*, const int64_t*, const int64_t*, int,      \
+                                           const V*, const V*, V*, hipStream_t);                              \
+  template void launch_fmm_up_equal<T, V>(int64_t, const int64_t*, const int64_t*, int, const V*, const V*,   \
+                                          V*, hipStream_t);                                                   \
+  template void launch_fmm_down_equal<T, V>(int64_t, const int64_t*, int, const V*, const V*, V*,             \
+                                            hipStream_t);                                                     \
+  template void launch_fmm_dft<T, V>(int64_t, int, int, int, const V*, const V*, const int64_t*, int,         \
+                                     const V*, V*, hipStream_t);                                              \
+  template void launch_fmm_theta<T, V>(int64_t, int, int, int, int, const T*, const V*, V*, hipStream_t);     \
+  template void launch_fmm_up_idft<T, V>(int64_t, const int64_t*, const int64_t*, int, int, int, const V*,    \
+                                         const V*, const V*, V*, hipStream_t);                                \
+  template void launch_fmm_down_idft<T, V>(int64_t, int, int, int, const V*, const V*, V*, hipStream_t);
+
+BEM_FMM_INST(double, double2)
+BEM_FMM_INST(float, float2)
+
+}  // namespace bem

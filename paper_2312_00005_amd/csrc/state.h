@@ -44,7 +44,8 @@ struct bem_mesh {
   bem::DevBuf<double2> d_V, d_w, d_partial, d_h;
 
   bem::FmmState* fmm_state = nullptr;
-  int fmm_L[16] = {0};
+  int fmm_L[16] = {0};     // FP64 operator
+  int fmm_L32[16] = {0};   // complex-FP32 operator of the mixed path
 
   ~bem_mesh() { bem::fmm_destroy(fmm_state); }
 };
