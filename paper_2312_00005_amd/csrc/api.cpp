@@ -141,12 +141,14 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   L.gim = m->gim;
   if (op == BEM_OP_A) {
     L.off = m->d_off.p;
+    L.seg = m->d_seg.p;
     L.items = m->d_items.p;
     if (prec == BEM_PREC_FP64) launch_near_f64(L, x, y, s);
     else launch_near_f32(L, x, y, s);
   } else {
     ensure_transposed_plan(m, s);
     L.off = m->d_off_t.p;
+    L.seg = m->d_seg_t.p;
     L.items = m->d_items_t.p;
     if (prec == BEM_PREC_FP64) launch_near_adj_f64(L, x, y, s);
     else launch_near_adj_f32(L, x, y, s);
@@ -179,8 +181,10 @@ void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
   T.pairs = P.pairs;
   T.points = P.points;
   T.max_m = P.max_m;
+  build_segments(T, N);
   m->plan_t = std::move(T);
   m->d_off_t.upload(m->plan_t.off, s);
+  m->d_seg_t.upload(m->plan_t.seg, s);
   m->d_items_t.upload(m->plan_t.items, s);
   BEM_HIP(hipStreamSynchronize(s));
   m->have_plan_t = true;
@@ -301,6 +305,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_geom32.upload(g32, s);
     m->d_perm.upload(m->tree.perm, s);
     m->d_off.upload(m->plan.off, s);
+    m->d_seg.upload(m->plan.seg, s);
     m->d_items.upload(m->plan.items, s);
     std::vector<double> u, w;
     gauss_legendre01(o->self_n, u, w);
@@ -488,7 +493,7 @@ bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,
 size_t bem_workspace_bytes(const bem_mesh* m) {
   if (!m) return 0;
   size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_perm.bytes() + m->d_off.bytes() +
-             m->d_items.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
+             m->d_items.bytes() + m->d_seg.bytes() + m->d_seg_t.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
              m->d_cfac.bytes() + m->d_diag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
              m->d_partial.bytes() + m->d_h.bytes();

@@ -128,6 +128,7 @@ Tree build_tree(const Geometry& gc, int levels, double root_edge, int leaf_size,
 //   bits 33..62  path, two bits per level (child index 0..3), level 0 lowest
 struct NearPlan {
   std::vector<int64_t> off;     // per target (tree order), size N+1
+  std::vector<int64_t> seg;     // per target 9 offsets: first item of order 1..8, then the end
   std::vector<uint64_t> items;
   int64_t pairs = 0;            // near pairs including self pairs
   int64_t points = 0;           // quadrature points per application
@@ -144,6 +145,9 @@ struct QuadParams {
 
 // targets: element positions (tree order); for target t the sources are
 // [src_ranges) given by a callback-free CSR: src_off/src_beg/src_end.
+// Per-target offsets of the rule-order segments of an item list sorted by order.
+void build_segments(NearPlan& P, int64_t N);
+
 NearPlan build_near_plan(const Geometry& g, const QuadParams& q,
                          const std::vector<int64_t>& tgt_src_off,
                          const std::vector<int64_t>& src_beg,

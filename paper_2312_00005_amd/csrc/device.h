@@ -17,6 +17,7 @@ struct NearLaunch {
   const double* geom;     // G_NFIELDS * N, tree order
   const float* geom32;    // same fields in float (mixed path)
   const int64_t* off;     // N + 1
+  const int64_t* seg;     // N * 9: start of the order-1..8 items of each target, then its end
   const uint64_t* items;
   const double2* cfac;    // c_j, tree order (nullptr: sound-hard everywhere)
   const double2* diag;    // A_ii, tree order

@@ -48,16 +48,17 @@ void launch_fmm_up_equal(int64_t np, const int64_t* cbeg, const int64_t* cend, i
 template <typename T, typename V>
 void launch_fmm_down_equal(int64_t nchild, const int64_t* parent, int nu, const V* shift, const V* locp,
                            V* locc, hipStream_t st);
-// F[c][t][mi] = sum_j in[c][t][j] E[mi][j]; optional per-(c,t,j) factor conj(shift)*parent values
-// mode 0: input in[c] directly (nt x nj); mode 1: input conj(shift[c]) * par[parent[c]]
+// F[c][t][mi] = sum_j in[c][t][j] Et[j][mi] (Et: DFT table stored j-major);
+// mode 0: input in[c] directly (nt x nj, nj <= 256); mode 1: input conj(shift[c]) * par[parent[c]]
 template <typename T, typename V>
 void launch_fmm_dft(int64_t nc, int nt, int nj, int nm, const V* in, const V* shift, const int64_t* parent,
                     int mode, const V* E, V* out, hipStream_t st);
-// out[c][to][mi] = sum_ti M[|m|][to][ti] in[c][ti][mi]
+// out[c][to][mi] = sum_ti M[to][ti][|m|] in[c][ti][mi], m = mi - mhalf (M stored to-major)
 template <typename T, typename V>
 void launch_fmm_theta(int64_t nc, int nto, int nti, int nm, int mhalf, const T* M, const V* in, V* out,
                       hipStream_t st);
 // up: sigp[p][t][j] = sum_{c in children(p)} shift[c][t,j] sum_mi G[c][t][mi] E[mi][j]
+// (nj <= 256, nm <= 256)
 template <typename T, typename V>
 void launch_fmm_up_idft(int64_t np, const int64_t* cbeg, const int64_t* cend, int nt, int nj, int nm,
                         const V* G, const V* E, const V* shift, V* sigp, hipStream_t st);

@@ -55,10 +55,10 @@ __global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t*
                          const double2* __restrict__ cfac, double k, const double* __restrict__ ra,
                          const double* __restrict__ rb, const double* __restrict__ rw, int nq,
                          double2* __restrict__ T64, float2* __restrict__ T32) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N * nu) return;
-  const int64_t j = idx / nu;
-  const int v = (int)(idx - j * nu);
+  const int64_t j = blockIdx.y;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nu) return;
+  const int64_t idx = j * nu + v;
   const int64_t c = ec[j];
   const double sx = s[3 * v], sy = s[3 * v + 1], sz = s[3 * v + 2];
   double P0[3], e1[3], e2[3];
@@ -97,10 +97,10 @@ __global__ void k_leaf_S(int64_t N, const double* __restrict__ g, const int64_t*
                          const double* __restrict__ zc, const double* __restrict__ s,
                          const double* __restrict__ w, int nu, double k, double gre, double gim,
                          double2* __restrict__ S64, float2* __restrict__ S32) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N * nu) return;
-  const int64_t i = idx / nu;
-  const int v = (int)(idx - i * nu);
+  const int64_t i = blockIdx.y;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nu) return;
+  const int64_t idx = i * nu + v;
   const int64_t c = ec[i];
   const double sx = s[3 * v], sy = s[3 * v + 1], sz = s[3 * v + 2];
   const double ph = k * ((g[CX * N + i] - zc[3 * c]) * sx + (g[(CX + 1) * N + i] - zc[3 * c + 1]) * sy +
@@ -184,10 +184,10 @@ __global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64
 __global__ void k_shift(int64_t nchild, const int64_t* __restrict__ parent, const double* __restrict__ zp,
                         const double* __restrict__ zc, const double* __restrict__ s, int nu, double k,
                         double2* __restrict__ S64, float2* __restrict__ S32) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nchild * nu) return;
-  const int64_t c = idx / nu;
-  const int v = (int)(idx - c * nu);
+  const int64_t c = blockIdx.y;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nu) return;
+  const int64_t idx = c * nu + v;
   const int64_t p = parent[c];
   const double ph = k * ((zp[3 * p] - zc[3 * c]) * s[3 * v] + (zp[3 * p + 1] - zc[3 * c + 1]) * s[3 * v + 1] +
                          (zp[3 * p + 2] - zc[3 * c + 2]) * s[3 * v + 2]);
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_disaggregate(int64_t N, const int64_t* 
 // tpos != NULL: conjugate transpose, loc_m = sum_q conj(D[tpos[q]]) sig_il[q]
 // where tpos[q] is the position of the reversed pair (il[q], m).
 template <typename T, typename V>
-__global__ __launch_bounds__(256) void k_translate(const int64_t* __restrict__ il_off,
+__global__ __launch_bounds__(64) void k_translate(const int64_t* __restrict__ il_off,
                                                    const int64_t* __restrict__ il,
                                                    const int64_t* __restrict__ tpos, int nu,
                                                    const V* __restrict__ D, const V* __restrict__ sig,
@@ -258,7 +258,19 @@ __global__ __launch_bounds__(256) void k_translate(const int64_t* __restrict__ i
   if (v >= nu) return;
   V acc = mk(T(0), T(0));
   if (!tpos) {
-    for (int64_t q = il_off[m]; q < il_off[m + 1]; ++q) acc = cadd(acc, cmul(D[q * nu + v], sig[il[q] * nu + v]));
+    const int64_t q0 = il_off[m], q1 = il_off[m + 1];
+    int64_t q = q0;
+    // four independent loads in flight per lane
+    for (; q + 4 <= q1; q += 4) {
+      const V d0 = D[q * nu + v], d1 = D[(q + 1) * nu + v], d2 = D[(q + 2) * nu + v], d3 = D[(q + 3) * nu + v];
+      const V s0 = sig[il[q] * nu + v], s1 = sig[il[q + 1] * nu + v], s2 = sig[il[q + 2] * nu + v],
+              s3 = sig[il[q + 3] * nu + v];
+      acc = cadd(acc, cmul(d0, s0));
+      acc = cadd(acc, cmul(d1, s1));
+      acc = cadd(acc, cmul(d2, s2));
+      acc = cadd(acc, cmul(d3, s3));
+    }
+    for (; q < q1; ++q) acc = cadd(acc, cmul(D[q * nu + v], sig[il[q] * nu + v]));
   } else {
     for (int64_t q = il_off[m]; q < il_off[m + 1]; ++q)
       acc = cadd(acc, cmulc(D[tpos[q] * nu + v], sig[il[q] * nu + v]));
@@ -290,84 +302,104 @@ __global__ __launch_bounds__(256) void k_down_equal(const int64_t* __restrict__ 
   locc[c * nu + v] = cadd(locc[c * nu + v], add);
 }
 
+// One 64-lane block per (cluster c, row t): out[c][t][mi] = sum_j val(j) Et[j][mi]
+// with Et the DFT table stored j-major (consecutive lanes read consecutive mi).
+// mode 0: val(j) = in[c][t][j]; mode 1: val(j) = conj(shift[c][t][j]) in[parent[c]][t][j].
 template <typename T, typename V>
-__global__ __launch_bounds__(256) void k_dft(int64_t total, int nt, int nj, int nm, const V* __restrict__ in,
-                                             const V* __restrict__ shift, const int64_t* __restrict__ parent,
-                                             int mode, const V* __restrict__ E, V* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int mi = (int)(idx % nm);
-  const int64_t ct = idx / nm;
-  const int t = (int)(ct % nt);
-  const int64_t c = ct / nt;
-  V acc = mk(T(0), T(0));
-  const int64_t row = (int64_t)t * nj;
+__global__ __launch_bounds__(64) void k_dft(int nt, int nj, int nm, const V* __restrict__ in,
+                                            const V* __restrict__ shift, const int64_t* __restrict__ parent,
+                                            int mode, const V* __restrict__ Et, V* __restrict__ out) {
+  __shared__ V row[256];
+  const int t = blockIdx.x;
+  const int64_t c = blockIdx.y;
+  const int64_t rowoff = (int64_t)t * nj;
   if (mode == 0) {
-    const V* src = in + c * (int64_t)nt * nj + row;
-    for (int j = 0; j < nj; ++j) acc = cadd(acc, cmul(src[j], E[(int64_t)mi * nj + j]));
+    const V* src = in + c * (int64_t)nt * nj + rowoff;
+    for (int j = threadIdx.x; j < nj; j += 64) row[j] = src[j];
   } else {
-    const V* src = in + parent[c] * (int64_t)nt * nj + row;
-    const V* sh = shift + c * (int64_t)nt * nj + row;
-    for (int j = 0; j < nj; ++j) acc = cadd(acc, cmul(cmulc(sh[j], src[j]), E[(int64_t)mi * nj + j]));
+    const V* src = in + parent[c] * (int64_t)nt * nj + rowoff;
+    const V* sh = shift + c * (int64_t)nt * nj + rowoff;
+    for (int j = threadIdx.x; j < nj; j += 64) row[j] = cmulc(sh[j], src[j]);
   }
-  out[idx] = acc;
+  __syncthreads();
+  V* o = out + (c * nt + t) * (int64_t)nm;
+  for (int mi = threadIdx.x; mi < nm; mi += 64) {
+    V acc = mk(T(0), T(0));
+    for (int j = 0; j < nj; ++j) acc = cadd(acc, cmul(row[j], Et[(int64_t)j * nm + mi]));
+    o[mi] = acc;
+  }
 }
 
+// One 64-lane block per (cluster c, output row to):
+// out[c][to][mi] = sum_ti M[to][ti][|m|] in[c][ti][mi], m = mi - mhalf.
 template <typename T, typename V>
-__global__ __launch_bounds__(256) void k_theta(int64_t total, int nto, int nti, int nm, int mhalf,
-                                               const T* __restrict__ M, const V* __restrict__ in,
-                                               V* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int mi = (int)(idx % nm);
-  const int64_t ct = idx / nm;
-  const int to = (int)(ct % nto);
-  const int64_t c = ct / nto;
-  int am = mi - mhalf;
-  if (am < 0) am = -am;
-  const T* Mr = M + ((int64_t)am * nto + to) * nti;
-  const V* src = in + c * (int64_t)nti * nm + mi;
-  V acc = mk(T(0), T(0));
-  for (int ti = 0; ti < nti; ++ti) {
-    const V a = src[(int64_t)ti * nm];
-    acc = mk(acc.x + Mr[ti] * a.x, acc.y + Mr[ti] * a.y);
+__global__ __launch_bounds__(64) void k_theta(int nto, int nti, int nm, int mhalf, int nmh, const T* __restrict__ M,
+                                              const V* __restrict__ in, V* __restrict__ out) {
+  const int to = blockIdx.x;
+  const int64_t c = blockIdx.y;
+  const V* src = in + c * (int64_t)nti * nm;
+  const T* Mr = M + (int64_t)to * nti * nmh;
+  V* o = out + (c * nto + to) * (int64_t)nm;
+  for (int mi = threadIdx.x; mi < nm; mi += 64) {
+    int am = mi - mhalf;
+    if (am < 0) am = -am;
+    T ar = 0, ai = 0;
+    for (int ti = 0; ti < nti; ++ti) {
+      const V a = src[(int64_t)ti * nm + mi];
+      const T w = Mr[(int64_t)ti * nmh + am];
+      ar += w * a.x;
+      ai += w * a.y;
+    }
+    o[mi] = mk(ar, ai);
   }
-  out[idx] = acc;
 }
 
+// One block per (parent p, row t), lanes over j:
+// sigp[p][t][j] = sum_{c in children(p)} shift[c][t][j] sum_mi G[c][t][mi] E[mi][j]
 template <typename T, typename V>
-__global__ __launch_bounds__(256) void k_up_idft(int64_t total, const int64_t* __restrict__ cbeg,
-                                                 const int64_t* __restrict__ cend, int nt, int nj, int nm,
-                                                 const V* __restrict__ G, const V* __restrict__ E,
-                                                 const V* __restrict__ shift, V* __restrict__ sigp) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int j = (int)(idx % nj);
-  const int64_t pt = idx / nj;
-  const int t = (int)(pt % nt);
-  const int64_t p = pt / nt;
-  V acc = mk(T(0), T(0));
+__global__ __launch_bounds__(128) void k_up_idft(const int64_t* __restrict__ cbeg, const int64_t* __restrict__ cend,
+                                                 int nt, int nj, int nm, const V* __restrict__ G,
+                                                 const V* __restrict__ E, const V* __restrict__ shift,
+                                                 V* __restrict__ sigp) {
+  __shared__ V g[256];
+  const int t = blockIdx.x;
+  const int64_t p = blockIdx.y;
+  V acc[2] = {mk(T(0), T(0)), mk(T(0), T(0))};
   for (int64_t c = cbeg[p]; c < cend[p]; ++c) {
-    const V* g = G + (c * nt + t) * (int64_t)nm;
-    V s = mk(T(0), T(0));
-    for (int mi = 0; mi < nm; ++mi) s = cadd(s, cmul(g[mi], E[(int64_t)mi * nj + j]));
-    acc = cadd(acc, cmul(shift[(c * nt + t) * (int64_t)nj + j], s));
+    __syncthreads();
+    const V* gc = G + (c * nt + t) * (int64_t)nm;
+    for (int mi = threadIdx.x; mi < nm; mi += blockDim.x) g[mi] = gc[mi];
+    __syncthreads();
+    for (int r = 0; r < 2; ++r) {
+      const int j = threadIdx.x + r * blockDim.x;
+      if (j >= nj) continue;
+      V s = mk(T(0), T(0));
+      for (int mi = 0; mi < nm; ++mi) s = cadd(s, cmul(g[mi], E[(int64_t)mi * nj + j]));
+      acc[r] = cadd(acc[r], cmul(shift[(c * nt + t) * (int64_t)nj + j], s));
+    }
   }
-  sigp[idx] = acc;
+  for (int r = 0; r < 2; ++r) {
+    const int j = threadIdx.x + r * blockDim.x;
+    if (j < nj) sigp[(p * nt + t) * (int64_t)nj + j] = acc[r];
+  }
 }
 
+// One block per (cluster c, row t), lanes over j: locc[c][t][j] += sum_mi K[c][t][mi] E[mi][j]
 template <typename T, typename V>
-__global__ __launch_bounds__(256) void k_down_idft(int64_t total, int nt, int nj, int nm,
-                                                   const V* __restrict__ K, const V* __restrict__ E,
-                                                   V* __restrict__ locc) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int j = (int)(idx % nj);
-  const int64_t ct = idx / nj;
-  const V* kk = K + ct * (int64_t)nm;
-  V s = mk(T(0), T(0));
-  for (int mi = 0; mi < nm; ++mi) s = cadd(s, cmul(kk[mi], E[(int64_t)mi * nj + j]));
-  locc[idx] = cadd(locc[idx], s);
+__global__ __launch_bounds__(128) void k_down_idft(int nt, int nj, int nm, const V* __restrict__ K,
+                                                   const V* __restrict__ E, V* __restrict__ locc) {
+  __shared__ V kk[256];
+  const int t = blockIdx.x;
+  const int64_t c = blockIdx.y;
+  const V* kr = K + (c * nt + t) * (int64_t)nm;
+  for (int mi = threadIdx.x; mi < nm; mi += blockDim.x) kk[mi] = kr[mi];
+  __syncthreads();
+  for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+    V s = mk(T(0), T(0));
+    for (int mi = 0; mi < nm; ++mi) s = cadd(s, cmul(kk[mi], E[(int64_t)mi * nj + j]));
+    const int64_t o = (c * nt + t) * (int64_t)nj + j;
+    locc[o] = cadd(locc[o], s);
+  }
 }
 
 }  // namespace
@@ -376,18 +408,16 @@ __global__ __launch_bounds__(256) void k_down_idft(int64_t total, int nt, int nj
 void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
                        int nu, const double2* cfac, double k, const double* ra, const double* rb,
                        const double* rw, int nq, double2* T64, float2* T32, hipStream_t st) {
-  const int64_t tot = N * nu;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(k_leaf_T, dim3(nblk(tot, 256)), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac, k, ra, rb,
+  if (N <= 0 || nu <= 0) return;
+  hipLaunchKernelGGL(k_leaf_T, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac, k, ra, rb,
                      rw, nq, T64, T32);
 }
 
 void launch_fmm_leaf_S(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
                        const double* w, int nu, double k, double gre, double gim, double2* S64, float2* S32,
                        hipStream_t st) {
-  const int64_t tot = N * nu;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(k_leaf_S, dim3(nblk(tot, 256)), dim3(256), 0, st, N, geom, ec, zc, s, w, nu, k, gre, gim,
+  if (N <= 0 || nu <= 0) return;
+  hipLaunchKernelGGL(k_leaf_S, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, ec, zc, s, w, nu, k, gre, gim,
                      S64, S32);
 }
 
@@ -401,9 +431,8 @@ void launch_fmm_translation(int64_t npairs, const int64_t* pm, const int64_t* pn
 
 void launch_fmm_shift(int64_t nchild, const int64_t* parent, const double* zp, const double* zc,
                       const double* s, int nu, double k, double2* S64, float2* S32, hipStream_t st) {
-  const int64_t tot = nchild * nu;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(k_shift, dim3(nblk(tot, 256)), dim3(256), 0, st, nchild, parent, zp, zc, s, nu, k, S64,
+  if (nchild <= 0 || nu <= 0) return;
+  hipLaunchKernelGGL(k_shift, dim3(nblk(nu, 256), (unsigned)nchild), dim3(256), 0, st, nchild, parent, zp, zc, s, nu, k, S64,
                      S32);
 }
 
@@ -433,7 +462,7 @@ template <typename T, typename V>
 void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* tpos, int nu,
                           const V* D, const V* sig, V* loc, hipStream_t st) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL((k_translate<T, V>), dim3(nblk(nu, 256), (unsigned)nc), dim3(256), 0, st, il_off, il, tpos,
+  hipLaunchKernelGGL((k_translate<T, V>), dim3(nblk(nu, 64), (unsigned)nc), dim3(64), 0, st, il_off, il, tpos,
                      nu, D, sig, loc);
 }
 
@@ -455,37 +484,34 @@ void launch_fmm_down_equal(int64_t nchild, const int64_t* parent, int nu, const 
 
 template <typename T, typename V>
 void launch_fmm_dft(int64_t nc, int nt, int nj, int nm, const V* in, const V* shift, const int64_t* parent,
-                    int mode, const V* E, V* out, hipStream_t st) {
-  const int64_t tot = nc * nt * (int64_t)nm;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL((k_dft<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, nt, nj, nm, in, shift, parent,
-                     mode, E, out);
+                    int mode, const V* Et, V* out, hipStream_t st) {
+  if (nc <= 0 || nt <= 0) return;
+  hipLaunchKernelGGL((k_dft<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(64), 0, st, nt, nj, nm, in, shift,
+                     parent, mode, Et, out);
 }
 
 template <typename T, typename V>
 void launch_fmm_theta(int64_t nc, int nto, int nti, int nm, int mhalf, const T* M, const V* in, V* out,
                       hipStream_t st) {
-  const int64_t tot = nc * nto * (int64_t)nm;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL((k_theta<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, nto, nti, nm, mhalf, M, in,
-                     out);
+  if (nc <= 0 || nto <= 0) return;
+  hipLaunchKernelGGL((k_theta<T, V>), dim3((unsigned)nto, (unsigned)nc), dim3(64), 0, st, nto, nti, nm, mhalf,
+                     mhalf + 1, M, in, out);
 }
 
 template <typename T, typename V>
 void launch_fmm_up_idft(int64_t np, const int64_t* cbeg, const int64_t* cend, int nt, int nj, int nm,
                         const V* G, const V* E, const V* shift, V* sigp, hipStream_t st) {
-  const int64_t tot = np * nt * (int64_t)nj;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL((k_up_idft<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, cbeg, cend, nt, nj, nm, G,
-                     E, shift, sigp);
+  if (np <= 0 || nt <= 0) return;
+  hipLaunchKernelGGL((k_up_idft<T, V>), dim3((unsigned)nt, (unsigned)np), dim3(128), 0, st, cbeg, cend, nt, nj, nm,
+                     G, E, shift, sigp);
 }
 
 template <typename T, typename V>
 void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const V* E, V* locc,
                           hipStream_t st) {
-  const int64_t tot = nc * nt * (int64_t)nj;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL((k_down_idft<T, V>), dim3(nblk(tot, 256)), dim3(256), 0, st, tot, nt, nj, nm, K, E, locc);
+  if (nc <= 0 || nt <= 0) return;
+  hipLaunchKernelGGL((k_down_idft<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(128), 0, st, nt, nj, nm, K, E,
+                     locc);
 }
 
 #define BEM_FMM_INST(T, V)                                                                                    \

@@ -46,8 +46,10 @@ struct FmmLevel {
   int Lc = 0, nm = 0;
   DevBuf<double> Mi64, Ma64, MiT64, MaT64;   // MiT/MaT: transposed per order (adjoint)
   DevBuf<float> Mi32, Ma32, MiT32, MaT32;
-  DevBuf<double2> Ec64, Ep64, Ecc64, Epc64, tA64, tB64;   // Ecc/Epc: conjugated twiddles
-  DevBuf<float2> Ec32, Ep32, Ecc32, Epc32, tA32, tB32;
+  // twiddles exp(-+ i m phi_j): Ec/Ep/Ecc order-major for the inverse DFTs,
+  // EcT/EpT/EpcT node-major for the forward DFTs (c: conjugated)
+  DevBuf<double2> Ec64, Ep64, Ecc64, EcT64, EpT64, EpcT64, tA64, tB64;
+  DevBuf<float2> Ec32, Ep32, Ecc32, EcT32, EpT32, EpcT32, tA32, tB32;
 };
 
 }  // namespace
@@ -247,7 +249,9 @@ struct Pick<double2> {
   static double* MiT(FmmLevel& l) { return l.MiT64.p; }
   static double* MaT(FmmLevel& l) { return l.MaT64.p; }
   static double2* Ecc(FmmLevel& l) { return l.Ecc64.p; }
-  static double2* Epc(FmmLevel& l) { return l.Epc64.p; }
+  static double2* EcT(FmmLevel& l) { return l.EcT64.p; }
+  static double2* EpT(FmmLevel& l) { return l.EpT64.p; }
+  static double2* EpcT(FmmLevel& l) { return l.EpcT64.p; }
   static double2* T(FmmSet* f) { return f->T64.p; }
   static double2* S(FmmSet* f) { return f->S64.p; }
 };
@@ -266,7 +270,9 @@ struct Pick<float2> {
   static float* MiT(FmmLevel& l) { return l.MiT32.p; }
   static float* MaT(FmmLevel& l) { return l.MaT32.p; }
   static float2* Ecc(FmmLevel& l) { return l.Ecc32.p; }
-  static float2* Epc(FmmLevel& l) { return l.Epc32.p; }
+  static float2* EcT(FmmLevel& l) { return l.EcT32.p; }
+  static float2* EpT(FmmLevel& l) { return l.EpT32.p; }
+  static float2* EpcT(FmmLevel& l) { return l.EpcT32.p; }
   static float2* T(FmmSet* f) { return f->T32.p; }
   static float2* S(FmmSet* f) { return f->S32.p; }
 };
@@ -285,7 +291,7 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hipStr
     if (!Lp.resample) {
       launch_fmm_up_equal<T, V>(Lp.nc, Lp.cbeg.p, Lp.cend.p, Lp.nu, P::shift(Lp), P::sig(Lc), P::sig(Lp), s);
     } else {
-      launch_fmm_dft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::sig(Lc), nullptr, nullptr, 0, P::Ec(Lp), P::tA(Lp), s);
+      launch_fmm_dft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::sig(Lc), nullptr, nullptr, 0, P::EcT(Lp), P::tA(Lp), s);
       launch_fmm_theta<T, V>(Lc.nc, Lp.L, Lc.L, Lp.nm, Lc.L - 1, P::Mi(Lp), P::tA(Lp), P::tB(Lp), s);
       launch_fmm_up_idft<T, V>(Lp.nc, Lp.cbeg.p, Lp.cend.p, Lp.L, 2 * Lp.L, Lp.nm, P::tB(Lp), P::Ep(Lp),
                                P::shift(Lp), P::sig(Lp), s);
@@ -301,7 +307,7 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hipStr
     if (!Lp.resample) {
       launch_fmm_down_equal<T, V>(Lc.nc, Lc.parent.p, Lp.nu, P::shift(Lp), P::loc(Lp), P::loc(Lc), s);
     } else {
-      launch_fmm_dft<T, V>(Lc.nc, Lp.L, 2 * Lp.L, Lp.nm, P::loc(Lp), P::shift(Lp), Lc.parent.p, 1, P::Ep(Lp),
+      launch_fmm_dft<T, V>(Lc.nc, Lp.L, 2 * Lp.L, Lp.nm, P::loc(Lp), P::shift(Lp), Lc.parent.p, 1, P::EpT(Lp),
                            P::tA(Lp), s);
       launch_fmm_theta<T, V>(Lc.nc, Lc.L, Lp.L, Lp.nm, Lc.L - 1, P::Ma(Lp), P::tA(Lp), P::tB(Lp), s);
       launch_fmm_down_idft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::tB(Lp), P::Ec(Lp), P::loc(Lc), s);
@@ -330,7 +336,7 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hi
     if (!Lp.resample) {
       launch_fmm_up_equal<T, V>(Lp.nc, Lp.cbeg.p, Lp.cend.p, Lp.nu, P::shift(Lp), P::loc(Lc), P::loc(Lp), s);
     } else {
-      launch_fmm_dft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::loc(Lc), nullptr, nullptr, 0, P::Ec(Lp), P::tA(Lp), s);
+      launch_fmm_dft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::loc(Lc), nullptr, nullptr, 0, P::EcT(Lp), P::tA(Lp), s);
       launch_fmm_theta<T, V>(Lc.nc, Lp.L, Lc.L, Lp.nm, Lc.L - 1, P::MaT(Lp), P::tA(Lp), P::tB(Lp), s);
       launch_fmm_up_idft<T, V>(Lp.nc, Lp.cbeg.p, Lp.cend.p, Lp.L, 2 * Lp.L, Lp.nm, P::tB(Lp), P::Ep(Lp),
                                P::shift(Lp), P::loc(Lp), s);
@@ -346,7 +352,7 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hi
     if (!Lp.resample) {
       launch_fmm_down_equal<T, V>(Lc.nc, Lc.parent.p, Lp.nu, P::shift(Lp), P::sig(Lp), P::sig(Lc), s);
     } else {
-      launch_fmm_dft<T, V>(Lc.nc, Lp.L, 2 * Lp.L, Lp.nm, P::sig(Lp), P::shift(Lp), Lc.parent.p, 1, P::Epc(Lp),
+      launch_fmm_dft<T, V>(Lc.nc, Lp.L, 2 * Lp.L, Lp.nm, P::sig(Lp), P::shift(Lp), Lc.parent.p, 1, P::EpcT(Lp),
                            P::tA(Lp), s);
       launch_fmm_theta<T, V>(Lc.nc, Lc.L, Lp.L, Lp.nm, Lc.L - 1, P::MiT(Lp), P::tA(Lp), P::tB(Lp), s);
       launch_fmm_down_idft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::tB(Lp), P::Ecc(Lp), P::sig(Lc), s);
@@ -383,6 +389,7 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
         if (xmin < 0.0 || v < xmin) xmin = v;
       }
     D.L = truncation_length(k, rmax, o, xmin, single);
+    if (D.L > 120) throw Error(BEM_E_ARG, "expansion length " + std::to_string(D.L) + " above the supported 120");
     if (single) m->fmm_L32[l] = D.L;
     else m->fmm_L[l] = D.L;
     D.nu = 2 * D.L * D.L;
@@ -420,21 +427,23 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     std::vector<std::vector<double>> Pp(Lp), Pc(Lc);
     for (int t = 0; t < Lp; ++t) assoc_legendre(Lc, xt[l][t], Pp[t]);
     for (int t = 0; t < Lc; ++t) assoc_legendre(Lc, xt[l + 1][t], Pc[t]);
-    std::vector<double> Mi((size_t)Lc * Lp * Lc), Ma((size_t)Lc * Lc * Lp);
+    // theta matrices stored [row out][row in][|m|]:
+    //   Mi [tp][tc][m] = (pi/Lc) M'_m[tp][tc] w_tc   (interpolation, child -> parent)
+    //   Ma [tc][tp][m] = (pi/Lp) M'_m[tp][tc] w_tp   (anterpolation, parent -> child)
+    //   MaT[tp][tc][m] = Ma[tc][tp][m]               (conjugate transpose of anterpolation)
+    //   MiT[tc][tp][m] = Mi[tp][tc][m]               (conjugate transpose of interpolation)
+    std::vector<double> Mi((size_t)Lp * Lc * Lc), Ma((size_t)Lc * Lp * Lc), MiT(Ma.size()), MaT(Mi.size());
     for (int mm = 0; mm < Lc; ++mm)
       for (int tp = 0; tp < Lp; ++tp)
         for (int tc = 0; tc < Lc; ++tc) {
           double acc = 0.0;
           for (int n = mm; n < Lc; ++n) acc += Pp[tp][(size_t)mm * Lc + n] * Pc[tc][(size_t)mm * Lc + n];
-          Mi[((size_t)mm * Lp + tp) * Lc + tc] = (M_PI / Lc) * acc * wt[l + 1][tc];
-          Ma[((size_t)mm * Lc + tc) * Lp + tp] = (M_PI / Lp) * acc * wt[l][tp];
-        }
-    std::vector<double> MiT((size_t)Lc * Lc * Lp), MaT((size_t)Lc * Lp * Lc);
-    for (int mm = 0; mm < Lc; ++mm)
-      for (int tp = 0; tp < Lp; ++tp)
-        for (int tc = 0; tc < Lc; ++tc) {
-          MiT[((size_t)mm * Lc + tc) * Lp + tp] = Mi[((size_t)mm * Lp + tp) * Lc + tc];
-          MaT[((size_t)mm * Lp + tp) * Lc + tc] = Ma[((size_t)mm * Lc + tc) * Lp + tp];
+          const double vi = (M_PI / Lc) * acc * wt[l + 1][tc];
+          const double va = (M_PI / Lp) * acc * wt[l][tp];
+          Mi[((size_t)tp * Lc + tc) * Lc + mm] = vi;
+          MaT[((size_t)tp * Lc + tc) * Lc + mm] = va;
+          Ma[((size_t)tc * Lp + tp) * Lc + mm] = va;
+          MiT[((size_t)tc * Lp + tp) * Lc + mm] = vi;
         }
     std::vector<double2> Ec((size_t)nm * 2 * Lc), Ep((size_t)nm * 2 * Lp);
     for (int mi = 0; mi < nm; ++mi) {
@@ -448,9 +457,16 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
         Ep[(size_t)mi * 2 * Lp + j] = make_double2(std::cos(ph), std::sin(ph));
       }
     }
-    std::vector<double2> Ecc(Ec.size()), Epc(Ep.size());
+    std::vector<double2> Ecc(Ec.size()), EcT(Ec.size()), EpT(Ep.size()), EpcT(Ep.size());
     for (size_t i = 0; i < Ec.size(); ++i) Ecc[i] = make_double2(Ec[i].x, -Ec[i].y);
-    for (size_t i = 0; i < Ep.size(); ++i) Epc[i] = make_double2(Ep[i].x, -Ep[i].y);
+    for (int mi = 0; mi < nm; ++mi) {
+      for (int j = 0; j < 2 * Lc; ++j) EcT[(size_t)j * nm + mi] = Ec[(size_t)mi * 2 * Lc + j];
+      for (int j = 0; j < 2 * Lp; ++j) {
+        const double2 e = Ep[(size_t)mi * 2 * Lp + j];
+        EpT[(size_t)j * nm + mi] = e;
+        EpcT[(size_t)j * nm + mi] = make_double2(e.x, -e.y);
+      }
+    }
     const size_t tmp = (size_t)C.nc * std::max(Lc, Lp) * nm;
     auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
     auto c32 = [](const std::vector<double2>& v) {
@@ -466,7 +482,9 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
       P.Ec32.upload(c32(Ec), s);
       P.Ep32.upload(c32(Ep), s);
       P.Ecc32.upload(c32(Ecc), s);
-      P.Epc32.upload(c32(Epc), s);
+      P.EcT32.upload(c32(EcT), s);
+      P.EpT32.upload(c32(EpT), s);
+      P.EpcT32.upload(c32(EpcT), s);
       P.tA32.alloc(tmp);
       P.tB32.alloc(tmp);
     } else {
@@ -477,7 +495,9 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
       P.Ec64.upload(Ec, s);
       P.Ep64.upload(Ep, s);
       P.Ecc64.upload(Ecc, s);
-      P.Epc64.upload(Epc, s);
+      P.EcT64.upload(EcT, s);
+      P.EpT64.upload(EpT, s);
+      P.EpcT64.upload(EpcT, s);
       P.tA64.alloc(tmp);
       P.tB64.alloc(tmp);
     }

@@ -402,7 +402,25 @@ NearPlan build_near_plan(const Geometry& g, const QuadParams& q,
   P.items.resize(P.off[N]);
 #pragma omp parallel for schedule(static)
   for (int64_t t = 0; t < N; ++t) std::copy(per[t].begin(), per[t].end(), P.items.begin() + P.off[t]);
+  build_segments(P, N);
   return P;
+}
+
+void build_segments(NearPlan& P, int64_t N) {
+  const int S = 9;
+  P.seg.assign((size_t)N * S, 0);
+  int64_t unsorted = 0;
+#pragma omp parallel for schedule(static) reduction(+ : unsorted)
+  for (int64_t t = 0; t < N; ++t) {
+    int64_t q = P.off[t];
+    for (int mc = 0; mc < 8; ++mc) {
+      P.seg[(size_t)t * S + mc] = q;
+      while (q < P.off[t + 1] && (int)((P.items[q] >> 26) & 7u) == mc) ++q;
+    }
+    P.seg[(size_t)t * S + 8] = P.off[t + 1];
+    if (q != P.off[t + 1]) ++unsorted;
+  }
+  if (unsorted) throw Error(BEM_E_STATE, "near-field items are not sorted by rule order");
 }
 
 }  // namespace bem

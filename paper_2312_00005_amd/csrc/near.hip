@@ -13,9 +13,10 @@
 //   K = G [ -a (Rh.n_j) - gamma (B (Rh.n_i)(Rh.n_j) + a (n_i.n_j)/r) ]
 //     + c_j G [ 1 + gamma a (Rh.n_i) ].
 //
-// Work layout: one 64-lane wavefront per target element; lanes stride over
-// the target's items (sorted by rule order, so most wavefront iterations run
-// one rule), each lane integrates its whole item and multiplies by x_j, and
+// Work layout: one 64-lane wavefront per target element; the target's items
+// are processed one rule order at a time (uniform point loop, rule tables in
+// scalar registers), lanes stride over the items of that order, each lane
+// integrates its whole item and multiplies by x_j, and
 // a shuffle reduction adds the lanes in a fixed order -- no atomics, so every
 // run is bit-identical.  The singular self term is not an item: it is folded
 // into the per-frequency diagonal A_ii (self-term kernel below).
@@ -68,7 +69,47 @@ template <> struct RuleTab<float> {
   __device__ static float w(int i) { return c_rule_w32[i]; }
 };
 
-__device__ inline void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+// sin and cos of x for |x| < 2^20: Cody & Waite reduction by pi/2 (pi/2 split
+// into three parts, the first two with 20 significant bits so that n*C1 and
+// n*C2 are exact), then the Taylor series of sin and cos on [-pi/4, pi/4]
+// truncated after the 1/17! and 1/16! terms (truncation error < 5e-17).  The
+// near-field phases kr are far below the range limit.
+__device__ inline void sincos_cw(double x, double* s, double* c) {
+  constexpr double kTwoOverPi = 0.6366197723675814;
+  constexpr double C1 = 1.5707950592041016, C2 = 1.2675900507019833e-06, C3 = 7.443547480486623e-13;
+  const double n = rint(x * kTwoOverPi);
+  double y = fma(-n, C1, x);
+  y = fma(-n, C2, y);
+  y = fma(-n, C3, y);
+  const double z = y * y;
+  // sin y = y (1 - z/3! + z^2/5! - ... - z^7/15! + z^8/17!)
+  double ps = 1.0 / 355687428096000.0;
+  ps = fma(ps, z, -1.0 / 1307674368000.0);
+  ps = fma(ps, z, 1.0 / 6227020800.0);
+  ps = fma(ps, z, -1.0 / 39916800.0);
+  ps = fma(ps, z, 1.0 / 362880.0);
+  ps = fma(ps, z, -1.0 / 5040.0);
+  ps = fma(ps, z, 1.0 / 120.0);
+  ps = fma(ps, z, -1.0 / 6.0);
+  const double sy = fma(y * z, ps, y);
+  // cos y = 1 - z/2! + z^2/4! - ... + z^8/16!
+  double pc = 1.0 / 20922789888000.0;
+  pc = fma(pc, z, -1.0 / 87178291200.0);
+  pc = fma(pc, z, 1.0 / 479001600.0);
+  pc = fma(pc, z, -1.0 / 3628800.0);
+  pc = fma(pc, z, 1.0 / 40320.0);
+  pc = fma(pc, z, -1.0 / 720.0);
+  pc = fma(pc, z, 1.0 / 24.0);
+  pc = fma(pc, z, -0.5);
+  const double cy = fma(z, pc, 1.0);
+  const int q = ((int)n) & 3;
+  const double a = (q & 1) ? cy : sy;
+  const double b = (q & 1) ? sy : cy;
+  *s = (q & 2) ? -a : a;
+  *c = ((q + 1) & 2) ? -b : b;
+}
+
+__device__ inline void sincos_t(double x, double* s, double* c) { sincos_cw(x, s, c); }
 __device__ inline void sincos_t(float x, float* s, float* c) { __sincosf(x, s, c); }
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
@@ -114,12 +155,13 @@ __device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t
 
 // Integrate one item: returns S1 (c-independent part) and S2 (c_j part),
 // both already multiplied by 2 * area of the (sub-)triangle.
+// m is the item's rule order; the caller passes it wavefront-uniform so the
+// rule tables are read with scalar loads.
 template <typename T, bool HAS_C>
-__device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64_t item, const T xi[3],
+__device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64_t item, int m, const T xi[3],
                                       const T ni[3], T k, T gre, T gim, T& s1r, T& s1i, T& s2r,
                                       T& s2i, int64_t& jout) {
   const int64_t j = (int64_t)(item & ((uint64_t(1) << 26) - 1));
-  const int m = (int)((item >> 26) & 7u) + 1;
   const int depth = (int)((item >> 29) & 15u);
   const uint64_t path = item >> 33;
   jout = j;
@@ -189,22 +231,28 @@ __global__ __launch_bounds__(256) void k_near(NearLaunch L, const T* __restrict_
   }
   const T k = (T)L.k, gre = (T)L.gre, gim = (T)L.gim;
   T accr = 0, acci = 0;
-  const int64_t e = L.off[t + 1];
-  for (int64_t it = L.off[t] + lane; it < e; it += 64) {
-    T s1r, s1i, s2r, s2i;
-    int64_t j;
-    integrate_item<T, HAS_C>(g, N, L.items[it], xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, j);
-    T vr = s1r, vi = s1i;
-    if (HAS_C) {
-      const double2 c = L.cfac[j];
-      const T cr = (T)c.x, ci = (T)c.y;
-      vr += cr * s2r - ci * s2i;
-      vi += cr * s2i + ci * s2r;
+  // the target's items are sorted by rule order; seg[t][m-1] .. seg[t][m]
+  // holds the order-m items, so every pass below runs one uniform rule
+  const int64_t* sg = L.seg + t * (kMaxRuleOrder + 1);
+  for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
+    const int64_t b = sg[mc], e = sg[mc + 1];
+    if (b == e) continue;
+    for (int64_t it = b + lane; it < e; it += 64) {
+      T s1r, s1i, s2r, s2i;
+      int64_t j;
+      integrate_item<T, HAS_C>(g, N, L.items[it], mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, j);
+      T vr = s1r, vi = s1i;
+      if (HAS_C) {
+        const double2 c = L.cfac[j];
+        const T cr = (T)c.x, ci = (T)c.y;
+        vr += cr * s2r - ci * s2i;
+        vi += cr * s2i + ci * s2r;
+      }
+      const double2 xj = x[j];
+      const T xr = (T)xj.x, xim = (T)xj.y;
+      accr += vr * xr - vi * xim;
+      acci += vr * xim + vi * xr;
     }
-    const double2 xj = x[j];
-    const T xr = (T)xj.x, xim = (T)xj.y;
-    accr += vr * xr - vi * xim;
-    acci += vr * xim + vi * xr;
   }
   double sr = wave_sum((double)accr);
   double si = wave_sum((double)acci);
@@ -233,31 +281,35 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
     ci = (T)c.y;
   }
   T accr = 0, acci = 0;
-  const int64_t e = L.off[jsrc + 1];
-  for (int64_t it = L.off[jsrc] + lane; it < e; it += 64) {
-    const uint64_t raw = L.items[it];
-    const int64_t i = (int64_t)(raw & ((uint64_t(1) << 26) - 1));
-    // rebuild the forward item (source jsrc) and integrate from target i
-    const uint64_t item = (raw & ~((uint64_t(1) << 26) - 1)) | (uint64_t)jsrc;
-    T xi[3], ni[3];
+  const int64_t* sg = L.seg + jsrc * (kMaxRuleOrder + 1);
+  for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
+    const int64_t b = sg[mc], e = sg[mc + 1];
+    if (b == e) continue;
+    for (int64_t it = b + lane; it < e; it += 64) {
+      const uint64_t raw = L.items[it];
+      const int64_t i = (int64_t)(raw & ((uint64_t(1) << 26) - 1));
+      // rebuild the forward item (source jsrc) and integrate from target i
+      const uint64_t item = (raw & ~((uint64_t(1) << 26) - 1)) | (uint64_t)jsrc;
+      T xi[3], ni[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      xi[c] = g[(CX + c) * N + i];
-      ni[c] = g[(NX + c) * N + i];
+      for (int c = 0; c < 3; ++c) {
+        xi[c] = g[(CX + c) * N + i];
+        ni[c] = g[(NX + c) * N + i];
+      }
+      T s1r, s1i, s2r, s2i;
+      int64_t jj;
+      integrate_item<T, HAS_C>(g, N, item, mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, jj);
+      T vr = s1r, vi = s1i;
+      if (HAS_C) {
+        vr += cr * s2r - ci * s2i;
+        vi += cr * s2i + ci * s2r;
+      }
+      const double2 xv = x[i];
+      const T xr = (T)xv.x, xim = (T)xv.y;
+      // conj(v) * x
+      accr += vr * xr + vi * xim;
+      acci += vr * xim - vi * xr;
     }
-    T s1r, s1i, s2r, s2i;
-    int64_t jj;
-    integrate_item<T, HAS_C>(g, N, item, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, jj);
-    T vr = s1r, vi = s1i;
-    if (HAS_C) {
-      vr += cr * s2r - ci * s2i;
-      vi += cr * s2i + ci * s2r;
-    }
-    const double2 xv = x[i];
-    const T xr = (T)xv.x, xim = (T)xv.y;
-    // conj(v) * x
-    accr += vr * xr + vi * xim;
-    acci += vr * xim - vi * xr;
   }
   double sr = wave_sum((double)accr);
   double si = wave_sum((double)acci);
