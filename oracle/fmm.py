@@ -198,6 +198,13 @@ def build_tree(geom, levels, leaf_size, admissibility, root_edge=0.0):
     return Tree(lv, perm)
 
 
+def default_levels(N):
+    """Level count when none is given (Sec. 3.3.4): the printed formula is
+    garbled; read as 1 + round(log2(sqrt(N) / 22.5) / 2), at least 1."""
+    v = 0.5 * math.log2(math.sqrt(N) / 22.5)
+    return max(1, 1 + math.floor(v + 0.5))
+
+
 def pair_partition_counts(tree, N):
     """Count how often every (i, j) pair is covered by a leaf near pair or by
     an interaction-list pair on some level (each must be exactly once)."""
