@@ -174,6 +174,57 @@ bem_status bem_apply(bem_mesh* m, bem_op op, bem_precision prec,
 bem_status bem_apply_part(bem_mesh* m, bem_op op, bem_precision prec, int part,
                           const bem_c128* x, bem_c128* y, void* stream);
 
+/* y = V x or y = V^H x with V = dA/dc, the matrix that multiplies diag(c) in
+ * A(c) = A(0) + V diag(c) (Eq. (SystemI)): V_ij = G_ij - gamma H'_ij off the
+ * diagonal and G_ii - gamma/2 on it.  Used by admittance gradients:
+ * dA/dbeta_e = -i k V e_e e_e^T.  Device vectors of n_tri. */
+bem_status bem_apply_dc(bem_mesh* m, bem_op op, bem_precision prec,
+                        const bem_c128* x, bem_c128* y, void* stream);
+
+/* Solve A^H x = rhs (the adjoint system of an admittance gradient) with the
+ * same GMRES / refinement settings as bem_solve.  Blocking; info may be NULL. */
+bem_status bem_solve_adjoint(bem_mesh* m, const bem_c128* rhs, bem_c128* x_out,
+                             bem_solve_info* info, void* stream);
+
+/* Incident pressure at arbitrary points (Sec. 2.4): kind 0 plane wave
+ * P0 exp(i k d.x) with d = src (normalised; zero is BEM_E_ARG), kind 1 point
+ * source P0 exp(i k R)/(4 pi R), R = |x - src|.  pts: device double[n_pts][3];
+ * out: device bem_c128[n_pts]; src is host memory.  Uses k of the problem. */
+bem_status bem_incident_field(bem_mesh* m, int kind, const double src[3],
+                              bem_c128 P0, int64_t n_pts, const double* pts,
+                              bem_c128* out, void* stream);
+
+/* Exterior pressure at field points from the representation formula
+ * (Eq. (BIE_I) with lambda = 1, tau = 1):
+ *   p_out[f] = p_inc[f] + sum_j (I^H(x_f, G_j) - c_j I^G(x_f, G_j)) p_surf[j],
+ * element integrals by the quasi-singular / regular rules of Sec. 3.1.3-3.1.4
+ * chosen per (point, element) pair.
+ *   pts    : device double[n_pts][3] (outside the body)
+ *   p_surf : device bem_c128[n_tri]; p_inc: device bem_c128[n_pts] or NULL
+ *   p_out  : device bem_c128[n_pts]
+ *   energy : device double[1] receiving sum_f |p_out[f]|^2, or NULL
+ * BEM_E_MESH if a point is so close to an element that subdivision overflows. */
+bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts,
+                     const bem_c128* p_surf, const bem_c128* p_inc,
+                     bem_c128* p_out, double* energy, void* stream);
+
+/* Conjugate transpose of the field map: y_surf[j] = sum_f conj(K_fj) g[f] with
+ * K = I^H - c I^G (part 0) or K = I^G alone (part 1).  g: device
+ * bem_c128[n_pts]; y_surf: device bem_c128[n_tri]. */
+bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts,
+                             const bem_c128* g, int part, bem_c128* y_surf,
+                             void* stream);
+
+/* Gradient of J = sum_f |p_f|^2 with respect to the per-element admittance
+ * Y_e (beta = rho_c Y) from one adjoint solve:
+ *   grad[e] = 2 Re{ -i k rho_c p_e ( -conj(w_e) - conj(h_e) ) }
+ * where p solves A p = b, w = V^H mu (bem_apply_dc, op A^H) with
+ * A^H mu = M^H p_field, and h = (I^G)^H p_field (bem_field_adjoint, part 1).
+ * All inputs device bem_c128[n_tri]; grad: device double[n_tri]. */
+bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w,
+                               const bem_c128* hg, double rho_c, double* grad,
+                               void* stream);
+
 /* Solve A p = rhs by GMRES (FP64 Krylov vectors and residuals; with
  * precision MIXED an FP64 outer refinement around a complex-FP32 inner
  * operator).  p_out: device bem_c128[n_tri]; v_out (may be NULL): normal

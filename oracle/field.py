@@ -15,20 +15,29 @@ from .integrals import offdiag_integrals
 from .operator import bc_factor
 
 
-def field_matrix(geom, pts, k, beta=None, p=None):
-    """M with p_field = p_inc + M p_surface, shape (n_pts, N)."""
+def field_parts(geom, pts, k, p=None):
+    """(I^G, I^H), each of shape (n_pts, N): the element integrals of G and
+    dG/dn_y seen from the field points."""
     pts = np.asarray(pts, dtype=np.float64)
     N = geom["x"].shape[0]
-    M = np.zeros((pts.shape[0], N), dtype=np.complex128)
-    c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
-    jj = np.arange(N)
+    IGm = np.zeros((pts.shape[0], N), dtype=np.complex128)
+    IHm = np.zeros((pts.shape[0], N), dtype=np.complex128)
     dummy_n = np.tile(np.array([0.0, 0.0, 1.0]), (N, 1))
     for f in range(pts.shape[0]):
         xf = np.tile(pts[f], (N, 1))
         IG, IH, _, _ = offdiag_integrals(xf, dummy_n, geom["P0"], geom["P1"], geom["P2"],
                                          geom["n"], geom["A"], k, p)
-        M[f, jj] = IH - c * IG
-    return M
+        IGm[f] = IG
+        IHm[f] = IH
+    return IGm, IHm
+
+
+def field_matrix(geom, pts, k, beta=None, p=None):
+    """M with p_field = p_inc + M p_surface, shape (n_pts, N)."""
+    IG, IH = field_parts(geom, pts, k, p)
+    if beta is None:
+        return IH
+    return IH - bc_factor(k, beta)[None, :] * IG
 
 
 def plane_wave(pts, k, d, P0=1.0):

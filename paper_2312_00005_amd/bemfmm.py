@@ -99,6 +99,12 @@ _SIGS = {
     "bem_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "bem_apply_part": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
     "bem_solve": (_i32, [_vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(bem_solve_info), _vp]),
+    "bem_apply_dc": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "bem_incident_field": (_i32, [_vp, _i32, _vp, bem_c128, _i64, _vp, _vp, _vp]),
+    "bem_field": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bem_field_adjoint": (_i32, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
+    "bem_grad_admittance": (_i32, [_vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
+    "bem_solve_adjoint": (_i32, [_vp, _vp, _vp, ctypes.POINTER(bem_solve_info), _vp]),
     "bem_mesh_stats": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "bem_mesh_destroy": (None, [_vp]),
@@ -168,6 +174,34 @@ def bem_apply(mesh, op, prec, x_ptr, y_ptr, stream):
 
 def bem_apply_part(mesh, op, prec, part, x_ptr, y_ptr, stream):
     _check(_lib.bem_apply_part(mesh, op, prec, part, x_ptr, y_ptr, stream))
+
+
+def bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream):
+    _check(_lib.bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream))
+
+
+def bem_incident_field(mesh, kind, src, P0, n_pts, pts_ptr, out_ptr, stream):
+    s3 = (ctypes.c_double * 3)(*[float(v) for v in src])
+    _check(_lib.bem_incident_field(mesh, int(kind), s3, bem_c128(P0.real, P0.imag), n_pts, pts_ptr, out_ptr,
+                                   stream))
+
+
+def bem_field(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream):
+    _check(_lib.bem_field(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream))
+
+
+def bem_field_adjoint(mesh, n_pts, pts_ptr, g_ptr, part, y_ptr, stream):
+    _check(_lib.bem_field_adjoint(mesh, n_pts, pts_ptr, g_ptr, part, y_ptr, stream))
+
+
+def bem_grad_admittance(mesh, p_ptr, w_ptr, hg_ptr, rho_c, grad_ptr, stream):
+    _check(_lib.bem_grad_admittance(mesh, p_ptr, w_ptr, hg_ptr, rho_c, grad_ptr, stream))
+
+
+def bem_solve_adjoint(mesh, rhs_ptr, x_ptr, stream):
+    info = bem_solve_info()
+    st = _lib.bem_solve_adjoint(mesh, rhs_ptr, x_ptr, ctypes.byref(info), stream)
+    return st, info
 
 
 def bem_solve(mesh, rhs_ptr, p_ptr, v_ptr, rho_c, stream):
@@ -302,6 +336,14 @@ def _dev_c128(t, n, name):
     return t.data_ptr()
 
 
+def _dev_pts(pts):
+    torch = _torch()
+    if not isinstance(pts, torch.Tensor) or pts.dtype != torch.float64 or not pts.is_cuda \
+            or pts.dim() != 2 or pts.shape[1] != 3:
+        raise TypeError("pts must be a float64 device tensor of shape (n, 3)")
+    return pts.contiguous()
+
+
 _PRECS = {"fp64": BEM_PREC_FP64, "mixed": BEM_PREC_MIXED, BEM_PREC_FP64: BEM_PREC_FP64,
           BEM_PREC_MIXED: BEM_PREC_MIXED}
 _OPS = {"A": BEM_OP_A, "AH": BEM_OP_AH, BEM_OP_A: BEM_OP_A, BEM_OP_AH: BEM_OP_AH}
@@ -376,6 +418,63 @@ class Mesh:
         bem_apply_part(self._h, _OPS[op], _PRECS[prec], int(part), xp, _dev_c128(out, self.n, "y"),
                        _stream())
         return out
+
+    def apply_dc(self, x, op="A", prec="fp64", out=None):
+        """y = V x (or V^H x), V = dA/dc."""
+        xp = _dev_c128(x, self.n, "x")
+        out = self._empty() if out is None else out
+        bem_apply_dc(self._h, _OPS[op], _PRECS[prec], xp, _dev_c128(out, self.n, "y"), _stream())
+        return out
+
+    def incident_plane_wave(self, pts, d=(0.0, 0.0, 1.0), P0=1.0):
+        pts = _dev_pts(pts)
+        out = self._empty(pts.shape[0])
+        bem_incident_field(self._h, 0, d, complex(P0), pts.shape[0], pts.data_ptr(), out.data_ptr(), _stream())
+        return out
+
+    def incident_point_source(self, pts, x0, P0=1.0):
+        pts = _dev_pts(pts)
+        out = self._empty(pts.shape[0])
+        bem_incident_field(self._h, 1, x0, complex(P0), pts.shape[0], pts.data_ptr(), out.data_ptr(), _stream())
+        return out
+
+    def field(self, pts, p_surf, p_inc=None, energy=False):
+        """Exterior pressure at field points pts (device float64 [n, 3]);
+        with energy=True also sum |p|^2 as a device float64 tensor of shape ()."""
+        torch = _torch()
+        pts = _dev_pts(pts)
+        npts = pts.shape[0]
+        out = self._empty(npts)
+        pinc = _dev_c128(p_inc, npts, "p_inc") if p_inc is not None else None
+        en = torch.zeros((), dtype=torch.float64, device="cuda") if energy else None
+        bem_field(self._h, npts, pts.data_ptr(), _dev_c128(p_surf, self.n, "p_surf"), pinc, out.data_ptr(),
+                  en.data_ptr() if en is not None else None, _stream())
+        return (out, en) if energy else out
+
+    def field_adjoint(self, pts, g, part=0):
+        """y = K^H g with K the field map (part 0) or its G part (part 1)."""
+        pts = _dev_pts(pts)
+        npts = pts.shape[0]
+        out = self._empty()
+        bem_field_adjoint(self._h, npts, pts.data_ptr(), _dev_c128(g, npts, "g"), int(part), out.data_ptr(),
+                          _stream())
+        return out
+
+    def grad_admittance(self, p, w, hg, rho_c):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        bem_grad_admittance(self._h, _dev_c128(p, self.n, "p"), _dev_c128(w, self.n, "w"),
+                            _dev_c128(hg, self.n, "hg"), float(rho_c), out.data_ptr(), _stream())
+        return out
+
+    def solve_adjoint(self, rhs, allow_noconv=False):
+        """x with A^H x = rhs; returns (x, info dict)."""
+        rp = _dev_c128(rhs, self.n, "rhs")
+        x = self._empty()
+        st, info = bem_solve_adjoint(self._h, rp, x.data_ptr(), _stream())
+        if st != BEM_OK and not (allow_noconv and st == BEM_E_NOCONV):
+            _check(st)
+        return x, info.as_dict()
 
     def solve(self, rhs, rho_c=None, allow_noconv=False):
         """Returns (p, v or None, info dict)."""

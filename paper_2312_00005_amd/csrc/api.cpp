@@ -124,10 +124,10 @@ void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, do
 }
 
 void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
-                     hipStream_t s) {
+                     hipStream_t s, bool vmode) {
   if (part == 2) {
     BEM_HIP(hipMemsetAsync(y, 0, m->N * sizeof(double2), s));
-    if (m->fmm) fmm_apply(m, op, prec, x, y, s);
+    if (m->fmm) fmm_apply(m, op, prec, x, y, s, vmode);
     return;
   }
   NearLaunch L{};
@@ -136,6 +136,7 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   L.geom32 = m->d_geom32.p;
   L.cfac = m->have_beta ? m->d_cfac.p : nullptr;
   L.diag = m->d_diag.p;
+  L.vdiag = m->d_vdiag.p;
   L.k = m->k;
   L.gre = m->gre;
   L.gim = m->gim;
@@ -143,18 +144,15 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
     L.off = m->d_off.p;
     L.seg = m->d_seg.p;
     L.items = m->d_items.p;
-    if (prec == BEM_PREC_FP64) launch_near_f64(L, x, y, s);
-    else launch_near_f32(L, x, y, s);
   } else {
     ensure_transposed_plan(m, s);
     L.off = m->d_off_t.p;
     L.seg = m->d_seg_t.p;
     L.items = m->d_items_t.p;
-    if (prec == BEM_PREC_FP64) launch_near_adj_f64(L, x, y, s);
-    else launch_near_adj_f32(L, x, y, s);
   }
+  launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
   BEM_HIP(hipGetLastError());
-  if (part == 0 && m->fmm) fmm_apply(m, op, prec, x, y, s);
+  if (part == 0 && m->fmm) fmm_apply(m, op, prec, x, y, s, vmode);
 }
 
 void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
@@ -326,6 +324,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_sol.alloc(n_tri);
     m->d_cfac.alloc(n_tri);
     m->d_diag.alloc(n_tri);
+    m->d_vdiag.alloc(n_tri);
     BEM_HIP(hipStreamSynchronize(s));
     *out = m.release();
     return BEM_OK;
@@ -358,6 +357,7 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     L.edge_t = m->d_edge_t.p;
     L.edge_w = m->d_edge_w.p;
     L.edge_pts = m->opt.edge_parts * m->opt.edge_gauss;
+    L.vdiag = m->d_vdiag.p;
     L.k = k;
     L.gre = m->gre;
     L.gim = m->gim;
@@ -396,6 +396,25 @@ bem_status bem_rhs_point_source(bem_mesh* m, const double x0[3], bem_c128 P0, be
   });
 }
 
+bem_status bem_incident_field(bem_mesh* m, int kind, const double src[3], bem_c128 P0, int64_t n_pts,
+                              const double* pts, bem_c128* out, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !src || (n_pts > 0 && (!pts || !out)) || n_pts < 0) return fail(BEM_E_ARG, "NULL argument");
+    if (kind != 0 && kind != 1) return fail(BEM_E_ARG, "kind must be 0 (plane wave) or 1 (point source)");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    double s3[3] = {src[0], src[1], src[2]};
+    if (kind == 0) {
+      const double n = std::sqrt(s3[0] * s3[0] + s3[1] * s3[1] + s3[2] * s3[2]);
+      if (!(n > 0.0)) return fail(BEM_E_ARG, "direction must be non-zero");
+      for (double& v : s3) v /= n;
+    }
+    hipStream_t s = as_stream(stream);
+    launch_incident(n_pts, pts, kind, m->k, s3, P0.re, P0.im, reinterpret_cast<double2*>(out), s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
 bem_status bem_apply(bem_mesh* m, bem_op op, bem_precision prec, const bem_c128* x, bem_c128* y,
                      void* stream) {
   return guarded([&]() -> bem_status {
@@ -425,6 +444,127 @@ bem_status bem_apply_part(bem_mesh* m, bem_op op, bem_precision prec, int part, 
     apply_tree_part(m, op, prec, part, m->d_x.p, m->d_y.p, s);
     launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(y), s);
     BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_apply_dc(bem_mesh* m, bem_op op, bem_precision prec, const bem_c128* x, bem_c128* y,
+                        void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !x || !y) return fail(BEM_E_ARG, "NULL argument");
+    if (op != BEM_OP_A && op != BEM_OP_AH) return fail(BEM_E_ARG, "unknown operator");
+    if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return fail(BEM_E_ARG, "unknown precision");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(x), m->d_x.p, s);
+    apply_tree_part(m, op, prec, 0, m->d_x.p, m->d_y.p, s, true);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(y), s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+namespace {
+
+FieldArgs field_args(bem_mesh* m, int64_t npts, int part) {
+  FieldArgs A{};
+  A.N = m->N;
+  A.npts = npts;
+  A.geom = m->d_geom.p;
+  A.cfac = m->have_beta ? m->d_cfac.p : nullptr;
+  A.k = m->k;
+  A.eps = m->opt.quad_eps;
+  A.ratio = m->opt.subdiv_ratio;
+  A.m_max = m->opt.quad_m_max;
+  A.split_on_cap = m->opt.quad_split_on_cap;
+  A.max_subdiv = m->opt.max_subdiv;
+  A.part = part;
+  return A;
+}
+
+void check_field_error(bem_mesh* m, DevBuf<int64_t>& err, hipStream_t s) {
+  int64_t e = -1;
+  BEM_HIP(hipMemcpyAsync(&e, err.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BEM_HIP(hipStreamSynchronize(s));
+  if (e >= 0) {
+    m->bad_element = m->tree.perm[e];
+    throw Error(BEM_E_MESH, "field point too close to element " + std::to_string(m->bad_element) +
+                                " (subdivision limit)", m->bad_element);
+  }
+}
+
+}  // namespace
+
+bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c128* p_surf,
+                     const bem_c128* p_inc, bem_c128* p_out, double* energy, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !pts || !p_surf || !p_out || n_pts < 0) return fail(BEM_E_ARG, "NULL argument");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    if (n_pts == 0) return BEM_OK;
+    hipStream_t s = as_stream(stream);
+    DevBuf<int64_t> err;
+    err.upload(std::vector<int64_t>{-1}, s);
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(p_surf), m->d_x.p, s);
+    launch_field(field_args(m, n_pts, 0), pts, m->d_x.p, reinterpret_cast<const double2*>(p_inc),
+                 reinterpret_cast<double2*>(p_out), err.p, s);
+    if (energy) launch_energy(n_pts, reinterpret_cast<const double2*>(p_out), energy, s);
+    BEM_HIP(hipGetLastError());
+    check_field_error(m, err, s);
+    return BEM_OK;
+  });
+}
+
+bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c128* g, int part,
+                             bem_c128* y_surf, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !pts || !g || !y_surf || n_pts < 0) return fail(BEM_E_ARG, "NULL argument");
+    if (part != 0 && part != 1) return fail(BEM_E_ARG, "part must be 0 or 1");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    DevBuf<int64_t> err;
+    err.upload(std::vector<int64_t>{-1}, s);
+    launch_field_adj(field_args(m, n_pts, part), pts, reinterpret_cast<const double2*>(g), m->d_y.p, err.p, s);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(y_surf), s);
+    BEM_HIP(hipGetLastError());
+    check_field_error(m, err, s);
+    return BEM_OK;
+  });
+}
+
+bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w, const bem_c128* hg,
+                               double rho_c, double* grad, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !p || !w || !hg || !grad) return fail(BEM_E_ARG, "NULL argument");
+    if (!(rho_c > 0.0)) return fail(BEM_E_ARG, "rho_c must be positive");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    launch_grad_admittance(m->N, m->k, rho_c, reinterpret_cast<const double2*>(p),
+                           reinterpret_cast<const double2*>(w), reinterpret_cast<const double2*>(hg), grad, s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_solve_adjoint(bem_mesh* m, const bem_c128* rhs, bem_c128* x_out, bem_solve_info* info,
+                             void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !rhs || !x_out) return fail(BEM_E_ARG, "NULL argument");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(rhs), m->d_b.p, s);
+    SolveResult r = solve_tree(m, m->d_b.p, m->d_sol.p, s, BEM_OP_AH);
+    launch_scatter(m->N, m->d_perm.p, m->d_sol.p, reinterpret_cast<double2*>(x_out), s);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(s));
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->iterations = r.iterations;
+      info->refinements = r.refinements;
+      info->rel_residual = r.rel_residual;
+      if (!r.converged) info->warnings |= BEM_WARN_NOT_CONVERGED;
+    }
+    if (!r.converged)
+      return fail(BEM_E_NOCONV, "GMRES stopped at relative residual " + std::to_string(r.rel_residual));
     return BEM_OK;
   });
 }
@@ -494,7 +634,7 @@ size_t bem_workspace_bytes(const bem_mesh* m) {
   if (!m) return 0;
   size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_perm.bytes() + m->d_off.bytes() +
              m->d_items.bytes() + m->d_seg.bytes() + m->d_seg_t.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
-             m->d_cfac.bytes() + m->d_diag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
+             m->d_cfac.bytes() + m->d_diag.bytes() + m->d_vdiag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
              m->d_partial.bytes() + m->d_h.bytes();
   return b + fmm_bytes(m);

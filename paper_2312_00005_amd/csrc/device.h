@@ -21,33 +21,56 @@ struct NearLaunch {
   const uint64_t* items;
   const double2* cfac;    // c_j, tree order (nullptr: sound-hard everywhere)
   const double2* diag;    // A_ii, tree order
+  const double2* vdiag;   // diagonal of dA/dc: G_ii - gamma/2 (tree order)
   double k;
   double gre, gim;        // coupling gamma
 };
 
-// y = diag x + sum over near items (tree-order vectors); accumulate = 1 adds
-// into y instead of overwriting it.
-void launch_near_f64(const NearLaunch& L, const double2* x, double2* y, hipStream_t s);
-void launch_near_f32(const NearLaunch& L, const double2* x, double2* y, hipStream_t s);
-// conjugate-transpose near field: y = conj(diag) x + sum_i conj(K_ij) x_i
-// over the transposed item lists (items indexed by source).
-void launch_near_adj_f64(const NearLaunch& Lt, const double2* x, double2* y, hipStream_t s);
-void launch_near_adj_f32(const NearLaunch& Lt, const double2* x, double2* y, hipStream_t s);
+// y = diag x + sum over near items (tree-order vectors), in FP64 or complex
+// FP32.  adjoint: conjugate transpose over the transposed item lists (items
+// indexed by source), y = conj(diag) x + sum_i conj(K_ij) x_i.  vmode: the
+// operator dA/dc instead of A.
+void launch_near(const NearLaunch& L, bool fp64, bool adjoint, bool vmode, const double2* x, double2* y,
+                 hipStream_t s);
 
 struct SelfLaunch {
   int64_t N;
   const double* geom;
   const double2* cfac;
+  double2* vdiag;         // optional output: G_ii - gamma/2
   const double* duffy_u; const double* duffy_w; int self_n;
   const double* edge_t; const double* edge_w; int edge_pts;
   double k, gre, gim;
 };
 void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s);
 
+struct FieldArgs {
+  int64_t N;             // elements
+  int64_t npts;          // field points
+  const double* geom;    // tree order
+  const double2* cfac;   // c_j (tree order) or NULL
+  double k;
+  double eps, ratio;     // quadrature tolerance, subdivision ratio
+  int m_max, split_on_cap, max_subdiv;
+  int part;              // 0: K = I^H - c I^G; 1: K = I^G
+};
+// out[f] = pinc[f] + sum_j K_fj p[j] (p in tree order); err[0] receives the
+// tree position of an element whose subdivision overflowed
+void launch_field(const FieldArgs& A, const double* pts, const double2* p, const double2* pinc, double2* out,
+                  int64_t* err, hipStream_t s);
+void launch_energy(int64_t n, const double2* p, double* energy, hipStream_t s);
+// y[j] = sum_f conj(K_fj) g[f] (y in tree order)
+void launch_field_adj(const FieldArgs& A, const double* pts, const double2* g, double2* y, int64_t* err,
+                      hipStream_t s);
+void launch_grad_admittance(int64_t N, double k, double rho_c, const double2* p, const double2* w,
+                            const double2* hg, double* grad, hipStream_t s);
+
 void launch_rhs_plane(int64_t N, const double* geom, double k, double gre, double gim,
                       const double* d, double p0re, double p0im, double2* out, hipStream_t s);
 void launch_rhs_point(int64_t N, const double* geom, double k, double gre, double gim,
                       const double* x0, double p0re, double p0im, double2* out, hipStream_t s);
+void launch_incident(int64_t n, const double* pts, int kind, double k, const double* src, double p0re,
+                     double p0im, double2* out, hipStream_t s);
 void launch_gather(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s);
 void launch_scatter(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s);
 void launch_cfac(int64_t N, const int64_t* perm, const double2* beta_caller, double k, double2* cfac,

@@ -6,10 +6,20 @@
 
 namespace bem {
 
+// Source factor c_j + ik s.n_j applied on the fly to the leaf aggregation rows.
+struct FactorArgs {
+  int64_t N;
+  const double* s;       // leaf sphere nodes (3 per node)
+  const double* n;       // element normals, field-major: n[d * N + j] (tree order)
+  const double2* cfac;   // c_j (NULL: sound-hard)
+  double k;
+};
+
 // ---------------------------------------------------------------- setup ---
 // Outputs of the setup kernels are written in FP64 and/or FP32 (a NULL
 // pointer skips that copy).
-// Leaf aggregation rows T'[j][nu] = (c_j + ik s.n_j) int_Gj exp(ik (z_c(j) - y).s) dy
+// Leaf aggregation rows T[j][nu] = int_Gj exp(ik (z_c(j) - y).s) dy (the source
+// factor is applied when the rows are used)
 // (conical rule with nq points: rule_a, rule_b, rule_w in device memory).
 void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* elem_cluster, const double* zc,
                        const double* s, int nu, const double2* cfac, double k, const double* ra,
@@ -28,13 +38,14 @@ void launch_fmm_shift(int64_t nchild, const int64_t* parent, const double* zp, c
 
 // ---------------------------------------------------------------- apply ---
 // T = double (V = double2) or float (V = float2)
-// conj_rows: use the complex conjugate of the row matrix (adjoint passes)
+// conj_rows: use the complex conjugate of the row matrix (adjoint passes);
+// F: multiply the rows by the source factor (NULL: plain rows)
 template <typename T, typename V>
 void launch_fmm_aggregate(int64_t nclust, const int64_t* ebeg, const int64_t* eend, int nu, const V* Tm,
-                          const double2* x, V* sig, bool conj_rows, hipStream_t st);
+                          const FactorArgs* F, const double2* x, V* sig, bool conj_rows, hipStream_t st);
 template <typename T, typename V>
-void launch_fmm_disaggregate(int64_t N, const int64_t* elem_cluster, int nu, const V* Sm, const V* loc,
-                             double2* y, bool conj_rows, hipStream_t st);
+void launch_fmm_disaggregate(int64_t N, const int64_t* elem_cluster, int nu, const V* Sm, const FactorArgs* F,
+                             const V* loc, double2* y, bool conj_rows, hipStream_t st);
 // tpos: NULL for the forward translation; for the conjugate transpose the
 // position of each reversed pair (the interaction lists are symmetric)
 template <typename T, typename V>

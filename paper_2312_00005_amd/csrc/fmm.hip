@@ -79,16 +79,7 @@ __global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t*
     ai += rw[q] * sn;
   }
   const double a2 = 2.0 * g[AREA * N + j];
-  ar *= a2;
-  ai *= a2;
-  // factor c_j + ik s.n_j
-  const double sn_ = sx * g[NX * N + j] + sy * g[(NX + 1) * N + j] + sz * g[(NX + 2) * N + j];
-  double fr = 0.0, fi = k * sn_;
-  if (cfac) {
-    fr += cfac[j].x;
-    fi += cfac[j].y;
-  }
-  const double tr = ar * fr - ai * fi, ti = ar * fi + ai * fr;
+  const double tr = ar * a2, ti = ai * a2;
   if (T64) T64[idx] = make_double2(tr, ti);
   if (T32) T32[idx] = make_float2((float)tr, (float)ti);
 }
@@ -198,19 +189,36 @@ __global__ void k_shift(int64_t nchild, const int64_t* __restrict__ parent, cons
 }
 
 // ------------------------------------------------------------ apply ---
-// CONJ: use conj(Tm) (the conjugate transpose of disaggregation)
-template <typename T, typename V, bool CONJ>
+// Source factor of the aggregation rows: c_j + ik s.n_j (the derivatives of
+// H and E fold into the outgoing plane wave; Sec. 3.3.1).
+template <typename T, typename V>
+__device__ inline V source_factor(const FactorArgs& F, int64_t j, int v) {
+  const T sx = (T)F.s[3 * v], sy = (T)F.s[3 * v + 1], sz = (T)F.s[3 * v + 2];
+  const T sn = sx * (T)F.n[j] + sy * (T)F.n[F.N + j] + sz * (T)F.n[2 * F.N + j];
+  T fr = 0, fi = (T)F.k * sn;
+  if (F.cfac) {
+    fr += (T)F.cfac[j].x;
+    fi += (T)F.cfac[j].y;
+  }
+  return mk(fr, fi);
+}
+
+// sig_c(nu) = sum_{j in c} r_j(nu) x_j with r = Tm (CONJ: conj(Tm)) times the
+// source factor when FACTOR
+template <typename T, typename V, bool CONJ, bool FACTOR>
 __global__ __launch_bounds__(256) void k_aggregate(const int64_t* __restrict__ ebeg,
                                                    const int64_t* __restrict__ eend, int nu,
-                                                   const V* __restrict__ Tm, const double2* __restrict__ x,
-                                                   V* __restrict__ sig) {
+                                                   const V* __restrict__ Tm, FactorArgs F,
+                                                   const double2* __restrict__ x, V* __restrict__ sig) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = blockIdx.y;
   if (v >= nu) return;
   V acc = mk(T(0), T(0));
   for (int64_t j = ebeg[c]; j < eend[c]; ++j) {
-    const V t = Tm[j * nu + v];
-    acc = cadd(acc, CONJ ? cmulc(t, from_d2<V>(x[j])) : cmul(t, from_d2<V>(x[j])));
+    V t = Tm[j * nu + v];
+    if (CONJ) t = mk(t.x, -t.y);
+    if (FACTOR) t = cmul(t, source_factor<T, V>(F, j, v));
+    acc = cadd(acc, cmul(t, from_d2<V>(x[j])));
   }
   sig[c * nu + v] = acc;
 }
@@ -221,18 +229,21 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// CONJ: use conj(Sm) (the conjugate transpose of aggregation)
-template <typename T, typename V, bool CONJ>
+// y_i += sum_nu r_i(nu) loc_c(i)(nu) with r = Sm, or conj(Sm * factor) for
+// the conjugate transpose of aggregation (CONJ; FACTOR adds the source factor)
+template <typename T, typename V, bool CONJ, bool FACTOR>
 __global__ __launch_bounds__(256) void k_disaggregate(int64_t N, const int64_t* __restrict__ ec, int nu,
-                                                      const V* __restrict__ Sm, const V* __restrict__ loc,
-                                                      double2* __restrict__ y) {
+                                                      const V* __restrict__ Sm, FactorArgs F,
+                                                      const V* __restrict__ loc, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
   const int64_t c = ec[i];
   T ar = 0, ai = 0;
   for (int v = lane; v < nu; v += 64) {
-    const V a = Sm[i * nu + v], b = loc[c * nu + v];
+    V a = Sm[i * nu + v];
+    if (FACTOR) a = cmul(a, source_factor<T, V>(F, i, v));
+    const V b = loc[c * nu + v];
     const T ay = CONJ ? -a.y : a.y;
     ar += a.x * b.x - ay * b.y;
     ai += a.x * b.y + ay * b.x;
@@ -438,24 +449,32 @@ void launch_fmm_shift(int64_t nchild, const int64_t* parent, const double* zp, c
 
 template <typename T, typename V>
 void launch_fmm_aggregate(int64_t nclust, const int64_t* ebeg, const int64_t* eend, int nu, const V* Tm,
-                          const double2* x, V* sig, bool conj_rows, hipStream_t st) {
+                          const FactorArgs* F, const double2* x, V* sig, bool conj_rows, hipStream_t st) {
   if (nclust <= 0) return;
-  if (conj_rows)
-    hipLaunchKernelGGL((k_aggregate<T, V, true>), dim3(nblk(nu, 256), (unsigned)nclust), dim3(256), 0, st, ebeg,
-                       eend, nu, Tm, x, sig);
-  else
-    hipLaunchKernelGGL((k_aggregate<T, V, false>), dim3(nblk(nu, 256), (unsigned)nclust), dim3(256), 0, st, ebeg,
-                       eend, nu, Tm, x, sig);
+  const dim3 grid(nblk(nu, 256), (unsigned)nclust);
+  FactorArgs fa = F ? *F : FactorArgs{};
+  if (conj_rows) {
+    if (F) hipLaunchKernelGGL((k_aggregate<T, V, true, true>), grid, dim3(256), 0, st, ebeg, eend, nu, Tm, fa, x, sig);
+    else hipLaunchKernelGGL((k_aggregate<T, V, true, false>), grid, dim3(256), 0, st, ebeg, eend, nu, Tm, fa, x, sig);
+  } else {
+    if (F) hipLaunchKernelGGL((k_aggregate<T, V, false, true>), grid, dim3(256), 0, st, ebeg, eend, nu, Tm, fa, x, sig);
+    else hipLaunchKernelGGL((k_aggregate<T, V, false, false>), grid, dim3(256), 0, st, ebeg, eend, nu, Tm, fa, x, sig);
+  }
 }
 
 template <typename T, typename V>
-void launch_fmm_disaggregate(int64_t N, const int64_t* ec, int nu, const V* Sm, const V* loc, double2* y,
-                             bool conj_rows, hipStream_t st) {
+void launch_fmm_disaggregate(int64_t N, const int64_t* ec, int nu, const V* Sm, const FactorArgs* F, const V* loc,
+                             double2* y, bool conj_rows, hipStream_t st) {
   if (N <= 0) return;
-  if (conj_rows)
-    hipLaunchKernelGGL((k_disaggregate<T, V, true>), dim3(nblk(N, 4)), dim3(256), 0, st, N, ec, nu, Sm, loc, y);
-  else
-    hipLaunchKernelGGL((k_disaggregate<T, V, false>), dim3(nblk(N, 4)), dim3(256), 0, st, N, ec, nu, Sm, loc, y);
+  FactorArgs fa = F ? *F : FactorArgs{};
+  const dim3 grid(nblk(N, 4));
+  if (conj_rows) {
+    if (F) hipLaunchKernelGGL((k_disaggregate<T, V, true, true>), grid, dim3(256), 0, st, N, ec, nu, Sm, fa, loc, y);
+    else hipLaunchKernelGGL((k_disaggregate<T, V, true, false>), grid, dim3(256), 0, st, N, ec, nu, Sm, fa, loc, y);
+  } else {
+    if (F) hipLaunchKernelGGL((k_disaggregate<T, V, false, true>), grid, dim3(256), 0, st, N, ec, nu, Sm, fa, loc, y);
+    else hipLaunchKernelGGL((k_disaggregate<T, V, false, false>), grid, dim3(256), 0, st, N, ec, nu, Sm, fa, loc, y);
+  }
 }
 
 template <typename T, typename V>
@@ -516,9 +535,9 @@ void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const 
 
 #define BEM_FMM_INST(T, V)                                                                                    \
   template void launch_fmm_aggregate<T, V>(int64_t, const int64_t*, const int64_t*, int, const V*,            \
-                                           const double2*, V*, bool, hipStream_t);                            \
-  template void launch_fmm_disaggregate<T, V>(int64_t, const int64_t*, int, const V*, const V*, double2*,     \
-                                              bool, hipStream_t);                                             \
+                                           const FactorArgs*, const double2*, V*, bool, hipStream_t);         \
+  template void launch_fmm_disaggregate<T, V>(int64_t, const int64_t*, int, const V*, const FactorArgs*,      \
+                                              const V*, double2*, bool, hipStream_t);                         \
   template void launch_fmm_translate<T, V>(int64_t, const int64_t*, const int64_t*, const int64_t*, int,      \
                                            const V*, const V*, V*, hipStream_t);                              \
   template void launch_fmm_up_equal<T, V>(int64_t, const int64_t*, const int64_t*, int, const V*, const V*,   \

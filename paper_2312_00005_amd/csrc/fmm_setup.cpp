@@ -68,6 +68,7 @@ struct FmmState {
   DevBuf<double> ra, rb, rw;
   int nq = 0;
   int t_order = 0;
+  double k_setup = -1.0;
 };
 
 void fmm_destroy(FmmState* f) { delete f; }
@@ -277,14 +278,26 @@ struct Pick<float2> {
   static float2* S(FmmSet* f) { return f->S32.p; }
 };
 
+FactorArgs factor_args(bem_mesh* m, const FmmLevel& leaf) {
+  FactorArgs a{};
+  a.N = m->N;
+  a.s = leaf.s.p;
+  a.n = m->d_geom.p + (int64_t)G_NX * m->N;
+  a.cfac = m->have_beta ? m->d_cfac.p : nullptr;
+  a.k = m->k;
+  return a;
+}
+
+// vmode: apply dA/dc (plain aggregation rows) instead of A
 template <typename T, typename V>
-void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hipStream_t s) {
+void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool vmode, hipStream_t s) {
   using P = Pick<V>;
   FmmSet* F = &FS->set[sizeof(T) == sizeof(float) ? 1 : 0];
   const int nl = (int)F->lv.size();
   FmmLevel& leaf = F->lv[nl - 1];
-  launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::T(F), x, P::sig(leaf), false,
-                             s);
+  const FactorArgs fa = factor_args(m, leaf);
+  launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::T(F), vmode ? nullptr : &fa, x,
+                             P::sig(leaf), false, s);
   for (int l = nl - 2; l >= 0; --l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
@@ -313,7 +326,7 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hipStr
       launch_fmm_down_idft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::tB(Lp), P::Ec(Lp), P::loc(Lc), s);
     }
   }
-  launch_fmm_disaggregate<T, V>(m->N, FS->elem_cluster.p, leaf.nu, P::S(F), P::loc(leaf), y, false, s);
+  launch_fmm_disaggregate<T, V>(m->N, FS->elem_cluster.p, leaf.nu, P::S(F), nullptr, P::loc(leaf), y, false, s);
   BEM_HIP(hipGetLastError());
 }
 
@@ -324,12 +337,14 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hipStr
 //   sig'_l = D_l^H loc'_l;  sig'_c += Interp^H(conj(shift_c) * sig'_p) (root -> leaf)
 //   y += T'^H sig'_leaf
 template <typename T, typename V>
-void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hipStream_t s) {
+void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool vmode, hipStream_t s) {
   using P = Pick<V>;
   FmmSet* F = &FS->set[sizeof(T) == sizeof(float) ? 1 : 0];
   const int nl = (int)F->lv.size();
   FmmLevel& leaf = F->lv[nl - 1];
-  launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::S(F), x, P::loc(leaf), true, s);
+  const FactorArgs fa = factor_args(m, leaf);
+  launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::S(F), nullptr, x, P::loc(leaf),
+                             true, s);
   for (int l = nl - 2; l >= 0; --l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
@@ -358,7 +373,8 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, hi
       launch_fmm_down_idft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::tB(Lp), P::Ecc(Lp), P::sig(Lc), s);
     }
   }
-  launch_fmm_disaggregate<T, V>(m->N, FS->elem_cluster.p, leaf.nu, P::T(F), P::sig(leaf), y, true, s);
+  launch_fmm_disaggregate<T, V>(m->N, FS->elem_cluster.p, leaf.nu, P::T(F), vmode ? nullptr : &fa, P::sig(leaf),
+                                y, true, s);
   BEM_HIP(hipGetLastError());
 }
 
@@ -512,8 +528,7 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     F->T64.alloc(m->N * leaf.nu);
     F->S64.alloc(m->N * leaf.nu);
   }
-  const double2* cf = m->have_beta ? m->d_cfac.p : nullptr;
-  launch_fmm_leaf_T(m->N, m->d_geom.p, FS->elem_cluster.p, leaf.z.p, leaf.s.p, leaf.nu, cf, k, FS->ra.p, FS->rb.p,
+  launch_fmm_leaf_T(m->N, m->d_geom.p, FS->elem_cluster.p, leaf.z.p, leaf.s.p, leaf.nu, nullptr, k, FS->ra.p, FS->rb.p,
                     FS->rw.p, FS->nq, single ? nullptr : F->T64.p, single ? F->T32.p : nullptr, s);
   launch_fmm_leaf_S(m->N, m->d_geom.p, FS->elem_cluster.p, leaf.z.p, leaf.s.p, leaf.w.p, leaf.nu, k, m->gre,
                     m->gim, single ? nullptr : F->S64.p, single ? F->S32.p : nullptr, s);
@@ -529,19 +544,23 @@ void fmm_setup_problem(bem_mesh* m, hipStream_t s) {
     upload_tree(m, m->fmm_state, s);
   }
   FmmState* F = m->fmm_state;
+  // nothing below depends on the admittance: a new beta at the same k reuses it
+  if (F->k_setup == m->k && F->t_order == m->opt.t_order) return;
+  F->k_setup = m->k;
   upload_rule(F, m->opt.t_order, s);
   setup_set(m, F, 0, s);
   setup_set(m, F, 1, s);
 }
 
-void fmm_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s) {
+void fmm_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s,
+               bool vmode) {
   if (!m->fmm_state) throw Error(BEM_E_STATE, "FMM not set up");
   if (op == BEM_OP_A) {
-    if (prec == BEM_PREC_FP64) fmm_apply_t<double, double2>(m, m->fmm_state, x, y, s);
-    else fmm_apply_t<float, float2>(m, m->fmm_state, x, y, s);
+    if (prec == BEM_PREC_FP64) fmm_apply_t<double, double2>(m, m->fmm_state, x, y, vmode, s);
+    else fmm_apply_t<float, float2>(m, m->fmm_state, x, y, vmode, s);
   } else {
-    if (prec == BEM_PREC_FP64) fmm_apply_adj_t<double, double2>(m, m->fmm_state, x, y, s);
-    else fmm_apply_adj_t<float, float2>(m, m->fmm_state, x, y, s);
+    if (prec == BEM_PREC_FP64) fmm_apply_adj_t<double, double2>(m, m->fmm_state, x, y, vmode, s);
+    else fmm_apply_adj_t<float, float2>(m, m->fmm_state, x, y, vmode, s);
   }
 }
 

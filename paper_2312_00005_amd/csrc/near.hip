@@ -156,8 +156,9 @@ __device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t
 // Integrate one item: returns S1 (c-independent part) and S2 (c_j part),
 // both already multiplied by 2 * area of the (sub-)triangle.
 // m is the item's rule order; the caller passes it wavefront-uniform so the
-// rule tables are read with scalar loads.
-template <typename T, bool HAS_C>
+// rule tables are read with scalar loads.  S1: the c-independent part
+// -(H - gamma E); S2: the part multiplied by c_j, (G - gamma H').
+template <typename T, bool WANT_S1, bool WANT_S2>
 __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64_t item, int m, const T xi[3],
                                       const T ni[3], T k, T gre, T gim, T& s1r, T& s1i, T& s2r,
                                       T& s2i, int64_t& jout) {
@@ -194,15 +195,17 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
     const T rny = (R[0] * nj[0] + R[1] * nj[1] + R[2] * nj[2]) * rinv;
     const T rnx = (R[0] * ni[0] + R[1] * ni[1] + R[2] * ni[2]) * rinv;
     // t1 = B rnx rny + a nn / r with a = (-1/r, k), B = (3/r^2 - k^2, -3k/r)
-    const T p = rnx * rny;
-    const T t1r = (T(3) * rinv * rinv - k * k) * p - nn * rinv * rinv;
-    const T t1i = -T(3) * k * rinv * p + k * nn * rinv;
-    // b1 = -a rny - gamma t1
-    const T b1r = rinv * rny - (gre * t1r - gim * t1i);
-    const T b1i = -k * rny - (gre * t1i + gim * t1r);
-    a1r += Gr * b1r - Gi * b1i;
-    a1i += Gr * b1i + Gi * b1r;
-    if (HAS_C) {
+    if (WANT_S1) {
+      const T p = rnx * rny;
+      const T t1r = (T(3) * rinv * rinv - k * k) * p - nn * rinv * rinv;
+      const T t1i = -T(3) * k * rinv * p + k * nn * rinv;
+      // b1 = -a rny - gamma t1
+      const T b1r = rinv * rny - (gre * t1r - gim * t1i);
+      const T b1i = -k * rny - (gre * t1i + gim * t1r);
+      a1r += Gr * b1r - Gi * b1i;
+      a1i += Gr * b1i + Gi * b1r;
+    }
+    if (WANT_S2) {
       // b2 = 1 + gamma a rnx
       const T b2r = T(1) + (-gre * rinv - gim * k) * rnx;
       const T b2i = (gre * k - gim * rinv) * rnx;
@@ -216,7 +219,9 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
   s2i = a2i * area2;
 }
 
-template <typename T, bool HAS_C>
+// VMODE: apply dA/dc -- the (G - gamma H') part without c_j, diagonal
+// G_ii - gamma/2 -- instead of A.
+template <typename T, bool HAS_C, bool VMODE>
 __global__ __launch_bounds__(256) void k_near(NearLaunch L, const T* __restrict__ g,
                                               const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
@@ -240,9 +245,13 @@ __global__ __launch_bounds__(256) void k_near(NearLaunch L, const T* __restrict_
     for (int64_t it = b + lane; it < e; it += 64) {
       T s1r, s1i, s2r, s2i;
       int64_t j;
-      integrate_item<T, HAS_C>(g, N, L.items[it], mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, j);
+      integrate_item<T, !VMODE, HAS_C || VMODE>(g, N, L.items[it], mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r,
+                                               s2i, j);
       T vr = s1r, vi = s1i;
-      if (HAS_C) {
+      if (VMODE) {
+        vr = s2r;
+        vi = s2i;
+      } else if (HAS_C) {
         const double2 c = L.cfac[j];
         const T cr = (T)c.x, ci = (T)c.y;
         vr += cr * s2r - ci * s2i;
@@ -257,7 +266,7 @@ __global__ __launch_bounds__(256) void k_near(NearLaunch L, const T* __restrict_
   double sr = wave_sum((double)accr);
   double si = wave_sum((double)acci);
   if (lane == 0) {
-    const double2 d = L.diag[t];
+    const double2 d = VMODE ? L.vdiag[t] : L.diag[t];
     const double2 xt = x[t];
     y[t] = make_double2(d.x * xt.x - d.y * xt.y + sr, d.x * xt.y + d.y * xt.x + si);
   }
@@ -266,7 +275,7 @@ __global__ __launch_bounds__(256) void k_near(NearLaunch L, const T* __restrict_
 // Conjugate transpose: items are indexed by source j ("targets" of this
 // launch are sources); the item's element field holds the collocation index i.
 // y_j = conj(A_jj) x_j + sum_i conj(K_ij) x_i.
-template <typename T, bool HAS_C>
+template <typename T, bool HAS_C, bool VMODE>
 __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restrict__ g,
                                                   const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
@@ -298,9 +307,12 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
       }
       T s1r, s1i, s2r, s2i;
       int64_t jj;
-      integrate_item<T, HAS_C>(g, N, item, mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, jj);
+      integrate_item<T, !VMODE, HAS_C || VMODE>(g, N, item, mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, jj);
       T vr = s1r, vi = s1i;
-      if (HAS_C) {
+      if (VMODE) {
+        vr = s2r;
+        vi = s2i;
+      } else if (HAS_C) {
         vr += cr * s2r - ci * s2i;
         vi += cr * s2i + ci * s2r;
       }
@@ -314,22 +326,26 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
   double sr = wave_sum((double)accr);
   double si = wave_sum((double)acci);
   if (lane == 0) {
-    const double2 d = L.diag[jsrc];
+    const double2 d = VMODE ? L.vdiag[jsrc] : L.diag[jsrc];
     const double2 xt = x[jsrc];
     y[jsrc] = make_double2(d.x * xt.x + d.y * xt.y + sr, d.x * xt.y - d.y * xt.x + si);
   }
 }
 
 template <typename T>
-void near_dispatch(const NearLaunch& L, const T* g, const double2* x, double2* y, hipStream_t s, bool adj) {
+void near_dispatch(const NearLaunch& L, const T* g, const double2* x, double2* y, hipStream_t s, bool adj,
+                   bool vmode) {
   if (L.N <= 0) return;
   dim3 grid((unsigned)((L.N + 3) / 4)), block(256);
-  if (!adj) {
-    if (L.cfac) hipLaunchKernelGGL((k_near<T, true>), grid, block, 0, s, L, g, x, y);
-    else hipLaunchKernelGGL((k_near<T, false>), grid, block, 0, s, L, g, x, y);
+  if (vmode) {
+    if (!adj) hipLaunchKernelGGL((k_near<T, false, true>), grid, block, 0, s, L, g, x, y);
+    else hipLaunchKernelGGL((k_near_adj<T, false, true>), grid, block, 0, s, L, g, x, y);
+  } else if (!adj) {
+    if (L.cfac) hipLaunchKernelGGL((k_near<T, true, false>), grid, block, 0, s, L, g, x, y);
+    else hipLaunchKernelGGL((k_near<T, false, false>), grid, block, 0, s, L, g, x, y);
   } else {
-    if (L.cfac) hipLaunchKernelGGL((k_near_adj<T, true>), grid, block, 0, s, L, g, x, y);
-    else hipLaunchKernelGGL((k_near_adj<T, false>), grid, block, 0, s, L, g, x, y);
+    if (L.cfac) hipLaunchKernelGGL((k_near_adj<T, true, false>), grid, block, 0, s, L, g, x, y);
+    else hipLaunchKernelGGL((k_near_adj<T, false, false>), grid, block, 0, s, L, g, x, y);
   }
 }
 
@@ -423,6 +439,210 @@ __global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict_
   double dr = 0.5 * (1.0 - gcr) + (L.gre * Er - L.gim * Ei) + (Gr * cr - Gi * ci);
   double di = -0.5 * gci + (L.gre * Ei + L.gim * Er) + (Gr * ci + Gi * cr);
   diag[t] = make_double2(dr, di);
+  // dA/dc on the diagonal: G_ii - gamma/2
+  if (L.vdiag) L.vdiag[t] = make_double2(Gr - 0.5 * L.gre, Gi - 0.5 * L.gim);
+}
+
+
+// ------------------------------------------------------------ field points ---
+// Exterior field (Eq. (BIE_I) with lambda = 1): K_fj = I^H(x_f, G_j) - c_j I^G(x_f, G_j)
+// with the quasi-singular / regular rules of Sec. 3.1.3-3.1.4 chosen on the fly
+// from r~ = |x_f - mid| / sqrt(A): split while r~ < ratio, else the estimator
+// order, capped or split as for the collocation plan.  The subdivision tree is
+// walked depth first without a stack: (depth, path) names the current
+// sub-triangle with the same child numbering as the near-field items.
+__device__ inline int field_order(double rt, double eps) {
+  const double q = 1.0 / (2.0 * rt);
+  for (int m = 1; m <= 64; ++m) {
+    const double eg = 32.0 * pow(q, (double)(2 * m + 1));
+    const double eh = 64.0 * (double)(2 * m + 1) * pow(q, (double)(2 * m + 2));
+    const double ee = 128.0 * (double)(m + 1) * (double)(2 * m + 1) * pow(q, (double)(2 * m + 3));
+    if (eg < eps && eh < eps && ee < eps) return m;
+  }
+  return 64;
+}
+
+// integrals (I^G, I^H) of element j seen from x; false on a subdivision overflow
+__device__ bool field_integrals(const FieldArgs& A, int64_t j, const double x[3], double2& IG, double2& IH) {
+  const int64_t N = A.N;
+  const double* g = A.geom;
+  const double nj[3] = {g[(NX + 0) * N + j], g[(NX + 1) * N + j], g[(NX + 2) * N + j]};
+  const double area0 = g[AREA * N + j];
+  const int max_depth = A.max_subdiv < 15 ? A.max_subdiv : 15;
+  int depth = 0;
+  uint64_t path = 0;
+  double gr = 0, gi = 0, hr = 0, hi = 0;
+  for (;;) {
+    double v0[3], v1[3], v2[3];
+    item_triangle<double>(g, N, j, depth, path, v0, v1, v2);
+    const double area = area0 * ldexp(1.0, -2 * depth);
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double dc = x[c] - (v0[c] + v1[c] + v2[c]) / 3.0;
+      d2 += dc * dc;
+    }
+    const double rt = sqrt(d2) / sqrt(area);
+    bool split = rt < A.ratio;
+    int m = 1;
+    if (!split) {
+      m = field_order(rt, A.eps);
+      if (m > A.m_max) {
+        if (A.split_on_cap) split = true;
+        else m = A.m_max;
+      }
+    }
+    if (split) {
+      if (depth >= max_depth) return false;
+      ++depth;  // first child: digit 0
+      continue;
+    }
+    const int base = c_rule_off[m - 1];
+    double e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) {
+      e1[c] = v1[c] - v0[c];
+      e2[c] = v2[c] - v0[c];
+    }
+    double sgr = 0, sgi = 0, shr = 0, shi = 0;
+    for (int q = 0; q < m * m; ++q) {
+      const double qa = c_rule_a[base + q], qb = c_rule_b[base + q], qw = c_rule_w[base + q];
+      double R[3];
+      for (int c = 0; c < 3; ++c) R[c] = (v0[c] + qa * e1[c] + qb * e2[c]) - x[c];
+      const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+      const double rinv = rsqrt(r2);
+      double sn, cs;
+      sincos(A.k * (r2 * rinv), &sn, &cs);
+      const double gs = qw * rinv * kInv4Pi;
+      const double Gr = gs * cs, Gi = gs * sn;
+      const double rny = (R[0] * nj[0] + R[1] * nj[1] + R[2] * nj[2]) * rinv;
+      // H = G (ik - 1/r) rny
+      sgr += Gr;
+      sgi += Gi;
+      shr += (-Gr * rinv - Gi * A.k) * rny;
+      shi += (Gr * A.k - Gi * rinv) * rny;
+    }
+    const double a2 = 2.0 * area;
+    gr += a2 * sgr;
+    gi += a2 * sgi;
+    hr += a2 * shr;
+    hi += a2 * shi;
+    // next sub-triangle in depth-first order
+    while (depth > 0) {
+      const int sh = 2 * (depth - 1);
+      if (((path >> sh) & 3u) < 3u) {
+        path += (uint64_t)1 << sh;
+        break;
+      }
+      path &= ~((uint64_t)3 << sh);
+      --depth;
+    }
+    if (depth == 0) break;
+  }
+  IG = make_double2(gr, gi);
+  IH = make_double2(hr, hi);
+  return true;
+}
+
+// p_out[f] = p_inc[f] + sum_j K_fj p[j]  (one wavefront per field point)
+__global__ __launch_bounds__(256) void k_field(FieldArgs A, const double* __restrict__ pts,
+                                               const double2* __restrict__ p, const double2* __restrict__ pinc,
+                                               double2* __restrict__ out, int64_t* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (f >= A.npts) return;
+  const double x[3] = {pts[3 * f], pts[3 * f + 1], pts[3 * f + 2]};
+  double ar = 0, ai = 0;
+  for (int64_t j = lane; j < A.N; j += 64) {
+    double2 IG, IH;
+    if (!field_integrals(A, j, x, IG, IH)) {
+      err[0] = j;
+      continue;
+    }
+    double kr = IH.x, ki = IH.y;
+    if (A.cfac && A.part == 0) {
+      const double2 c = A.cfac[j];
+      kr -= c.x * IG.x - c.y * IG.y;
+      ki -= c.x * IG.y + c.y * IG.x;
+    }
+    if (A.part == 1) {
+      kr = IG.x;
+      ki = IG.y;
+    }
+    const double2 pj = p[j];
+    ar += kr * pj.x - ki * pj.y;
+    ai += kr * pj.y + ki * pj.x;
+  }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (lane == 0) {
+    const double2 b = pinc ? pinc[f] : make_double2(0.0, 0.0);
+    out[f] = make_double2(b.x + ar, b.y + ai);
+  }
+}
+
+// y[j] = sum_f conj(K_fj) g[f]  (one wavefront per element); part 1: K = I^G
+__global__ __launch_bounds__(256) void k_field_adj(FieldArgs A, const double* __restrict__ pts,
+                                                   const double2* __restrict__ gv, double2* __restrict__ y,
+                                                   int64_t* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= A.N) return;
+  double ar = 0, ai = 0;
+  double cr = 0, ci = 0;
+  if (A.cfac && A.part == 0) {
+    cr = A.cfac[j].x;
+    ci = A.cfac[j].y;
+  }
+  for (int64_t f = lane; f < A.npts; f += 64) {
+    const double x[3] = {pts[3 * f], pts[3 * f + 1], pts[3 * f + 2]};
+    double2 IG, IH;
+    if (!field_integrals(A, j, x, IG, IH)) {
+      err[0] = j;
+      continue;
+    }
+    double kr, ki;
+    if (A.part == 1) {
+      kr = IG.x;
+      ki = IG.y;
+    } else {
+      kr = IH.x - (cr * IG.x - ci * IG.y);
+      ki = IH.y - (cr * IG.y + ci * IG.x);
+    }
+    const double2 gf = gv[f];
+    // conj(K) g
+    ar += kr * gf.x + ki * gf.y;
+    ai += kr * gf.y - ki * gf.x;
+  }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (lane == 0) y[j] = make_double2(ar, ai);
+}
+
+// energy[0] = sum_f |p_f|^2 (one block)
+__global__ __launch_bounds__(256) void k_energy(int64_t n, const double2* __restrict__ p, double* __restrict__ energy) {
+  __shared__ double part[4];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += p[i].x * p[i].x + p[i].y * p[i].y;
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) energy[0] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// grad[e] = 2 Re{ dc p_e (-conj(w_e) - conj(hg_e)) },  dc = -i k rho_c
+// (caller order; the derivative of sum_f |p_f|^2 with respect to Y_e, with
+// beta = rho_c Y; w = V^H mu from the adjoint solve, hg = (I^G)^H p_field)
+__global__ void k_grad_admittance(int64_t N, double k, double rho_c, const double2* __restrict__ p,
+                                  const double2* __restrict__ w, const double2* __restrict__ hg,
+                                  double* __restrict__ grad) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const double2 pe = p[e], we = w[e], he = hg[e];
+  // t = -conj(w) - conj(hg)
+  const double tr = -we.x - he.x, ti = we.y + he.y;
+  // u = p_e t
+  const double ur = pe.x * tr - pe.y * ti, ui = pe.x * ti + pe.y * tr;
+  // Re{ -i k rho_c u } = k rho_c Im(u)
+  grad[e] = 2.0 * k * rho_c * ui;
 }
 
 // -------------------------------------------------------- small kernels ---
@@ -455,6 +675,27 @@ __global__ void k_rhs_point(int64_t N, const double* __restrict__ g, double k, d
   const double fr = -rn / R, fi = k * rn;
   const double qr = pr * fr - pi * fi, qi = pr * fi + pi * fr;
   out[t] = make_double2(pr - (gre * qr - gim * qi), pi - (gre * qi + gim * qr));
+}
+
+// incident pressure at arbitrary points: kind 0 plane wave along s, kind 1
+// point source at s (Sec. 2.4)
+__global__ void k_incident(int64_t n, const double* __restrict__ pts, int kind, double k, double s0, double s1,
+                           double s2, double p0r, double p0i, double2* __restrict__ out) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  const double x0 = pts[3 * f], x1 = pts[3 * f + 1], x2 = pts[3 * f + 2];
+  double ph, sc = 1.0;
+  if (kind == 0) {
+    ph = k * (x0 * s0 + x1 * s1 + x2 * s2);
+  } else {
+    const double R0 = x0 - s0, R1 = x1 - s1, R2 = x2 - s2;
+    const double R = sqrt(R0 * R0 + R1 * R1 + R2 * R2);
+    ph = k * R;
+    sc = kInv4Pi / R;
+  }
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  out[f] = make_double2(sc * (p0r * cs - p0i * sn), sc * (p0r * sn + p0i * cs));
 }
 
 __global__ void k_gather(int64_t N, const int64_t* __restrict__ perm, const double2* __restrict__ src,
@@ -491,17 +732,10 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-void launch_near_f64(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
-  near_dispatch<double>(L, L.geom, x, y, s, false);
-}
-void launch_near_f32(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
-  near_dispatch<float>(L, L.geom32, x, y, s, false);
-}
-void launch_near_adj_f64(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
-  near_dispatch<double>(L, L.geom, x, y, s, true);
-}
-void launch_near_adj_f32(const NearLaunch& L, const double2* x, double2* y, hipStream_t s) {
-  near_dispatch<float>(L, L.geom32, x, y, s, true);
+void launch_near(const NearLaunch& L, bool fp64, bool adjoint, bool vmode, const double2* x, double2* y,
+                 hipStream_t s) {
+  if (fp64) near_dispatch<double>(L, L.geom, x, y, s, adjoint, vmode);
+  else near_dispatch<float>(L, L.geom32, x, y, s, adjoint, vmode);
 }
 
 void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s) {
@@ -523,6 +757,13 @@ void launch_rhs_point(int64_t N, const double* geom, double k, double gre, doubl
                      x0[0], x0[1], x0[2], p0re, p0im, out);
 }
 
+void launch_incident(int64_t n, const double* pts, int kind, double k, const double* src, double p0re,
+                     double p0im, double2* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_incident, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, pts, kind, k, src[0], src[1],
+                     src[2], p0re, p0im, out);
+}
+
 void launch_gather(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s) {
   if (N <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, perm, src, dst);
@@ -537,6 +778,28 @@ void launch_cfac(int64_t N, const int64_t* perm, const double2* beta, double k, 
                  hipStream_t s) {
   if (N <= 0) return;
   hipLaunchKernelGGL(k_cfac, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, perm, beta, k, cf);
+}
+
+void launch_field(const FieldArgs& A, const double* pts, const double2* p, const double2* pinc, double2* out,
+                  int64_t* err, hipStream_t s) {
+  if (A.npts <= 0) return;
+  hipLaunchKernelGGL(k_field, dim3(blocks_for(A.npts, 4)), dim3(256), 0, s, A, pts, p, pinc, out, err);
+}
+
+void launch_energy(int64_t n, const double2* p, double* energy, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, s, n, p, energy);
+}
+
+void launch_field_adj(const FieldArgs& A, const double* pts, const double2* g, double2* y, int64_t* err,
+                      hipStream_t s) {
+  if (A.N <= 0) return;
+  hipLaunchKernelGGL(k_field_adj, dim3(blocks_for(A.N, 4)), dim3(256), 0, s, A, pts, g, y, err);
+}
+
+void launch_grad_admittance(int64_t N, double k, double rho_c, const double2* p, const double2* w,
+                            const double2* hg, double* grad, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_grad_admittance, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, k, rho_c, p, w, hg, grad);
 }
 
 void launch_velocity(int64_t N, const double2* beta, double rho_c, const double2* p, double2* v,

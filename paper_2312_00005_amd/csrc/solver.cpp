@@ -33,7 +33,7 @@ double vec_norm(bem_mesh* m, const double2* v, const Work& W, hipStream_t s) {
 // One restarted GMRES solve of A x = b with operator precision prec.  x holds
 // the initial guess (x_zero: treat it as zero).  Stops when the residual
 // estimate falls below tol_abs, or after maxit iterations in total.
-int gmres(bem_mesh* m, bem_precision prec, const double2* b, double2* x, bool x_zero, double tol_abs,
+int gmres(bem_mesh* m, bem_op op, bem_precision prec, const double2* b, double2* x, bool x_zero, double tol_abs,
           int maxit, const Work& W, hipStream_t s, bool* converged) {
   const int64_t N = W.N;
   const int R = W.restart;
@@ -51,7 +51,7 @@ int gmres(bem_mesh* m, bem_precision prec, const double2* b, double2* x, bool x_
       BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
       x_zero = false;
     } else {
-      apply_tree(m, BEM_OP_A, prec, x, w, s);
+      apply_tree(m, op, prec, x, w, s);
       launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), w, r, s);
     }
     double beta = vec_norm(m, r, W, s);
@@ -66,7 +66,7 @@ int gmres(bem_mesh* m, bem_precision prec, const double2* b, double2* x, bool x_
     int jend = -1;
     bool done = false;
     for (int j = 0; j < R; ++j) {
-      apply_tree(m, BEM_OP_A, prec, V + (int64_t)j * N, w, s);
+      apply_tree(m, op, prec, V + (int64_t)j * N, w, s);
       ++iters;
       // classical Gram-Schmidt, twice
       launch_multidot(N, j + 1, V, N, w, m->d_partial.p, W.nblk, s);
@@ -124,7 +124,7 @@ int gmres(bem_mesh* m, bem_precision prec, const double2* b, double2* x, bool x_
     BEM_HIP(hipStreamSynchronize(s));
     if (done && iters >= maxit) {
       // recompute the true residual to decide
-      apply_tree(m, BEM_OP_A, prec, x, w, s);
+      apply_tree(m, op, prec, x, w, s);
       launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), w, r, s);
       *converged = vec_norm(m, r, W, s) <= tol_abs;
       return iters;
@@ -134,7 +134,7 @@ int gmres(bem_mesh* m, bem_precision prec, const double2* b, double2* x, bool x_
 
 }  // namespace
 
-SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s) {
+SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s, bem_op op) {
   const int64_t N = m->N;
   Work W{N, std::max(1, std::min(m->opt.gmres_restart, 200)), multidot_blocks(N)};
   m->d_V.alloc((size_t)(W.restart + 1) * N);
@@ -153,7 +153,7 @@ SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s)
   const double tol = m->opt.gmres_tol;
   if (m->opt.precision == BEM_PREC_FP64) {
     bool conv = false;
-    out.iterations = gmres(m, BEM_PREC_FP64, b, x, true, tol * bnorm, m->opt.gmres_maxit, W, s, &conv);
+    out.iterations = gmres(m, op, BEM_PREC_FP64, b, x, true, tol * bnorm, m->opt.gmres_maxit, W, s, &conv);
   } else {
     // FP64 iterative refinement around the complex-FP32 operator
     BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
@@ -165,17 +165,17 @@ SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s)
       if (rn <= tol * bnorm) break;
       bool conv = false;
       // save rr: gmres uses d_r internally
-      out.iterations += gmres(m, BEM_PREC_MIXED, rr, d, true, m->opt.inner_tol * rn,
+      out.iterations += gmres(m, op, BEM_PREC_MIXED, rr, d, true, m->opt.inner_tol * rn,
                               m->opt.gmres_maxit, W, s, &conv);
       ++out.refinements;
       launch_axpby(N, make_double2(1, 0), x, make_double2(1, 0), d, x, s);
-      apply_tree(m, BEM_OP_A, BEM_PREC_FP64, x, m->d_w.p, s);
+      apply_tree(m, op, BEM_PREC_FP64, x, m->d_w.p, s);
       launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), m->d_w.p, rr, s);
       if (out.iterations >= m->opt.gmres_maxit) break;
     }
   }
   // true FP64 residual
-  apply_tree(m, BEM_OP_A, BEM_PREC_FP64, x, m->d_w.p, s);
+  apply_tree(m, op, BEM_PREC_FP64, x, m->d_w.p, s);
   launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), m->d_w.p, m->d_r.p, s);
   out.rel_residual = vec_norm(m, m->d_r.p, W, s) / bnorm;
   out.converged = out.rel_residual <= tol * (1.0 + 1e-6);

@@ -38,6 +38,7 @@ struct bem_mesh {
   bem::DevBuf<double2> d_beta;     // caller order
   bem::DevBuf<double2> d_cfac;     // tree order, c_j = -i k beta_j
   bem::DevBuf<double2> d_diag;     // tree order, A_ii
+  bem::DevBuf<double2> d_vdiag;    // tree order, diagonal of dA/dc
 
   // work vectors (tree order)
   bem::DevBuf<double2> d_x, d_y, d_r, d_b, d_sol, d_tmp;
@@ -55,12 +56,15 @@ namespace bem {
 // tree-order operator application (x_t, y_t device, length N)
 void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s);
 // part 0: whole operator; 1: diagonal + near field; 2: far field only
+// vmode: dA/dc (the matrix that multiplies diag(c)) instead of A
 void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
-                     hipStream_t s);
+                     hipStream_t s, bool vmode = false);
 
 // FMM far field: y += far(x), tree order.  No-op if the mesh has no FMM.
 void fmm_setup_problem(bem_mesh* m, hipStream_t s);
-void fmm_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s);
+// vmode: apply dA/dc (the matrix multiplying diag(c)) instead of A
+void fmm_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s,
+               bool vmode = false);
 size_t fmm_bytes(const bem_mesh* m);
 
 struct SolveResult {
@@ -69,7 +73,8 @@ struct SolveResult {
   double rel_residual = 0.0;
   bool converged = false;
 };
-SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s);
+// solve op(A) x = b (op = A or A^H)
+SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s, bem_op op = BEM_OP_A);
 
 void ensure_transposed_plan(bem_mesh* m, hipStream_t s);
 

@@ -43,6 +43,16 @@ def _k(nodes, tris, epw):
     return 2 * math.pi / (epw * synth.mean_edge_length(nodes, tris))
 
 
+def _amplification(F, k):
+    """Largest growth (2L+1)|h_L(k X_min)| of the translation operators."""
+    amp = 1.0
+    for Lv, L in zip(F.tree.levels, F.L):
+        xm = ofmm.level_min_separation(Lv)
+        if xm is not None:
+            amp = max(amp, (2 * L + 1) * ofmm.hankel_abs(L, k * xm))
+    return amp
+
+
 FAR_CASES = [
     # mesh subdiv, levels, leaf, admissibility, preset, elements per wavelength, with beta
     (3, 2, 32, 2.0, "paper", 6.0, False),
@@ -73,11 +83,7 @@ def test_far_field_matches_oracle_fmm(bem, subdiv, levels, leaf, adm, pre, epw, 
     assert np.max(np.abs(y_or)) > 0
     # rounding differences are amplified by the translation operator's growth
     # (2L+1)|h_L(k X_min)| at small arguments: allow ten times that bound
-    amp = 1.0
-    for Lv, L in zip(F.tree.levels, F.L):
-        xm = ofmm.level_min_separation(Lv)
-        if xm is not None:
-            amp = max(amp, (2 * L + 1) * ofmm.hankel_abs(L, k * xm))
+    amp = _amplification(F, k)
     tol = max(1e-11, 10 * 2.2e-16 * amp)
     announce(f"  L={F.L} amplification={amp:.2e} tol={tol:.1e}")
     assert rel_max(y, y_or) < tol
@@ -86,11 +92,7 @@ def test_far_field_matches_oracle_fmm(bem, subdiv, levels, leaf, adm, pre, epw, 
     # construction of the lengths
     F32 = ofmm.FMM(g, k, p, levels, leaf, beta=beta, tree=F.tree, single=True)
     y_or32 = F32.apply(x)
-    amp32 = 1.0
-    for Lv, L in zip(F32.tree.levels, F32.L):
-        xm = ofmm.level_min_separation(Lv)
-        if xm is not None:
-            amp32 = max(amp32, (2 * L + 1) * ofmm.hankel_abs(L, k * xm))
+    amp32 = _amplification(F32, k)
     tol32 = max(3e-5, 10 * 2.0 ** -23 * amp32)
     announce(f"  L32={F32.L} amplification={amp32:.2e} tol32={tol32:.1e}")
     y32 = to_host(m.apply_part(xd, 2, prec="mixed"))
@@ -178,8 +180,10 @@ def test_full_size_solve(bem, c2, prec):
 @pytest.mark.parametrize("subdiv,levels,epw", [(4, 3, 6.0), (4, 3, 20.0), (3, 2, 6.0)])
 def test_conjugate_transpose_dot_product(bem, subdiv, levels, epw):
     """<A x, y> = <x, A^H y> for the far field alone and for the whole
-    operator, FP64 to 1e-12 and complex-FP32 to 1e-5 (the library's forward
-    operator is itself pinned to the oracle above)."""
+    operator, FP64 to 1e-12 (or ten times the translation operators' rounding
+    amplification 2^-52 (2L+1)|h_L(k X_min)| where that is larger) and
+    complex-FP32 to 1e-5 (the library's forward operator is itself pinned to
+    the oracle above)."""
     announce(f"adjoint dot test ico{subdiv} levels={levels} epw={epw}")
     nodes, tris = synth.icosphere(subdiv)
     N = len(tris)
@@ -192,7 +196,11 @@ def test_conjugate_transpose_dot_product(bem, subdiv, levels, epw):
     x = synth.complex_normal(N, seed=4)
     y = synth.complex_normal(N, seed=6)
     xd, yd = to_dev(x), to_dev(y)
-    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+    g = element_geometry(nodes, tris)
+    amp = _amplification(ofmm.FMM(g, k, preset("tight", admissibility=adm), levels, 32, beta=beta), k)
+    tol64 = max(1e-12, 10 * 2.2e-16 * amp)
+    announce(f"  amplification={amp:.2e} tol64={tol64:.1e}")
+    for prec, tol in (("fp64", tol64), ("mixed", 1e-5)):
         for part in (2, 0):
             Ax = to_host(m.apply_part(xd, part, prec=prec))
             AHy = to_host(m.apply_part(yd, part, op="AH", prec=prec))
