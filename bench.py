@@ -33,6 +33,10 @@ WORKLOADS = {
                elems_per_wavelength=6.0),
     # 1280-triangle rigid sphere, k = 1, every pair by direct quadrature
     "c1": dict(mesh=("icosphere", 3), use_fmm=0, preset="tight", k=1.0),
+    # head-like graded ellipsoid with a bump (~60k triangles), 16 kHz in air,
+    # point source 1 mm off the bump, 5-level FMM
+    "c3": dict(mesh=("graded", None), use_fmm=1, levels=5, leaf_size=32, preset="mixed",
+               k=2 * math.pi * 16000.0 / 343.0, source="point"),
 }
 
 
@@ -66,7 +70,12 @@ def main():
     from paper_2312_00005_amd import bemfmm
 
     wl = WORKLOADS[args.workload]
-    nodes, tris = synth.icosphere(wl["mesh"][1])
+    src = None
+    if wl["mesh"][0] == "graded":
+        nodes, tris, apex, apex_n = synth.graded_ellipsoid_bump()
+        src = tuple(apex + 1e-3 * apex_n)
+    else:
+        nodes, tris = synth.icosphere(wl["mesh"][1])
     N = len(tris)
     if "k" in wl:
         k = wl["k"]
@@ -123,7 +132,10 @@ def main():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ms.set_problem(k)
-            rhs = ms.rhs_plane_wave((0.0, 0.0, 1.0))
+            if wl.get("source") == "point":
+                rhs = ms.rhs_point_source(src)
+            else:
+                rhs = ms.rhs_plane_wave((0.0, 0.0, 1.0))
             p, _, info = ms.solve(rhs)
             torch.cuda.synchronize()
             solves[prec] = dict(seconds=time.perf_counter() - t0, iterations=info["iterations"],
@@ -149,8 +161,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64 (fp32 operator; fp64 diagonal, Krylov and refinement)",
-        "data": "synthetic (seeded icosphere mesh and complex-normal vector)",
-        "config": {"workload": f"{args.workload}: rigid sphere N={N}, k={k:.4f}, "
+        "data": "synthetic (seeded mesh and complex-normal vector)",
+        "config": {"workload": f"{args.workload}: "
+                   + ("graded ellipsoid with bump" if src is not None else "rigid sphere")
+                   + f" N={N}, k={k:.4f}, "
                    + (f"{wl['levels']}-level FMM leaf~{wl['leaf_size']}" if wl["use_fmm"] else "all pairs direct")
                    + f", preset {wl['preset']}",
                    "n_elements": N, "k": k, "preset": wl["preset"]},

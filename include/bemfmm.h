@@ -110,6 +110,21 @@ typedef struct bem_options {
   double l_eps_mixed;       /* expansion accuracy of the complex-FP32 operator;
                                its L is also capped so that FP32 rounding times
                                (2L+1)|h_L(k X_min)| stays below l_eps_mixed/10 */
+  int32_t precond;          /* right preconditioner of GMRES (the role of
+                               the near-field preconditioning of Sec. 3.2):
+                               0 none; 1 block Jacobi -- the dense near-field
+                               blocks of the leaf clusters (split into pieces
+                               of at most 64 elements) inverted per
+                               frequency; 2 diagonal (Jacobi) scaling */
+  double gamma_re;          /* Burton-Miller coupling                        */
+  double gamma_im_k;        /*   gamma = gamma_re + i gamma_im_k / k; the
+                               paper's gamma = i/k is (0, 1) (Sec. 2.5).
+                               Any gamma with a non-zero imaginary part gives
+                               a uniquely solvable system; on non-spherical
+                               bodies at ka >> 1, (0, -1) places the spectrum
+                               of the discrete operator in the right
+                               half-plane and Krylov iterations converge far
+                               faster.  gamma_im_k = 0 is BEM_E_ARG. */
 } bem_options;
 
 typedef struct bem_solve_info {

@@ -33,7 +33,7 @@ from .operator import coupling, dense, lu_solve, rhs_plane_wave, rhs_point_sourc
 
 def dense_dc(geom, k, p=None, gamma=None):
     """V = dA/dc (the matrix that multiplies diag(c)), shape (N, N)."""
-    gamma = coupling(k, gamma)
+    gamma = coupling(k, gamma, p)
     N = geom["x"].shape[0]
     V = np.zeros((N, N), dtype=np.complex128)
     ii, jj = np.nonzero(~np.eye(N, dtype=bool))
@@ -61,12 +61,12 @@ def incident(pts, k, source):
     return P0 * np.exp(1j * k * R) / (4.0 * np.pi * R)
 
 
-def _rhs(geom, k, source):
+def _rhs(geom, k, source, p=None):
     kind, s, P0 = source
     if kind == "plane":
         d = np.asarray(s, dtype=np.float64)
-        return rhs_plane_wave(geom, k, d / np.linalg.norm(d), P0)
-    return rhs_point_source(geom, k, np.asarray(s, dtype=np.float64), P0)
+        return rhs_plane_wave(geom, k, d / np.linalg.norm(d), P0, p=p)
+    return rhs_point_source(geom, k, np.asarray(s, dtype=np.float64), P0, p=p)
 
 
 def objective(nodes, tris, Y, k, rho_c, pts, source, p=None):
@@ -74,7 +74,7 @@ def objective(nodes, tris, Y, k, rho_c, pts, source, p=None):
     geom = element_geometry(nodes, tris)
     beta = rho_c * np.asarray(Y, dtype=np.complex128)
     A = dense(geom, k, beta=beta, p=p)
-    ps = lu_solve(A, _rhs(geom, k, source))
+    ps = lu_solve(A, _rhs(geom, k, source, p))
     IG, IH = field_parts(geom, pts, k, p)
     c = -1j * k * beta
     M = IH - IG * c[None, :]

@@ -357,7 +357,7 @@ class FMM:
         self.geom = geom
         self.k = k
         self.p = p
-        self.gamma = coupling(k, gamma)
+        self.gamma = coupling(k, gamma, p)
         N = geom["x"].shape[0]
         self.c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
         self.tree = tree if tree is not None else build_tree(geom, levels, leaf_size, p["admissibility"])

@@ -34,8 +34,14 @@ from .geometry import element_geometry
 from .integrals import offdiag_integrals, self_integrals
 
 
-def coupling(k, gamma=None):
-    return 1j / k if gamma is None else gamma
+def coupling(k, gamma=None, p=None):
+    """gamma: given explicitly, else from the preset p (gamma_re +
+    i gamma_im_k / k), else the paper's i/k."""
+    if gamma is not None:
+        return gamma
+    if p is not None and "gamma_im_k" in p:
+        return p.get("gamma_re", 0.0) + 1j * p["gamma_im_k"] / k
+    return 1j / k
 
 
 def bc_factor(k, beta):
@@ -47,7 +53,7 @@ def bc_factor(k, beta):
 
 def rows(geom, row_idx, k, beta=None, p=None, gamma=None, cols=None, stats=None):
     """Rows ``row_idx`` of the dense operator A (optionally only ``cols``)."""
-    gamma = coupling(k, gamma)
+    gamma = coupling(k, gamma, p)
     N = geom["x"].shape[0]
     c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
     row_idx = np.asarray(row_idx, dtype=np.int64)
@@ -86,15 +92,15 @@ def dense(geom, k, beta=None, p=None, gamma=None, stats=None):
 
 def diagonal(geom, k, beta=None, p=None, gamma=None):
     """Diagonal entries A_ii (self terms plus the 1/2 jump term)."""
-    gamma = coupling(k, gamma)
+    gamma = coupling(k, gamma, p)
     N = geom["x"].shape[0]
     c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
     Gs, Es = self_integrals(geom, k, p)
     return 0.5 * (1.0 - gamma * c) + gamma * Es + Gs * c
 
 
-def rhs_plane_wave(geom, k, d, P0=1.0, gamma=None):
-    gamma = coupling(k, gamma)
+def rhs_plane_wave(geom, k, d, P0=1.0, gamma=None, p=None):
+    gamma = coupling(k, gamma, p)
     d = np.asarray(d, dtype=np.float64)
     x, n = geom["x"], geom["n"]
     pinc = P0 * np.exp(1j * k * (x @ d))
@@ -102,8 +108,8 @@ def rhs_plane_wave(geom, k, d, P0=1.0, gamma=None):
     return pinc - gamma * dn
 
 
-def rhs_point_source(geom, k, xs, P0=1.0, gamma=None):
-    gamma = coupling(k, gamma)
+def rhs_point_source(geom, k, xs, P0=1.0, gamma=None, p=None):
+    gamma = coupling(k, gamma, p)
     xs = np.asarray(xs, dtype=np.float64)
     x, n = geom["x"], geom["n"]
     Rv = x - xs

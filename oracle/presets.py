@@ -14,6 +14,11 @@ expansion length so that the FMM agrees with the dense operator to ~1e-7.
 ``mixed``: the quadrature and tree of ``tight``; it differs only in number
 format on the GPU, so the oracle treats it like ``tight``.
 
+Coupling: ``paper`` keeps the paper's gamma = i/k (Sec. 2.5);
+``tight``/``mixed``/``reference`` use gamma = -i/k, the other sign of the
+imaginary coupling, with which the spectrum of the discrete operator lies in
+the right half-plane (gamma = gamma_re + i gamma_im_k / k).
+
 ``reference``: oracle-only, used to measure each preset's own quadrature
 error.
 """
@@ -24,19 +29,23 @@ PRESETS = {
     "paper": dict(quad_eps=1e-3, m_max=6, split_on_cap=False, subdiv_ratio=1.3,
                   max_subdiv=15, self_n=4, edge_parts=4, edge_gauss=3,
                   admissibility=2.0 / math.sqrt(3.0), l_factor=1.8, l_min=8,
-                  l_mode=0, fmm_eps=1e-3, fmm_eps_mixed=1e-3, t_order=4),
+                  l_mode=0, fmm_eps=1e-3, fmm_eps_mixed=1e-3, t_order=4,
+                  gamma_re=0.0, gamma_im_k=1.0),
     "tight": dict(quad_eps=1e-8, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
                   max_subdiv=15, self_n=12, edge_parts=8, edge_gauss=6,
                   admissibility=3.0, l_factor=1.8, l_min=8,
-                  l_mode=1, fmm_eps=1e-7, fmm_eps_mixed=1e-4, t_order=6),
+                  l_mode=1, fmm_eps=1e-7, fmm_eps_mixed=1e-4, t_order=6,
+                  gamma_re=0.0, gamma_im_k=-1.0),
     "mixed": dict(quad_eps=1e-8, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
                   max_subdiv=15, self_n=12, edge_parts=8, edge_gauss=6,
                   admissibility=3.0, l_factor=1.8, l_min=8,
-                  l_mode=1, fmm_eps=1e-7, fmm_eps_mixed=1e-4, t_order=6),
+                  l_mode=1, fmm_eps=1e-7, fmm_eps_mixed=1e-4, t_order=6,
+                  gamma_re=0.0, gamma_im_k=-1.0),
     "reference": dict(quad_eps=1e-12, m_max=6, split_on_cap=True, subdiv_ratio=1.3,
                       max_subdiv=15, self_n=20, edge_parts=16, edge_gauss=10,
                       admissibility=3.0, l_factor=1.8, l_min=8,
-                      l_mode=1, fmm_eps=1e-10, fmm_eps_mixed=1e-4, t_order=8),
+                      l_mode=1, fmm_eps=1e-10, fmm_eps_mixed=1e-4, t_order=8,
+                      gamma_re=0.0, gamma_im_k=-1.0),
 }
 
 

@@ -58,7 +58,8 @@ class bem_options(ctypes.Structure):
         ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
         ("gmres_maxit", ctypes.c_int32), ("gmres_tol", ctypes.c_double),
         ("refine_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-        ("l_eps_mixed", ctypes.c_double),
+        ("l_eps_mixed", ctypes.c_double), ("precond", ctypes.c_int32),
+        ("gamma_re", ctypes.c_double), ("gamma_im_k", ctypes.c_double),
     ]
 
     def as_dict(self):

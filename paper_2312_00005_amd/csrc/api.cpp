@@ -60,6 +60,9 @@ void set_paper(bem_options* o) {
   o->refine_maxit = 20;
   o->inner_tol = 1e-3;
   o->l_eps_mixed = 1e-3;
+  o->precond = 0;
+  o->gamma_re = 0.0;
+  o->gamma_im_k = 1.0;
 }
 
 void upload_rules() {
@@ -113,6 +116,9 @@ void check_options(const bem_options* o) {
   }
   if (o->precision != BEM_PREC_FP64 && o->precision != BEM_PREC_MIXED)
     throw Error(BEM_E_ARG, "unknown precision");
+  if (o->precond < 0 || o->precond > 2) throw Error(BEM_E_ARG, "precond must be 0, 1 or 2");
+  if (!std::isfinite(o->gamma_re) || !std::isfinite(o->gamma_im_k) || o->gamma_im_k == 0.0)
+    throw Error(BEM_E_ARG, "the coupling needs a finite gamma with a non-zero imaginary part");
 }
 
 }  // namespace
@@ -153,6 +159,92 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
   BEM_HIP(hipGetLastError());
   if (part == 0 && m->fmm) fmm_apply(m, op, prec, x, y, s, vmode);
+}
+
+BlockArgs block_args(const bem_mesh* m) {
+  BlockArgs B{};
+  B.nblk = m->nblk;
+  B.elem_blk = m->d_elem_blk.p;
+  B.beg = m->d_blk_beg.p;
+  B.n = m->d_blk_n.p;
+  B.off = m->d_blk_off.p;
+  return B;
+}
+
+void precondition(bem_mesh* m, bem_op op, const double2* x, double2* y, hipStream_t s) {
+  if (m->precond_ready) {
+    launch_block_apply(m->N, block_args(m), m->d_blk_inv.p, op == BEM_OP_AH, x, y, s);
+  } else {
+    BEM_HIP(hipMemcpyAsync(y, x, m->N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+// Partition the elements (tree order) into the preconditioner's blocks: each
+// leaf cluster (the whole mesh without FMM) split evenly into pieces of at
+// most max_n (<= kMaxBlock) elements.
+void build_blocks(bem_mesh* m, int max_n) {
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  if (m->fmm) {
+    const Level& leaf = m->tree.lv.back();
+    for (int64_t c = 0; c < leaf.nc; ++c) ranges.emplace_back(leaf.ebeg[c], leaf.eend[c]);
+  } else {
+    ranges.emplace_back(0, m->N);
+  }
+  std::vector<int64_t> beg, off;
+  std::vector<int32_t> nn, eb(m->N, -1);
+  int64_t total = 0;
+  for (const auto& r : ranges) {
+    const int64_t len = r.second - r.first;
+    if (len <= 0) continue;
+    const int64_t pieces = (len + max_n - 1) / max_n;
+    for (int64_t q = 0; q < pieces; ++q) {
+      const int64_t pb = r.first + len * q / pieces, pe = r.first + len * (q + 1) / pieces;
+      for (int64_t e = pb; e < pe; ++e) eb[e] = (int32_t)beg.size();
+      beg.push_back(pb);
+      nn.push_back((int32_t)(pe - pb));
+      off.push_back(total);
+      total += (pe - pb) * (pe - pb);
+    }
+  }
+  for (int64_t e = 0; e < m->N; ++e)
+    if (eb[e] < 0) throw Error(BEM_E_MESH, "element outside every leaf cluster", m->tree.perm[e]);
+  hipStream_t s = nullptr;
+  m->nblk = (int64_t)beg.size();
+  m->blk_entries = total;
+  m->d_elem_blk.upload(eb, s);
+  m->d_blk_beg.upload(beg, s);
+  m->d_blk_n.upload(nn, s);
+  m->d_blk_off.upload(off, s);
+  m->d_blk_sing.alloc(m->nblk);
+  m->d_blk_a.alloc(total);
+  m->d_blk_inv.alloc(total);
+}
+
+// assemble and invert the blocks for the current problem
+void setup_preconditioner(bem_mesh* m, hipStream_t s) {
+  m->precond_ready = false;
+  if (!m->opt.precond || m->nblk == 0) return;
+  NearLaunch L{};
+  L.N = m->N;
+  L.geom = m->d_geom.p;
+  L.cfac = m->have_beta ? m->d_cfac.p : nullptr;
+  L.diag = m->d_diag.p;
+  L.off = m->d_off.p;
+  L.seg = m->d_seg.p;
+  L.items = m->d_items.p;
+  L.k = m->k;
+  L.gre = m->gre;
+  L.gim = m->gim;
+  const BlockArgs B = block_args(m);
+  launch_block_assemble(L, B, m->d_blk_a.p, s);
+  launch_block_invert(B, m->d_blk_a.p, m->d_blk_inv.p, m->d_blk_sing.p, s);
+  BEM_HIP(hipGetLastError());
+  std::vector<int32_t> sing(m->nblk);
+  BEM_HIP(hipMemcpyAsync(sing.data(), m->d_blk_sing.p, m->nblk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BEM_HIP(hipStreamSynchronize(s));
+  m->singular_blocks = 0;
+  for (int32_t v : sing) m->singular_blocks += v;
+  m->precond_ready = true;
 }
 
 void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
@@ -277,6 +369,10 @@ bem_status bem_options_default(bem_options* o, const char* preset) {
       o->edge_gauss = 6;
       o->gmres_tol = 1e-6;
       o->l_eps_mixed = 1e-4;
+      // the other sign of the imaginary coupling: the discrete spectrum lies
+      // in the right half-plane, where block Jacobi also pays off
+      o->gamma_im_k = -1.0;
+      o->precond = 1;
       if (p == "mixed") o->precision = BEM_PREC_MIXED;
       return BEM_OK;
     }
@@ -325,6 +421,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_cfac.alloc(n_tri);
     m->d_diag.alloc(n_tri);
     m->d_vdiag.alloc(n_tri);
+    if (o->precond) build_blocks(m.get(), o->precond == 1 ? kMaxBlock : 1);
     BEM_HIP(hipStreamSynchronize(s));
     *out = m.release();
     return BEM_OK;
@@ -339,8 +436,8 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     if (!(k > 0.0) || !std::isfinite(k)) return fail(BEM_E_ARG, "k must be positive and finite");
     hipStream_t s = as_stream(stream);
     m->k = k;
-    m->gre = 0.0;
-    m->gim = 1.0 / k;  // gamma = i / k (Sec. 2.5)
+    m->gre = m->opt.gamma_re;
+    m->gim = m->opt.gamma_im_k / k;  // gamma = i / k for (0, 1) (Sec. 2.5)
     m->have_beta = beta != nullptr;
     if (beta) {
       m->d_beta.alloc(m->N);
@@ -363,6 +460,7 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     L.gim = m->gim;
     launch_self_terms(L, m->d_diag.p, s);
     BEM_HIP(hipGetLastError());
+    setup_preconditioner(m, s);
     if (m->fmm) fmm_setup_problem(m, s);
     m->have_problem = true;
     return BEM_OK;
@@ -636,7 +734,9 @@ size_t bem_workspace_bytes(const bem_mesh* m) {
              m->d_items.bytes() + m->d_seg.bytes() + m->d_seg_t.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
              m->d_cfac.bytes() + m->d_diag.bytes() + m->d_vdiag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
-             m->d_partial.bytes() + m->d_h.bytes();
+             m->d_partial.bytes() + m->d_h.bytes() + m->d_z.bytes() + m->d_elem_blk.bytes() +
+             m->d_blk_n.bytes() + m->d_blk_sing.bytes() + m->d_blk_beg.bytes() + m->d_blk_off.bytes() +
+             m->d_blk_a.bytes() + m->d_blk_inv.bytes();
   return b + fmm_bytes(m);
 }
 

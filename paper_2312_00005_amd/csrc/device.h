@@ -44,6 +44,29 @@ struct SelfLaunch {
 };
 void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s);
 
+// Block-Jacobi preconditioner: the elements (tree order) are partitioned into
+// contiguous blocks of at most kMaxBlock elements; block b covers
+// [beg[b], beg[b] + n[b]) and its dense n x n matrix (column-major) starts at
+// off[b] in the block storage.
+constexpr int kMaxBlock = 64;
+struct BlockArgs {
+  int64_t nblk;
+  const int32_t* elem_blk;  // N: block of each element
+  const int64_t* beg;       // nblk
+  const int32_t* n;         // nblk
+  const int64_t* off;       // nblk
+};
+// a[off + jl * n + il] = A_(beg + il, beg + jl): diagonal plus the near-field
+// entries inside the block, in FP64
+void launch_block_assemble(const NearLaunch& L, const BlockArgs& B, double2* a, hipStream_t s);
+// inverse of every block by Gauss-Jordan elimination with partial pivoting;
+// a block with a zero pivot gets the inverse of its diagonal and sets
+// singular[b] = 1
+void launch_block_invert(const BlockArgs& B, const double2* a, double2* inv, int32_t* singular, hipStream_t s);
+// y = M x with M = blockdiag(inv) (conj_t: M^H); x and y must not alias
+void launch_block_apply(int64_t N, const BlockArgs& B, const double2* inv, bool conj_t, const double2* x,
+                        double2* y, hipStream_t s);
+
 struct FieldArgs {
   int64_t N;             // elements
   int64_t npts;          // field points

@@ -69,6 +69,7 @@ struct FmmState {
   int nq = 0;
   int t_order = 0;
   double k_setup = -1.0;
+  double gre_setup = 0.0, gim_setup = 0.0;
 };
 
 void fmm_destroy(FmmState* f) { delete f; }
@@ -545,8 +546,11 @@ void fmm_setup_problem(bem_mesh* m, hipStream_t s) {
   }
   FmmState* F = m->fmm_state;
   // nothing below depends on the admittance: a new beta at the same k reuses it
-  if (F->k_setup == m->k && F->t_order == m->opt.t_order) return;
+  if (F->k_setup == m->k && F->t_order == m->opt.t_order && F->gre_setup == m->gre && F->gim_setup == m->gim)
+    return;
   F->k_setup = m->k;
+  F->gre_setup = m->gre;
+  F->gim_setup = m->gim;
   upload_rule(F, m->opt.t_order, s);
   setup_set(m, F, 0, s);
   setup_set(m, F, 1, s);

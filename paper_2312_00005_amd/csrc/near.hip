@@ -444,6 +444,75 @@ __global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict_
 }
 
 
+
+// ------------------------------------------------ preconditioner blocks ---
+// One wavefront per row t: the row's near items whose source lies in t's block
+// are integrated (FP64) and summed per column in a fixed order (lane order of
+// the item chunks), so the assembly is deterministic; lane jl owns column jl.
+template <bool HAS_C>
+__global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs B, double2* __restrict__ a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= L.N) return;
+  const int64_t N = L.N;
+  const double* g = L.geom;
+  const int blk = B.elem_blk[t];
+  const int64_t b0 = B.beg[blk];
+  const int n = B.n[blk];
+  const int64_t off = B.off[blk];
+  const int il = (int)(t - b0);
+  double xi[3], ni[3];
+  for (int c = 0; c < 3; ++c) {
+    xi[c] = g[(CX + c) * N + t];
+    ni[c] = g[(NX + c) * N + t];
+  }
+  double accr = 0.0, acci = 0.0;
+  const int64_t* sg = L.seg + t * (kMaxRuleOrder + 1);
+  for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
+    const int64_t e = sg[mc + 1];
+    for (int64_t base = sg[mc]; base < e; base += 64) {
+      const int64_t it = base + lane;
+      int64_t j = -1;
+      bool in = false;
+      if (it < e) {
+        j = (int64_t)(L.items[it] & ((uint64_t(1) << 26) - 1));
+        in = j >= b0 && j < b0 + n;
+      }
+      double vr = 0.0, vi = 0.0;
+      if (in) {
+        double s1r, s1i, s2r, s2i;
+        int64_t jj;
+        integrate_item<double, true, HAS_C>(g, N, L.items[it], mc + 1, xi, ni, L.k, L.gre, L.gim, s1r, s1i, s2r,
+                                            s2i, jj);
+        vr = s1r;
+        vi = s1i;
+        if (HAS_C) {
+          const double2 c = L.cfac[j];
+          vr += c.x * s2r - c.y * s2i;
+          vi += c.x * s2i + c.y * s2r;
+        }
+      }
+      uint64_t mask = __ballot(in);
+      const int jl = in ? (int)(j - b0) : -1;
+      while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int cj = __shfl(jl, src);
+        const double wr = __shfl(vr, src), wi = __shfl(vi, src);
+        if (lane == cj) {
+          accr += wr;
+          acci += wi;
+        }
+      }
+    }
+  }
+  if (lane == il) {
+    accr += L.diag[t].x;
+    acci += L.diag[t].y;
+  }
+  if (lane < n) a[off + (int64_t)lane * n + il] = make_double2(accr, acci);
+}
+
 // ------------------------------------------------------------ field points ---
 // Exterior field (Eq. (BIE_I) with lambda = 1): K_fj = I^H(x_f, G_j) - c_j I^G(x_f, G_j)
 // with the quasi-singular / regular rules of Sec. 3.1.3-3.1.4 chosen on the fly
@@ -784,6 +853,14 @@ void launch_field(const FieldArgs& A, const double* pts, const double2* p, const
                   int64_t* err, hipStream_t s) {
   if (A.npts <= 0) return;
   hipLaunchKernelGGL(k_field, dim3(blocks_for(A.npts, 4)), dim3(256), 0, s, A, pts, p, pinc, out, err);
+}
+
+void launch_block_assemble(const NearLaunch& L, const BlockArgs& B, double2* a, hipStream_t s) {
+  if (L.N <= 0) return;
+  if (L.cfac)
+    hipLaunchKernelGGL(k_block_assemble<true>, dim3(blocks_for(L.N, 4)), dim3(256), 0, s, L, B, a);
+  else
+    hipLaunchKernelGGL(k_block_assemble<false>, dim3(blocks_for(L.N, 4)), dim3(256), 0, s, L, B, a);
 }
 
 void launch_energy(int64_t n, const double2* p, double* energy, hipStream_t s) {

@@ -1,6 +1,8 @@
 // Krylov driver: restarted GMRES with classical Gram-Schmidt applied twice,
 // FP64 basis vectors and FP64 residuals (Sec. 3.2 uses CGS with a 1e-9
-// tolerance and a 250-iteration cap; GMRES takes its place here).  With the
+// tolerance and a 250-iteration cap; GMRES takes its place here), right
+// preconditioned by the block-Jacobi inverse M (A M u = b, x = M u), so that
+// its residual is the residual of the unpreconditioned system.  With the
 // mixed precision option the inner solves run on the complex-FP32 operator
 // inside an FP64 iterative-refinement loop: r = b - A x with the FP64
 // operator, inner GMRES on A d = r, x += d.
@@ -66,7 +68,12 @@ int gmres(bem_mesh* m, bem_op op, bem_precision prec, const double2* b, double2*
     int jend = -1;
     bool done = false;
     for (int j = 0; j < R; ++j) {
-      apply_tree(m, op, prec, V + (int64_t)j * N, w, s);
+      if (m->precond_ready) {
+        precondition(m, op, V + (int64_t)j * N, m->d_z.p, s);
+        apply_tree(m, op, prec, m->d_z.p, w, s);
+      } else {
+        apply_tree(m, op, prec, V + (int64_t)j * N, w, s);
+      }
       ++iters;
       // classical Gram-Schmidt, twice
       launch_multidot(N, j + 1, V, N, w, m->d_partial.p, W.nblk, s);
@@ -120,7 +127,15 @@ int gmres(bem_mesh* m, bem_op op, bem_precision prec, const double2* b, double2*
     std::vector<double2> yh(nj);
     for (int i = 0; i < nj; ++i) yh[i] = make_double2(y[i].real(), y[i].imag());
     BEM_HIP(hipMemcpyAsync(dh, yh.data(), nj * sizeof(double2), hipMemcpyHostToDevice, s));
-    launch_multiaxpy(N, nj, V, N, dh, 1.0, x, s);
+    if (m->precond_ready) {
+      // x += M (V y)
+      BEM_HIP(hipMemsetAsync(m->d_z.p, 0, N * sizeof(double2), s));
+      launch_multiaxpy(N, nj, V, N, dh, 1.0, m->d_z.p, s);
+      precondition(m, op, m->d_z.p, w, s);
+      launch_axpby(N, make_double2(1, 0), x, make_double2(1, 0), w, x, s);
+    } else {
+      launch_multiaxpy(N, nj, V, N, dh, 1.0, x, s);
+    }
     BEM_HIP(hipStreamSynchronize(s));
     if (done && iters >= maxit) {
       // recompute the true residual to decide
@@ -141,6 +156,7 @@ SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s,
   m->d_w.alloc(N);
   m->d_r.alloc(N);
   m->d_tmp.alloc(N);
+  m->d_z.alloc(N);
   m->d_partial.alloc((size_t)(W.restart + 1) * W.nblk + 8);
   m->d_h.alloc(2 * (W.restart + 1) + 8);
   SolveResult out;

@@ -40,9 +40,18 @@ struct bem_mesh {
   bem::DevBuf<double2> d_diag;     // tree order, A_ii
   bem::DevBuf<double2> d_vdiag;    // tree order, diagonal of dA/dc
 
+  // block-Jacobi preconditioner (tree order)
+  int64_t nblk = 0;
+  int64_t blk_entries = 0;
+  bool precond_ready = false;
+  int64_t singular_blocks = 0;
+  bem::DevBuf<int32_t> d_elem_blk, d_blk_n, d_blk_sing;
+  bem::DevBuf<int64_t> d_blk_beg, d_blk_off;
+  bem::DevBuf<double2> d_blk_a, d_blk_inv;
+
   // work vectors (tree order)
   bem::DevBuf<double2> d_x, d_y, d_r, d_b, d_sol, d_tmp;
-  bem::DevBuf<double2> d_V, d_w, d_partial, d_h;
+  bem::DevBuf<double2> d_V, d_w, d_z, d_partial, d_h;
 
   bem::FmmState* fmm_state = nullptr;
   int fmm_L[16] = {0};     // FP64 operator
@@ -59,6 +68,10 @@ void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, do
 // vmode: dA/dc (the matrix that multiplies diag(c)) instead of A
 void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
                      hipStream_t s, bool vmode = false);
+
+// y = M x with the block-Jacobi preconditioner (M^H for op AH); a copy when
+// there is none.  x and y must not alias.
+void precondition(bem_mesh* m, bem_op op, const double2* x, double2* y, hipStream_t s);
 
 // FMM far field: y += far(x), tree order.  No-op if the mesh has no FMM.
 void fmm_setup_problem(bem_mesh* m, hipStream_t s);

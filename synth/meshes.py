@@ -125,7 +125,8 @@ def _stereo_zoom(p, s):
     mesh becomes graded with a fine-to-coarse edge ratio of s**2 while
     every triangle keeps its angles."""
     x, y, z = p[:, 0], p[:, 1], p[:, 2]
-    den = 1.0 + x
+    pole = 1.0 + x < 1e-12
+    den = np.where(pole, 1.0, 1.0 + x)
     wy = y / den / s
     wz = z / den / s
     r2 = wy * wy + wz * wz
@@ -133,6 +134,8 @@ def _stereo_zoom(p, s):
     out[:, 0] = (1.0 - r2) / (1.0 + r2)
     out[:, 1] = 2.0 * wy / (1.0 + r2)
     out[:, 2] = 2.0 * wz / (1.0 + r2)
+    # the projection pole is a fixed point of the map
+    out[pole] = (-1.0, 0.0, 0.0)
     return out
 
 
@@ -148,8 +151,6 @@ def graded_ellipsoid_bump(freq=55, semi_axes=(0.075, 0.09, 0.11),
     rho**2 = (y / bump_half[0])**2 + (z / bump_half[1])**2 < 1 and x > 0.
     Returns ``(nodes, tris, apex, apex_normal)``."""
     nodes, tris = geodesic_sphere(freq, 1.0)
-    # a point exactly at -x would be the projection pole; the geodesic mesh
-    # has no vertex there (icosahedron vertices are off-axis)
     nodes = _stereo_zoom(nodes, grading ** 0.5)
     a = np.asarray(semi_axes, dtype=np.float64)
     e = nodes * a

@@ -46,8 +46,10 @@ def test_presets(bem):
     assert p.max_subdiv == 15 and p.self_n == 4 and p.edge_parts == 4 and p.edge_gauss == 3
     assert p.l_factor == 1.8 and p.l_min == 8 and abs(p.admissibility - 2 / 3 ** 0.5) < 1e-15
     assert p.gmres_maxit == 250
+    assert p.gamma_re == 0.0 and p.gamma_im_k == 1.0 and p.precond == 0
     t = bem.bem_options_default("tight")
     assert t.quad_split_on_cap == 1 and t.admissibility == 3.0
+    assert t.gamma_im_k == -1.0 and t.precond == 1
     m = bem.bem_options_default("mixed")
     assert m.precision == bem.BEM_PREC_MIXED
     with pytest.raises(bem.BemError) as e:

@@ -66,7 +66,7 @@ def gpu_mesh(bem, nodes, tris, pre, k, beta):
     return m
 
 
-CASES = [("ico3", "paper", 1.0, False), ("ico3", "tight", 4.0, False),
+CASES = [("ico3", "paper", 1.0, False), ("ico3", "tight", 4.0, False), ("ico3", "paper", 4.0, False),
          ("ragged", "paper", 6.0, True), ("oct", "paper", 2.0, False), ("patch", "tight", 3.0, True)]
 
 
@@ -98,19 +98,20 @@ def test_apply_is_bitwise_deterministic(bem):
     assert np.array_equal(a, b)
 
 
-def test_rhs_matches_oracle(bem):
-    announce("rhs")
+@pytest.mark.parametrize("pre", ["paper", "tight"])
+def test_rhs_matches_oracle(bem, pre):
+    announce(f"rhs {pre}")
     nodes, tris = _mesh("ico3")
     g = element_geometry(nodes, tris)
     k = 2.5
-    m = gpu_mesh(bem, nodes, tris, "paper", k, None)
+    m = gpu_mesh(bem, nodes, tris, pre, k, None)
     d = np.array([0.3, -0.4, 0.866])
     d /= np.linalg.norm(d)
     b = to_host(m.rhs_plane_wave(tuple(d), 1.5 - 0.5j))
-    assert rel_max(b, op.rhs_plane_wave(g, k, d, P0=1.5 - 0.5j)) < 1e-13
+    assert rel_max(b, op.rhs_plane_wave(g, k, d, P0=1.5 - 0.5j, p=preset(pre))) < 1e-13
     xs = (0.2, 1.7, -0.4)
     b = to_host(m.rhs_point_source(xs, 2.0))
-    assert rel_max(b, op.rhs_point_source(g, k, xs, P0=2.0)) < 1e-13
+    assert rel_max(b, op.rhs_point_source(g, k, xs, P0=2.0, p=preset(pre))) < 1e-13
 
 
 def test_solve_matches_lu_and_analytic(bem):
@@ -154,3 +155,36 @@ def test_noconv_status(bem):
     assert e.value.status == bem.BEM_E_NOCONV
     p, _, info = m.solve(rhs, allow_noconv=True)
     assert info["warnings"] & bem.BEM_WARN_NOT_CONVERGED
+
+
+def test_block_preconditioner_is_exact_inverse_on_one_block(bem):
+    """With every element in one preconditioner block (20 triangles, no FMM)
+    the block inverse is A^{-1}: right-preconditioned GMRES converges in one
+    iteration, to the LU solution."""
+    announce("block preconditioner icosahedron N=20")
+    nodes, tris = synth.icosphere(0)
+    g = element_geometry(nodes, tris)
+    k = 1.7
+    beta = (1.0 + 0.5 * synth.uniform01(len(tris), seed=3)) + 0.2j
+    A = op.dense(g, k, beta=beta, p=preset("paper"))
+    b = op.rhs_plane_wave(g, k, (0.0, 0.0, 1.0))
+    m = bem.Mesh(nodes, tris, "paper", use_fmm=0, gmres_tol=1e-12, precond=1)
+    m.set_problem(k, to_dev(beta))
+    p, _, info = m.solve(to_dev(b))
+    assert info["iterations"] == 1
+    assert rel_l2(to_host(p), op.lu_solve(A, b)) < 1e-12
+    x, info_h = m.solve_adjoint(to_dev(b))
+    assert info_h["iterations"] == 1
+    assert rel_l2(to_host(x), op.lu_solve(A.conj().T, b)) < 1e-12
+
+
+@pytest.mark.parametrize("pre,precond", [("paper", 0), ("paper", 1), ("paper", 2), ("tight", 1)])
+def test_solve_with_and_without_preconditioner(bem, pre, precond):
+    announce(f"solve ico3 {pre} precond={precond}")
+    nodes, tris, g, beta, A = oracle_case("ico3", pre, 4.0, False)
+    b = op.rhs_plane_wave(g, 4.0, (0.0, 0.0, 1.0), p=preset(pre))
+    m = bem.Mesh(nodes, tris, pre, use_fmm=0, gmres_tol=1e-11, precond=precond)
+    m.set_problem(4.0, None)
+    p, _, info = m.solve(to_dev(b))
+    announce(f"  iterations {info['iterations']}")
+    assert rel_l2(to_host(p), op.lu_solve(A, b)) < 1e-9

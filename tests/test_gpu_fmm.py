@@ -165,7 +165,7 @@ def test_full_size_solve(bem, c2, prec):
     rhs = m.rhs_plane_wave((0.0, 0.0, 1.0))
     p, _, info = m.solve(rhs)
     p = to_host(p)
-    b = op.rhs_plane_wave(g, k, [0, 0, 1])
+    b = op.rhs_plane_wave(g, k, [0, 0, 1], p=preset("tight"))
     # residual of the GPU solution in the oracle's dense operator, sampled rows
     res = Ar @ p - b[rows]
     rr = np.linalg.norm(res) / np.linalg.norm(b[rows])

@@ -110,3 +110,42 @@ def test_reciprocity_of_point_sources():
     p_ab = field.point_source(xb[None], k, xa) + Mb @ pa
     p_ba = field.point_source(xa[None], k, xb) + Ma @ pb
     assert abs(p_ab[0] - p_ba[0]) < 5e-3 * abs(p_ab[0])
+
+
+@pytest.mark.parametrize("n,beta", [(0, 0.0), (1, 0.0), (0, 0.8 + 0.1j)])
+def test_modal_eigenvalues_converge_other_coupling_sign(n, beta):
+    # gamma = -i/k: the same closed form with the coupling's sign flipped
+    # (errors are already near the constant-element stall on the coarse
+    # mesh, so the check is a small and decreasing error)
+    k = 2.0
+    e2 = _modal_err(2, k, n, beta, gamma=-1j / k)
+    e3 = _modal_err(3, k, n, beta, gamma=-1j / k)
+    assert e3 < 0.02 and e3 < 0.8 * e2
+
+
+def test_coupling_from_preset():
+    k = 3.0
+    assert op.coupling(k, None, preset("paper")) == 1j / k
+    assert op.coupling(k, None, preset("tight")) == -1j / k
+    assert op.coupling(k, 0.5j, preset("tight")) == 0.5j
+    assert op.coupling(k) == 1j / k
+
+
+def test_coupling_sign_and_spectrum():
+    """On the sphere both signs give the same |lambda_n|; with gamma = -i/k
+    every modal eigenvalue has a positive real part, while gamma = +i/k
+    sends the propagating degrees (n < ka) around the origin.  The discrete
+    operator of a non-spherical body shows the same split."""
+    k = 27.7
+    lp = np.array([sphere.bm_eigenvalue(n, k, gamma=1j / k) for n in range(70)])
+    lm = np.array([sphere.bm_eigenvalue(n, k, gamma=-1j / k) for n in range(70)])
+    assert np.allclose(np.abs(lp), np.abs(lm), rtol=1e-12)
+    assert lm.real.min() > 0.4
+    assert lp.real.min() < -0.5
+    nodes, tris, _, _ = synth.graded_ellipsoid_bump(freq=6, grading=1.0, bump_height=0.0)
+    g = element_geometry(nodes, tris)
+    kk = 2 * np.pi * 4000.0 / 343.0
+    ev_m = np.linalg.eigvals(op.dense(g, kk, p=preset("paper"), gamma=-1j / kk))
+    ev_p = np.linalg.eigvals(op.dense(g, kk, p=preset("paper"), gamma=1j / kk))
+    assert ev_m.real.min() > 0.3
+    assert ev_p.real.min() < 0.0
