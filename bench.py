@@ -50,7 +50,12 @@ def parse():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-near-only", action="store_true",
-                    help="run only near-field applications (for counter collection)")
+                    help="run only complex-FP32 near-field applications, then a 512 MiB copy "
+                         "that calibrates the HBM byte counters (for rocprofv3 --pmc runs)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) "
+                         "of --profile-near-only runs into the traffic record read by the bench")
+    ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json"))
     return ap.parse_args()
 
 
@@ -58,8 +63,94 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+NEAR_KERNEL = "k_near<float, false, false>"
+CAL_BYTES = 512 * 2 ** 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json")
+
+
+def kernel_source_hash():
+    """Hash of the sources that define the near-field kernel; a traffic
+    record measured on other sources is not used."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("near.hip", "device.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_2312_00005_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def summarize_counters(fetch_csv, write_csv, out):
+    """Per-dispatch averages of FETCH_SIZE / WRITE_SIZE (KiB) for the
+    near-field kernel and for the calibration copy, and the HBM bytes per
+    near-field launch scaled by the copy's measured/known ratio."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+
+    def pick(d, pred):
+        keys = [k for k in d if pred(k)]
+        if not keys:
+            raise SystemExit(f"no dispatch matched in {sorted(d)[:8]}")
+        return max(keys, key=lambda k: max(d[k]))
+
+    near_f = pick(fetch, lambda k: NEAR_KERNEL in k)
+    near_w = pick(write, lambda k: NEAR_KERNEL in k)
+    cal_f = pick(fetch, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
+    cal_w = pick(write, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
+    avg = lambda v: sum(v) / len(v)
+    f_scale = max(fetch[cal_f]) / CAL_BYTES
+    w_scale = max(write[cal_w]) / CAL_BYTES
+    rec = {
+        "kernel": NEAR_KERNEL,
+        "workload": "c2: 20480-triangle sphere, 3-level FMM, tight quadrature, complex-FP32 near field",
+        "fetch_bytes_per_launch_raw": avg(fetch[near_f]),
+        "write_bytes_per_launch_raw": avg(write[near_w]),
+        "launches": len(fetch[near_f]),
+        "calibration": {"kernel": cal_f, "known_bytes": CAL_BYTES,
+                        "fetch_bytes": max(fetch[cal_f]), "write_bytes": max(write[cal_w]),
+                        "fetch_scale": f_scale, "write_scale": w_scale},
+        "hbm_bytes_per_launch": avg(fetch[near_f]) / f_scale + avg(write[near_w]) / w_scale,
+        "source_sha256": kernel_source_hash(),
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- "
+            "python bench.py --profile-near-only --steps 3 --warmup 1",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- "
+            "python bench.py --profile-near-only --steps 3 --warmup 1",
+            "python bench.py --summarize-counters gpurun_out/pmc_fetch/f_counter_collection.csv "
+            "gpurun_out/pmc_write/w_counter_collection.csv",
+        ],
+    }
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def measured_traffic():
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.traffic_out)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(frequency sharding across GPUs is a design note only).", file=sys.stderr)
@@ -98,6 +189,15 @@ def main():
     stats = mesh.stats()
     x = torch.from_numpy(synth.complex_normal(N, seed=4)).to("cuda")
     y = torch.empty_like(x)
+    if args.profile_near_only:
+        for _ in range(args.warmup + args.steps):
+            mesh.apply_part(x, 1, prec="mixed", out=y)
+        src = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"profiled {args.warmup + args.steps} near-field applications and one {CAL_BYTES} B copy")
+        return
 
     def timed(fn, steps):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -175,10 +275,11 @@ def main():
         "setup_s": {"mesh": t_mesh, "per_frequency": t_setup},
         "solve_s_per_frequency": {p: solves[p]["seconds"] for p in solves},
         "solve": solves,
-        "roofline": {"bound": "alu", "kernel": "k_near<float,false>", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": NEAR_KERNEL, "achieved": achieved,
                      "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp32"],
-                     "traffic": None,
-                     "fp64_kernel": {"kernel": "k_near<double,false>",
+                     "traffic": measured_traffic(),
+                     "flops_per_launch": near_flops, "flops_per_point": FLOPS_PER_POINT,
+                     "fp64_kernel": {"kernel": "k_near<double, false, false>",
                                      "achieved": near_flops / res["fp64"]["t_near"] / 1e12,
                                      "peak": PEAK_TFLOPS["fp64"],
                                      "frac": near_flops / res["fp64"]["t_near"] / 1e12 / PEAK_TFLOPS["fp64"]}},
