@@ -125,6 +125,13 @@ typedef struct bem_options {
                                of the discrete operator in the right
                                half-plane and Krylov iterations converge far
                                faster.  gamma_im_k = 0 is BEM_E_ARG. */
+  int32_t far_direct;       /* 1: keep the cluster tree and near plan but
+                               evaluate the far field by direct quadrature of
+                               every admissible pair (same rules as the near
+                               plan, chosen per pair on the fly; nothing
+                               stored) instead of the FMM -- for frequencies
+                               where the expansion is unstable (k X_min small,
+                               Sec. 3.3.1) or too long.  Needs use_fmm = 1. */
 } bem_options;
 
 typedef struct bem_solve_info {

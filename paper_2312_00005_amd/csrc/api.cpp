@@ -117,6 +117,8 @@ void check_options(const bem_options* o) {
   if (o->precision != BEM_PREC_FP64 && o->precision != BEM_PREC_MIXED)
     throw Error(BEM_E_ARG, "unknown precision");
   if (o->precond < 0 || o->precond > 2) throw Error(BEM_E_ARG, "precond must be 0, 1 or 2");
+  if (o->far_direct != 0 && o->far_direct != 1) throw Error(BEM_E_ARG, "far_direct must be 0 or 1");
+  if (o->far_direct && !o->use_fmm) throw Error(BEM_E_ARG, "far_direct needs the cluster tree (use_fmm = 1)");
   if (!std::isfinite(o->gamma_re) || !std::isfinite(o->gamma_im_k) || o->gamma_im_k == 0.0)
     throw Error(BEM_E_ARG, "the coupling needs a finite gamma with a non-zero imaginary part");
 }
@@ -133,7 +135,7 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
                      hipStream_t s, bool vmode) {
   if (part == 2) {
     BEM_HIP(hipMemsetAsync(y, 0, m->N * sizeof(double2), s));
-    if (m->fmm) fmm_apply(m, op, prec, x, y, s, vmode);
+    far_apply(m, op, prec, x, y, s, vmode);
     return;
   }
   NearLaunch L{};
@@ -158,7 +160,86 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   }
   launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
   BEM_HIP(hipGetLastError());
-  if (part == 0 && m->fmm) fmm_apply(m, op, prec, x, y, s, vmode);
+  if (part == 0) far_apply(m, op, prec, x, y, s, vmode);
+}
+
+void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s, bool vmode) {
+  if (!m->fmm) return;
+  if (!m->far_direct) {
+    fmm_apply(m, op, prec, x, y, s, vmode);
+    return;
+  }
+  FarLaunch F{};
+  F.N = m->N;
+  F.geom = m->d_geom.p;
+  F.geom32 = m->d_geom32.p;
+  F.cfac = m->have_beta ? m->d_cfac.p : nullptr;
+  F.elem_leaf = m->d_elem_leaf.p;
+  F.far_off = m->d_far_off.p;
+  F.far_beg = m->d_far_beg.p;
+  F.far_end = m->d_far_end.p;
+  for (int q = 0; q < kMaxRuleOrder; ++q) F.rt2_min[q] = m->far_rt2_min[q];
+  F.ratio2 = m->opt.subdiv_ratio * m->opt.subdiv_ratio;
+  F.m_max = m->opt.quad_m_max;
+  F.split_on_cap = m->opt.quad_split_on_cap;
+  F.max_subdiv = m->opt.max_subdiv;
+  F.k = m->k;
+  F.gre = m->gre;
+  F.gim = m->gim;
+  launch_far_direct(F, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
+  BEM_HIP(hipGetLastError());
+}
+
+// Per leaf cluster, the element intervals (tree order) outside its near
+// clusters, and the r~^2 thresholds of the rule orders for the direct far
+// field: order m suffices iff all three a-priori estimates of Sec. 3.1.4 are
+// below eps, i.e. iff q = 1/(2 r~) < q_m with q_m the smallest of the three
+// roots.
+void build_far_direct(bem_mesh* m) {
+  const Level& leaf = m->tree.lv.back();
+  std::vector<int32_t> el(m->N, -1);
+  std::vector<int64_t> off(leaf.nc + 1, 0), fb, fe;
+  for (int64_t c = 0; c < leaf.nc; ++c) {
+    for (int64_t e = leaf.ebeg[c]; e < leaf.eend[c]; ++e) el[e] = (int32_t)c;
+    std::vector<std::pair<int64_t, int64_t>> near;
+    near.emplace_back(leaf.ebeg[c], leaf.eend[c]);
+    for (int64_t q = leaf.nr_off[c]; q < leaf.nr_off[c + 1]; ++q)
+      near.emplace_back(leaf.ebeg[leaf.nr[q]], leaf.eend[leaf.nr[q]]);
+    std::sort(near.begin(), near.end());
+    int64_t pos = 0;
+    for (const auto& r : near) {
+      if (r.first > pos) {
+        fb.push_back(pos);
+        fe.push_back(r.first);
+      }
+      pos = std::max(pos, r.second);
+    }
+    if (pos < m->N) {
+      fb.push_back(pos);
+      fe.push_back(m->N);
+    }
+    off[c + 1] = (int64_t)fb.size();
+  }
+  for (int64_t e = 0; e < m->N; ++e)
+    if (el[e] < 0) throw Error(BEM_E_MESH, "element outside every leaf cluster", m->tree.perm[e]);
+  const double eps = m->opt.quad_eps;
+  for (int mm = 1; mm <= kMaxRuleOrder; ++mm) {
+    const double q1 = std::pow(eps / 32.0, 1.0 / (2 * mm + 1));
+    const double q2 = std::pow(eps / (64.0 * (2 * mm + 1)), 1.0 / (2 * mm + 2));
+    const double q3 = std::pow(eps / (128.0 * (mm + 1) * (2 * mm + 1)), 1.0 / (2 * mm + 3));
+    const double qm = std::min(q1, std::min(q2, q3));
+    const double rt = 1.0 / (2.0 * qm);
+    m->far_rt2_min[mm - 1] = rt * rt;
+  }
+  hipStream_t s = nullptr;
+  m->d_elem_leaf.upload(el, s);
+  m->d_far_off.upload(off, s);
+  if (fb.empty()) {
+    fb.push_back(0);
+    fe.push_back(0);
+  }
+  m->d_far_beg.upload(fb, s);
+  m->d_far_end.upload(fe, s);
 }
 
 BlockArgs block_args(const bem_mesh* m) {
@@ -391,6 +472,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->opt = *o;
     m->N = n_tri;
     m->fmm = o->use_fmm != 0;
+    m->far_direct = o->far_direct != 0;
     build_host(n_nodes, xyz, n_tri, tri, *o, m->tree, m->g, m->plan, m->bad_element);
     upload_rules();
     hipStream_t s = nullptr;
@@ -422,6 +504,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_diag.alloc(n_tri);
     m->d_vdiag.alloc(n_tri);
     if (o->precond) build_blocks(m.get(), o->precond == 1 ? kMaxBlock : 1);
+    if (m->far_direct) build_far_direct(m.get());
     BEM_HIP(hipStreamSynchronize(s));
     *out = m.release();
     return BEM_OK;
@@ -461,7 +544,7 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     launch_self_terms(L, m->d_diag.p, s);
     BEM_HIP(hipGetLastError());
     setup_preconditioner(m, s);
-    if (m->fmm) fmm_setup_problem(m, s);
+    if (m->fmm && !m->far_direct) fmm_setup_problem(m, s);
     m->have_problem = true;
     return BEM_OK;
   });

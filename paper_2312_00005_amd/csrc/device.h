@@ -33,6 +33,29 @@ struct NearLaunch {
 void launch_near(const NearLaunch& L, bool fp64, bool adjoint, bool vmode, const double2* x, double2* y,
                  hipStream_t s);
 
+// Far field by direct on-the-fly quadrature: every pair whose leaf clusters
+// are admissible (complement of the near list), with the same rule selection
+// as the near plan evaluated per pair (order from r~, subdivision while
+// r~ < ratio).  far_off/far_beg/far_end: per leaf cluster the element
+// intervals (tree order) outside its near clusters.
+struct FarLaunch {
+  int64_t N;
+  const double* geom;
+  const float* geom32;
+  const double2* cfac;
+  const int32_t* elem_leaf;
+  const int64_t* far_off;
+  const int64_t* far_beg;
+  const int64_t* far_end;
+  double rt2_min[kMaxRuleOrder];  // order m suffices iff r~^2 > rt2_min[m-1]
+  double ratio2;
+  int m_max, split_on_cap, max_subdiv;
+  double k, gre, gim;
+};
+// y += far(x) (adjoint: y += far^H x; vmode: the dA/dc part), tree order
+void launch_far_direct(const FarLaunch& F, bool fp64, bool adjoint, bool vmode, const double2* x, double2* y,
+                       hipStream_t s);
+
 struct SelfLaunch {
   int64_t N;
   const double* geom;

@@ -445,6 +445,164 @@ __global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict_
 
 
 
+
+// ----------------------------------------------- direct far field (no FMM) ---
+template <typename T>
+__device__ inline const T* far_geom(const FarLaunch& F);
+template <>
+__device__ inline const double* far_geom<double>(const FarLaunch& F) { return F.geom; }
+template <>
+__device__ inline const float* far_geom<float>(const FarLaunch& F) { return F.geom32; }
+
+// order for r~^2 (0: split)
+__device__ inline int far_order(const FarLaunch& F, double rt2) {
+  if (rt2 < F.ratio2) return 0;
+  for (int m = 1; m <= F.m_max; ++m)
+    if (rt2 > F.rt2_min[m - 1]) return m;
+  return F.split_on_cap ? 0 : F.m_max;
+}
+
+// One (collocation i, element j) pair that needs subdivision: depth-first walk
+// over (depth, path) without a stack, per-sub-triangle rule as in the plan.
+template <typename T, bool WANT_S1, bool WANT_S2>
+__device__ void far_pair_split(const FarLaunch& F, const T* g, int64_t j, const T xi[3], const T ni[3], T& s1r,
+                               T& s1i, T& s2r, T& s2i) {
+  const int64_t N = F.N;
+  const T k = (T)F.k, gre = (T)F.gre, gim = (T)F.gim;
+  const double area0 = (double)g[AREA * N + j];
+  int depth = 0;
+  uint64_t path = 0;
+  s1r = s1i = s2r = s2i = T(0);
+  for (;;) {
+    T v0[3], v1[3], v2[3];
+    item_triangle<T>(g, N, j, depth, path, v0, v1, v2);
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double dc = (double)xi[c] - ((double)v0[c] + (double)v1[c] + (double)v2[c]) / 3.0;
+      d2 += dc * dc;
+    }
+    const double area = area0 * ldexp(1.0, -2 * depth);
+    int m = far_order(F, d2 / area);
+    if (m == 0 && depth < F.max_subdiv && depth < 15) {
+      ++depth;
+      continue;
+    }
+    if (m == 0) m = F.m_max;  // depth limit: the plan refuses such meshes, never reached
+    const uint64_t item = (uint64_t)j | ((uint64_t)depth << 29) | (path << 33);
+    T a1r, a1i, a2r, a2i;
+    int64_t jj;
+    integrate_item<T, WANT_S1, WANT_S2>(g, N, item, m, xi, ni, k, gre, gim, a1r, a1i, a2r, a2i, jj);
+    s1r += a1r;
+    s1i += a1i;
+    s2r += a2r;
+    s2i += a2i;
+    while (depth > 0) {
+      const int sh = 2 * (depth - 1);
+      if (((path >> sh) & 3u) < 3u) {
+        path += (uint64_t)1 << sh;
+        break;
+      }
+      path &= ~((uint64_t)3 << sh);
+      --depth;
+    }
+    if (depth == 0) break;
+  }
+}
+
+// One wavefront per row r: forward r = collocation point i, lanes over far
+// source elements j; adjoint r = source element j, lanes over far collocation
+// points i (the far relation of leaf clusters is symmetric).
+template <typename T, bool HAS_C, bool VMODE, bool ADJ>
+__global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* __restrict__ x,
+                                                    double2* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= F.N) return;
+  const int64_t N = F.N;
+  const T* g = far_geom<T>(F);
+  const T k = (T)F.k, gre = (T)F.gre, gim = (T)F.gim;
+  T xr[3], nr[3];
+  for (int c = 0; c < 3; ++c) {
+    xr[c] = g[(CX + c) * N + r];
+    nr[c] = g[(NX + c) * N + r];
+  }
+  T cr = 0, ci = 0;
+  if (ADJ && HAS_C) {
+    const double2 c = F.cfac[r];
+    cr = (T)c.x;
+    ci = (T)c.y;
+  }
+  const int leaf = F.elem_leaf[r];
+  T accr = 0, acci = 0;
+  for (int64_t q = F.far_off[leaf]; q < F.far_off[leaf + 1]; ++q) {
+    const int64_t e = F.far_end[q];
+    for (int64_t base = F.far_beg[q]; base < e; base += 64) {
+      const int64_t o = base + lane;  // the other element of the pair
+      const bool valid = o < e;
+      const int64_t oi = valid ? o : r;
+      // collocation point and element of this lane's pair
+      const int64_t i = ADJ ? oi : r;
+      const int64_t j = ADJ ? r : oi;
+      T xi[3], ni[3];
+      for (int c = 0; c < 3; ++c) {
+        xi[c] = ADJ ? g[(CX + c) * N + i] : xr[c];
+        ni[c] = ADJ ? g[(NX + c) * N + i] : nr[c];
+      }
+      int m = -1;
+      if (valid) {
+        double d2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          const double dc = (double)xi[c] - (double)g[(CX + c) * N + j];
+          d2 += dc * dc;
+        }
+        m = far_order(F, d2 / (double)g[AREA * N + j]);
+      }
+      T s1r = 0, s1i = 0, s2r = 0, s2i = 0;
+      // one uniform rule per pass
+      for (int mc = 1; mc <= kMaxRuleOrder; ++mc) {
+        if (__ballot(m == mc) == 0) continue;
+        if (m == mc) {
+          int64_t jj;
+          integrate_item<T, !VMODE, HAS_C || VMODE>(g, N, (uint64_t)j, mc, xi, ni, k, gre, gim, s1r, s1i, s2r,
+                                                   s2i, jj);
+        }
+      }
+      if (__ballot(m == 0) != 0 && m == 0)
+        far_pair_split<T, !VMODE, HAS_C || VMODE>(F, g, j, xi, ni, s1r, s1i, s2r, s2i);
+      if (!valid) continue;
+      T vr = s1r, vi = s1i;
+      if (VMODE) {
+        vr = s2r;
+        vi = s2i;
+      } else if (HAS_C) {
+        T ccr = cr, cci = ci;
+        if (!ADJ) {
+          const double2 c = F.cfac[j];
+          ccr = (T)c.x;
+          cci = (T)c.y;
+        }
+        vr += ccr * s2r - cci * s2i;
+        vi += ccr * s2i + cci * s2r;
+      }
+      const double2 xv = x[oi];
+      const T xa = (T)xv.x, xb = (T)xv.y;
+      if (ADJ) {
+        accr += vr * xa + vi * xb;
+        acci += vr * xb - vi * xa;
+      } else {
+        accr += vr * xa - vi * xb;
+        acci += vr * xb + vi * xa;
+      }
+    }
+  }
+  const double sr = wave_sum((double)accr);
+  const double si = wave_sum((double)acci);
+  if (lane == 0) {
+    const double2 yo = y[r];
+    y[r] = make_double2(yo.x + sr, yo.y + si);
+  }
+}
+
 // ------------------------------------------------ preconditioner blocks ---
 // One wavefront per row t: the row's near items whose source lies in t's block
 // are integrated (FP64) and summed per column in a fixed order (lane order of
@@ -853,6 +1011,33 @@ void launch_field(const FieldArgs& A, const double* pts, const double2* p, const
                   int64_t* err, hipStream_t s) {
   if (A.npts <= 0) return;
   hipLaunchKernelGGL(k_field, dim3(blocks_for(A.npts, 4)), dim3(256), 0, s, A, pts, p, pinc, out, err);
+}
+
+template <typename T, bool HAS_C, bool VMODE, bool ADJ>
+void far_launch_t(const FarLaunch& F, const double2* x, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_far_direct<T, HAS_C, VMODE, ADJ>), dim3(blocks_for(F.N, 4)), dim3(256), 0, s, F, x, y);
+}
+
+template <typename T>
+void far_launch_p(const FarLaunch& F, bool adjoint, bool vmode, const double2* x, double2* y, hipStream_t s) {
+  const bool c = F.cfac != nullptr;
+  if (vmode) {
+    if (adjoint) far_launch_t<T, false, true, true>(F, x, y, s);
+    else far_launch_t<T, false, true, false>(F, x, y, s);
+  } else if (c) {
+    if (adjoint) far_launch_t<T, true, false, true>(F, x, y, s);
+    else far_launch_t<T, true, false, false>(F, x, y, s);
+  } else {
+    if (adjoint) far_launch_t<T, false, false, true>(F, x, y, s);
+    else far_launch_t<T, false, false, false>(F, x, y, s);
+  }
+}
+
+void launch_far_direct(const FarLaunch& F, bool fp64, bool adjoint, bool vmode, const double2* x, double2* y,
+                       hipStream_t s) {
+  if (F.N <= 0) return;
+  if (fp64) far_launch_p<double>(F, adjoint, vmode, x, y, s);
+  else far_launch_p<float>(F, adjoint, vmode, x, y, s);
 }
 
 void launch_block_assemble(const NearLaunch& L, const BlockArgs& B, double2* a, hipStream_t s) {

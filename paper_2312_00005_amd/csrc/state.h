@@ -40,6 +40,12 @@ struct bem_mesh {
   bem::DevBuf<double2> d_diag;     // tree order, A_ii
   bem::DevBuf<double2> d_vdiag;    // tree order, diagonal of dA/dc
 
+  // direct far field (far_direct option)
+  bool far_direct = false;
+  bem::DevBuf<int32_t> d_elem_leaf;
+  bem::DevBuf<int64_t> d_far_off, d_far_beg, d_far_end;
+  double far_rt2_min[8] = {0};
+
   // block-Jacobi preconditioner (tree order)
   int64_t nblk = 0;
   int64_t blk_entries = 0;
@@ -72,6 +78,11 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
 // y = M x with the block-Jacobi preconditioner (M^H for op AH); a copy when
 // there is none.  x and y must not alias.
 void precondition(bem_mesh* m, bem_op op, const double2* x, double2* y, hipStream_t s);
+
+// far field (FMM or direct quadrature): y += far(x), tree order; no-op
+// without a cluster tree
+void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s,
+               bool vmode = false);
 
 // FMM far field: y += far(x), tree order.  No-op if the mesh has no FMM.
 void fmm_setup_problem(bem_mesh* m, hipStream_t s);
