@@ -289,6 +289,18 @@ bem_status bem_tree_perm(const bem_tree* t, int64_t* perm);
 /* near pairs (self included), quadrature items and points of one application */
 bem_status bem_tree_plan_stats(const bem_tree* t, int64_t* pairs, int64_t* items,
                                int64_t* points);
+/* Expansion lengths the tree would get at wavenumber k under options o (the
+ * admissibility and length rule of o; Eq. (FMMTruncation) and the stability
+ * cap): L[level] for the FP64 operator, L32[level] for the complex-FP32 one
+ * (both host int32[levels]), *capped = 1 if the cap lowered any length below
+ * the accuracy-driven one (the expansion is then less accurate than asked:
+ * k X_min too small, Sec. 3.3.1), *bytes = estimated far-field device memory
+ * of bem_set_problem.  Any output may be NULL.  BEM_E_STATE for a tree built
+ * without use_fmm. */
+bem_status bem_tree_fmm_lengths(const bem_tree* t, double k, const bem_options* o,
+                                int32_t* L, int32_t* L32, int32_t* capped,
+                                double* bytes);
+
 void bem_tree_destroy(bem_tree* t);
 
 const char* bem_last_error(void);

@@ -361,9 +361,14 @@ class FMM:
         N = geom["x"].shape[0]
         self.c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
         self.tree = tree if tree is not None else build_tree(geom, levels, leaf_size, p["admissibility"])
-        self.L = [truncation_length(k, float(Lv["r"].max()), p, level_min_separation(Lv), single)
-                  for Lv in self.tree.levels]
-        self.grids = [sphere_grid(L) for L in self.L]
+        # levels above the first one with interaction pairs carry nothing:
+        # no expansion there (length 0)
+        nl = len(self.tree.levels)
+        self.top = next((l for l, Lv in enumerate(self.tree.levels) if any(len(q) for q in Lv["il"])), nl - 1)
+        self.L = [0 if l < self.top else
+                  truncation_length(k, float(Lv["r"].max()), p, level_min_separation(Lv), single)
+                  for l, Lv in enumerate(self.tree.levels)]
+        self.grids = [sphere_grid(L) if L > 0 else None for L in self.L]
 
     def leaf_signature_matrix(self, c_idx):
         """Rows nu, columns the elements of leaf cluster c: T_nu_j (c_j + ik s.n_j)."""
@@ -403,7 +408,7 @@ class FMM:
         leaf = tr.levels[-1]
         sig[-1] = np.stack([self.leaf_signature_matrix(c) @ x[g] for c, g in enumerate(leaf["groups"])])
         # upward: interpolate child signatures to the parent grid and shift
-        for l in range(nl - 2, -1, -1):
+        for l in range(nl - 2, self.top - 1, -1):
             Lv, Cv = tr.levels[l], tr.levels[l + 1]
             I = interpolation_matrix(self.L[l + 1], self.L[l])
             sp = self.grids[l][0]
@@ -413,9 +418,9 @@ class FMM:
                     shift = np.exp(1j * k * (sp @ (Lv["z"][p] - Cv["z"][c])))
                     out[p] += shift * (I @ sig[l + 1][c])
             sig[l] = out
-        # translation on every level
-        loc = []
-        for l in range(nl):
+        # translation on every level from the first one with pairs
+        loc = [None] * self.top
+        for l in range(self.top, nl):
             Lv = tr.levels[l]
             s = self.grids[l][0]
             out = np.zeros_like(sig[l])
@@ -427,7 +432,7 @@ class FMM:
                 np.add.at(out, m_, D * sig[l][n_])
             loc.append(out)
         # downward: shift to the child centre and anterpolate
-        for l in range(nl - 1):
+        for l in range(self.top, nl - 1):
             Lv, Cv = tr.levels[l], tr.levels[l + 1]
             Am = anterpolation_matrix(self.L[l], self.L[l + 1])
             sp = self.grids[l][0]

@@ -117,6 +117,7 @@ _SIGS = {
     "bem_tree_level_data": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_tree_perm": (_i32, [_vp, _vp]),
     "bem_tree_plan_stats": (_i32, [_vp, _vp, _vp, _vp]),
+    "bem_tree_fmm_lengths": (_i32, [_vp, _dbl, ctypes.POINTER(bem_options), _vp, _vp, _vp, _vp]),
     "bem_tree_destroy": (None, [_vp]),
 }
 
@@ -283,6 +284,17 @@ def bem_tree_destroy(tree):
     _lib.bem_tree_destroy(tree)
 
 
+def bem_tree_fmm_lengths(tree, k, options):
+    nl = bem_tree_levels(tree)
+    L = (_i32 * 16)()
+    L32 = (_i32 * 16)()
+    capped = _i32()
+    nbytes = _dbl()
+    _check(_lib.bem_tree_fmm_lengths(tree, float(k), ctypes.byref(options), L, L32, ctypes.byref(capped),
+                                     ctypes.byref(nbytes)))
+    return {"L": list(L[:nl]), "L_mixed": list(L32[:nl]), "capped": bool(capped.value), "bytes": nbytes.value}
+
+
 class HostTree:
     """Host-only cluster tree and near-field plan (no GPU needed)."""
 
@@ -296,6 +308,7 @@ class HostTree:
         self._tris = np.ascontiguousarray(tris, dtype=np.int32)
         self.n = int(self._tris.shape[0])
         self._h = None
+        self.options = options
         self._h = bem_tree_build(self._nodes.shape[0], self._nodes.ctypes.data, self.n,
                                  self._tris.ctypes.data, options)
 
@@ -315,6 +328,11 @@ class HostTree:
 
     def plan_stats(self):
         return bem_tree_plan_stats(self._h)
+
+    def fmm_lengths(self, k):
+        """Expansion lengths at wavenumber k, whether the stability cap lowered
+        any, and the estimated far-field device bytes."""
+        return bem_tree_fmm_lengths(self._h, k, self.options)
 
 
 # ---- torch convenience layer -------------------------------------------------

@@ -893,6 +893,24 @@ bem_status bem_tree_plan_stats(const bem_tree* t, int64_t* pairs, int64_t* items
   });
 }
 
+bem_status bem_tree_fmm_lengths(const bem_tree* t, double k, const bem_options* o, int32_t* L, int32_t* L32,
+                                int32_t* capped, double* bytes) {
+  return guarded([&]() -> bem_status {
+    if (!t || !o) return fail(BEM_E_ARG, "NULL argument");
+    if (!t->fmm) return fail(BEM_E_STATE, "the tree was built without use_fmm");
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(BEM_E_ARG, "k must be positive and finite");
+    check_options(o);
+    const FmmPlanInfo I = fmm_plan_info(t->tree, t->N, k, *o);
+    for (int l = 0; l < I.levels && l < 16; ++l) {
+      if (L) L[l] = I.L[l];
+      if (L32) L32[l] = I.L32[l];
+    }
+    if (capped) *capped = I.capped ? 1 : 0;
+    if (bytes) *bytes = I.bytes;
+    return BEM_OK;
+  });
+}
+
 void bem_tree_destroy(bem_tree* t) { delete t; }
 
 void bem_mesh_destroy(bem_mesh* m) { delete m; }

@@ -58,6 +58,7 @@ struct FmmLevel {
 // the complex-FP32 operator of the mixed path (its own truncation lengths).
 struct FmmSet {
   std::vector<FmmLevel> lv;
+  int top = 0;  // first level with interaction pairs; levels above it carry nothing
   DevBuf<double2> T64, S64;
   DevBuf<float2> T32, S32;
 };
@@ -299,7 +300,7 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
   const FactorArgs fa = factor_args(m, leaf);
   launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::T(F), vmode ? nullptr : &fa, x,
                              P::sig(leaf), false, s);
-  for (int l = nl - 2; l >= 0; --l) {
+  for (int l = nl - 2; l >= F->top; --l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
     if (!Lp.resample) {
@@ -311,11 +312,11 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
                                P::shift(Lp), P::sig(Lp), s);
     }
   }
-  for (int l = 0; l < nl; ++l) {
+  for (int l = F->top; l < nl; ++l) {
     FmmLevel& L = F->lv[l];
     launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, nullptr, L.nu, P::D(L), P::sig(L), P::loc(L), s);
   }
-  for (int l = 0; l + 1 < nl; ++l) {
+  for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
     if (!Lp.resample) {
@@ -346,7 +347,7 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bo
   const FactorArgs fa = factor_args(m, leaf);
   launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::S(F), nullptr, x, P::loc(leaf),
                              true, s);
-  for (int l = nl - 2; l >= 0; --l) {
+  for (int l = nl - 2; l >= F->top; --l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
     if (!Lp.resample) {
@@ -358,11 +359,11 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bo
                                P::shift(Lp), P::loc(Lp), s);
     }
   }
-  for (int l = 0; l < nl; ++l) {
+  for (int l = F->top; l < nl; ++l) {
     FmmLevel& L = F->lv[l];
     launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.tpos.p, L.nu, P::D(L), P::loc(L), P::sig(L), s);
   }
-  for (int l = 0; l + 1 < nl; ++l) {
+  for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
     if (!Lp.resample) {
@@ -391,7 +392,19 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
   const int nl = (int)T.lv.size();
   const double k = m->k;
   std::vector<std::vector<double>> xt(nl), wt(nl);
-  for (int l = 0; l < nl; ++l) {
+  F->top = nl - 1;
+  for (int l = 0; l < nl; ++l)
+    if (F->lv[l].npairs > 0) {
+      F->top = l;
+      break;
+    }
+  for (int l = 0; l < F->top; ++l) {
+    F->lv[l].L = 0;
+    F->lv[l].nu = 0;
+    if (single) m->fmm_L32[l] = 0;
+    else m->fmm_L[l] = 0;
+  }
+  for (int l = F->top; l < nl; ++l) {
     FmmLevel& D = F->lv[l];
     const Level& L = T.lv[l];
     double rmax = 0.0;
@@ -427,7 +440,7 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     launch_fmm_translation(D.npairs, D.pm.p, D.pn.p, D.z.p, D.s.p, D.nu, D.L, k, single ? nullptr : D.D64.p,
                            single ? D.D32.p : nullptr, s);
   }
-  for (int l = 0; l + 1 < nl; ++l) {
+  for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& P = F->lv[l];
     FmmLevel& C = F->lv[l + 1];
     if (single) P.shift32.alloc(C.nc * P.nu);
@@ -581,6 +594,43 @@ size_t fmm_bytes(const bem_mesh* m) {
          L.tA64.bytes() + L.tB64.bytes() + L.tA32.bytes() + L.tB32.bytes();
   }
   return b;
+}
+
+FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options& o) {
+  FmmPlanInfo I;
+  const int nl = (int)T.lv.size();
+  I.levels = nl;
+  int top = nl - 1;
+  for (int l = 0; l < nl; ++l)
+    if (!T.lv[l].il.empty()) {
+      top = l;
+      break;
+    }
+  for (int l = top; l < nl && l < 16; ++l) {
+    const Level& L = T.lv[l];
+    double rmax = 0.0;
+    for (double r : L.r) rmax = std::max(rmax, r);
+    double xmin = -1.0;
+    for (int64_t c = 0; c < L.nc; ++c)
+      for (int64_t q = L.il_off[c]; q < L.il_off[c + 1]; ++q) {
+        const int64_t n = L.il[q];
+        const double d0 = L.z[3 * c] - L.z[3 * n], d1 = L.z[3 * c + 1] - L.z[3 * n + 1],
+                     d2 = L.z[3 * c + 2] - L.z[3 * n + 2];
+        const double v = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        if (xmin < 0.0 || v < xmin) xmin = v;
+      }
+    for (int single = 0; single < 2; ++single) {
+      const int la = truncation_length(k, rmax, o, -1.0, single != 0);
+      const int lc = truncation_length(k, rmax, o, xmin, single != 0);
+      (single ? I.L32 : I.L)[l] = lc;
+      if (xmin >= 0.0 && lc < la) I.capped = true;
+      const double nu = 2.0 * lc * lc;
+      const double b = single ? 8.0 : 16.0;
+      I.bytes += b * nu * ((double)L.il.size() + 2.0 * (double)L.nc);
+      if (l == nl - 1) I.bytes += 2.0 * b * nu * (double)N;
+    }
+  }
+  return I;
 }
 
 }  // namespace bem

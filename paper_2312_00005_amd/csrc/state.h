@@ -91,6 +91,19 @@ void fmm_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, dou
                bool vmode = false);
 size_t fmm_bytes(const bem_mesh* m);
 
+// Expansion lengths a tree would get at wavenumber k (FP64 and complex-FP32
+// sets), whether the stability cap lowered any of them below the accuracy
+// length, and an estimate of the far-field device bytes (translation values,
+// signatures, locals, leaf rows; both sets).
+struct FmmPlanInfo {
+  int levels = 0;
+  int L[16] = {0};
+  int L32[16] = {0};
+  bool capped = false;
+  double bytes = 0.0;
+};
+FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options& o);
+
 struct SolveResult {
   int iterations = 0;
   int refinements = 0;

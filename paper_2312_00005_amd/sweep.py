@@ -1,0 +1,118 @@
+"""Frequency sweep on one mesh.
+
+For every frequency the far-field method is chosen from what the library
+reports about each candidate cluster tree (bem_tree_fmm_lengths): the deepest
+tree whose expansion lengths are not lowered by the stability cap (k X_min
+large enough, Sec. 3.3.1), stay within the supported length and fit the
+memory budget runs the FMM; otherwise the far field is evaluated by direct
+quadrature (far_direct), which has no low-frequency breakdown and needs no
+translation memory.  Frequencies that share a method share one device plan
+(geometry, tree, near plan built once) and are solved back to back; with
+several streams, consecutive frequencies of a group run concurrently, each on
+its own HIP stream and mesh instance (one host thread per stream; the library
+calls release the interpreter lock).  This module only schedules calls into
+the library.
+"""
+
+import math
+import threading
+import time
+
+from . import bemfmm
+
+
+def wavenumbers(freqs, c=343.0):
+    return [2.0 * math.pi * f / c for f in freqs]
+
+
+def choose_methods(trees, ks, max_L=120, memory_budget=96e9):
+    """Per wavenumber ("fmm", depth) or ("direct", depth); trees: {depth: HostTree}."""
+    out = []
+    deepest = max(trees)
+    for k in ks:
+        pick = ("direct", deepest)
+        for d in sorted(trees, reverse=True):
+            info = trees[d].fmm_lengths(k)
+            if info["capped"] or info["bytes"] > memory_budget:
+                continue
+            if max(info["L"] + info["L_mixed"]) > max_L:
+                continue
+            pick = ("fmm", d)
+            break
+        out.append(pick)
+    return out
+
+
+class FrequencySweep:
+    """Solve the exterior problem at every frequency of ``freqs`` on one mesh."""
+
+    def __init__(self, nodes, tris, freqs, c=343.0, preset="mixed", depths=(4, 3, 2), leaf_size=32,
+                 memory_budget=96e9, max_L=120, streams=2, **overrides):
+        self.nodes, self.tris = nodes, tris
+        self.freqs = list(freqs)
+        self.ks = wavenumbers(self.freqs, c)
+        self.preset = preset
+        self.leaf_size = leaf_size
+        self.overrides = overrides
+        self.streams = max(1, int(streams))
+        t0 = time.perf_counter()
+        trees = {d: bemfmm.HostTree(nodes, tris, preset, levels=d, leaf_size=leaf_size, **overrides)
+                 for d in depths}
+        self.methods = choose_methods(trees, self.ks, max_L=max_L, memory_budget=memory_budget)
+        self.plan_seconds = time.perf_counter() - t0
+        self.lengths = [trees[d].fmm_lengths(k) for (kind, d), k in zip(self.methods, self.ks)]
+        del trees
+
+    def _mesh(self, method):
+        kind, d = method
+        return bemfmm.Mesh(self.nodes, self.tris, self.preset, use_fmm=1, levels=d, leaf_size=self.leaf_size,
+                           far_direct=1 if kind == "direct" else 0, **self.overrides)
+
+    def run(self, source=("plane", (0.0, 0.0, 1.0), 1.0), keep_solutions=True):
+        """Returns a list of per-frequency dicts (k, method, info, seconds and
+        the device solution p) plus timing totals."""
+        import torch
+        groups = {}
+        for i, m in enumerate(self.methods):
+            groups.setdefault(m, []).append(i)
+        results = [None] * len(self.ks)
+        errors = []
+        t_setup = 0.0
+        t0 = time.perf_counter()
+        for method, idx in groups.items():
+            ts = time.perf_counter()
+            meshes = [self._mesh(method) for _ in range(min(self.streams, len(idx)))]
+            t_setup += time.perf_counter() - ts
+            streams = [torch.cuda.Stream() for _ in meshes]
+
+            def worker(w):
+                try:
+                    with torch.cuda.stream(streams[w]):
+                        mesh = meshes[w]
+                        for i in idx[w::len(meshes)]:
+                            k = self.ks[i]
+                            t1 = time.perf_counter()
+                            mesh.set_problem(k)
+                            kind, s, P0 = source
+                            b = mesh.rhs_plane_wave(s, P0) if kind == "plane" else mesh.rhs_point_source(s, P0)
+                            p, _, info = mesh.solve(b, allow_noconv=True)
+                            streams[w].synchronize()
+                            results[i] = {"f": self.freqs[i], "k": k, "method": self.methods[i], "info": info,
+                                          "seconds": time.perf_counter() - t1,
+                                          "p": p if keep_solutions else None}
+                except Exception as e:  # reported after the join
+                    errors.append(e)
+
+            threads = [threading.Thread(target=worker, args=(w,)) for w in range(len(meshes))]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+            for mesh in meshes:
+                mesh.close()
+            if errors:
+                raise errors[0]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return results, {"wall_s": wall, "mesh_setup_s": t_setup, "plan_choice_s": self.plan_seconds,
+                         "solve_s_per_frequency": (wall - t_setup) / len(self.ks)}
