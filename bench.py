@@ -19,11 +19,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic flops per near-field quadrature point of the fused kernel
-# (point, r, 1/r, exp(ikr), the four kernels combined, complex accumulate;
-# rsqrt, sin and cos counted as one flop each); 91 with admittance terms
-FLOPS_PER_POINT = 74
-FLOPS_PER_POINT_BC = 91
+# algorithmic flops per near-field quadrature point of the fused kernel, FMA
+# counted as two, rsqrt, sin and cos as one each: the quadratic form for
+# |y - x|^2 (10), rsqrt, r, phase, sin, cos (5), weight and G (3), the two
+# normal projections (6), the hypersingular combination t1 (10), b1 (10) and
+# the complex accumulation (8); 68 with the admittance terms
+FLOPS_PER_POINT = 52
+FLOPS_PER_POINT_BC = 68
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 WORKLOADS = {

@@ -46,11 +46,12 @@ void launch_fmm_aggregate(int64_t nclust, const int64_t* ebeg, const int64_t* ee
 template <typename T, typename V>
 void launch_fmm_disaggregate(int64_t N, const int64_t* elem_cluster, int nu, const V* Sm, const FactorArgs* F,
                              const V* loc, double2* y, bool conj_rows, hipStream_t st);
-// tpos: NULL for the forward translation; for the conjugate transpose the
-// position of each reversed pair (the interaction lists are symmetric)
+// code[q] = 2 slot + flip for interaction entry q = (m, n): D_mn is slot
+// `slot` of D at node nu (flip 0) or at the antipodal node (flip 1).
+// adjoint: loc_n = sum_m conj(D_mn) sig_m over the entries (n, m) of n.
 template <typename T, typename V>
-void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* tpos, int nu,
-                          const V* D, const V* sig, V* loc, hipStream_t st);
+void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint,
+                          int L, int nu, const V* D, const V* sig, V* loc, hipStream_t st);
 // Sig_p = sum_children shift * Sig_c (grids coincide)
 template <typename T, typename V>
 void launch_fmm_up_equal(int64_t np, const int64_t* cbeg, const int64_t* cend, int nu, const V* shift,

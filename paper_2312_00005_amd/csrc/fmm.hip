@@ -255,36 +255,44 @@ __global__ __launch_bounds__(256) void k_disaggregate(int64_t N, const int64_t* 
   }
 }
 
-// tpos == NULL: loc_m = sum_q D[q] sig_il[q] over m's pairs q;
-// tpos != NULL: conjugate transpose, loc_m = sum_q conj(D[tpos[q]]) sig_il[q]
-// where tpos[q] is the position of the reversed pair (il[q], m).
-template <typename T, typename V>
+// loc_m = sum_q D_(m, il[q]) sig_il[q] over m's entries q, with D_mn read from
+// slot code[q] >> 1 at node v or, if code[q] & 1, at the antipodal node
+// (t, j) -> (L-1-t, j+L mod 2L).  ADJ: loc_n = sum_q conj(D_(il[q], n)) sig_il[q]:
+// the same slot with the flip inverted.
+template <typename T, typename V, bool ADJ>
 __global__ __launch_bounds__(64) void k_translate(const int64_t* __restrict__ il_off,
                                                    const int64_t* __restrict__ il,
-                                                   const int64_t* __restrict__ tpos, int nu,
+                                                   const int64_t* __restrict__ code, int L, int nu,
                                                    const V* __restrict__ D, const V* __restrict__ sig,
                                                    V* __restrict__ loc) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t m = blockIdx.y;
   if (v >= nu) return;
+  const int twoL = 2 * L;
+  const int t = v / twoL, j = v - t * twoL;
+  const int va = (L - 1 - t) * twoL + (j < L ? j + L : j - L);
   V acc = mk(T(0), T(0));
-  if (!tpos) {
-    const int64_t q0 = il_off[m], q1 = il_off[m + 1];
-    int64_t q = q0;
-    // four independent loads in flight per lane
-    for (; q + 4 <= q1; q += 4) {
-      const V d0 = D[q * nu + v], d1 = D[(q + 1) * nu + v], d2 = D[(q + 2) * nu + v], d3 = D[(q + 3) * nu + v];
-      const V s0 = sig[il[q] * nu + v], s1 = sig[il[q + 1] * nu + v], s2 = sig[il[q + 2] * nu + v],
-              s3 = sig[il[q + 3] * nu + v];
-      acc = cadd(acc, cmul(d0, s0));
-      acc = cadd(acc, cmul(d1, s1));
-      acc = cadd(acc, cmul(d2, s2));
-      acc = cadd(acc, cmul(d3, s3));
+  const int64_t q0 = il_off[m], q1 = il_off[m + 1];
+  int64_t q = q0;
+  // four independent loads in flight per lane
+  for (; q + 4 <= q1; q += 4) {
+    V d[4], sg[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t c = code[q + u];
+      const bool flip = ((c & 1) != 0) != ADJ;
+      d[u] = D[(c >> 1) * nu + (flip ? va : v)];
+      sg[u] = sig[il[q + u] * nu + v];
     }
-    for (; q < q1; ++q) acc = cadd(acc, cmul(D[q * nu + v], sig[il[q] * nu + v]));
-  } else {
-    for (int64_t q = il_off[m]; q < il_off[m + 1]; ++q)
-      acc = cadd(acc, cmulc(D[tpos[q] * nu + v], sig[il[q] * nu + v]));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = cadd(acc, ADJ ? cmulc(d[u], sg[u]) : cmul(d[u], sg[u]));
+  }
+  for (; q < q1; ++q) {
+    const int64_t c = code[q];
+    const bool flip = ((c & 1) != 0) != ADJ;
+    const V dv = D[(c >> 1) * nu + (flip ? va : v)];
+    const V sv = sig[il[q] * nu + v];
+    acc = cadd(acc, ADJ ? cmulc(dv, sv) : cmul(dv, sv));
   }
   loc[m * nu + v] = acc;
 }
@@ -478,11 +486,15 @@ void launch_fmm_disaggregate(int64_t N, const int64_t* ec, int nu, const V* Sm, 
 }
 
 template <typename T, typename V>
-void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* tpos, int nu,
-                          const V* D, const V* sig, V* loc, hipStream_t st) {
+void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint,
+                          int L, int nu, const V* D, const V* sig, V* loc, hipStream_t st) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL((k_translate<T, V>), dim3(nblk(nu, 64), (unsigned)nc), dim3(64), 0, st, il_off, il, tpos,
-                     nu, D, sig, loc);
+  if (adjoint)
+    hipLaunchKernelGGL((k_translate<T, V, true>), dim3(nblk(nu, 64), (unsigned)nc), dim3(64), 0, st, il_off, il,
+                       code, L, nu, D, sig, loc);
+  else
+    hipLaunchKernelGGL((k_translate<T, V, false>), dim3(nblk(nu, 64), (unsigned)nc), dim3(64), 0, st, il_off, il,
+                       code, L, nu, D, sig, loc);
 }
 
 template <typename T, typename V>
@@ -538,8 +550,8 @@ void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const 
                                            const FactorArgs*, const double2*, V*, bool, hipStream_t);         \
   template void launch_fmm_disaggregate<T, V>(int64_t, const int64_t*, int, const V*, const FactorArgs*,      \
                                               const V*, double2*, bool, hipStream_t);                         \
-  template void launch_fmm_translate<T, V>(int64_t, const int64_t*, const int64_t*, const int64_t*, int,      \
-                                           const V*, const V*, V*, hipStream_t);                              \
+  template void launch_fmm_translate<T, V>(int64_t, const int64_t*, const int64_t*, const int64_t*, bool, int, \
+                                           int, const V*, const V*, V*, hipStream_t);                         \
   template void launch_fmm_up_equal<T, V>(int64_t, const int64_t*, const int64_t*, int, const V*, const V*,   \
                                           V*, hipStream_t);                                                   \
   template void launch_fmm_down_equal<T, V>(int64_t, const int64_t*, int, const V*, const V*, V*,             \

@@ -32,7 +32,7 @@ struct FmmLevel {
   int L = 0, nu = 0;
   int64_t nc = 0;
   DevBuf<double> s, w, z;
-  DevBuf<int64_t> il_off, il, pm, pn, tpos;
+  DevBuf<int64_t> il_off, il, pm, pn, code;
   int64_t npairs = 0;
   DevBuf<double2> D64;
   DevBuf<float2> D32;
@@ -121,19 +121,32 @@ void sphere_grid(int L, std::vector<double>& s, std::vector<double>& w, std::vec
   gauss_legendre01(L, x01, w01);
   xt.resize(L);
   wt.resize(L);
+  // exactly antipodal: node L-1-t is -node t, azimuth j+L is azimuth j + pi,
+  // so that s(t, j) = -s(L-1-t, j+L) bit for bit
   for (int t = 0; t < L; ++t) {
-    xt[t] = 2.0 * x01[t] - 1.0;
-    wt[t] = 2.0 * w01[t];
+    const int tm = L - 1 - t;
+    if (t < tm) {
+      xt[t] = 2.0 * x01[t] - 1.0;
+      wt[t] = 2.0 * w01[t];
+    } else if (t == tm) {
+      xt[t] = 0.0;
+      wt[t] = 2.0 * w01[t];
+    } else {
+      xt[t] = -xt[tm];
+      wt[t] = wt[tm];
+    }
   }
   s.resize(3 * 2 * L * L);
   w.resize(2 * L * L);
   for (int t = 0; t < L; ++t) {
     const double ct = xt[t], st = std::sqrt(1.0 - ct * ct);
     for (int j = 0; j < 2 * L; ++j) {
-      const double ph = j * M_PI / L;
       const int v = t * 2 * L + j;
-      s[3 * v] = st * std::cos(ph);
-      s[3 * v + 1] = st * std::sin(ph);
+      const int jj = j < L ? j : j - L;
+      const double ph = jj * M_PI / L;
+      const double sg = j < L ? 1.0 : -1.0;
+      s[3 * v] = sg * (st * std::cos(ph));
+      s[3 * v + 1] = sg * (st * std::sin(ph));
       s[3 * v + 2] = ct;
       w[v] = wt[t] * M_PI / L;
     }
@@ -186,22 +199,36 @@ void upload_tree(bem_mesh* m, FmmState* F, hipStream_t s) {
         pm.push_back(c);
         pn.push_back(L.il[q]);
       }
-    D.npairs = (int64_t)pm.size();
-    upload_vec(D.pm, pm, s);
-    upload_vec(D.pn, pn, s);
-    // position of the reversed pair (n, m) of every pair (m, n): the lists are
-    // symmetric because the admissibility test is
-    std::vector<int64_t> tpos(pm.size());
+    // Translation values are stored once per unordered pair {m, n} (m < n),
+    // for X = z_m - z_n: D(-X, s) = D(X, -s), and the sphere grid is exactly
+    // symmetric under s -> -s, so pair (n, m) reads the same slot at the
+    // antipodal node.  code[q] = 2 slot + (m > n) for interaction entry q = (m, n).
+    // The lists are symmetric because the admissibility test is.
+    std::vector<int64_t> upm, upn, code(pm.size());
+    std::vector<int64_t> slot_of(pm.size(), -1);
+    for (int64_t q = 0; q < (int64_t)pm.size(); ++q)
+      if (pm[q] < pn[q]) {
+        slot_of[q] = (int64_t)upm.size();
+        upm.push_back(pm[q]);
+        upn.push_back(pn[q]);
+      }
     for (int64_t c = 0; c < L.nc; ++c)
       for (int64_t q = L.il_off[c]; q < L.il_off[c + 1]; ++q) {
         const int64_t n = L.il[q];
+        if (c < n) {
+          code[q] = 2 * slot_of[q];
+          continue;
+        }
         const int64_t* b = L.il.data() + L.il_off[n];
         const int64_t* e = L.il.data() + L.il_off[n + 1];
         const int64_t* f = std::lower_bound(b, e, c);
-        if (f == e || *f != c) throw Error(BEM_E_STATE, "interaction lists are not symmetric");
-        tpos[q] = L.il_off[n] + (f - b);
+        if (f == e || *f != c || c == n) throw Error(BEM_E_STATE, "interaction lists are not symmetric");
+        code[q] = 2 * slot_of[L.il_off[n] + (f - b)] + 1;
       }
-    upload_vec(D.tpos, tpos, s);
+    D.npairs = (int64_t)upm.size();
+    upload_vec(D.pm, upm, s);
+    upload_vec(D.pn, upn, s);
+    upload_vec(D.code, code, s);
     upload_vec(D.parent, L.parent, s);
     if (l + 1 < nl) {
       upload_vec(D.cbeg, L.cbeg, s);
@@ -314,7 +341,8 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
   }
   for (int l = F->top; l < nl; ++l) {
     FmmLevel& L = F->lv[l];
-    launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, nullptr, L.nu, P::D(L), P::sig(L), P::loc(L), s);
+    launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.code.p, false, L.L, L.nu, P::D(L), P::sig(L), P::loc(L),
+                               s);
   }
   for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& Lp = F->lv[l];
@@ -361,7 +389,8 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bo
   }
   for (int l = F->top; l < nl; ++l) {
     FmmLevel& L = F->lv[l];
-    launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.tpos.p, L.nu, P::D(L), P::loc(L), P::sig(L), s);
+    launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.code.p, true, L.L, L.nu, P::D(L), P::loc(L), P::sig(L),
+                               s);
   }
   for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& Lp = F->lv[l];
@@ -626,7 +655,7 @@ FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options&
       if (xmin >= 0.0 && lc < la) I.capped = true;
       const double nu = 2.0 * lc * lc;
       const double b = single ? 8.0 : 16.0;
-      I.bytes += b * nu * ((double)L.il.size() + 2.0 * (double)L.nc);
+      I.bytes += b * nu * (0.5 * (double)L.il.size() + 2.0 * (double)L.nc);
       if (l == nl - 1) I.bytes += 2.0 * b * nu * (double)N;
     }
   }

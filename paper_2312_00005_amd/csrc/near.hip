@@ -33,14 +33,22 @@ __constant__ float c_rule_a32[kRulePoints];
 __constant__ float c_rule_b32[kRulePoints];
 __constant__ float c_rule_w32[kRulePoints];
 __constant__ int c_rule_off[kMaxRuleOrder + 1];
+// weights divided by 4 pi (the Green's function's factor folded in)
+__constant__ double c_rule_ws[kRulePoints];
+__constant__ float c_rule_ws32[kRulePoints];
 
 void upload_rule_tables(const double* a, const double* b, const double* w, const int* off) {
-  float a32[kRulePoints], b32[kRulePoints], w32[kRulePoints];
+  float a32[kRulePoints], b32[kRulePoints], w32[kRulePoints], ws32[kRulePoints];
+  double ws[kRulePoints];
   for (int i = 0; i < kRulePoints; ++i) {
     a32[i] = (float)a[i];
     b32[i] = (float)b[i];
     w32[i] = (float)w[i];
+    ws[i] = w[i] * 0.079577471545947667884441881686257181;
+    ws32[i] = (float)ws[i];
   }
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_ws), ws, sizeof(double) * kRulePoints);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_ws32), ws32, sizeof(float) * kRulePoints);
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a), a, sizeof(double) * kRulePoints);
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b), b, sizeof(double) * kRulePoints);
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_w), w, sizeof(double) * kRulePoints);
@@ -62,11 +70,13 @@ template <> struct RuleTab<double> {
   __device__ static double a(int i) { return c_rule_a[i]; }
   __device__ static double b(int i) { return c_rule_b[i]; }
   __device__ static double w(int i) { return c_rule_w[i]; }
+  __device__ static double ws(int i) { return c_rule_ws[i]; }
 };
 template <> struct RuleTab<float> {
   __device__ static float a(int i) { return c_rule_a32[i]; }
   __device__ static float b(int i) { return c_rule_b32[i]; }
   __device__ static float w(int i) { return c_rule_w32[i]; }
+  __device__ static float ws(int i) { return c_rule_ws32[i]; }
 };
 
 // sin and cos of x for |x| < 2^20: Cody & Waite reduction by pi/2 (pi/2 split
@@ -111,6 +121,22 @@ __device__ inline void sincos_cw(double x, double* s, double* c) {
 
 __device__ inline void sincos_t(double x, double* s, double* c) { sincos_cw(x, s, c); }
 __device__ inline void sincos_t(float x, float* s, float* c) { __sincosf(x, s, c); }
+
+// Phase of exp(ikr) in the unit the sine/cosine below take: radians in FP64
+// (Cody-Waite reduction above), revolutions in FP32 (the hardware sine and
+// cosine take revolutions, so k/(2 pi) is folded into the per-item constant).
+template <typename T> struct Phase;
+template <> struct Phase<double> {
+  __device__ static double scale(double k) { return k; }
+  __device__ static void sincos(double x, double* s, double* c) { sincos_cw(x, s, c); }
+};
+template <> struct Phase<float> {
+  __device__ static float scale(float k) { return k * 0.15915494309189535f; }
+  __device__ static void sincos(float x, float* s, float* c) {
+    *s = __builtin_amdgcn_sinf(x);
+    *c = __builtin_amdgcn_cosf(x);
+  }
+};
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
 
@@ -158,6 +184,11 @@ __device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t
 // m is the item's rule order; the caller passes it wavefront-uniform so the
 // rule tables are read with scalar loads.  S1: the c-independent part
 // -(H - gamma E); S2: the part multiplied by c_j, (G - gamma H').
+// With d0 = v0 - x_i and the point y = v0 + a e1 + b e2 in the (flat) source
+// triangle, everything the kernels need is a low-order polynomial in (a, b)
+// with per-item coefficients: |y - x|^2 is a quadratic form, (y - x).n_j = d0.n_j
+// (e1, e2 lie in the source plane) and (y - x).n_i is affine, so a point costs
+// a few FMAs besides rsqrt, sin and cos.
 template <typename T, bool WANT_S1, bool WANT_S2>
 __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64_t item, int m, const T xi[3],
                                       const T ni[3], T k, T gre, T gim, T& s1r, T& s1i, T& s2r,
@@ -168,49 +199,67 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
   jout = j;
   T v0[3], v1[3], v2[3];
   item_triangle<T>(g, N, j, depth, path, v0, v1, v2);
-  T e1[3], e2[3], nj[3];
+  T d0[3], e1[3], e2[3], nj[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    d0[c] = v0[c] - xi[c];
     e1[c] = v1[c] - v0[c];
     e2[c] = v2[c] - v0[c];
     nj[c] = g[(NX + c) * N + j];
   }
+  // |d0 + a e1 + b e2|^2 = q00 + a (qa1 + a q11) + b (qb1 + b q22 + a q12)
+  const T q00 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
+  const T qa1 = T(2) * (d0[0] * e1[0] + d0[1] * e1[1] + d0[2] * e1[2]);
+  const T qb1 = T(2) * (d0[0] * e2[0] + d0[1] * e2[1] + d0[2] * e2[2]);
+  const T q11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+  const T q22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+  const T q12 = T(2) * (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]);
+  // (y - x).n_j and (y - x).n_i = c0 + a c1 + b c2
+  const T hn = d0[0] * nj[0] + d0[1] * nj[1] + d0[2] * nj[2];
+  const T c0 = d0[0] * ni[0] + d0[1] * ni[1] + d0[2] * ni[2];
+  const T c1 = e1[0] * ni[0] + e1[1] * ni[1] + e1[2] * ni[2];
+  const T c2 = e2[0] * ni[0] + e2[1] * ni[1] + e2[2] * ni[2];
   const T area2 = T(2) * g[AREA * N + j] * (T)ldexp(1.0, -2 * depth);
   const T nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
+  const T kph = Phase<T>::scale(k);
+  const T kk = k * k, k3 = T(3) * k;
+  // gamma a = (gre + i gim)(-1/r + ik) = (-gre/r - gim k) + i (gre k - gim/r)
   const int base = c_rule_off[m - 1];
   const int np = m * m;
   T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
   for (int q = 0; q < np; ++q) {
-    const T qa = RuleTab<T>::a(base + q), qb = RuleTab<T>::b(base + q), qw = RuleTab<T>::w(base + q);
-    T R[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) R[c] = (v0[c] + qa * e1[c] + qb * e2[c]) - xi[c];
-    const T r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    const T qa = RuleTab<T>::a(base + q), qb = RuleTab<T>::b(base + q), qw = RuleTab<T>::ws(base + q);
+    const T ta = fma(qa, q11, qa1);
+    T tb = fma(qb, q22, qb1);
+    tb = fma(qa, q12, tb);
+    T r2 = fma(qa, ta, q00);
+    r2 = fma(qb, tb, r2);
     const T rinv = rsqrt_t(r2);
     const T r = r2 * rinv;
     T sn, cs;
-    sincos_t(k * r, &sn, &cs);
-    const T gs = qw * rinv * T(kInv4Pi);
+    Phase<T>::sincos(kph * r, &sn, &cs);
+    const T gs = qw * rinv;
     const T Gr = gs * cs, Gi = gs * sn;
-    const T rny = (R[0] * nj[0] + R[1] * nj[1] + R[2] * nj[2]) * rinv;
-    const T rnx = (R[0] * ni[0] + R[1] * ni[1] + R[2] * ni[2]) * rinv;
-    // t1 = B rnx rny + a nn / r with a = (-1/r, k), B = (3/r^2 - k^2, -3k/r)
+    const T rny = hn * rinv;
+    const T rnx = fma(qb, c2, fma(qa, c1, c0)) * rinv;
     if (WANT_S1) {
+      // t1 = B rnx rny + a nn / r with a = (-1/r, k), B = (3/r^2 - k^2, -3k/r)
       const T p = rnx * rny;
-      const T t1r = (T(3) * rinv * rinv - k * k) * p - nn * rinv * rinv;
-      const T t1i = -T(3) * k * rinv * p + k * nn * rinv;
+      const T ri2 = rinv * rinv;
+      const T t1r = fma(fma(T(3), ri2, -kk), p, -nn * ri2);
+      const T t1i = rinv * fma(-k3, p, k * nn);
       // b1 = -a rny - gamma t1
-      const T b1r = rinv * rny - (gre * t1r - gim * t1i);
-      const T b1i = -k * rny - (gre * t1i + gim * t1r);
-      a1r += Gr * b1r - Gi * b1i;
-      a1i += Gr * b1i + Gi * b1r;
+      const T b1r = fma(rinv, rny, -fma(gre, t1r, -gim * t1i));
+      const T b1i = fma(-k, rny, -fma(gre, t1i, gim * t1r));
+      a1r = fma(Gr, b1r, fma(-Gi, b1i, a1r));
+      a1i = fma(Gr, b1i, fma(Gi, b1r, a1i));
     }
     if (WANT_S2) {
       // b2 = 1 + gamma a rnx
-      const T b2r = T(1) + (-gre * rinv - gim * k) * rnx;
-      const T b2i = (gre * k - gim * rinv) * rnx;
-      a2r += Gr * b2r - Gi * b2i;
-      a2i += Gr * b2i + Gi * b2r;
+      const T b2r = fma(fma(-gre, rinv, -gim * k), rnx, T(1));
+      const T b2i = fma(gre, k, -gim * rinv) * rnx;
+      a2r = fma(Gr, b2r, fma(-Gi, b2i, a2r));
+      a2i = fma(Gr, b2i, fma(Gi, b2r, a2i));
     }
   }
   s1r = a1r * area2;
