@@ -132,6 +132,10 @@ typedef struct bem_options {
                                stored) instead of the FMM -- for frequencies
                                where the expansion is unstable (k X_min small,
                                Sec. 3.3.1) or too long.  Needs use_fmm = 1. */
+  int32_t use_graphs;       /* 1: bem_solve / bem_solve_adjoint replay the
+                               operator application (near field and far field
+                               kernels) of each GMRES iteration as a captured
+                               HIP graph; recaptured after bem_set_problem */
 } bem_options;
 
 typedef struct bem_solve_info {

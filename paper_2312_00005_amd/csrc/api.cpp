@@ -63,6 +63,8 @@ void set_paper(bem_options* o) {
   o->precond = 0;
   o->gamma_re = 0.0;
   o->gamma_im_k = 1.0;
+  o->far_direct = 0;
+  o->use_graphs = 1;
 }
 
 void upload_rules() {
@@ -118,6 +120,7 @@ void check_options(const bem_options* o) {
     throw Error(BEM_E_ARG, "unknown precision");
   if (o->precond < 0 || o->precond > 2) throw Error(BEM_E_ARG, "precond must be 0, 1 or 2");
   if (o->far_direct != 0 && o->far_direct != 1) throw Error(BEM_E_ARG, "far_direct must be 0 or 1");
+  if (o->use_graphs != 0 && o->use_graphs != 1) throw Error(BEM_E_ARG, "use_graphs must be 0 or 1");
   if (o->far_direct && !o->use_fmm) throw Error(BEM_E_ARG, "far_direct needs the cluster tree (use_fmm = 1)");
   if (!std::isfinite(o->gamma_re) || !std::isfinite(o->gamma_im_k) || o->gamma_im_k == 0.0)
     throw Error(BEM_E_ARG, "the coupling needs a finite gamma with a non-zero imaginary part");
@@ -519,6 +522,7 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     if (!(k > 0.0) || !std::isfinite(k)) return fail(BEM_E_ARG, "k must be positive and finite");
     hipStream_t s = as_stream(stream);
     m->k = k;
+    ++m->problem_stamp;
     m->gre = m->opt.gamma_re;
     m->gim = m->opt.gamma_im_k / k;  // gamma = i / k for (0, 1) (Sec. 2.5)
     m->have_beta = beta != nullptr;

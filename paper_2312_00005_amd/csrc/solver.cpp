@@ -23,6 +23,42 @@ struct Work {
   int nblk;
 };
 
+// y = A x (tree order) for the Krylov loop: with use_graphs the kernel
+// sequence of one application is captured once per (operator, precision,
+// buffers, problem) on a private stream and replayed on s.
+void apply_iter(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s) {
+  if (!m->opt.use_graphs) {
+    apply_tree(m, op, prec, x, y, s);
+    return;
+  }
+  auto& G = m->graphs[op == BEM_OP_AH ? 1 : 0][prec == BEM_PREC_MIXED ? 1 : 0];
+  if (!G.exec || G.stamp != m->problem_stamp || G.in != x || G.out != y) {
+    if (G.exec) {
+      BEM_HIP(hipGraphExecDestroy(G.exec));
+      G.exec = nullptr;
+    }
+    if (op == BEM_OP_AH) ensure_transposed_plan(m, s);
+    if (!m->cap_stream) BEM_HIP(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    BEM_HIP(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      apply_tree(m, op, prec, x, y, m->cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(m->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    BEM_HIP(hipStreamEndCapture(m->cap_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BEM_HIP(e);
+    G.stamp = m->problem_stamp;
+    G.in = x;
+    G.out = y;
+  }
+  BEM_HIP(hipGraphLaunch(G.exec, s));
+}
+
 double vec_norm(bem_mesh* m, const double2* v, const Work& W, hipStream_t s) {
   launch_multidot(W.N, 1, v, W.N, v, m->d_partial.p, W.nblk, s);
   launch_reduce_partials(1, W.nblk, m->d_partial.p, m->d_h.p, s);
@@ -70,10 +106,10 @@ int gmres(bem_mesh* m, bem_op op, bem_precision prec, const double2* b, double2*
     for (int j = 0; j < R; ++j) {
       if (m->precond_ready) {
         precondition(m, op, V + (int64_t)j * N, m->d_z.p, s);
-        apply_tree(m, op, prec, m->d_z.p, w, s);
       } else {
-        apply_tree(m, op, prec, V + (int64_t)j * N, w, s);
+        BEM_HIP(hipMemcpyAsync(m->d_z.p, V + (int64_t)j * N, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
       }
+      apply_iter(m, op, prec, m->d_z.p, w, s);
       ++iters;
       // classical Gram-Schmidt, twice
       launch_multidot(N, j + 1, V, N, w, m->d_partial.p, W.nblk, s);

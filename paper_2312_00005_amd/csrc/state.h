@@ -40,6 +40,17 @@ struct bem_mesh {
   bem::DevBuf<double2> d_diag;     // tree order, A_ii
   bem::DevBuf<double2> d_vdiag;    // tree order, diagonal of dA/dc
 
+  // captured operator applications of the Krylov driver, [op][precision]
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    uint64_t stamp = 0;
+    const void* in = nullptr;
+    void* out = nullptr;
+  };
+  GraphSlot graphs[2][2];
+  uint64_t problem_stamp = 0;   // bumped by every bem_set_problem
+  hipStream_t cap_stream = nullptr;
+
   // direct far field (far_direct option)
   bool far_direct = false;
   bem::DevBuf<int32_t> d_elem_leaf;
@@ -63,7 +74,13 @@ struct bem_mesh {
   int fmm_L[16] = {0};     // FP64 operator
   int fmm_L32[16] = {0};   // complex-FP32 operator of the mixed path
 
-  ~bem_mesh() { bem::fmm_destroy(fmm_state); }
+  ~bem_mesh() {
+    for (auto& row : graphs)
+      for (auto& gs : row)
+        if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    bem::fmm_destroy(fmm_state);
+  }
 };
 
 namespace bem {
