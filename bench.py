@@ -193,6 +193,8 @@ def main():
     mesh.set_problem(k)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    tune = mesh.autotune()
+    log(f"launch shapes {tune}")
     stats = mesh.stats()
     x = torch.from_numpy(synth.complex_normal(N, seed=4)).to("cuda")
     y = torch.empty_like(x)
@@ -280,6 +282,7 @@ def main():
         "near_ms": {p: res[p]["t_near"] * 1e3 for p in res},
         "near_quad_points": pts,
         "setup_s": {"mesh": t_mesh, "per_frequency": t_setup},
+        "launch_shapes": tune,
         "solve_s_per_frequency": {p: solves[p]["seconds"] for p in solves},
         "solve": solves,
         "roofline": {"bound": "alu", "kernel": NEAR_KERNEL, "achieved": achieved,

@@ -251,6 +251,16 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
                                const bem_c128* hg, double rho_c, double* grad,
                                void* stream);
 
+/* Choose launch shapes by timing them on this mesh and problem: near-field
+ * targets per workgroup (1, 2, 4, 8) and translation threads per workgroup
+ * (64, 128, 256), for the FP64 and the complex-FP32 operator.  Results are
+ * kept in the mesh and used by every later application; near_wpb and
+ * translate_tpb (host int32[2]: FP64, FP32) receive them and may be NULL.
+ * Runs about 30 operator parts on the stream; results are unchanged by the
+ * choice (each output keeps its owner and summation order). */
+bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb,
+                        void* stream);
+
 /* Solve A p = rhs by GMRES (FP64 Krylov vectors and residuals; with
  * precision MIXED an FP64 outer refinement around a complex-FP32 inner
  * operator).  p_out: device bem_c128[n_tri]; v_out (may be NULL): normal

@@ -103,6 +103,7 @@ _SIGS = {
     "bem_solve": (_i32, [_vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(bem_solve_info), _vp]),
     "bem_apply_dc": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "bem_incident_field": (_i32, [_vp, _i32, _vp, bem_c128, _i64, _vp, _vp, _vp]),
+    "bem_autotune": (_i32, [_vp, _vp, _vp, _vp]),
     "bem_field": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_field_adjoint": (_i32, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
     "bem_grad_admittance": (_i32, [_vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
@@ -181,6 +182,13 @@ def bem_apply_part(mesh, op, prec, part, x_ptr, y_ptr, stream):
 
 def bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream):
     _check(_lib.bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream))
+
+
+def bem_autotune(mesh, stream):
+    w = (_i32 * 2)()
+    t = (_i32 * 2)()
+    _check(_lib.bem_autotune(mesh, w, t, stream))
+    return {"near_wpb": {"fp64": w[0], "mixed": w[1]}, "translate_tpb": {"fp64": t[0], "mixed": t[1]}}
 
 
 def bem_incident_field(mesh, kind, src, P0, n_pts, pts_ptr, out_ptr, stream):
@@ -445,6 +453,10 @@ class Mesh:
         out = self._empty() if out is None else out
         bem_apply_dc(self._h, _OPS[op], _PRECS[prec], xp, _dev_c128(out, self.n, "y"), _stream())
         return out
+
+    def autotune(self):
+        """Time the launch-shape candidates on this problem and keep the fastest."""
+        return bem_autotune(self._h, _stream())
 
     def incident_plane_wave(self, pts, d=(0.0, 0.0, 1.0), P0=1.0):
         pts = _dev_pts(pts)

@@ -151,6 +151,7 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   L.k = m->k;
   L.gre = m->gre;
   L.gim = m->gim;
+  L.wpb = m->tune_wpb[prec == BEM_PREC_FP64 ? 0 : 1];
   if (op == BEM_OP_A) {
     L.off = m->d_off.p;
     L.seg = m->d_seg.p;
@@ -596,6 +597,67 @@ bem_status bem_incident_field(bem_mesh* m, int kind, const double src[3], bem_c1
     hipStream_t s = as_stream(stream);
     launch_incident(n_pts, pts, kind, m->k, s3, P0.re, P0.im, reinterpret_cast<double2*>(out), s);
     BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m) return fail(BEM_E_ARG, "mesh is NULL");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0, e1;
+    BEM_HIP(hipEventCreate(&e0));
+    BEM_HIP(hipEventCreate(&e1));
+    auto timed = [&](auto&& fn) {
+      fn();  // warm-up
+      BEM_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) fn();
+      BEM_HIP(hipEventRecord(e1, s));
+      BEM_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
+    };
+    try {
+      BEM_HIP(hipMemsetAsync(m->d_x.p, 0, m->N * sizeof(double2), s));
+      for (int pi = 0; pi < 2; ++pi) {
+        const bem_precision prec = pi == 0 ? BEM_PREC_FP64 : BEM_PREC_MIXED;
+        float best = -1.0f;
+        int pick = 4;
+        for (int w : {1, 2, 4, 8}) {
+          m->tune_wpb[pi] = w;
+          const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 1, m->d_x.p, m->d_y.p, s); });
+          if (best < 0.0f || t < best) {
+            best = t;
+            pick = w;
+          }
+        }
+        m->tune_wpb[pi] = pick;
+        if (m->fmm && !m->far_direct) {
+          best = -1.0f;
+          pick = 64;
+          for (int tpb : {64, 128, 256}) {
+            m->tune_tpb[pi] = tpb;
+            const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 2, m->d_x.p, m->d_y.p, s); });
+            if (best < 0.0f || t < best) {
+              best = t;
+              pick = tpb;
+            }
+          }
+          m->tune_tpb[pi] = pick;
+        }
+        if (near_wpb) near_wpb[pi] = m->tune_wpb[pi];
+        if (translate_tpb) translate_tpb[pi] = m->tune_tpb[pi];
+      }
+      ++m->problem_stamp;  // captured applications used the old shapes
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    BEM_HIP(hipEventDestroy(e0));
+    BEM_HIP(hipEventDestroy(e1));
     return BEM_OK;
   });
 }

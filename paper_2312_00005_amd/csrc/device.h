@@ -24,6 +24,7 @@ struct NearLaunch {
   const double2* vdiag;   // diagonal of dA/dc: G_ii - gamma/2 (tree order)
   double k;
   double gre, gim;        // coupling gamma
+  int wpb;                // targets (wavefronts) per workgroup of the forward kernel: 1, 2, 4 or 8
 };
 
 // y = diag x + sum over near items (tree-order vectors), in FP64 or complex

@@ -51,7 +51,7 @@ void launch_fmm_disaggregate(int64_t N, const int64_t* elem_cluster, int nu, con
 // adjoint: loc_n = sum_m conj(D_mn) sig_m over the entries (n, m) of n.
 template <typename T, typename V>
 void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint,
-                          int L, int nu, const V* D, const V* sig, V* loc, hipStream_t st);
+                          int L, int nu, const V* D, const V* sig, V* loc, int tpb, hipStream_t st);
 // Sig_p = sum_children shift * Sig_c (grids coincide)
 template <typename T, typename V>
 void launch_fmm_up_equal(int64_t np, const int64_t* cbeg, const int64_t* cend, int nu, const V* shift,

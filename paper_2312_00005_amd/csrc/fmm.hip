@@ -259,8 +259,8 @@ __global__ __launch_bounds__(256) void k_disaggregate(int64_t N, const int64_t* 
 // slot code[q] >> 1 at node v or, if code[q] & 1, at the antipodal node
 // (t, j) -> (L-1-t, j+L mod 2L).  ADJ: loc_n = sum_q conj(D_(il[q], n)) sig_il[q]:
 // the same slot with the flip inverted.
-template <typename T, typename V, bool ADJ>
-__global__ __launch_bounds__(64) void k_translate(const int64_t* __restrict__ il_off,
+template <typename T, typename V, bool ADJ, int TPB>
+__global__ __launch_bounds__(TPB) void k_translate(const int64_t* __restrict__ il_off,
                                                    const int64_t* __restrict__ il,
                                                    const int64_t* __restrict__ code, int L, int nu,
                                                    const V* __restrict__ D, const V* __restrict__ sig,
@@ -485,16 +485,24 @@ void launch_fmm_disaggregate(int64_t N, const int64_t* ec, int nu, const V* Sm, 
   }
 }
 
+template <typename T, typename V, int TPB>
+void translate_tpb(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint, int L,
+                   int nu, const V* D, const V* sig, V* loc, hipStream_t st) {
+  const dim3 grid(nblk(nu, TPB), (unsigned)nc);
+  if (adjoint)
+    hipLaunchKernelGGL((k_translate<T, V, true, TPB>), grid, dim3(TPB), 0, st, il_off, il, code, L, nu, D, sig, loc);
+  else
+    hipLaunchKernelGGL((k_translate<T, V, false, TPB>), grid, dim3(TPB), 0, st, il_off, il, code, L, nu, D, sig,
+                       loc);
+}
+
 template <typename T, typename V>
 void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint,
-                          int L, int nu, const V* D, const V* sig, V* loc, hipStream_t st) {
+                          int L, int nu, const V* D, const V* sig, V* loc, int tpb, hipStream_t st) {
   if (nc <= 0) return;
-  if (adjoint)
-    hipLaunchKernelGGL((k_translate<T, V, true>), dim3(nblk(nu, 64), (unsigned)nc), dim3(64), 0, st, il_off, il,
-                       code, L, nu, D, sig, loc);
-  else
-    hipLaunchKernelGGL((k_translate<T, V, false>), dim3(nblk(nu, 64), (unsigned)nc), dim3(64), 0, st, il_off, il,
-                       code, L, nu, D, sig, loc);
+  if (tpb == 128) translate_tpb<T, V, 128>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
+  else if (tpb == 256) translate_tpb<T, V, 256>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
+  else translate_tpb<T, V, 64>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
 }
 
 template <typename T, typename V>
@@ -551,7 +559,7 @@ void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const 
   template void launch_fmm_disaggregate<T, V>(int64_t, const int64_t*, int, const V*, const FactorArgs*,      \
                                               const V*, double2*, bool, hipStream_t);                         \
   template void launch_fmm_translate<T, V>(int64_t, const int64_t*, const int64_t*, const int64_t*, bool, int, \
-                                           int, const V*, const V*, V*, hipStream_t);                         \
+                                           int, const V*, const V*, V*, int, hipStream_t);                    \
   template void launch_fmm_up_equal<T, V>(int64_t, const int64_t*, const int64_t*, int, const V*, const V*,   \
                                           V*, hipStream_t);                                                   \
   template void launch_fmm_down_equal<T, V>(int64_t, const int64_t*, int, const V*, const V*, V*,             \

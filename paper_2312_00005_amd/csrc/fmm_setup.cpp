@@ -342,7 +342,7 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
   for (int l = F->top; l < nl; ++l) {
     FmmLevel& L = F->lv[l];
     launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.code.p, false, L.L, L.nu, P::D(L), P::sig(L), P::loc(L),
-                               s);
+                               m->tune_tpb[sizeof(T) == sizeof(float) ? 1 : 0], s);
   }
   for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& Lp = F->lv[l];
@@ -390,7 +390,7 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bo
   for (int l = F->top; l < nl; ++l) {
     FmmLevel& L = F->lv[l];
     launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.code.p, true, L.L, L.nu, P::D(L), P::loc(L), P::sig(L),
-                               s);
+                               m->tune_tpb[sizeof(T) == sizeof(float) ? 1 : 0], s);
   }
   for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& Lp = F->lv[l];

@@ -270,11 +270,12 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
 
 // VMODE: apply dA/dc -- the (G - gamma H') part without c_j, diagonal
 // G_ii - gamma/2 -- instead of A.
-template <typename T, bool HAS_C, bool VMODE>
-__global__ __launch_bounds__(256) void k_near(NearLaunch L, const T* __restrict__ g,
-                                              const double2* __restrict__ x, double2* __restrict__ y) {
+// WPB wavefronts (targets) per workgroup; the launch shape is a tuning choice
+template <typename T, bool HAS_C, bool VMODE, int WPB = 4>
+__global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __restrict__ g,
+                                                   const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t t = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
   if (t >= L.N) return;  // the whole wavefront leaves together
   const int64_t N = L.N;
   T xi[3], ni[3];
@@ -381,6 +382,13 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
   }
 }
 
+template <typename T, int WPB>
+void near_forward(const NearLaunch& L, const T* g, const double2* x, double2* y, hipStream_t s) {
+  dim3 grid((unsigned)((L.N + WPB - 1) / WPB)), block(64 * WPB);
+  if (L.cfac) hipLaunchKernelGGL((k_near<T, true, false, WPB>), grid, block, 0, s, L, g, x, y);
+  else hipLaunchKernelGGL((k_near<T, false, false, WPB>), grid, block, 0, s, L, g, x, y);
+}
+
 template <typename T>
 void near_dispatch(const NearLaunch& L, const T* g, const double2* x, double2* y, hipStream_t s, bool adj,
                    bool vmode) {
@@ -390,8 +398,12 @@ void near_dispatch(const NearLaunch& L, const T* g, const double2* x, double2* y
     if (!adj) hipLaunchKernelGGL((k_near<T, false, true>), grid, block, 0, s, L, g, x, y);
     else hipLaunchKernelGGL((k_near_adj<T, false, true>), grid, block, 0, s, L, g, x, y);
   } else if (!adj) {
-    if (L.cfac) hipLaunchKernelGGL((k_near<T, true, false>), grid, block, 0, s, L, g, x, y);
-    else hipLaunchKernelGGL((k_near<T, false, false>), grid, block, 0, s, L, g, x, y);
+    switch (L.wpb) {
+      case 1: near_forward<T, 1>(L, g, x, y, s); break;
+      case 2: near_forward<T, 2>(L, g, x, y, s); break;
+      case 8: near_forward<T, 8>(L, g, x, y, s); break;
+      default: near_forward<T, 4>(L, g, x, y, s); break;
+    }
   } else {
     if (L.cfac) hipLaunchKernelGGL((k_near_adj<T, true, false>), grid, block, 0, s, L, g, x, y);
     else hipLaunchKernelGGL((k_near_adj<T, false, false>), grid, block, 0, s, L, g, x, y);

@@ -40,6 +40,10 @@ struct bem_mesh {
   bem::DevBuf<double2> d_diag;     // tree order, A_ii
   bem::DevBuf<double2> d_vdiag;    // tree order, diagonal of dA/dc
 
+  // launch shapes chosen by bem_autotune, [0] FP64, [1] complex FP32
+  int tune_wpb[2] = {4, 4};     // near-field targets per workgroup
+  int tune_tpb[2] = {64, 64};   // translation threads per workgroup
+
   // captured operator applications of the Krylov driver, [op][precision]
   struct GraphSlot {
     hipGraphExec_t exec = nullptr;

@@ -42,3 +42,23 @@ def test_graph_solves_match_eager(bem, far_direct, pre):
         assert out[0][1] == out[1][1] and out[0][3] == out[1][3]
         assert np.array_equal(out[0][0], out[1][0])
         assert np.array_equal(out[0][2], out[1][2])
+
+
+def test_autotune_keeps_results(bem):
+    """Every launch shape the tuner may pick gives bit-identical operator
+    applications (one owner per output, fixed summation order)."""
+    announce("autotune ico5 tight")
+    nodes, tris = synth.icosphere(5)
+    k = 2 * math.pi / (6.0 * synth.mean_edge_length(nodes, tris))
+    m = bem.Mesh(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=32)
+    m.set_problem(k)
+    x = to_dev(synth.complex_normal(len(tris), seed=4))
+    before = {p: to_host(m.apply(x, prec=p)) for p in ("fp64", "mixed")}
+    picks = m.autotune()
+    announce(f"  picks {picks}")
+    assert set(picks["near_wpb"].values()) <= {1, 2, 4, 8}
+    assert set(picks["translate_tpb"].values()) <= {64, 128, 256}
+    for p in ("fp64", "mixed"):
+        assert np.array_equal(to_host(m.apply(x, prec=p)), before[p])
+    p1, _, info = m.solve(m.rhs_plane_wave((0.0, 0.0, 1.0)))
+    assert info["rel_residual"] < 1e-6
