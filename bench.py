@@ -68,7 +68,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-NEAR_KERNEL = "k_near<float, false, false>"
+NEAR_KERNEL = "k_near<float, false, false"
 CAL_BYTES = 512 * 2 ** 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json")
 
@@ -289,7 +289,7 @@ def main():
                      "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp32"],
                      "traffic": measured_traffic(),
                      "flops_per_launch": near_flops, "flops_per_point": FLOPS_PER_POINT,
-                     "fp64_kernel": {"kernel": "k_near<double, false, false>",
+                     "fp64_kernel": {"kernel": "k_near<double, false, false",
                                      "achieved": near_flops / res["fp64"]["t_near"] / 1e12,
                                      "peak": PEAK_TFLOPS["fp64"],
                                      "frac": near_flops / res["fp64"]["t_near"] / 1e12 / PEAK_TFLOPS["fp64"]}},
