@@ -36,6 +36,9 @@ __constant__ int c_rule_off[kMaxRuleOrder + 1];
 // weights divided by 4 pi (the Green's function's factor folded in)
 __constant__ double c_rule_ws[kRulePoints];
 __constant__ float c_rule_ws32[kRulePoints];
+// 2/pi, C1, C2, C3 (pi/2 in three parts), the sin coefficients 1/17! ... -1/3!
+// (highest first), the cos coefficients 1/16! ... -1/2!
+__constant__ double c_sincos[4 + 8 + 8];
 
 void upload_rule_tables(const double* a, const double* b, const double* w, const int* off) {
   float a32[kRulePoints], b32[kRulePoints], w32[kRulePoints], ws32[kRulePoints];
@@ -48,6 +51,14 @@ void upload_rule_tables(const double* a, const double* b, const double* w, const
     ws32[i] = (float)ws[i];
   }
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_ws), ws, sizeof(double) * kRulePoints);
+  // sin/cos reduction: pi/2 split into three parts, the first two with 20
+  // significant bits so that n*C1 and n*C2 are exact; Taylor coefficients
+  const double sc[20] = {0.6366197723675814, 1.5707950592041016, 1.2675900507019833e-06, 7.443547480486623e-13,
+                         1.0 / 355687428096000.0, -1.0 / 1307674368000.0, 1.0 / 6227020800.0,
+                         -1.0 / 39916800.0, 1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,
+                         1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
+                         -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5};
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_sincos), sc, sizeof(sc));
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_ws32), ws32, sizeof(float) * kRulePoints);
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a), a, sizeof(double) * kRulePoints);
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b), b, sizeof(double) * kRulePoints);
@@ -84,33 +95,25 @@ template <> struct RuleTab<float> {
 // n*C2 are exact), then the Taylor series of sin and cos on [-pi/4, pi/4]
 // truncated after the 1/17! and 1/16! terms (truncation error < 5e-17).  The
 // near-field phases kr are far below the range limit.
+// The constants of sincos_cw live in constant memory (c_sincos) rather than
+// as literals so that the compiler keeps them in scalar registers across the
+// point loop instead of re-materialising 64-bit immediates for every point.
 __device__ inline void sincos_cw(double x, double* s, double* c) {
-  constexpr double kTwoOverPi = 0.6366197723675814;
-  constexpr double C1 = 1.5707950592041016, C2 = 1.2675900507019833e-06, C3 = 7.443547480486623e-13;
-  const double n = rint(x * kTwoOverPi);
-  double y = fma(-n, C1, x);
-  y = fma(-n, C2, y);
-  y = fma(-n, C3, y);
+  const double* K = c_sincos;
+  const double n = rint(x * K[0]);
+  double y = fma(-n, K[1], x);
+  y = fma(-n, K[2], y);
+  y = fma(-n, K[3], y);
   const double z = y * y;
   // sin y = y (1 - z/3! + z^2/5! - ... - z^7/15! + z^8/17!)
-  double ps = 1.0 / 355687428096000.0;
-  ps = fma(ps, z, -1.0 / 1307674368000.0);
-  ps = fma(ps, z, 1.0 / 6227020800.0);
-  ps = fma(ps, z, -1.0 / 39916800.0);
-  ps = fma(ps, z, 1.0 / 362880.0);
-  ps = fma(ps, z, -1.0 / 5040.0);
-  ps = fma(ps, z, 1.0 / 120.0);
-  ps = fma(ps, z, -1.0 / 6.0);
+  double ps = K[4];
+#pragma unroll
+  for (int i = 5; i < 12; ++i) ps = fma(ps, z, K[i]);
   const double sy = fma(y * z, ps, y);
   // cos y = 1 - z/2! + z^2/4! - ... + z^8/16!
-  double pc = 1.0 / 20922789888000.0;
-  pc = fma(pc, z, -1.0 / 87178291200.0);
-  pc = fma(pc, z, 1.0 / 479001600.0);
-  pc = fma(pc, z, -1.0 / 3628800.0);
-  pc = fma(pc, z, 1.0 / 40320.0);
-  pc = fma(pc, z, -1.0 / 720.0);
-  pc = fma(pc, z, 1.0 / 24.0);
-  pc = fma(pc, z, -0.5);
+  double pc = K[12];
+#pragma unroll
+  for (int i = 13; i < 20; ++i) pc = fma(pc, z, K[i]);
   const double cy = fma(z, pc, 1.0);
   const int q = ((int)n) & 3;
   const double a = (q & 1) ? cy : sy;
