@@ -162,9 +162,23 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
     L.seg = m->d_seg_t.p;
     L.items = m->d_items_t.p;
   }
+  if (part == 0 && m->fmm) {
+    // fork: far field into d_far on the side stream, near field into y on s
+    // (stream, events and buffer are made with the mesh: nothing here may
+    // allocate, so that the sequence can be captured)
+    BEM_HIP(hipEventRecord(m->ev_fork, s));
+    BEM_HIP(hipStreamWaitEvent(m->side_stream, m->ev_fork, 0));
+    launch_zero(m->N, m->d_far.p, m->side_stream);
+    far_apply(m, op, prec, x, m->d_far.p, m->side_stream, vmode);
+    BEM_HIP(hipEventRecord(m->ev_join, m->side_stream));
+    launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
+    BEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
+    launch_axpby(m->N, make_double2(1, 0), y, make_double2(1, 0), m->d_far.p, y, s);
+    BEM_HIP(hipGetLastError());
+    return;
+  }
   launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
   BEM_HIP(hipGetLastError());
-  if (part == 0) far_apply(m, op, prec, x, y, s, vmode);
 }
 
 void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s, bool vmode) {
@@ -508,6 +522,12 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_diag.alloc(n_tri);
     m->d_vdiag.alloc(n_tri);
     if (o->precond) build_blocks(m.get(), o->precond == 1 ? kMaxBlock : 1);
+    if (m->fmm) {
+      BEM_HIP(hipStreamCreateWithFlags(&m->side_stream, hipStreamNonBlocking));
+      BEM_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+      BEM_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
+      m->d_far.alloc(n_tri);
+    }
     if (m->far_direct) build_far_direct(m.get());
     BEM_HIP(hipStreamSynchronize(s));
     *out = m.release();
@@ -885,7 +905,7 @@ size_t bem_workspace_bytes(const bem_mesh* m) {
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
              m->d_partial.bytes() + m->d_h.bytes() + m->d_z.bytes() + m->d_elem_blk.bytes() +
              m->d_blk_n.bytes() + m->d_blk_sing.bytes() + m->d_blk_beg.bytes() + m->d_blk_off.bytes() +
-             m->d_blk_a.bytes() + m->d_blk_inv.bytes();
+             m->d_blk_a.bytes() + m->d_blk_inv.bytes() + m->d_far.bytes();
   return b + fmm_bytes(m);
 }
 

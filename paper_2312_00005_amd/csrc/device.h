@@ -132,6 +132,8 @@ void launch_reduce_partials(int nv, int nblk, const double2* partial, double2* h
 void launch_multiaxpy(int64_t N, int nv, const double2* V, int64_t ldv, const double2* h,
                       double sign, double2* w, hipStream_t s);
 void launch_scale_copy(int64_t N, const double2* w, double2 alpha, double2* out, hipStream_t s);
+// out = 0 (a kernel, so that it can sit in a captured graph)
+void launch_zero(int64_t N, double2* out, hipStream_t s);
 void launch_axpby(int64_t N, double2 a, const double2* x, double2 b, const double2* y, double2* out,
                   hipStream_t s);
 int multidot_blocks(int64_t N);

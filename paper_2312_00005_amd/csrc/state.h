@@ -55,6 +55,12 @@ struct bem_mesh {
   uint64_t problem_stamp = 0;   // bumped by every bem_set_problem
   hipStream_t cap_stream = nullptr;
 
+  // the far field runs on a second stream, concurrently with the near field
+  // (into d_far), and is added after both finish
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bem::DevBuf<double2> d_far;
+
   // direct far field (far_direct option)
   bool far_direct = false;
   bem::DevBuf<int32_t> d_elem_leaf;
@@ -83,6 +89,9 @@ struct bem_mesh {
       for (auto& gs : row)
         if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     bem::fmm_destroy(fmm_state);
   }
 };
