@@ -541,15 +541,18 @@ template <typename T, typename V>
 void launch_fmm_up_idft(int64_t np, const int64_t* cbeg, const int64_t* cend, int nt, int nj, int nm,
                         const V* G, const V* E, const V* shift, V* sigp, hipStream_t st) {
   if (np <= 0 || nt <= 0) return;
-  hipLaunchKernelGGL((k_up_idft<T, V>), dim3((unsigned)nt, (unsigned)np), dim3(128), 0, st, cbeg, cend, nt, nj, nm,
-                     G, E, shift, sigp);
+  // one wavefront covers nj <= 64; the kernel walks two chunks of blockDim
+  const unsigned threads = nj <= 64 ? 64 : 128;
+  hipLaunchKernelGGL((k_up_idft<T, V>), dim3((unsigned)nt, (unsigned)np), dim3(threads), 0, st, cbeg, cend, nt, nj,
+                     nm, G, E, shift, sigp);
 }
 
 template <typename T, typename V>
 void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const V* E, V* locc,
                           hipStream_t st) {
   if (nc <= 0 || nt <= 0) return;
-  hipLaunchKernelGGL((k_down_idft<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(128), 0, st, nt, nj, nm, K, E,
+  const unsigned threads = nj <= 64 ? 64 : 128;
+  hipLaunchKernelGGL((k_down_idft<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(threads), 0, st, nt, nj, nm, K, E,
                      locc);
 }
 
