@@ -47,7 +47,7 @@ class FrequencySweep:
     """Solve the exterior problem at every frequency of ``freqs`` on one mesh."""
 
     def __init__(self, nodes, tris, freqs, c=343.0, preset="mixed", depths=(4, 3, 2), leaf_size=32,
-                 memory_budget=96e9, max_L=120, streams=2, **overrides):
+                 memory_budget=96e9, max_L=120, streams=1, **overrides):
         self.nodes, self.tris = nodes, tris
         self.freqs = list(freqs)
         self.ks = wavenumbers(self.freqs, c)
