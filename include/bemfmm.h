@@ -229,6 +229,7 @@ bem_status bem_incident_field(bem_mesh* m, int kind, const double src[3],
  *   p_surf : device bem_c128[n_tri]; p_inc: device bem_c128[n_pts] or NULL
  *   p_out  : device bem_c128[n_pts]
  *   energy : device double[1] receiving sum_f |p_out[f]|^2, or NULL
+ * n_pts = 0 is allowed (pts, p_inc, p_out may then be NULL; energy = 0).
  * BEM_E_MESH if a point is so close to an element that subdivision overflows. */
 bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts,
                      const bem_c128* p_surf, const bem_c128* p_inc,

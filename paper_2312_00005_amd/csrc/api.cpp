@@ -765,9 +765,12 @@ void check_field_error(bem_mesh* m, DevBuf<int64_t>& err, hipStream_t s) {
 bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c128* p_surf,
                      const bem_c128* p_inc, bem_c128* p_out, double* energy, void* stream) {
   return guarded([&]() -> bem_status {
-    if (!m || !pts || !p_surf || !p_out || n_pts < 0) return fail(BEM_E_ARG, "NULL argument");
+    if (!m || !p_surf || n_pts < 0 || (n_pts > 0 && (!pts || !p_out))) return fail(BEM_E_ARG, "NULL argument");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
-    if (n_pts == 0) return BEM_OK;
+    if (n_pts == 0) {
+      if (energy) BEM_HIP(hipMemsetAsync(energy, 0, sizeof(double), as_stream(stream)));
+      return BEM_OK;
+    }
     hipStream_t s = as_stream(stream);
     DevBuf<int64_t> err;
     err.upload(std::vector<int64_t>{-1}, s);
@@ -784,7 +787,7 @@ bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c1
 bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c128* g, int part,
                              bem_c128* y_surf, void* stream) {
   return guarded([&]() -> bem_status {
-    if (!m || !pts || !g || !y_surf || n_pts < 0) return fail(BEM_E_ARG, "NULL argument");
+    if (!m || !y_surf || n_pts < 0 || (n_pts > 0 && (!pts || !g))) return fail(BEM_E_ARG, "NULL argument");
     if (part != 0 && part != 1) return fail(BEM_E_ARG, "part must be 0 or 1");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
     hipStream_t s = as_stream(stream);
