@@ -278,7 +278,9 @@ template <typename T, bool HAS_C, bool VMODE, int WPB = 4>
 __global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __restrict__ g,
                                                    const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+  // the target is uniform across the wavefront: say so, so that its data go
+  // through scalar loads and registers
+  const int64_t t = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (t >= L.N) return;  // the whole wavefront leaves together
   const int64_t N = L.N;
   T xi[3], ni[3];
@@ -332,7 +334,7 @@ template <typename T, bool HAS_C, bool VMODE>
 __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restrict__ g,
                                                   const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
-  const int64_t jsrc = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t jsrc = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (jsrc >= L.N) return;
   const int64_t N = L.N;
   const T k = (T)L.k, gre = (T)L.gre, gim = (T)L.gim;
@@ -580,7 +582,7 @@ template <typename T, bool HAS_C, bool VMODE, bool ADJ>
 __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* __restrict__ x,
                                                     double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (r >= F.N) return;
   const int64_t N = F.N;
   const T* g = far_geom<T>(F);
@@ -674,7 +676,7 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
 template <bool HAS_C>
 __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs B, double2* __restrict__ a) {
   const int lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (t >= L.N) return;
   const int64_t N = L.N;
   const double* g = L.geom;
