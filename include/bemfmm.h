@@ -136,6 +136,12 @@ typedef struct bem_options {
                                operator application (near field and far field
                                kernels) of each GMRES iteration as a captured
                                HIP graph; recaptured after bem_set_problem */
+  int32_t level_rows;       /* far-field level transfer: 0 = band-limited
+                               interpolation / anterpolation between levels
+                               (leaf rows only); 1 = the paper's explicit
+                               element-to-cluster rows T(l), S(l) stored on
+                               every level with interaction pairs (Sec. 3.3.4;
+                               memory N * sum_l 2 L_l^2 per row set) */
 } bem_options;
 
 typedef struct bem_solve_info {

@@ -353,7 +353,8 @@ def anterpolation_matrix(Lp, Lc):
 class FMM:
     """Far-field operator of the multilevel FMM in plain steps."""
 
-    def __init__(self, geom, k, p, levels, leaf_size, beta=None, gamma=None, tree=None, single=False):
+    def __init__(self, geom, k, p, levels, leaf_size, beta=None, gamma=None, tree=None, single=False,
+                 level_rows=False):
         self.geom = geom
         self.k = k
         self.p = p
@@ -369,14 +370,18 @@ class FMM:
                   truncation_length(k, float(Lv["r"].max()), p, level_min_separation(Lv), single)
                   for l, Lv in enumerate(self.tree.levels)]
         self.grids = [sphere_grid(L) if L > 0 else None for L in self.L]
+        # level_rows: the paper's variant -- every level aggregates from and
+        # disaggregates to the elements with its own rows T(l), S(l)
+        # (Sec. 3.3.4), no interpolation between levels
+        self.level_rows = level_rows
 
-    def leaf_signature_matrix(self, c_idx):
-        """Rows nu, columns the elements of leaf cluster c: T_nu_j (c_j + ik s.n_j)."""
-        leaf = self.tree.levels[-1]
+    def signature_matrix(self, l, c_idx):
+        """Rows nu, columns the elements of cluster c on level l: T_nu_j (c_j + ik s.n_j)."""
+        Lv = self.tree.levels[l]
         g = self.geom
-        els = leaf["groups"][c_idx]
-        z = leaf["z"][c_idx]
-        s, _, _, _ = self.grids[-1]
+        els = Lv["groups"][c_idx]
+        z = Lv["z"][c_idx]
+        s, _, _, _ = self.grids[l]
         a, b, w = conical(self.p["t_order"])
         P0, P1, P2 = g["P0"][els], g["P1"][els], g["P2"][els]
         y = (P0[:, None, :] + a[None, :, None] * (P1 - P0)[:, None, :]
@@ -387,20 +392,52 @@ class FMM:
         fac = self.c[els][None, :] + 1j * self.k * (s @ g["n"][els].T)
         return T * fac
 
-    def leaf_distribution_matrix(self, c_idx):
-        """Rows the elements of leaf cluster c, columns nu:
+    def distribution_matrix(self, l, c_idx):
+        """Rows the elements of cluster c on level l, columns nu:
         ik/(16 pi^2) w_nu (1 - gamma ik s.n_i) exp(ik (x_i - z).s)."""
-        leaf = self.tree.levels[-1]
+        Lv = self.tree.levels[l]
         g = self.geom
-        els = leaf["groups"][c_idx]
-        z = leaf["z"][c_idx]
-        s, w, _, _ = self.grids[-1]
+        els = Lv["groups"][c_idx]
+        z = Lv["z"][c_idx]
+        s, w, _, _ = self.grids[l]
         k = self.k
         S = np.exp(1j * k * ((g["x"][els] - z) @ s.T))
         fac = 1.0 - self.gamma * 1j * k * (g["n"][els] @ s.T)
         return (1j * k / (16 * math.pi ** 2)) * w[None, :] * fac * S
 
+    def leaf_signature_matrix(self, c_idx):
+        return self.signature_matrix(len(self.tree.levels) - 1, c_idx)
+
+    def leaf_distribution_matrix(self, c_idx):
+        return self.distribution_matrix(len(self.tree.levels) - 1, c_idx)
+
+    def _translate(self, l, sig):
+        Lv = self.tree.levels[l]
+        s = self.grids[l][0]
+        out = np.zeros_like(sig)
+        pm = np.array([m for m in range(len(Lv["groups"])) for _ in Lv["il"][m]], dtype=np.int64)
+        pn = np.array([n for m in range(len(Lv["groups"])) for n in Lv["il"][m]], dtype=np.int64)
+        for b in range(0, pm.size, 2000):
+            m_, n_ = pm[b:b + 2000], pn[b:b + 2000]
+            D = translations(self.k, Lv["z"][m_] - Lv["z"][n_], s, self.L[l])
+            np.add.at(out, m_, D * sig[n_])
+        return out
+
+    def _apply_level_rows(self, x):
+        y = np.zeros(x.shape[0], dtype=np.complex128)
+        for l in range(self.top, len(self.tree.levels)):
+            Lv = self.tree.levels[l]
+            if not any(len(q) for q in Lv["il"]):
+                continue
+            sig = np.stack([self.signature_matrix(l, c) @ x[g] for c, g in enumerate(Lv["groups"])])
+            loc = self._translate(l, sig)
+            for c, g in enumerate(Lv["groups"]):
+                y[g] += self.distribution_matrix(l, c) @ loc[c]
+        return y
+
     def apply(self, x):
+        if self.level_rows:
+            return self._apply_level_rows(x)
         tr = self.tree
         nl = len(tr.levels)
         k = self.k

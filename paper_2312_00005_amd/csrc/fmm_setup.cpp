@@ -39,6 +39,11 @@ struct FmmLevel {
   DevBuf<double2> sig64, loc64;
   DevBuf<float2> sig32, loc32;
   DevBuf<int64_t> cbeg, cend, parent;
+  // element-to-cluster rows of this level (level_rows option): element ranges
+  // of the clusters, element -> cluster map, T'/S' rows on this level's grid
+  DevBuf<int64_t> ebeg, eend, ec;
+  DevBuf<double2> T64, S64;
+  DevBuf<float2> T32, S32;
   // transition from the children (next level) to this level's grid
   DevBuf<double2> shift64;
   DevBuf<float2> shift32;
@@ -234,6 +239,14 @@ void upload_tree(bem_mesh* m, FmmState* F, hipStream_t s) {
       upload_vec(D.cbeg, L.cbeg, s);
       upload_vec(D.cend, L.cend, s);
     }
+    if (m->opt.level_rows) {
+      upload_vec(D.ebeg, L.ebeg, s);
+      upload_vec(D.eend, L.eend, s);
+      std::vector<int64_t> lec(m->N, 0);
+      for (int64_t c = 0; c < L.nc; ++c)
+        for (int64_t e = L.ebeg[c]; e < L.eend[c]; ++e) lec[e] = c;
+      upload_vec(D.ec, lec, s);
+    }
   }
   const Level& leaf = T.lv.back();
   upload_vec(F->leaf_ebeg, leaf.ebeg, s);
@@ -284,6 +297,8 @@ struct Pick<double2> {
   static double2* EpcT(FmmLevel& l) { return l.EpcT64.p; }
   static double2* T(FmmSet* f) { return f->T64.p; }
   static double2* S(FmmSet* f) { return f->S64.p; }
+  static double2* Tl(FmmLevel& l) { return l.T64.p; }
+  static double2* Sl(FmmLevel& l) { return l.S64.p; }
 };
 template <>
 struct Pick<float2> {
@@ -305,6 +320,8 @@ struct Pick<float2> {
   static float2* EpcT(FmmLevel& l) { return l.EpcT32.p; }
   static float2* T(FmmSet* f) { return f->T32.p; }
   static float2* S(FmmSet* f) { return f->S32.p; }
+  static float2* Tl(FmmLevel& l) { return l.T32.p; }
+  static float2* Sl(FmmLevel& l) { return l.S32.p; }
 };
 
 FactorArgs factor_args(bem_mesh* m, const FmmLevel& leaf) {
@@ -325,6 +342,21 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
   const int nl = (int)F->lv.size();
   FmmLevel& leaf = F->lv[nl - 1];
   const FactorArgs fa = factor_args(m, leaf);
+  if (m->opt.level_rows) {
+    // every level straight from and to the elements: sig_l = T'_l x, loc_l = D_l sig_l, y += S'_l loc_l
+    for (int l = F->top; l < nl; ++l) {
+      FmmLevel& L = F->lv[l];
+      if (L.npairs == 0) continue;
+      const FactorArgs fl = factor_args(m, L);
+      launch_fmm_aggregate<T, V>(L.nc, L.ebeg.p, L.eend.p, L.nu, P::Tl(L), vmode ? nullptr : &fl, x, P::sig(L), false,
+                                 s);
+      launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.code.p, false, L.L, L.nu, P::D(L), P::sig(L), P::loc(L),
+                                 m->tune_tpb[sizeof(T) == sizeof(float) ? 1 : 0], s);
+      launch_fmm_disaggregate<T, V>(m->N, L.ec.p, L.nu, P::Sl(L), nullptr, P::loc(L), y, false, s);
+    }
+    BEM_HIP(hipGetLastError());
+    return;
+  }
   launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::T(F), vmode ? nullptr : &fa, x,
                              P::sig(leaf), false, s);
   for (int l = nl - 2; l >= F->top; --l) {
@@ -372,6 +404,20 @@ void fmm_apply_adj_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bo
   FmmSet* F = &FS->set[sizeof(T) == sizeof(float) ? 1 : 0];
   const int nl = (int)F->lv.size();
   FmmLevel& leaf = F->lv[nl - 1];
+  if (m->opt.level_rows) {
+    // conjugate transpose of each level: loc'_l = S'_l^H x, sig'_l = D_l^H loc'_l, y += T'_l^H sig'_l
+    for (int l = F->top; l < nl; ++l) {
+      FmmLevel& L = F->lv[l];
+      if (L.npairs == 0) continue;
+      const FactorArgs fl = factor_args(m, L);
+      launch_fmm_aggregate<T, V>(L.nc, L.ebeg.p, L.eend.p, L.nu, P::Sl(L), nullptr, x, P::loc(L), true, s);
+      launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.code.p, true, L.L, L.nu, P::D(L), P::loc(L), P::sig(L),
+                                 m->tune_tpb[sizeof(T) == sizeof(float) ? 1 : 0], s);
+      launch_fmm_disaggregate<T, V>(m->N, L.ec.p, L.nu, P::Tl(L), vmode ? nullptr : &fl, P::sig(L), y, true, s);
+    }
+    BEM_HIP(hipGetLastError());
+    return;
+  }
   const FactorArgs fa = factor_args(m, leaf);
   launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::S(F), nullptr, x, P::loc(leaf),
                              true, s);
@@ -469,7 +515,7 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     launch_fmm_translation(D.npairs, D.pm.p, D.pn.p, D.z.p, D.s.p, D.nu, D.L, k, single ? nullptr : D.D64.p,
                            single ? D.D32.p : nullptr, s);
   }
-  for (int l = F->top; l + 1 < nl; ++l) {
+  for (int l = F->top; l + 1 < nl && !o.level_rows; ++l) {
     FmmLevel& P = F->lv[l];
     FmmLevel& C = F->lv[l + 1];
     if (single) P.shift32.alloc(C.nc * P.nu);
@@ -563,6 +609,27 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     // the uploads read host vectors that go out of scope: finish them first
     BEM_HIP(hipStreamSynchronize(s));
   }
+  if (o.level_rows) {
+    // the paper's explicit element-to-cluster rows on every level with pairs
+    for (int l = F->top; l < nl; ++l) {
+      FmmLevel& L = F->lv[l];
+      if (L.npairs == 0) continue;
+      if (single) {
+        L.T32.alloc(m->N * L.nu);
+        L.S32.alloc(m->N * L.nu);
+      } else {
+        L.T64.alloc(m->N * L.nu);
+        L.S64.alloc(m->N * L.nu);
+      }
+      launch_fmm_leaf_T(m->N, m->d_geom.p, L.ec.p, L.z.p, L.s.p, L.nu, nullptr, k, FS->ra.p, FS->rb.p, FS->rw.p,
+                        FS->nq, single ? nullptr : L.T64.p, single ? L.T32.p : nullptr, s);
+      launch_fmm_leaf_S(m->N, m->d_geom.p, L.ec.p, L.z.p, L.s.p, L.w.p, L.nu, k, m->gre, m->gim,
+                        single ? nullptr : L.S64.p, single ? L.S32.p : nullptr, s);
+    }
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(s));
+    return;
+  }
   FmmLevel& leaf = F->lv[nl - 1];
   if (single) {
     F->T32.alloc(m->N * leaf.nu);
@@ -620,7 +687,8 @@ size_t fmm_bytes(const bem_mesh* m) {
     b += L.D64.bytes() + L.D32.bytes() + L.sig64.bytes() + L.loc64.bytes() + L.sig32.bytes() + L.loc32.bytes() +
          L.shift64.bytes() + L.shift32.bytes() + L.Mi64.bytes() + L.Ma64.bytes() + L.Mi32.bytes() +
          L.Ma32.bytes() + L.MiT64.bytes() + L.MaT64.bytes() + L.MiT32.bytes() + L.MaT32.bytes() +
-         L.tA64.bytes() + L.tB64.bytes() + L.tA32.bytes() + L.tB32.bytes();
+         L.tA64.bytes() + L.tB64.bytes() + L.tA32.bytes() + L.tB32.bytes() + L.T64.bytes() + L.S64.bytes() +
+         L.T32.bytes() + L.S32.bytes() + L.ec.bytes();
   }
   return b;
 }
@@ -656,7 +724,7 @@ FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options&
       const double nu = 2.0 * lc * lc;
       const double b = single ? 8.0 : 16.0;
       I.bytes += b * nu * (0.5 * (double)L.il.size() + 2.0 * (double)L.nc);
-      if (l == nl - 1) I.bytes += 2.0 * b * nu * (double)N;
+      if (l == nl - 1 || (o.level_rows && !L.il.empty())) I.bytes += 2.0 * b * nu * (double)N;
     }
   }
   return I;

@@ -207,3 +207,41 @@ def test_conjugate_transpose_dot_product(bem, subdiv, levels, epw):
             lhs = np.vdot(y, Ax)
             rhs = np.vdot(AHy, x)
             assert abs(lhs - rhs) < tol * np.linalg.norm(Ax) * np.linalg.norm(y), (prec, part, lhs, rhs)
+
+
+@pytest.mark.parametrize("with_beta", [False, True])
+def test_level_rows_far_field_matches_oracle(bem, with_beta):
+    """The paper's level transfer (level_rows = 1: element-to-cluster rows on
+    every level with interaction pairs) against the oracle's same variant,
+    FP64 and complex FP32, its conjugate transpose by the dot-product
+    identity, and the whole operator against the interpolating variant (both
+    approximate the same far field to the expansion accuracy)."""
+    announce(f"level rows ico4 levels=3 beta={with_beta}")
+    nodes, tris = synth.icosphere(4)
+    g = element_geometry(nodes, tris)
+    N = len(tris)
+    k = _k(nodes, tris, 6.0)
+    beta = (1.0 + 0.5 * synth.uniform01(N, seed=1)) + 0.1j if with_beta else None
+    p = preset("tight")
+    F = ofmm.FMM(g, k, p, 3, 32, beta=beta, level_rows=True)
+    assert sum(1 for L in F.tree.levels if any(len(il) for il in L["il"])) >= 2
+    x = synth.complex_normal(N, seed=4)
+    y_or = F.apply(x)
+    m = bem.Mesh(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=32, level_rows=1)
+    m.set_problem(k, None if beta is None else to_dev(beta))
+    xd = to_dev(x)
+    amp = _amplification(F, k)
+    tol = max(1e-11, 10 * 2.2e-16 * amp)
+    assert rel_max(to_host(m.apply_part(xd, 2)), y_or) < tol
+    F32 = ofmm.FMM(g, k, p, 3, 32, beta=beta, tree=F.tree, single=True, level_rows=True)
+    tol32 = max(3e-5, 10 * 2.0 ** -23 * _amplification(F32, k))
+    assert rel_max(to_host(m.apply_part(xd, 2, prec="mixed")), F32.apply(x)) < tol32
+    yv = synth.complex_normal(N, seed=6)
+    Ax = to_host(m.apply(xd))
+    AHy = to_host(m.apply(to_dev(yv), op="AH"))
+    assert abs(np.vdot(yv, Ax) - np.vdot(AHy, x)) < tol * np.linalg.norm(Ax) * np.linalg.norm(yv)
+    mi = bem.Mesh(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=32)
+    mi.set_problem(k, None if beta is None else to_dev(beta))
+    d = rel_l2(Ax, to_host(mi.apply(xd)))
+    announce(f"  L={F.L} level rows vs interpolation: {d:.2e}")
+    assert d < 1e-6
