@@ -142,6 +142,10 @@ typedef struct bem_options {
                                element-to-cluster rows T(l), S(l) stored on
                                every level with interaction pairs (Sec. 3.3.4;
                                memory N * sum_l 2 L_l^2 per row set) */
+  int32_t solver;           /* 0: restarted GMRES (CGS2 orthogonalisation);
+                               1: conjugate gradient squared, the paper's
+                               iterative solver (Sec. 3.2); both right
+                               preconditioned, gmres_maxit caps iterations */
 } bem_options;
 
 typedef struct bem_solve_info {

@@ -61,6 +61,7 @@ class bem_options(ctypes.Structure):
         ("l_eps_mixed", ctypes.c_double), ("precond", ctypes.c_int32),
         ("gamma_re", ctypes.c_double), ("gamma_im_k", ctypes.c_double),
         ("far_direct", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("level_rows", ctypes.c_int32),
+        ("solver", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -122,6 +122,7 @@ void check_options(const bem_options* o) {
   if (o->far_direct != 0 && o->far_direct != 1) throw Error(BEM_E_ARG, "far_direct must be 0 or 1");
   if (o->use_graphs != 0 && o->use_graphs != 1) throw Error(BEM_E_ARG, "use_graphs must be 0 or 1");
   if (o->level_rows != 0 && o->level_rows != 1) throw Error(BEM_E_ARG, "level_rows must be 0 or 1");
+  if (o->solver != 0 && o->solver != 1) throw Error(BEM_E_ARG, "solver must be 0 (GMRES) or 1 (CGS)");
   if (o->far_direct && !o->use_fmm) throw Error(BEM_E_ARG, "far_direct needs the cluster tree (use_fmm = 1)");
   if (!std::isfinite(o->gamma_re) || !std::isfinite(o->gamma_im_k) || o->gamma_im_k == 0.0)
     throw Error(BEM_E_ARG, "the coupling needs a finite gamma with a non-zero imaginary part");

@@ -183,12 +183,97 @@ int gmres(bem_mesh* m, bem_op op, bem_precision prec, const double2* b, double2*
   }
 }
 
+// Conjugate gradient squared (the paper's iterative solver, Sec. 3.2), right
+// preconditioned like GMRES: on A M y = b with x = M y,
+//   r = b - A x, rh = r, u = p = r, rho = (rh, r);
+//   v = A M p, alpha = rho / (rh, v), q = u - alpha v, w = u + q,
+//   x += alpha M w, r -= alpha A M w, rho' = (rh, r), beta = rho'/rho,
+//   u = r + beta q, p = u + beta (q + beta p).
+// Two operator applications per iteration; stops on the residual norm, after
+// maxit iterations, or on a breakdown (rho or (rh, v) zero).
+int cgs(bem_mesh* m, bem_op op, bem_precision prec, const double2* b, double2* x, bool x_zero, double tol_abs,
+        int maxit, const Work& W, hipStream_t s, bool* converged) {
+  const int64_t N = W.N;
+  double2* V = m->d_V.p;
+  double2* rh = V;             // rh and r adjacent: one pass gives (rh, r) and (r, r)
+  double2* r = V + N;
+  double2* u = V + 2 * N;
+  double2* p = V + 3 * N;
+  double2* q = V + 4 * N;
+  double2* v = V + 5 * N;
+  double2* w = V + 6 * N;
+  double2* z = m->d_z.p;
+  double2* dh = m->d_h.p;
+  *converged = false;
+  auto dots = [&](int nv, const double2* vecs, const double2* with, double2* out) {
+    launch_multidot(N, nv, vecs, N, with, m->d_partial.p, W.nblk, s);
+    launch_reduce_partials(nv, W.nblk, m->d_partial.p, dh, s);
+    BEM_HIP(hipMemcpyAsync(out, dh, nv * sizeof(double2), hipMemcpyDeviceToHost, s));
+    BEM_HIP(hipStreamSynchronize(s));
+  };
+  auto apply_m = [&](const double2* in, double2* out) {  // out = A M in
+    precondition(m, op, in, z, s);
+    apply_iter(m, op, prec, z, out, s);
+  };
+  if (x_zero) {
+    BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
+    BEM_HIP(hipMemcpyAsync(r, b, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  } else {
+    apply_tree(m, op, prec, x, w, s);
+    launch_axpby(N, make_double2(1, 0), b, make_double2(-1, 0), w, r, s);
+  }
+  BEM_HIP(hipMemcpyAsync(rh, r, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  BEM_HIP(hipMemcpyAsync(u, r, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  BEM_HIP(hipMemcpyAsync(p, r, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  double2 hr[2];
+  dots(2, rh, r, hr);
+  cd rho(hr[0].x, hr[0].y);
+  if (std::sqrt(std::max(0.0, hr[1].x)) <= tol_abs) {
+    *converged = true;
+    return 0;
+  }
+  int it = 0;
+  while (it < maxit) {
+    ++it;
+    apply_m(p, v);
+    double2 sv;
+    dots(1, rh, v, &sv);
+    const cd sigma(sv.x, sv.y);
+    if (sigma == cd(0.0) || rho == cd(0.0)) break;
+    const cd alpha = rho / sigma;
+    const double2 a2 = make_double2(alpha.real(), alpha.imag());
+    // q = u - alpha v, w = u + q
+    launch_axpby(N, make_double2(1, 0), u, make_double2(-a2.x, -a2.y), v, q, s);
+    launch_axpby(N, make_double2(1, 0), u, make_double2(1, 0), q, w, s);
+    // x += alpha M w; r -= alpha A M w  (v is free again: it holds A M w)
+    precondition(m, op, w, z, s);
+    launch_axpby(N, make_double2(1, 0), x, a2, z, x, s);
+    apply_iter(m, op, prec, z, v, s);
+    launch_axpby(N, make_double2(1, 0), r, make_double2(-a2.x, -a2.y), v, r, s);
+    dots(2, rh, r, hr);
+    if (std::sqrt(std::max(0.0, hr[1].x)) <= tol_abs) {
+      *converged = true;
+      break;
+    }
+    const cd rho_new(hr[0].x, hr[0].y);
+    const cd beta = rho_new / rho;
+    rho = rho_new;
+    const double2 b2 = make_double2(beta.real(), beta.imag());
+    // u = r + beta q; p = u + beta (q + beta p)
+    launch_axpby(N, make_double2(1, 0), r, b2, q, u, s);
+    launch_axpby(N, make_double2(1, 0), q, b2, p, p, s);
+    launch_axpby(N, make_double2(1, 0), u, b2, p, p, s);
+  }
+  BEM_HIP(hipStreamSynchronize(s));
+  return it;
+}
+
 }  // namespace
 
 SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s, bem_op op) {
   const int64_t N = m->N;
   Work W{N, std::max(1, std::min(m->opt.gmres_restart, 200)), multidot_blocks(N)};
-  m->d_V.alloc((size_t)(W.restart + 1) * N);
+  m->d_V.alloc((size_t)std::max(W.restart + 1, 8) * N);
   m->d_w.alloc(N);
   m->d_r.alloc(N);
   m->d_tmp.alloc(N);
@@ -196,6 +281,7 @@ SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s,
   m->d_partial.alloc((size_t)(W.restart + 1) * W.nblk + 8);
   m->d_h.alloc(2 * (W.restart + 1) + 8);
   SolveResult out;
+  auto krylov = m->opt.solver == 1 ? cgs : gmres;
   const double bnorm = vec_norm(m, b, W, s);
   if (bnorm == 0.0) {
     BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
@@ -205,7 +291,7 @@ SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s,
   const double tol = m->opt.gmres_tol;
   if (m->opt.precision == BEM_PREC_FP64) {
     bool conv = false;
-    out.iterations = gmres(m, op, BEM_PREC_FP64, b, x, true, tol * bnorm, m->opt.gmres_maxit, W, s, &conv);
+    out.iterations = krylov(m, op, BEM_PREC_FP64, b, x, true, tol * bnorm, m->opt.gmres_maxit, W, s, &conv);
   } else {
     // FP64 iterative refinement around the complex-FP32 operator
     BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
@@ -217,8 +303,8 @@ SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s,
       if (rn <= tol * bnorm) break;
       bool conv = false;
       // save rr: gmres uses d_r internally
-      out.iterations += gmres(m, op, BEM_PREC_MIXED, rr, d, true, m->opt.inner_tol * rn,
-                              m->opt.gmres_maxit, W, s, &conv);
+      out.iterations += krylov(m, op, BEM_PREC_MIXED, rr, d, true, m->opt.inner_tol * rn,
+                               m->opt.gmres_maxit, W, s, &conv);
       ++out.refinements;
       launch_axpby(N, make_double2(1, 0), x, make_double2(1, 0), d, x, s);
       apply_tree(m, op, BEM_PREC_FP64, x, m->d_w.p, s);

@@ -188,3 +188,21 @@ def test_solve_with_and_without_preconditioner(bem, pre, precond):
     p, _, info = m.solve(to_dev(b))
     announce(f"  iterations {info['iterations']}")
     assert rel_l2(to_host(p), op.lu_solve(A, b)) < 1e-9
+
+
+@pytest.mark.parametrize("pre,precision", [("paper", "fp64"), ("tight", "fp64"), ("tight", "mixed")])
+def test_cgs_solver_matches_lu(bem, pre, precision):
+    """The paper's CGS solver (solver = 1), right preconditioned when the preset
+    preconditions, A and A^H, against LU."""
+    announce(f"CGS ico3 {pre} {precision}")
+    nodes, tris, g, beta, A = oracle_case("ico3", pre, 4.0, False)
+    b = op.rhs_plane_wave(g, 4.0, (0.0, 0.0, 1.0), p=preset(pre))
+    m = bem.Mesh(nodes, tris, pre, use_fmm=0, gmres_tol=1e-10, solver=1,
+                 precision=bem.BEM_PREC_MIXED if precision == "mixed" else bem.BEM_PREC_FP64)
+    m.set_problem(4.0, None)
+    p, _, info = m.solve(to_dev(b))
+    announce(f"  iterations {info['iterations']} refinements {info['refinements']}")
+    assert info["rel_residual"] < 1e-10
+    assert rel_l2(to_host(p), op.lu_solve(A, b)) < 1e-8
+    x, info_h = m.solve_adjoint(to_dev(b))
+    assert rel_l2(to_host(x), op.lu_solve(A.conj().T, b)) < 1e-8
