@@ -29,22 +29,26 @@ struct Error : std::runtime_error {
                          std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Owning device buffer.
+// Owning device buffer.  alloc() keeps the allocation when the new size fits
+// (capacity only grows), so per-frequency state re-sized for every wavenumber
+// of a sweep does not go back to the allocator each time.
 template <class T>
 struct DevBuf {
   T* p = nullptr;
-  size_t n = 0;
+  size_t n = 0;    // elements in use
+  size_t cap = 0;  // elements allocated
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) { o.p = nullptr; o.n = o.cap = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       n = o.n;
+      cap = o.cap;
       o.p = nullptr;
-      o.n = 0;
+      o.n = o.cap = 0;
     }
     return *this;
   }
@@ -52,14 +56,17 @@ struct DevBuf {
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
-    n = 0;
+    n = cap = 0;
   }
   void alloc(size_t count) {
-    if (count == n && p) return;
+    if (p && count <= cap) {
+      n = count;
+      return;
+    }
     release();
     if (count == 0) return;
     BEM_HIP(hipMalloc(&p, count * sizeof(T)));
-    n = count;
+    n = cap = count;
   }
   // Copy a host vector to the device and wait for the copy (setup paths only:
   // the caller's vector may be released right after the call).
@@ -70,7 +77,7 @@ struct DevBuf {
       BEM_HIP(hipStreamSynchronize(s));
     }
   }
-  size_t bytes() const { return n * sizeof(T); }
+  size_t bytes() const { return cap * sizeof(T); }
 };
 
 // ---------------------------------------------------------------- rules ---

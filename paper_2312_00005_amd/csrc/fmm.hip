@@ -19,6 +19,7 @@
 // Every output element has a single owner thread or wavefront and sums in a
 // fixed order (no atomics): results are bit-reproducible.
 #include "fmm.h"
+#include "sincos_cw.h"
 
 #include <cmath>
 
@@ -74,7 +75,7 @@ __global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t*
   double ar = 0.0, ai = 0.0;
   for (int q = 0; q < nq; ++q) {
     double sn, cs;
-    sincos(base - ra[q] * pe1 - rb[q] * pe2, &sn, &cs);
+    sincos_cw_lit(base - ra[q] * pe1 - rb[q] * pe2, &sn, &cs);
     ar += rw[q] * cs;
     ai += rw[q] * sn;
   }
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ s, int nu, int L, double k,
                                                      double2* __restrict__ D64, float2* __restrict__ D32) {
-  extern __shared__ double2 coef[];  // L + 1 values i^l (2l+1) h_l(k|X|)
+  extern __shared__ double2 coef[];  // L + 1 values i^l (2l+1) h_l(k|X|), then the recurrence factors
+  double* rec = reinterpret_cast<double*>(coef + (L + 1));  // (2l+1)/(l+1) and l/(l+1), l < L
   const int64_t q = blockIdx.x;
   if (q >= npairs) return;
   const int64_t a = pm[q], b = pn[q];
@@ -150,6 +152,10 @@ __global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64
       coef[l] = make_double2((2.0 * l + 1.0) * cr, (2.0 * l + 1.0) * ci);
     }
   }
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    rec[2 * l] = (2.0 * l + 1.0) / (l + 1.0);
+    rec[2 * l + 1] = (double)l / (l + 1.0);
+  }
   __syncthreads();
   const double u0 = X0 / r, u1 = X1 / r, u2 = X2 / r;
   for (int v = threadIdx.x; v < nu; v += blockDim.x) {
@@ -161,7 +167,8 @@ __global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64
       di += coef[1].y * ct;
     }
     for (int l = 1; l < L; ++l) {
-      const double pn1 = ((2.0 * l + 1.0) * ct * p - l * pm1) / (l + 1.0);
+      // Bonnet: P_{l+1} = ((2l+1) x P_l - l P_{l-1}) / (l+1), factors from LDS
+      const double pn1 = fma(rec[2 * l] * ct, p, -rec[2 * l + 1] * pm1);
       pm1 = p;
       p = pn1;
       dr += coef[l + 1].x * p;
@@ -444,7 +451,8 @@ void launch_fmm_translation(int64_t npairs, const int64_t* pm, const int64_t* pn
                             const double* s, int nu, int L, double k, double2* D64, float2* D32,
                             hipStream_t st) {
   if (npairs <= 0) return;
-  hipLaunchKernelGGL(k_translation, dim3((unsigned)npairs), dim3(256), (L + 1) * sizeof(double2), st, npairs,
+  hipLaunchKernelGGL(k_translation, dim3((unsigned)npairs), dim3(256), (L + 1) * sizeof(double2) + 2 * L * sizeof(double),
+                     st, npairs,
                      pm, pn, z, s, nu, L, k, D64, D32);
 }
 
