@@ -154,6 +154,7 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   L.gre = m->gre;
   L.gim = m->gim;
   L.wpb = m->tune_wpb[prec == BEM_PREC_FP64 ? 0 : 1];
+  L.order = m->d_order.p;
   if (op == BEM_OP_A) {
     L.off = m->d_off.p;
     L.seg = m->d_seg.p;
@@ -503,6 +504,38 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_off.upload(m->plan.off, s);
     m->d_seg.upload(m->plan.seg, s);
     m->d_items.upload(m->plan.items, s);
+    {
+      // forward near-field schedule: groups of targets by decreasing work, the
+      // work of a target being its wavefront passes (64 items each) weighted
+      // by the rule's points plus a per-item setup of about two points
+      std::vector<double> work(n_tri, 0.0);
+      for (int64_t t = 0; t < n_tri; ++t)
+        for (int mm = 1; mm <= kMaxRuleOrder; ++mm) {
+          const int64_t cnt = m->plan.seg[t * (kMaxRuleOrder + 1) + mm] - m->plan.seg[t * (kMaxRuleOrder + 1) + mm - 1];
+          work[t] += (double)((cnt + 63) / 64) * (mm * mm + 2);
+        }
+      // whole leaf clusters move together (their targets share sources, so
+      // tree order within a cluster keeps the source data in cache)
+      std::vector<std::pair<int64_t, int64_t>> groups;
+      if (m->fmm) {
+        const Level& leaf = m->tree.lv.back();
+        for (int64_t c = 0; c < leaf.nc; ++c) groups.emplace_back(leaf.ebeg[c], leaf.eend[c]);
+      } else {
+        for (int64_t t = 0; t < n_tri; t += 64) groups.emplace_back(t, std::min<int64_t>(n_tri, t + 64));
+      }
+      std::vector<double> gw(groups.size(), 0.0);
+      for (size_t q = 0; q < groups.size(); ++q)
+        for (int64_t t = groups[q].first; t < groups[q].second; ++t) gw[q] += work[t];
+      std::vector<size_t> go(groups.size());
+      for (size_t q = 0; q < go.size(); ++q) go[q] = q;
+      std::stable_sort(go.begin(), go.end(), [&](size_t a, size_t b) { return gw[a] > gw[b]; });
+      std::vector<int32_t> order;
+      order.reserve(n_tri);
+      for (size_t q : go)
+        for (int64_t t = groups[q].first; t < groups[q].second; ++t) order.push_back((int32_t)t);
+      if ((int64_t)order.size() != n_tri) throw std::runtime_error("internal: leaf clusters do not cover the mesh");
+      m->d_order.upload(order, s);
+    }
     std::vector<double> u, w;
     gauss_legendre01(o->self_n, u, w);
     m->d_duffy_u.upload(u, s);
@@ -904,7 +937,7 @@ bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,
 
 size_t bem_workspace_bytes(const bem_mesh* m) {
   if (!m) return 0;
-  size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_perm.bytes() + m->d_off.bytes() +
+  size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_perm.bytes() + m->d_off.bytes() + m->d_order.bytes() +
              m->d_items.bytes() + m->d_seg.bytes() + m->d_seg_t.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
              m->d_cfac.bytes() + m->d_diag.bytes() + m->d_vdiag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +

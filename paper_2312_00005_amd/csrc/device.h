@@ -25,6 +25,7 @@ struct NearLaunch {
   double k;
   double gre, gim;        // coupling gamma
   int wpb;                // targets (wavefronts) per workgroup of the forward kernel: 1, 2, 4 or 8
+  const int32_t* order;   // forward kernel: visiting order of the targets (NULL: tree order)
 };
 
 // y = diag x + sum over near items (tree-order vectors), in FP64 or complex

@@ -279,9 +279,11 @@ __global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __rest
                                                    const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
   // the target is uniform across the wavefront: say so, so that its data go
-  // through scalar loads and registers
-  const int64_t t = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (t >= L.N) return;  // the whole wavefront leaves together
+  // through scalar loads and registers.  Targets are visited in L.order
+  // (groups of decreasing work), so the last wavefronts to start are short ones.
+  const int64_t w = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= L.N) return;  // the whole wavefront leaves together
+  const int64_t t = L.order ? (int64_t)L.order[w] : w;
   const int64_t N = L.N;
   T xi[3], ni[3];
 #pragma unroll

@@ -27,6 +27,7 @@ struct bem_mesh {
   bem::DevBuf<float> d_geom32;
   bem::DevBuf<int64_t> d_perm;
   bem::DevBuf<int64_t> d_off, d_off_t, d_seg, d_seg_t;
+  bem::DevBuf<int32_t> d_order;    // targets by decreasing near-field work
   bem::DevBuf<uint64_t> d_items, d_items_t;
   bem::DevBuf<double> d_duffy_u, d_duffy_w, d_edge_t, d_edge_w;
 
