@@ -190,8 +190,19 @@ __device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t
 // With d0 = v0 - x_i and the point y = v0 + a e1 + b e2 in the (flat) source
 // triangle, everything the kernels need is a low-order polynomial in (a, b)
 // with per-item coefficients: |y - x|^2 is a quadratic form, (y - x).n_j = d0.n_j
-// (e1, e2 lie in the source plane) and (y - x).n_i is affine, so a point costs
-// a few FMAs besides rsqrt, sin and cos.
+// (e1, e2 lie in the source plane) and (y - x).n_i = cx is affine.
+// Written in u = 1/r, with H = hn + gamma nn (hn = (y - x).n_j, nn = n_i.n_j)
+// and sigma = 3 hn cx, the two integrands (weight w, kernel e^{ikr}/(4 pi r))
+// collapse to
+//   S1:  w e^{ikr} u^2 [-ik H + u (H + sigma gamma (k^2/3 + iku - u^2))],
+//   S2:  w e^{ikr} u   [1 + cx u gamma (ik - u)].
+// The loop runs in U = 1/(kap r), kap the phase unit per length (k for
+// radians, k/(2 pi) for revolutions): the quadratic form is scaled by kap^2,
+// so the phase is r2 U and the powers of kap move into per-launch constants
+//   Q0 = gamma k^2/3, Q1 = i gamma k kap, Q2 = -gamma kap^2,
+// and into the per-item factors kap^3 (S1) and kap (S2):
+//   S1 = kap^3 w e^{i theta} U^2 [Hk + U (H + sigma (Q0 + U (Q1 + U Q2)))],
+//   S2 = kap   w e^{i theta} U   [1 + cx U (Q1 + U Q2)],   Hk = -i (k/kap) H.
 template <typename T, bool WANT_S1, bool WANT_S2>
 __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64_t item, int m, const T xi[3],
                                       const T ni[3], T k, T gre, T gim, T& s1r, T& s1i, T& s2r,
@@ -210,23 +221,36 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
     e2[c] = v2[c] - v0[c];
     nj[c] = g[(NX + c) * N + j];
   }
-  // |d0 + a e1 + b e2|^2 = q00 + a (qa1 + a q11) + b (qb1 + b q22 + a q12)
-  const T q00 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
-  const T qa1 = T(2) * (d0[0] * e1[0] + d0[1] * e1[1] + d0[2] * e1[2]);
-  const T qb1 = T(2) * (d0[0] * e2[0] + d0[1] * e2[1] + d0[2] * e2[2]);
-  const T q11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
-  const T q22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
-  const T q12 = T(2) * (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]);
-  // (y - x).n_j and (y - x).n_i = c0 + a c1 + b c2
+  // per-launch constants (loop invariant for every caller)
+  const T kap = Phase<T>::scale(k), kap2 = kap * kap;
+  const T kr = k / kap;
+  const T k23 = k * k * T(1.0 / 3.0), kk = k * kap;
+  const T Q0r = gre * k23, Q0i = gim * k23;
+  const T Q1r = -gim * kk, Q1i = gre * kk;
+  const T Q2r = -gre * kap2, Q2i = -gim * kap2;
+  // kap^2 |d0 + a e1 + b e2|^2 = q00 + a (qa1 + a q11) + b (qb1 + b q22 + a q12)
+  const T q00 = kap2 * (d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2]);
+  const T qa1 = kap2 * T(2) * (d0[0] * e1[0] + d0[1] * e1[1] + d0[2] * e1[2]);
+  const T qb1 = kap2 * T(2) * (d0[0] * e2[0] + d0[1] * e2[1] + d0[2] * e2[2]);
+  const T q11 = kap2 * (e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  const T q22 = kap2 * (e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+  const T q12 = kap2 * T(2) * (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]);
+  // hn = (y - x).n_j; cx = (y - x).n_i = c0 + a c1 + b c2
   const T hn = d0[0] * nj[0] + d0[1] * nj[1] + d0[2] * nj[2];
-  const T c0 = d0[0] * ni[0] + d0[1] * ni[1] + d0[2] * ni[2];
-  const T c1 = e1[0] * ni[0] + e1[1] * ni[1] + e1[2] * ni[2];
-  const T c2 = e2[0] * ni[0] + e2[1] * ni[1] + e2[2] * ni[2];
-  const T area2 = T(2) * g[AREA * N + j] * (T)ldexp(1.0, -2 * depth);
+  T c0 = d0[0] * ni[0] + d0[1] * ni[1] + d0[2] * ni[2];
+  T c1 = e1[0] * ni[0] + e1[1] * ni[1] + e1[2] * ni[2];
+  T c2 = e2[0] * ni[0] + e2[1] * ni[1] + e2[2] * ni[2];
+  const T h3 = T(3) * hn;
+  if (!WANT_S2) {
+    // only sigma is needed: fold 3 hn into the affine coefficients
+    c0 *= h3;
+    c1 *= h3;
+    c2 *= h3;
+  }
   const T nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
-  const T kph = Phase<T>::scale(k);
-  const T kk = k * k, k3 = T(3) * k;
-  // gamma a = (gre + i gim)(-1/r + ik) = (-gre/r - gim k) + i (gre k - gim/r)
+  const T Hr = fma(gre, nn, hn), Hi = gim * nn;
+  const T Hkr = kr * Hi, Hki = -kr * Hr;
+  const T area2 = T(2) * g[AREA * N + j] * (T)ldexp(1.0, -2 * depth);
   const int base = c_rule_off[m - 1];
   const int np = m * m;
   T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
@@ -237,38 +261,36 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
     tb = fma(qa, q12, tb);
     T r2 = fma(qa, ta, q00);
     r2 = fma(qb, tb, r2);
-    const T rinv = rsqrt_t(r2);
-    const T r = r2 * rinv;
+    const T U = rsqrt_t(r2);
     T sn, cs;
-    Phase<T>::sincos(kph * r, &sn, &cs);
-    const T gs = qw * rinv;
-    const T Gr = gs * cs, Gi = gs * sn;
-    const T rny = hn * rinv;
-    const T rnx = fma(qb, c2, fma(qa, c1, c0)) * rinv;
+    Phase<T>::sincos(r2 * U, &sn, &cs);
+    // cx, or sigma when S2 is not wanted
+    const T cx = fma(qb, c2, fma(qa, c1, c0));
+    const T Rr = fma(U, Q2r, Q1r), Ri = fma(U, Q2i, Q1i);
+    const T qwU = qw * U;
     if (WANT_S1) {
-      // t1 = B rnx rny + a nn / r with a = (-1/r, k), B = (3/r^2 - k^2, -3k/r)
-      const T p = rnx * rny;
-      const T ri2 = rinv * rinv;
-      const T t1r = fma(fma(T(3), ri2, -kk), p, -nn * ri2);
-      const T t1i = rinv * fma(-k3, p, k * nn);
-      // b1 = -a rny - gamma t1
-      const T b1r = fma(rinv, rny, -fma(gre, t1r, -gim * t1i));
-      const T b1i = fma(-k, rny, -fma(gre, t1i, gim * t1r));
-      a1r = fma(Gr, b1r, fma(-Gi, b1i, a1r));
-      a1i = fma(Gr, b1i, fma(Gi, b1r, a1i));
+      const T sg = WANT_S2 ? h3 * cx : cx;
+      const T Wr = fma(sg, fma(U, Rr, Q0r), Hr);
+      const T Wi = fma(sg, fma(U, Ri, Q0i), Hi);
+      const T Vr = fma(U, Wr, Hkr), Vi = fma(U, Wi, Hki);
+      const T g2 = qwU * U;
+      const T Gr = g2 * cs, Gi = g2 * sn;
+      a1r = fma(Gr, Vr, fma(-Gi, Vi, a1r));
+      a1i = fma(Gr, Vi, fma(Gi, Vr, a1i));
     }
     if (WANT_S2) {
-      // b2 = 1 + gamma a rnx
-      const T b2r = fma(fma(-gre, rinv, -gim * k), rnx, T(1));
-      const T b2i = fma(gre, k, -gim * rinv) * rnx;
-      a2r = fma(Gr, b2r, fma(-Gi, b2i, a2r));
-      a2i = fma(Gr, b2i, fma(Gi, b2r, a2i));
+      const T cU = cx * U;
+      const T Zr = fma(cU, Rr, T(1)), Zi = cU * Ri;
+      const T Gr = qwU * cs, Gi = qwU * sn;
+      a2r = fma(Gr, Zr, fma(-Gi, Zi, a2r));
+      a2i = fma(Gr, Zi, fma(Gi, Zr, a2i));
     }
   }
-  s1r = a1r * area2;
-  s1i = a1i * area2;
-  s2r = a2r * area2;
-  s2i = a2i * area2;
+  const T f1 = area2 * kap2 * kap, f2 = area2 * kap;
+  s1r = a1r * f1;
+  s1i = a1i * f1;
+  s2r = a2r * f2;
+  s2i = a2i * f2;
 }
 
 // VMODE: apply dA/dc -- the (G - gamma H') part without c_j, diagonal
