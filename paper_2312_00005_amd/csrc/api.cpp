@@ -155,6 +155,10 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   L.gim = m->gim;
   L.wpb = m->tune_wpb[prec == BEM_PREC_FP64 ? 0 : 1];
   L.order = m->d_order.p;
+  L.rec = m->d_rec.p;
+  L.rec32 = m->d_rec32.p;
+  L.kap = m->kap;
+  L.kap32 = m->kap32;
   if (op == BEM_OP_A) {
     L.off = m->d_off.p;
     L.seg = m->d_seg.p;
@@ -207,6 +211,10 @@ void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, dou
   F.k = m->k;
   F.gre = m->gre;
   F.gim = m->gim;
+  F.rec = m->d_rec.p;
+  F.rec32 = m->d_rec32.p;
+  F.kap = m->kap;
+  F.kap32 = m->kap32;
   launch_far_direct(F, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
   BEM_HIP(hipGetLastError());
 }
@@ -337,6 +345,8 @@ void setup_preconditioner(bem_mesh* m, hipStream_t s) {
   L.k = m->k;
   L.gre = m->gre;
   L.gim = m->gim;
+  L.rec = m->d_rec.p;
+  L.kap = m->kap;
   const BlockArgs B = block_args(m);
   launch_block_assemble(L, B, m->d_blk_a.p, s);
   launch_block_invert(B, m->d_blk_a.p, m->d_blk_inv.p, m->d_blk_sing.p, s);
@@ -500,6 +510,8 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_geom.upload(m->g.f, s);
     std::vector<float> g32(m->g.f.begin(), m->g.f.end());
     m->d_geom32.upload(g32, s);
+    m->d_rec.alloc((size_t)n_tri * 16);
+    m->d_rec32.alloc((size_t)n_tri * 16);
     m->d_perm.upload(m->tree.perm, s);
     m->d_off.upload(m->plan.off, s);
     m->d_seg.upload(m->plan.seg, s);
@@ -602,6 +614,10 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     L.gre = m->gre;
     L.gim = m->gim;
     launch_self_terms(L, m->d_diag.p, s);
+    // quadrature records: phase unit k (FP64, radians), k / (2 pi) (FP32, revolutions)
+    m->kap = k;
+    m->kap32 = (double)(float)(k / (2.0 * M_PI));
+    launch_records(m->N, m->d_geom.p, m->kap, m->kap32, m->d_rec.p, m->d_rec32.p, s);
     BEM_HIP(hipGetLastError());
     setup_preconditioner(m, s);
     if (m->fmm && !m->far_direct) fmm_setup_problem(m, s);
@@ -937,7 +953,7 @@ bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,
 
 size_t bem_workspace_bytes(const bem_mesh* m) {
   if (!m) return 0;
-  size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_perm.bytes() + m->d_off.bytes() + m->d_order.bytes() +
+  size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_rec.bytes() + m->d_rec32.bytes() + m->d_perm.bytes() + m->d_off.bytes() + m->d_order.bytes() +
              m->d_items.bytes() + m->d_seg.bytes() + m->d_seg_t.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
              m->d_cfac.bytes() + m->d_diag.bytes() + m->d_vdiag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +

@@ -26,6 +26,9 @@ struct NearLaunch {
   double gre, gim;        // coupling gamma
   int wpb;                // targets (wavefronts) per workgroup of the forward kernel: 1, 2, 4 or 8
   const int32_t* order;   // forward kernel: visiting order of the targets (NULL: tree order)
+  const double* rec;      // element records for the FP64 kernels (launch_records), scale kap
+  const float* rec32;     // element records for the FP32 kernels, scale kap32
+  double kap, kap32;      // k (phase in radians) and k / (2 pi) rounded to float (phase in revolutions)
 };
 
 // y = diag x + sum over near items (tree-order vectors), in FP64 or complex
@@ -53,6 +56,9 @@ struct FarLaunch {
   double ratio2;
   int m_max, split_on_cap, max_subdiv;
   double k, gre, gim;
+  const double* rec;      // as in NearLaunch
+  const float* rec32;
+  double kap, kap32;
 };
 // y += far(x) (adjoint: y += far^H x; vmode: the dA/dc part), tree order
 void launch_far_direct(const FarLaunch& F, bool fp64, bool adjoint, bool vmode, const double2* x, double2* y,
@@ -68,6 +74,13 @@ struct SelfLaunch {
   double k, gre, gim;
 };
 void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s);
+
+// Per-element records of the quadrature kernels, 16 values per element
+// (tree order): v0, e1 = v1 - v0, e2 = v2 - v0 multiplied by the scale, the
+// normal, the scaled |e1|^2, |e2|^2, 2 e1.e2 and 2 area.  rec: scale kap
+// (FP64), rec32: scale kap32 (FP32).
+void launch_records(int64_t N, const double* geom, double kap, double kap32, double* rec, float* rec32,
+                    hipStream_t s);
 
 // Block-Jacobi preconditioner: the elements (tree order) are partitioned into
 // contiguous blocks of at most kMaxBlock elements; block b covers

@@ -182,11 +182,71 @@ __device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t
   }
 }
 
+// Source-element records (built per wavenumber by k_records): 16 values per
+// element, all lengths multiplied by kap, the phase unit per length (k for
+// radians in FP64, k/(2 pi) for revolutions in FP32):
+//   v0 (3), e1 = v1 - v0 (3), e2 = v2 - v0 (3), n (3),
+//   |e1|^2, |e2|^2, 2 e1.e2, 2 area.
+// One element is 64 (FP32) or 128 (FP64) contiguous bytes, read with 16-byte
+// loads: one gather per cache line instead of one per field.
+constexpr int kRec = 16;
+template <typename T> struct Rec;
+template <> struct Rec<float> {
+  __device__ static void load(const float* __restrict__ rec, int64_t j, float r[kRec]) {
+    const float4* p = reinterpret_cast<const float4*>(rec) + 4 * j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = p[q];
+      r[4 * q] = v.x;
+      r[4 * q + 1] = v.y;
+      r[4 * q + 2] = v.z;
+      r[4 * q + 3] = v.w;
+    }
+  }
+};
+template <> struct Rec<double> {
+  __device__ static void load(const double* __restrict__ rec, int64_t j, double r[kRec]) {
+    const double2* p = reinterpret_cast<const double2*>(rec) + 8 * j;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double2 v = p[q];
+      r[2 * q] = v.x;
+      r[2 * q + 1] = v.y;
+    }
+  }
+};
+
+// Per-launch constants of the point loop (see integrate_item), from the
+// wavenumber k, the scale kap and the coupling gamma = gre + i gim.
+template <typename T> struct PointConsts {
+  T kr;                      // k / kap
+  T kgr, kgi;                // kap gamma
+  T Q0r, Q0i, Q1r, Q1i, Q2r, Q2i;
+  T ikap;                    // 1 / kap
+};
+template <typename T>
+__device__ inline PointConsts<T> point_consts(double k, double kap, double gre, double gim) {
+  PointConsts<T> P;
+  const double k2 = k * k / (3.0 * kap);
+  P.kr = (T)(k / kap);
+  P.kgr = (T)(kap * gre);
+  P.kgi = (T)(kap * gim);
+  P.Q0r = (T)(gre * k2);  // gamma k^2 / (3 kap)
+  P.Q0i = (T)(gim * k2);
+  P.Q1r = (T)(-gim * k);  // i gamma k
+  P.Q1i = (T)(gre * k);
+  P.Q2r = (T)(-gre * kap);  // -gamma kap
+  P.Q2i = (T)(-gim * kap);
+  P.ikap = (T)(1.0 / kap);
+  return P;
+}
+
 // Integrate one item: returns S1 (c-independent part) and S2 (c_j part),
 // both already multiplied by 2 * area of the (sub-)triangle.
 // m is the item's rule order; the caller passes it wavefront-uniform so the
 // rule tables are read with scalar loads.  S1: the c-independent part
 // -(H - gamma E); S2: the part multiplied by c_j, (G - gamma H').
+// xs: the collocation point times kap; ni its normal.
 // With d0 = v0 - x_i and the point y = v0 + a e1 + b e2 in the (flat) source
 // triangle, everything the kernels need is a low-order polynomial in (a, b)
 // with per-item coefficients: |y - x|^2 is a quadratic form, (y - x).n_j = d0.n_j
@@ -196,45 +256,60 @@ __device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t
 // collapse to
 //   S1:  w e^{ikr} u^2 [-ik H + u (H + sigma gamma (k^2/3 + iku - u^2))],
 //   S2:  w e^{ikr} u   [1 + cx u gamma (ik - u)].
-// The loop runs in U = 1/(kap r), kap the phase unit per length (k for
-// radians, k/(2 pi) for revolutions): the quadratic form is scaled by kap^2,
-// so the phase is r2 U and the powers of kap move into per-launch constants
-//   Q0 = gamma k^2/3, Q1 = i gamma k kap, Q2 = -gamma kap^2,
-// and into the per-item factors kap^3 (S1) and kap (S2):
-//   S1 = kap^3 w e^{i theta} U^2 [Hk + U (H + sigma (Q0 + U (Q1 + U Q2)))],
-//   S2 = kap   w e^{i theta} U   [1 + cx U (Q1 + U Q2)],   Hk = -i (k/kap) H.
+// The loop runs on the kap-scaled geometry of the records, in U = 1/(kap r):
+// the phase is kap r = r2 U with r2 the scaled quadratic form, and with
+// primes for scaled lengths (hn' = kap hn, cx' = kap cx, H' = kap H,
+// sigma' = 3 hn' cx', area' = kap^2 area)
+//   S1 = w e^{i theta} U^2 [Hk + U (H' + sigma' (Q0 + U (Q1 + U Q2)))] 2 area',
+//   S2 = w e^{i theta} U   [1 + cx' U (Q1 + U Q2)] 2 area' / kap,
+// Hk = -i (k/kap) H', Q0 = gamma k^2/(3 kap), Q1 = i gamma k, Q2 = -gamma kap.
+// Sub-triangles are formed in edge form: the children (P0, M01, M20),
+// (P1, M12, M01), (P2, M20, M12), (M01, M12, M20) of (P0, P1, P2), with
+// midpoints M, have v0 = P0, P1, P2, M01 and edges that are halves of
+// +-e1, +-e2, e2 - e1.
 template <typename T, bool WANT_S1, bool WANT_S2>
-__device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64_t item, int m, const T xi[3],
-                                      const T ni[3], T k, T gre, T gim, T& s1r, T& s1i, T& s2r,
+__device__ inline void integrate_item(const T* __restrict__ rec, uint64_t item, int m, const T xs[3],
+                                      const T ni[3], const PointConsts<T>& P, T& s1r, T& s1i, T& s2r,
                                       T& s2i, int64_t& jout) {
   const int64_t j = (int64_t)(item & ((uint64_t(1) << 26) - 1));
   const int depth = (int)((item >> 29) & 15u);
   const uint64_t path = item >> 33;
   jout = j;
-  T v0[3], v1[3], v2[3];
-  item_triangle<T>(g, N, j, depth, path, v0, v1, v2);
-  T d0[3], e1[3], e2[3], nj[3];
+  T r[kRec];
+  Rec<T>::load(rec, j, r);
+  T v0[3] = {r[0], r[1], r[2]}, e1[3] = {r[3], r[4], r[5]}, e2[3] = {r[6], r[7], r[8]};
+  const T nj[3] = {r[9], r[10], r[11]};
+  T q11 = r[12], q22 = r[13], q12 = r[14], area2 = r[15];
+  if (depth > 0) {
+    for (int d = 0; d < depth; ++d) {
+      const int ch = (int)((path >> (2 * d)) & 3u);
+      // v0 += al e1 + be e2; (e1, e2) <- (a11 e1 + a12 e2, a21 e1 + a22 e2)
+      const T al = ch == 1 ? T(1) : (ch == 3 ? T(0.5) : T(0));
+      const T be = ch == 2 ? T(1) : T(0);
+      const T a11 = ch == 0 ? T(0.5) : (ch == 1 ? T(-0.5) : T(0));
+      const T a12 = ch == 0 ? T(0) : (ch == 2 ? T(-0.5) : T(0.5));
+      const T a21 = ch == 0 ? T(0) : (ch == 2 ? T(0.5) : T(-0.5));
+      const T a22 = ch == 1 ? T(0) : (ch == 2 ? T(-0.5) : T(0.5));
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    d0[c] = v0[c] - xi[c];
-    e1[c] = v1[c] - v0[c];
-    e2[c] = v2[c] - v0[c];
-    nj[c] = g[(NX + c) * N + j];
+      for (int c = 0; c < 3; ++c) {
+        const T f1 = e1[c], f2 = e2[c];
+        v0[c] = fma(al, f1, fma(be, f2, v0[c]));
+        e1[c] = fma(a11, f1, a12 * f2);
+        e2[c] = fma(a21, f1, a22 * f2);
+      }
+    }
+    q11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+    q22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    q12 = T(2) * (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]);
+    area2 = ldexp(area2, -2 * depth);
   }
-  // per-launch constants (loop invariant for every caller)
-  const T kap = Phase<T>::scale(k), kap2 = kap * kap;
-  const T kr = k / kap;
-  const T k23 = k * k * T(1.0 / 3.0), kk = k * kap;
-  const T Q0r = gre * k23, Q0i = gim * k23;
-  const T Q1r = -gim * kk, Q1i = gre * kk;
-  const T Q2r = -gre * kap2, Q2i = -gim * kap2;
-  // kap^2 |d0 + a e1 + b e2|^2 = q00 + a (qa1 + a q11) + b (qb1 + b q22 + a q12)
-  const T q00 = kap2 * (d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2]);
-  const T qa1 = kap2 * T(2) * (d0[0] * e1[0] + d0[1] * e1[1] + d0[2] * e1[2]);
-  const T qb1 = kap2 * T(2) * (d0[0] * e2[0] + d0[1] * e2[1] + d0[2] * e2[2]);
-  const T q11 = kap2 * (e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
-  const T q22 = kap2 * (e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
-  const T q12 = kap2 * T(2) * (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]);
+  T d0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) d0[c] = v0[c] - xs[c];
+  // |d0 + a e1 + b e2|^2 = q00 + a (qa1 + a q11) + b (qb1 + b q22 + a q12)
+  const T q00 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
+  const T qa1 = T(2) * (d0[0] * e1[0] + d0[1] * e1[1] + d0[2] * e1[2]);
+  const T qb1 = T(2) * (d0[0] * e2[0] + d0[1] * e2[1] + d0[2] * e2[2]);
   // hn = (y - x).n_j; cx = (y - x).n_i = c0 + a c1 + b c2
   const T hn = d0[0] * nj[0] + d0[1] * nj[1] + d0[2] * nj[2];
   T c0 = d0[0] * ni[0] + d0[1] * ni[1] + d0[2] * ni[2];
@@ -248,9 +323,8 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
     c2 *= h3;
   }
   const T nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
-  const T Hr = fma(gre, nn, hn), Hi = gim * nn;
-  const T Hkr = kr * Hi, Hki = -kr * Hr;
-  const T area2 = T(2) * g[AREA * N + j] * (T)ldexp(1.0, -2 * depth);
+  const T Hr = fma(P.kgr, nn, hn), Hi = P.kgi * nn;
+  const T Hkr = P.kr * Hi, Hki = -P.kr * Hr;
   const int base = c_rule_off[m - 1];
   const int np = m * m;
   T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
@@ -266,12 +340,12 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
     Phase<T>::sincos(r2 * U, &sn, &cs);
     // cx, or sigma when S2 is not wanted
     const T cx = fma(qb, c2, fma(qa, c1, c0));
-    const T Rr = fma(U, Q2r, Q1r), Ri = fma(U, Q2i, Q1i);
+    const T Rr = fma(U, P.Q2r, P.Q1r), Ri = fma(U, P.Q2i, P.Q1i);
     const T qwU = qw * U;
     if (WANT_S1) {
       const T sg = WANT_S2 ? h3 * cx : cx;
-      const T Wr = fma(sg, fma(U, Rr, Q0r), Hr);
-      const T Wi = fma(sg, fma(U, Ri, Q0i), Hi);
+      const T Wr = fma(sg, fma(U, Rr, P.Q0r), Hr);
+      const T Wi = fma(sg, fma(U, Ri, P.Q0i), Hi);
       const T Vr = fma(U, Wr, Hkr), Vi = fma(U, Wi, Hki);
       const T g2 = qwU * U;
       const T Gr = g2 * cs, Gi = g2 * sn;
@@ -286,12 +360,19 @@ __device__ inline void integrate_item(const T* __restrict__ g, int64_t N, uint64
       a2i = fma(Gr, Zi, fma(Gi, Zr, a2i));
     }
   }
-  const T f1 = area2 * kap2 * kap, f2 = area2 * kap;
-  s1r = a1r * f1;
-  s1i = a1i * f1;
+  const T f2 = area2 * P.ikap;
+  s1r = a1r * area2;
+  s1i = a1i * area2;
   s2r = a2r * f2;
   s2i = a2i * f2;
 }
+
+template <typename T> __device__ inline const T* near_rec(const NearLaunch& L);
+template <> __device__ inline const double* near_rec<double>(const NearLaunch& L) { return L.rec; }
+template <> __device__ inline const float* near_rec<float>(const NearLaunch& L) { return L.rec32; }
+template <typename T> __device__ inline double near_kap(const NearLaunch& L);
+template <> __device__ inline double near_kap<double>(const NearLaunch& L) { return L.kap; }
+template <> __device__ inline double near_kap<float>(const NearLaunch& L) { return L.kap32; }
 
 // VMODE: apply dA/dc -- the (G - gamma H') part without c_j, diagonal
 // G_ii - gamma/2 -- instead of A.
@@ -307,13 +388,15 @@ __global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __rest
   if (w >= L.N) return;  // the whole wavefront leaves together
   const int64_t t = L.order ? (int64_t)L.order[w] : w;
   const int64_t N = L.N;
-  T xi[3], ni[3];
+  const double kap = near_kap<T>(L);
+  const T* __restrict__ rec = near_rec<T>(L);
+  T xs[3], ni[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    xi[c] = g[(CX + c) * N + t];
+    xs[c] = (T)(kap * L.geom[(CX + c) * N + t]);
     ni[c] = g[(NX + c) * N + t];
   }
-  const T k = (T)L.k, gre = (T)L.gre, gim = (T)L.gim;
+  const PointConsts<T> P = point_consts<T>(L.k, kap, L.gre, L.gim);
   T accr = 0, acci = 0;
   // the target's items are sorted by rule order; seg[t][m-1] .. seg[t][m]
   // holds the order-m items, so every pass below runs one uniform rule
@@ -324,8 +407,7 @@ __global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __rest
     for (int64_t it = b + lane; it < e; it += 64) {
       T s1r, s1i, s2r, s2i;
       int64_t j;
-      integrate_item<T, !VMODE, HAS_C || VMODE>(g, N, L.items[it], mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r,
-                                               s2i, j);
+      integrate_item<T, !VMODE, HAS_C || VMODE>(rec, L.items[it], mc + 1, xs, ni, P, s1r, s1i, s2r, s2i, j);
       T vr = s1r, vi = s1i;
       if (VMODE) {
         vr = s2r;
@@ -361,7 +443,9 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
   const int64_t jsrc = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (jsrc >= L.N) return;
   const int64_t N = L.N;
-  const T k = (T)L.k, gre = (T)L.gre, gim = (T)L.gim;
+  const double kap = near_kap<T>(L);
+  const T* __restrict__ rec = near_rec<T>(L);
+  const PointConsts<T> P = point_consts<T>(L.k, kap, L.gre, L.gim);
   T cr = 0, ci = 0;
   if (HAS_C) {
     const double2 c = L.cfac[jsrc];
@@ -378,15 +462,15 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
       const int64_t i = (int64_t)(raw & ((uint64_t(1) << 26) - 1));
       // rebuild the forward item (source jsrc) and integrate from target i
       const uint64_t item = (raw & ~((uint64_t(1) << 26) - 1)) | (uint64_t)jsrc;
-      T xi[3], ni[3];
+      T xs[3], ni[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        xi[c] = g[(CX + c) * N + i];
+        xs[c] = (T)(kap * L.geom[(CX + c) * N + i]);
         ni[c] = g[(NX + c) * N + i];
       }
       T s1r, s1i, s2r, s2i;
       int64_t jj;
-      integrate_item<T, !VMODE, HAS_C || VMODE>(g, N, item, mc + 1, xi, ni, k, gre, gim, s1r, s1i, s2r, s2i, jj);
+      integrate_item<T, !VMODE, HAS_C || VMODE>(rec, item, mc + 1, xs, ni, P, s1r, s1i, s2r, s2i, jj);
       T vr = s1r, vi = s1i;
       if (VMODE) {
         vr = s2r;
@@ -436,6 +520,44 @@ void near_dispatch(const NearLaunch& L, const T* g, const double2* x, double2* y
   } else {
     if (L.cfac) hipLaunchKernelGGL((k_near_adj<T, true, false>), grid, block, 0, s, L, g, x, y);
     else hipLaunchKernelGGL((k_near_adj<T, false, false>), grid, block, 0, s, L, g, x, y);
+  }
+}
+
+// ------------------------------------------------------ element records ---
+// Records of the integration kernels (layout at Rec above), FP64 with scale
+// kap and FP32 with scale kap32; the scaled quantities are formed in FP64.
+__global__ __launch_bounds__(256) void k_records(int64_t N, const double* __restrict__ g, double kap,
+                                                 double kap32, double* __restrict__ rec,
+                                                 float* __restrict__ rec32) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  double v0[3], e1[3], e2[3], n[3];
+  for (int c = 0; c < 3; ++c) {
+    v0[c] = g[(P0X + c) * N + t];
+    e1[c] = g[(P1X + c) * N + t] - v0[c];
+    e2[c] = g[(P2X + c) * N + t] - v0[c];
+    n[c] = g[(NX + c) * N + t];
+  }
+  const double area = g[AREA * N + t];
+  for (int p = 0; p < 2; ++p) {
+    const double s = p == 0 ? kap : kap32;
+    double r[kRec], f1[3], f2[3];
+    for (int c = 0; c < 3; ++c) {
+      r[c] = s * v0[c];
+      f1[c] = s * e1[c];
+      f2[c] = s * e2[c];
+      r[3 + c] = f1[c];
+      r[6 + c] = f2[c];
+      r[9 + c] = n[c];
+    }
+    r[12] = f1[0] * f1[0] + f1[1] * f1[1] + f1[2] * f1[2];
+    r[13] = f2[0] * f2[0] + f2[1] * f2[1] + f2[2] * f2[2];
+    r[14] = 2.0 * (f1[0] * f2[0] + f1[1] * f2[1] + f1[2] * f2[2]);
+    r[15] = 2.0 * area * s * s;
+    for (int q = 0; q < kRec; ++q) {
+      if (p == 0) rec[kRec * t + q] = r[q];
+      else rec32[kRec * t + q] = (float)r[q];
+    }
   }
 }
 
@@ -543,6 +665,12 @@ template <>
 __device__ inline const double* far_geom<double>(const FarLaunch& F) { return F.geom; }
 template <>
 __device__ inline const float* far_geom<float>(const FarLaunch& F) { return F.geom32; }
+template <typename T> __device__ inline const T* far_rec(const FarLaunch& F);
+template <> __device__ inline const double* far_rec<double>(const FarLaunch& F) { return F.rec; }
+template <> __device__ inline const float* far_rec<float>(const FarLaunch& F) { return F.rec32; }
+template <typename T> __device__ inline double far_kap(const FarLaunch& F);
+template <> __device__ inline double far_kap<double>(const FarLaunch& F) { return F.kap; }
+template <> __device__ inline double far_kap<float>(const FarLaunch& F) { return F.kap32; }
 
 // order for r~^2 (0: split)
 __device__ inline int far_order(const FarLaunch& F, double rt2) {
@@ -554,11 +682,12 @@ __device__ inline int far_order(const FarLaunch& F, double rt2) {
 
 // One (collocation i, element j) pair that needs subdivision: depth-first walk
 // over (depth, path) without a stack, per-sub-triangle rule as in the plan.
+// The rule choice uses the unscaled geometry g, the integration the records.
 template <typename T, bool WANT_S1, bool WANT_S2>
-__device__ void far_pair_split(const FarLaunch& F, const T* g, int64_t j, const T xi[3], const T ni[3], T& s1r,
-                               T& s1i, T& s2r, T& s2i) {
+__device__ void far_pair_split(const FarLaunch& F, const T* g, const T* rec, int64_t j, const T xi[3],
+                               const T xs[3], const T ni[3], const PointConsts<T>& P, T& s1r, T& s1i, T& s2r,
+                               T& s2i) {
   const int64_t N = F.N;
-  const T k = (T)F.k, gre = (T)F.gre, gim = (T)F.gim;
   const double area0 = (double)g[AREA * N + j];
   int depth = 0;
   uint64_t path = 0;
@@ -581,7 +710,7 @@ __device__ void far_pair_split(const FarLaunch& F, const T* g, int64_t j, const 
     const uint64_t item = (uint64_t)j | ((uint64_t)depth << 29) | (path << 33);
     T a1r, a1i, a2r, a2i;
     int64_t jj;
-    integrate_item<T, WANT_S1, WANT_S2>(g, N, item, m, xi, ni, k, gre, gim, a1r, a1i, a2r, a2i, jj);
+    integrate_item<T, WANT_S1, WANT_S2>(rec, item, m, xs, ni, P, a1r, a1i, a2r, a2i, jj);
     s1r += a1r;
     s1i += a1i;
     s2r += a2r;
@@ -610,11 +739,14 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
   if (r >= F.N) return;
   const int64_t N = F.N;
   const T* g = far_geom<T>(F);
-  const T k = (T)F.k, gre = (T)F.gre, gim = (T)F.gim;
-  T xr[3], nr[3];
+  const T* __restrict__ rec = far_rec<T>(F);
+  const double kap = far_kap<T>(F);
+  const PointConsts<T> P = point_consts<T>(F.k, kap, F.gre, F.gim);
+  T xr[3], nr[3], xsr[3];
   for (int c = 0; c < 3; ++c) {
     xr[c] = g[(CX + c) * N + r];
     nr[c] = g[(NX + c) * N + r];
+    xsr[c] = (T)(kap * F.geom[(CX + c) * N + r]);
   }
   T cr = 0, ci = 0;
   if (ADJ && HAS_C) {
@@ -633,10 +765,11 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
       // collocation point and element of this lane's pair
       const int64_t i = ADJ ? oi : r;
       const int64_t j = ADJ ? r : oi;
-      T xi[3], ni[3];
+      T xi[3], ni[3], xs[3];
       for (int c = 0; c < 3; ++c) {
         xi[c] = ADJ ? g[(CX + c) * N + i] : xr[c];
         ni[c] = ADJ ? g[(NX + c) * N + i] : nr[c];
+        xs[c] = ADJ ? (T)(kap * F.geom[(CX + c) * N + i]) : xsr[c];
       }
       int m = -1;
       if (valid) {
@@ -653,12 +786,11 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
         if (__ballot(m == mc) == 0) continue;
         if (m == mc) {
           int64_t jj;
-          integrate_item<T, !VMODE, HAS_C || VMODE>(g, N, (uint64_t)j, mc, xi, ni, k, gre, gim, s1r, s1i, s2r,
-                                                   s2i, jj);
+          integrate_item<T, !VMODE, HAS_C || VMODE>(rec, (uint64_t)j, mc, xs, ni, P, s1r, s1i, s2r, s2i, jj);
         }
       }
       if (__ballot(m == 0) != 0 && m == 0)
-        far_pair_split<T, !VMODE, HAS_C || VMODE>(F, g, j, xi, ni, s1r, s1i, s2r, s2i);
+        far_pair_split<T, !VMODE, HAS_C || VMODE>(F, g, rec, j, xi, xs, ni, P, s1r, s1i, s2r, s2i);
       if (!valid) continue;
       T vr = s1r, vi = s1i;
       if (VMODE) {
@@ -709,9 +841,10 @@ __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs 
   const int n = B.n[blk];
   const int64_t off = B.off[blk];
   const int il = (int)(t - b0);
-  double xi[3], ni[3];
+  const PointConsts<double> P = point_consts<double>(L.k, L.kap, L.gre, L.gim);
+  double xs[3], ni[3];
   for (int c = 0; c < 3; ++c) {
-    xi[c] = g[(CX + c) * N + t];
+    xs[c] = L.kap * g[(CX + c) * N + t];
     ni[c] = g[(NX + c) * N + t];
   }
   double accr = 0.0, acci = 0.0;
@@ -730,7 +863,7 @@ __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs 
       if (in) {
         double s1r, s1i, s2r, s2i;
         int64_t jj;
-        integrate_item<double, true, HAS_C>(g, N, L.items[it], mc + 1, xi, ni, L.k, L.gre, L.gim, s1r, s1i, s2r,
+        integrate_item<double, true, HAS_C>(L.rec, L.items[it], mc + 1, xs, ni, P, s1r, s1i, s2r,
                                             s2i, jj);
         vr = s1r;
         vi = s1i;
@@ -1053,6 +1186,12 @@ void launch_near(const NearLaunch& L, bool fp64, bool adjoint, bool vmode, const
                  hipStream_t s) {
   if (fp64) near_dispatch<double>(L, L.geom, x, y, s, adjoint, vmode);
   else near_dispatch<float>(L, L.geom32, x, y, s, adjoint, vmode);
+}
+
+void launch_records(int64_t N, const double* geom, double kap, double kap32, double* rec, float* rec32,
+                    hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_records, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, geom, kap, kap32, rec, rec32);
 }
 
 void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s) {

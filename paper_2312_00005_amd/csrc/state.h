@@ -28,6 +28,9 @@ struct bem_mesh {
   bem::DevBuf<int64_t> d_perm;
   bem::DevBuf<int64_t> d_off, d_off_t, d_seg, d_seg_t;
   bem::DevBuf<int32_t> d_order;    // targets by decreasing near-field work
+  bem::DevBuf<double> d_rec;       // element records of the quadrature kernels (per wavenumber)
+  bem::DevBuf<float> d_rec32;
+  double kap = 0.0, kap32 = 0.0;   // their scales
   bem::DevBuf<uint64_t> d_items, d_items_t;
   bem::DevBuf<double> d_duffy_u, d_duffy_w, d_edge_t, d_edge_w;
 
