@@ -146,6 +146,13 @@ typedef struct bem_options {
                                1: conjugate gradient squared, the paper's
                                iterative solver (Sec. 3.2); both right
                                preconditioned, gmres_maxit caps iterations */
+  int32_t near_waves_per_cu;/* forward near-field kernel: 0 = one wavefront
+                               per collocation point, all launched at once;
+                               n in [1, 64] = n resident wavefronts per compute
+                               unit, each looping over collocation points, so
+                               that the far-field kernels on the side stream
+                               find free wavefront slots (a tuning choice;
+                               results are identical) */
 } bem_options;
 
 typedef struct bem_solve_info {
@@ -263,14 +270,17 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
                                void* stream);
 
 /* Choose launch shapes by timing them on this mesh and problem: near-field
- * targets per workgroup (1, 2, 4, 8) and translation threads per workgroup
- * (64, 128, 256), for the FP64 and the complex-FP32 operator.  Results are
- * kept in the mesh and used by every later application; near_wpb and
- * translate_tpb (host int32[2]: FP64, FP32) receive them and may be NULL.
- * Runs about 30 operator parts on the stream; results are unchanged by the
- * choice (each output keeps its owner and summation order). */
+ * targets per workgroup (1, 2, 4, 8), translation threads per workgroup
+ * (64, 128, 256) and, with the cluster tree, the resident near-field
+ * wavefronts per compute unit while the far field runs beside it (0, 8, 12,
+ * 16, 24; see near_waves_per_cu), for the FP64 and the complex-FP32
+ * operator.  Results are kept in the mesh and used by every later
+ * application; near_wpb, translate_tpb and near_waves (host int32[2]: FP64,
+ * FP32) receive them and may be NULL.  Runs about 50 operator parts on the
+ * stream; results are unchanged by the choice (each output keeps its owner
+ * and summation order). */
 bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb,
-                        void* stream);
+                        int32_t* near_waves, void* stream);
 
 /* Solve A p = rhs by GMRES (FP64 Krylov vectors and residuals; with
  * precision MIXED an FP64 outer refinement around a complex-FP32 inner

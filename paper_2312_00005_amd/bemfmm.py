@@ -61,7 +61,7 @@ class bem_options(ctypes.Structure):
         ("l_eps_mixed", ctypes.c_double), ("precond", ctypes.c_int32),
         ("gamma_re", ctypes.c_double), ("gamma_im_k", ctypes.c_double),
         ("far_direct", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("level_rows", ctypes.c_int32),
-        ("solver", ctypes.c_int32),
+        ("solver", ctypes.c_int32), ("near_waves_per_cu", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -104,7 +104,7 @@ _SIGS = {
     "bem_solve": (_i32, [_vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(bem_solve_info), _vp]),
     "bem_apply_dc": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "bem_incident_field": (_i32, [_vp, _i32, _vp, bem_c128, _i64, _vp, _vp, _vp]),
-    "bem_autotune": (_i32, [_vp, _vp, _vp, _vp]),
+    "bem_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "bem_field": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_field_adjoint": (_i32, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
     "bem_grad_admittance": (_i32, [_vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
@@ -188,8 +188,10 @@ def bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream):
 def bem_autotune(mesh, stream):
     w = (_i32 * 2)()
     t = (_i32 * 2)()
-    _check(_lib.bem_autotune(mesh, w, t, stream))
-    return {"near_wpb": {"fp64": w[0], "mixed": w[1]}, "translate_tpb": {"fp64": t[0], "mixed": t[1]}}
+    nw = (_i32 * 2)()
+    _check(_lib.bem_autotune(mesh, w, t, nw, stream))
+    return {"near_wpb": {"fp64": w[0], "mixed": w[1]}, "translate_tpb": {"fp64": t[0], "mixed": t[1]},
+            "near_waves_per_cu": {"fp64": nw[0], "mixed": nw[1]}}
 
 
 def bem_incident_field(mesh, kind, src, P0, n_pts, pts_ptr, out_ptr, stream):

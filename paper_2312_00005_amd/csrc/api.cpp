@@ -123,6 +123,8 @@ void check_options(const bem_options* o) {
   if (o->use_graphs != 0 && o->use_graphs != 1) throw Error(BEM_E_ARG, "use_graphs must be 0 or 1");
   if (o->level_rows != 0 && o->level_rows != 1) throw Error(BEM_E_ARG, "level_rows must be 0 or 1");
   if (o->solver != 0 && o->solver != 1) throw Error(BEM_E_ARG, "solver must be 0 (GMRES) or 1 (CGS)");
+  if (o->near_waves_per_cu < 0 || o->near_waves_per_cu > 64)
+    throw Error(BEM_E_ARG, "near_waves_per_cu must be in [0, 64]");
   if (o->far_direct && !o->use_fmm) throw Error(BEM_E_ARG, "far_direct needs the cluster tree (use_fmm = 1)");
   if (!std::isfinite(o->gamma_re) || !std::isfinite(o->gamma_im_k) || o->gamma_im_k == 0.0)
     throw Error(BEM_E_ARG, "the coupling needs a finite gamma with a non-zero imaginary part");
@@ -159,6 +161,8 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   L.rec32 = m->d_rec32.p;
   L.kap = m->kap;
   L.kap32 = m->kap32;
+  // a resident near-field grid only while the far field runs beside it
+  L.nwaves = part == 0 && m->fmm ? (int64_t)m->tune_nwaves[prec == BEM_PREC_FP64 ? 0 : 1] * m->n_cu : 0;
   if (op == BEM_OP_A) {
     L.off = m->d_off.p;
     L.seg = m->d_seg.p;
@@ -502,9 +506,16 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     auto m = std::make_unique<bem_mesh>();
     m->opt = *o;
     m->N = n_tri;
+    m->tune_nwaves[0] = m->tune_nwaves[1] = o->near_waves_per_cu;
     m->fmm = o->use_fmm != 0;
     m->far_direct = o->far_direct != 0;
     build_host(n_nodes, xyz, n_tri, tri, *o, m->tree, m->g, m->plan, m->bad_element);
+    {
+      int dev = 0, ncu = 0;
+      BEM_HIP(hipGetDevice(&dev));
+      BEM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      if (ncu > 0) m->n_cu = ncu;
+    }
     upload_rules();
     hipStream_t s = nullptr;
     m->d_geom.upload(m->g.f, s);
@@ -672,7 +683,8 @@ bem_status bem_incident_field(bem_mesh* m, int kind, const double src[3], bem_c1
   });
 }
 
-bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, void* stream) {
+bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, int32_t* near_waves,
+                        void* stream) {
   return guarded([&]() -> bem_status {
     if (!m) return fail(BEM_E_ARG, "mesh is NULL");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
@@ -718,8 +730,24 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           }
           m->tune_tpb[pi] = pick;
         }
+        if (m->fmm) {
+          // resident near-field wavefronts per compute unit while the far
+          // field runs beside it on the side stream (whole applications)
+          best = -1.0f;
+          pick = 0;
+          for (int nw : {0, 8, 12, 16, 24}) {
+            m->tune_nwaves[pi] = nw;
+            const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
+            if (best < 0.0f || t < best) {
+              best = t;
+              pick = nw;
+            }
+          }
+          m->tune_nwaves[pi] = pick;
+        }
         if (near_wpb) near_wpb[pi] = m->tune_wpb[pi];
         if (translate_tpb) translate_tpb[pi] = m->tune_tpb[pi];
+        if (near_waves) near_waves[pi] = m->tune_nwaves[pi];
       }
       ++m->problem_stamp;  // captured applications used the old shapes
     } catch (...) {

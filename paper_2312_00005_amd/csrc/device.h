@@ -29,6 +29,7 @@ struct NearLaunch {
   const double* rec;      // element records for the FP64 kernels (launch_records), scale kap
   const float* rec32;     // element records for the FP32 kernels, scale kap32
   double kap, kap32;      // k (phase in radians) and k / (2 pi) rounded to float (phase in revolutions)
+  int64_t nwaves;         // forward kernel: wavefronts launched (0: one per target)
 };
 
 // y = diag x + sum over near items (tree-order vectors), in FP64 or complex

@@ -36,6 +36,12 @@ __constant__ int c_rule_off[kMaxRuleOrder + 1];
 // weights divided by 4 pi (the Green's function's factor folded in)
 __constant__ double c_rule_ws[kRulePoints];
 __constant__ float c_rule_ws32[kRulePoints];
+// (a, b, w / 4 pi) of every rule point in one record, for one scalar load
+// per point
+struct alignas(16) RulePt32 { float a, b, w, pad; };
+struct alignas(32) RulePt64 { double a, b, w, pad; };
+__constant__ RulePt32 c_rule_pt32[kRulePoints];
+__constant__ RulePt64 c_rule_pt64[kRulePoints];
 // 2/pi, C1, C2, C3 (pi/2 in three parts), the sin coefficients 1/17! ... -1/3!
 // (highest first), the cos coefficients 1/16! ... -1/2!
 __constant__ double c_sincos[4 + 8 + 8];
@@ -51,6 +57,14 @@ void upload_rule_tables(const double* a, const double* b, const double* w, const
     ws32[i] = (float)ws[i];
   }
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_ws), ws, sizeof(double) * kRulePoints);
+  RulePt32 pt32[kRulePoints];
+  RulePt64 pt64[kRulePoints];
+  for (int i = 0; i < kRulePoints; ++i) {
+    pt32[i] = RulePt32{a32[i], b32[i], ws32[i], 0.0f};
+    pt64[i] = RulePt64{a[i], b[i], ws[i], 0.0};
+  }
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt32), pt32, sizeof(pt32));
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt64), pt64, sizeof(pt64));
   // sin/cos reduction: pi/2 split into three parts, the first two with 20
   // significant bits so that n*C1 and n*C2 are exact; Taylor coefficients
   const double sc[20] = {0.6366197723675814, 1.5707950592041016, 1.2675900507019833e-06, 7.443547480486623e-13,
@@ -82,12 +96,14 @@ template <> struct RuleTab<double> {
   __device__ static double b(int i) { return c_rule_b[i]; }
   __device__ static double w(int i) { return c_rule_w[i]; }
   __device__ static double ws(int i) { return c_rule_ws[i]; }
+  __device__ static RulePt64 pt(int i) { return c_rule_pt64[i]; }
 };
 template <> struct RuleTab<float> {
   __device__ static float a(int i) { return c_rule_a32[i]; }
   __device__ static float b(int i) { return c_rule_b32[i]; }
   __device__ static float w(int i) { return c_rule_w32[i]; }
   __device__ static float ws(int i) { return c_rule_ws32[i]; }
+  __device__ static RulePt32 pt(int i) { return c_rule_pt32[i]; }
 };
 
 // sin and cos of x for |x| < 2^20: Cody & Waite reduction by pi/2 (pi/2 split
@@ -267,16 +283,12 @@ __device__ inline PointConsts<T> point_consts(double k, double kap, double gre, 
 // (P1, M12, M01), (P2, M20, M12), (M01, M12, M20) of (P0, P1, P2), with
 // midpoints M, have v0 = P0, P1, P2, M01 and edges that are halves of
 // +-e1, +-e2, e2 - e1.
+// integrate_loaded: the same with the source's record r already in registers.
 template <typename T, bool WANT_S1, bool WANT_S2>
-__device__ inline void integrate_item(const T* __restrict__ rec, uint64_t item, int m, const T xs[3],
-                                      const T ni[3], const PointConsts<T>& P, T& s1r, T& s1i, T& s2r,
-                                      T& s2i, int64_t& jout) {
-  const int64_t j = (int64_t)(item & ((uint64_t(1) << 26) - 1));
+__device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, const T xs[3], const T ni[3],
+                                        const PointConsts<T>& P, T& s1r, T& s1i, T& s2r, T& s2i) {
   const int depth = (int)((item >> 29) & 15u);
   const uint64_t path = item >> 33;
-  jout = j;
-  T r[kRec];
-  Rec<T>::load(rec, j, r);
   T v0[3] = {r[0], r[1], r[2]}, e1[3] = {r[3], r[4], r[5]}, e2[3] = {r[6], r[7], r[8]};
   const T nj[3] = {r[9], r[10], r[11]};
   T q11 = r[12], q22 = r[13], q12 = r[14], area2 = r[15];
@@ -328,8 +340,11 @@ __device__ inline void integrate_item(const T* __restrict__ rec, uint64_t item, 
   const int base = c_rule_off[m - 1];
   const int np = m * m;
   T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+#pragma unroll 2
   for (int q = 0; q < np; ++q) {
-    const T qa = RuleTab<T>::a(base + q), qb = RuleTab<T>::b(base + q), qw = RuleTab<T>::ws(base + q);
+    // (a, b, w) of the point in one scalar load
+    const auto rp = RuleTab<T>::pt(base + q);
+    const T qa = rp.a, qb = rp.b, qw = rp.w;
     const T ta = fma(qa, q11, qa1);
     T tb = fma(qb, q22, qb1);
     tb = fma(qa, q12, tb);
@@ -367,6 +382,17 @@ __device__ inline void integrate_item(const T* __restrict__ rec, uint64_t item, 
   s2i = a2i * f2;
 }
 
+template <typename T, bool WANT_S1, bool WANT_S2>
+__device__ inline void integrate_item(const T* __restrict__ rec, uint64_t item, int m, const T xs[3],
+                                      const T ni[3], const PointConsts<T>& P, T& s1r, T& s1i, T& s2r,
+                                      T& s2i, int64_t& jout) {
+  const int64_t j = (int64_t)(item & ((uint64_t(1) << 26) - 1));
+  jout = j;
+  T r[kRec];
+  Rec<T>::load(rec, j, r);
+  integrate_loaded<T, WANT_S1, WANT_S2>(r, item, m, xs, ni, P, s1r, s1i, s2r, s2i);
+}
+
 template <typename T> __device__ inline const T* near_rec(const NearLaunch& L);
 template <> __device__ inline const double* near_rec<double>(const NearLaunch& L) { return L.rec; }
 template <> __device__ inline const float* near_rec<float>(const NearLaunch& L) { return L.rec32; }
@@ -374,62 +400,100 @@ template <typename T> __device__ inline double near_kap(const NearLaunch& L);
 template <> __device__ inline double near_kap<double>(const NearLaunch& L) { return L.kap; }
 template <> __device__ inline double near_kap<float>(const NearLaunch& L) { return L.kap32; }
 
+// One pipeline slot of the forward kernel: an item and what its source
+// contributes besides the rule (record, x_j, c_j).
+template <typename T> struct Slot {
+  uint64_t item;
+  T r[kRec];
+  double2 x, c;
+};
+template <typename T, bool NEED_C>
+__device__ inline void load_slot(const NearLaunch& L, const T* __restrict__ rec, const double2* __restrict__ x,
+                                 uint64_t item, Slot<T>& S) {
+  const int64_t j = (int64_t)(item & ((uint64_t(1) << 26) - 1));
+  S.item = item;
+  Rec<T>::load(rec, j, S.r);
+  S.x = x[j];
+  if (NEED_C) S.c = L.cfac[j];
+}
+// acc += K_ij x_j (VMODE: the dA/dc entry) for the slot's item
+template <typename T, bool HAS_C, bool VMODE>
+__device__ inline void accumulate_slot(const Slot<T>& S, int m, const T xs[3], const T ni[3],
+                                       const PointConsts<T>& P, T& accr, T& acci) {
+  T s1r, s1i, s2r, s2i;
+  integrate_loaded<T, !VMODE, HAS_C || VMODE>(S.r, S.item, m, xs, ni, P, s1r, s1i, s2r, s2i);
+  T vr = s1r, vi = s1i;
+  if (VMODE) {
+    vr = s2r;
+    vi = s2i;
+  } else if (HAS_C) {
+    const T cr = (T)S.c.x, ci = (T)S.c.y;
+    vr += cr * s2r - ci * s2i;
+    vi += cr * s2i + ci * s2r;
+  }
+  const T xr = (T)S.x.x, xim = (T)S.x.y;
+  accr += vr * xr - vi * xim;
+  acci += vr * xim + vi * xr;
+}
+
 // VMODE: apply dA/dc -- the (G - gamma H') part without c_j, diagonal
 // G_ii - gamma/2 -- instead of A.
-// WPB wavefronts (targets) per workgroup; the launch shape is a tuning choice
+// WPB wavefronts per workgroup; the launch shape is a tuning choice.  With
+// one wavefront per target the grid covers all targets; a smaller grid
+// (L.nwaves) keeps its wavefronts resident and each loops over the targets
+// w, w + stride, ..., leaving wavefront slots to kernels that run beside it.
 template <typename T, bool HAS_C, bool VMODE, int WPB = 4>
 __global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __restrict__ g,
                                                    const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
-  // the target is uniform across the wavefront: say so, so that its data go
-  // through scalar loads and registers.  Targets are visited in L.order
-  // (groups of decreasing work), so the last wavefronts to start are short ones.
-  const int64_t w = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= L.N) return;  // the whole wavefront leaves together
-  const int64_t t = L.order ? (int64_t)L.order[w] : w;
   const int64_t N = L.N;
   const double kap = near_kap<T>(L);
   const T* __restrict__ rec = near_rec<T>(L);
-  T xs[3], ni[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    xs[c] = (T)(kap * L.geom[(CX + c) * N + t]);
-    ni[c] = g[(NX + c) * N + t];
-  }
   const PointConsts<T> P = point_consts<T>(L.k, kap, L.gre, L.gim);
-  T accr = 0, acci = 0;
-  // the target's items are sorted by rule order; seg[t][m-1] .. seg[t][m]
-  // holds the order-m items, so every pass below runs one uniform rule
-  const int64_t* sg = L.seg + t * (kMaxRuleOrder + 1);
-  for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
-    const int64_t b = sg[mc], e = sg[mc + 1];
-    if (b == e) continue;
-    for (int64_t it = b + lane; it < e; it += 64) {
-      T s1r, s1i, s2r, s2i;
-      int64_t j;
-      integrate_item<T, !VMODE, HAS_C || VMODE>(rec, L.items[it], mc + 1, xs, ni, P, s1r, s1i, s2r, s2i, j);
-      T vr = s1r, vi = s1i;
-      if (VMODE) {
-        vr = s2r;
-        vi = s2i;
-      } else if (HAS_C) {
-        const double2 c = L.cfac[j];
-        const T cr = (T)c.x, ci = (T)c.y;
-        vr += cr * s2r - ci * s2i;
-        vi += cr * s2i + ci * s2r;
-      }
-      const double2 xj = x[j];
-      const T xr = (T)xj.x, xim = (T)xj.y;
-      accr += vr * xr - vi * xim;
-      acci += vr * xim + vi * xr;
+  constexpr bool NEED_C = HAS_C && !VMODE;
+  const int64_t stride = (int64_t)gridDim.x * WPB;
+  // the target is uniform across the wavefront: say so, so that its data go
+  // through scalar loads and registers.  Targets are visited in L.order
+  // (groups of decreasing work), so the last wavefronts to start are short ones.
+  for (int64_t w = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); w < N;
+       w += stride) {
+    const int64_t t = L.order ? (int64_t)L.order[w] : w;
+    T xs[3], ni[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xs[c] = (T)(kap * L.geom[(CX + c) * N + t]);
+      ni[c] = g[(NX + c) * N + t];
     }
-  }
-  double sr = wave_sum((double)accr);
-  double si = wave_sum((double)acci);
-  if (lane == 0) {
-    const double2 d = VMODE ? L.vdiag[t] : L.diag[t];
-    const double2 xt = x[t];
-    y[t] = make_double2(d.x * xt.x - d.y * xt.y + sr, d.x * xt.y + d.y * xt.x + si);
+    T accr = 0, acci = 0;
+    // the target's items are sorted by rule order; seg[t][m-1] .. seg[t][m]
+    // holds the order-m items, so every pass below runs one uniform rule
+    const int64_t* sg = L.seg + t * (kMaxRuleOrder + 1);
+    for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
+      const int64_t b = sg[mc], e = sg[mc + 1];
+      if (b == e) continue;
+      // passes of 64 items; each pass loads the next pass's item (index
+      // clamped into the segment) before integrating its own
+      const int64_t npass = (e - b + 63) >> 6;
+      const int64_t last = e - 1;
+      int64_t it = b + lane;
+      uint64_t item = L.items[it < last ? it : last];
+      for (int64_t p = 0; p < npass; ++p, it += 64) {
+        const uint64_t next = L.items[it + 64 < last ? it + 64 : last];
+        if (it < e) {
+          Slot<T> S;
+          load_slot<T, NEED_C>(L, rec, x, item, S);
+          accumulate_slot<T, HAS_C, VMODE>(S, mc + 1, xs, ni, P, accr, acci);
+        }
+        item = next;
+      }
+    }
+    double sr = wave_sum((double)accr);
+    double si = wave_sum((double)acci);
+    if (lane == 0) {
+      const double2 d = VMODE ? L.vdiag[t] : L.diag[t];
+      const double2 xt = x[t];
+      y[t] = make_double2(d.x * xt.x - d.y * xt.y + sr, d.x * xt.y + d.y * xt.x + si);
+    }
   }
 }
 
@@ -497,7 +561,8 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
 
 template <typename T, int WPB>
 void near_forward(const NearLaunch& L, const T* g, const double2* x, double2* y, hipStream_t s) {
-  dim3 grid((unsigned)((L.N + WPB - 1) / WPB)), block(64 * WPB);
+  const int64_t waves = L.nwaves > 0 && L.nwaves < L.N ? L.nwaves : L.N;
+  dim3 grid((unsigned)((waves + WPB - 1) / WPB)), block(64 * WPB);
   if (L.cfac) hipLaunchKernelGGL((k_near<T, true, false, WPB>), grid, block, 0, s, L, g, x, y);
   else hipLaunchKernelGGL((k_near<T, false, false, WPB>), grid, block, 0, s, L, g, x, y);
 }

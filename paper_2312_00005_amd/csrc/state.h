@@ -31,6 +31,7 @@ struct bem_mesh {
   bem::DevBuf<double> d_rec;       // element records of the quadrature kernels (per wavenumber)
   bem::DevBuf<float> d_rec32;
   double kap = 0.0, kap32 = 0.0;   // their scales
+  int n_cu = 256;                  // compute units of the mesh's device
   bem::DevBuf<uint64_t> d_items, d_items_t;
   bem::DevBuf<double> d_duffy_u, d_duffy_w, d_edge_t, d_edge_w;
 
@@ -47,6 +48,7 @@ struct bem_mesh {
   // launch shapes chosen by bem_autotune, [0] FP64, [1] complex FP32
   int tune_wpb[2] = {4, 4};     // near-field targets per workgroup
   int tune_tpb[2] = {64, 64};   // translation threads per workgroup
+  int tune_nwaves[2] = {0, 0};  // resident near-field wavefronts per CU beside the far field (0: one per target)
 
   // captured operator applications of the Krylov driver, [op][precision]
   struct GraphSlot {

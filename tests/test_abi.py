@@ -85,6 +85,10 @@ def test_invalid_arguments(bem):
     with pytest.raises(bem.BemError) as e:
         bem.Mesh(nodes, tris, "paper", use_fmm=0, gmres_restart=0)
     assert e.value.status == bem.BEM_E_ARG
+    for nw in (-1, 65):
+        with pytest.raises(bem.BemError) as e:
+            bem.Mesh(nodes, tris, "paper", use_fmm=0, near_waves_per_cu=nw)
+        assert e.value.status == bem.BEM_E_ARG
     with pytest.raises(bem.BemError):
         bem.bem_mesh_create(3, None, 1, None, bem.bem_options_default("paper"))
 

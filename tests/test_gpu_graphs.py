@@ -58,7 +58,14 @@ def test_autotune_keeps_results(bem):
     announce(f"  picks {picks}")
     assert set(picks["near_wpb"].values()) <= {1, 2, 4, 8}
     assert set(picks["translate_tpb"].values()) <= {64, 128, 256}
+    assert set(picks["near_waves_per_cu"].values()) <= {0, 8, 12, 16, 24}
     for p in ("fp64", "mixed"):
         assert np.array_equal(to_host(m.apply(x, prec=p)), before[p])
+    # a resident near-field grid (each wavefront looping over targets) changes
+    # no output either
+    m8 = bem.Mesh(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=32, near_waves_per_cu=8)
+    m8.set_problem(k)
+    for p in ("fp64", "mixed"):
+        assert np.array_equal(to_host(m8.apply(x, prec=p)), before[p])
     p1, _, info = m.solve(m.rhs_plane_wave((0.0, 0.0, 1.0)))
     assert info["rel_residual"] < 1e-6
