@@ -19,13 +19,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic flops per near-field quadrature point of the fused kernel, FMA
-# counted as two, rsqrt, sin and cos as one each: the quadratic form for
-# |y - x|^2 (10), rsqrt, r, phase, sin, cos (5), weight and G (3), the two
-# normal projections (6), the hypersingular combination t1 (10), b1 (10) and
-# the complex accumulation (8); 68 with the admittance terms
-FLOPS_PER_POINT = 52
-FLOPS_PER_POINT_BC = 68
+# algorithmic flops per near-field quadrature point of the fused formula (the
+# Burton-Miller integrand as a polynomial in the scaled inverse distance U),
+# FMA counted as two, rsqrt, sin and cos as one each: the quadratic form for
+# the scaled |y - x|^2 (10), rsqrt and phase (2), sin and cos (2), the affine
+# normal projection (4), the Horner form in U (16), weight times U^2 and the
+# phase factor (4), the complex accumulation (8); 61 with the admittance terms
+FLOPS_PER_POINT = 46
+FLOPS_PER_POINT_BC = 61
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 WORKLOADS = {
