@@ -315,9 +315,51 @@ __device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, c
     q12 = T(2) * (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]);
     area2 = ldexp(area2, -2 * depth);
   }
+  const T nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
   T d0[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) d0[c] = v0[c] - xs[c];
+  if (m == 1) {
+    // one rule point (most far pairs): the integrand at y itself, without
+    // the quadratic-form coefficients
+    const auto rp = RuleTab<T>::pt(c_rule_off[0]);
+    T d[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c] = fma(rp.a, e1[c], fma(rp.b, e2[c], d0[c]));
+    const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const T U = rsqrt_t(r2);
+    T sn, cs;
+    Phase<T>::sincos(r2 * U, &sn, &cs);
+    const T hn = d[0] * nj[0] + d[1] * nj[1] + d[2] * nj[2];
+    const T cx = d[0] * ni[0] + d[1] * ni[1] + d[2] * ni[2];
+    const T Rr = fma(U, P.Q2r, P.Q1r), Ri = fma(U, P.Q2i, P.Q1i);
+    const T qwU = rp.w * U;
+    T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+    if (WANT_S1) {
+      const T sg = T(3) * hn * cx;
+      const T Hr = fma(P.kgr, nn, hn), Hi = P.kgi * nn;
+      const T Wr = fma(sg, fma(U, Rr, P.Q0r), Hr);
+      const T Wi = fma(sg, fma(U, Ri, P.Q0i), Hi);
+      const T Vr = fma(U, Wr, P.kr * Hi), Vi = fma(U, Wi, -P.kr * Hr);
+      const T g2 = qwU * U;
+      const T Gr = g2 * cs, Gi = g2 * sn;
+      a1r = fma(Gr, Vr, -Gi * Vi);
+      a1i = fma(Gr, Vi, Gi * Vr);
+    }
+    if (WANT_S2) {
+      const T cU = cx * U;
+      const T Zr = fma(cU, Rr, T(1)), Zi = cU * Ri;
+      const T Gr = qwU * cs, Gi = qwU * sn;
+      a2r = fma(Gr, Zr, -Gi * Zi);
+      a2i = fma(Gr, Zi, Gi * Zr);
+    }
+    const T f2 = area2 * P.ikap;
+    s1r = a1r * area2;
+    s1i = a1i * area2;
+    s2r = a2r * f2;
+    s2i = a2i * f2;
+    return;
+  }
   // |d0 + a e1 + b e2|^2 = q00 + a (qa1 + a q11) + b (qb1 + b q22 + a q12)
   const T q00 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
   const T qa1 = T(2) * (d0[0] * e1[0] + d0[1] * e1[1] + d0[2] * e1[2]);
@@ -334,7 +376,6 @@ __device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, c
     c1 *= h3;
     c2 *= h3;
   }
-  const T nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
   const T Hr = fma(P.kgr, nn, hn), Hi = P.kgi * nn;
   const T Hkr = P.kr * Hi, Hki = -P.kr * Hr;
   const int base = c_rule_off[m - 1];
@@ -738,10 +779,11 @@ template <> __device__ inline double far_kap<double>(const FarLaunch& F) { retur
 template <> __device__ inline double far_kap<float>(const FarLaunch& F) { return F.kap32; }
 
 // order for r~^2 (0: split)
-__device__ inline int far_order(const FarLaunch& F, double rt2) {
-  if (rt2 < F.ratio2) return 0;
+// r~^2 = d2 / area, compared as d2 against threshold * area (no division)
+__device__ inline int far_order(const FarLaunch& F, double d2, double area) {
+  if (d2 < F.ratio2 * area) return 0;
   for (int m = 1; m <= F.m_max; ++m)
-    if (rt2 > F.rt2_min[m - 1]) return m;
+    if (d2 > F.rt2_min[m - 1] * area) return m;
   return F.split_on_cap ? 0 : F.m_max;
 }
 
@@ -766,7 +808,7 @@ __device__ void far_pair_split(const FarLaunch& F, const T* g, const T* rec, int
       d2 += dc * dc;
     }
     const double area = area0 * ldexp(1.0, -2 * depth);
-    int m = far_order(F, d2 / area);
+    int m = far_order(F, d2, area);
     if (m == 0 && depth < F.max_subdiv && depth < 15) {
       ++depth;
       continue;
@@ -843,7 +885,7 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
           const double dc = (double)xi[c] - (double)g[(CX + c) * N + j];
           d2 += dc * dc;
         }
-        m = far_order(F, d2 / (double)g[AREA * N + j]);
+        m = far_order(F, d2, (double)g[AREA * N + j]);
       }
       T s1r = 0, s1i = 0, s2r = 0, s2i = 0;
       // one uniform rule per pass
