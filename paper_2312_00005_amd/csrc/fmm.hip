@@ -328,11 +328,173 @@ __global__ __launch_bounds__(256) void k_down_equal(const int64_t* __restrict__ 
   locc[c * nu + v] = cadd(locc[c * nu + v], add);
 }
 
+// Level-transfer kernels: small dense products whose table (DFT matrix, or
+// a cluster's input rows for the theta resampling) is shared by every row of
+// a cluster.  A block holds kXferRows rows, one per wavefront, and stages
+// the table in LDS when it fits in kXferTab bytes (TAB), so the table is
+// read from L2 once per block instead of once per row.
+constexpr int kXferRows = 4;
+constexpr size_t kXferTab = 49152;
+// row-blocked forms only for launches of at least this many blocks
+constexpr int64_t kXferMinBlocks = 2048;
+
+// out[c][t][mi] = sum_j val(j) Et[j][mi], Et stored j-major (consecutive lanes
+// read consecutive mi).  mode 0: val(j) = in[c][t][j]; mode 1: val(j) =
+// conj(shift[c][t][j]) in[parent[c]][t][j].
+template <typename T, typename V, bool TAB>
+__global__ __launch_bounds__(256) void k_dft(int nt, int nj, int nm, int rl, const V* __restrict__ in,
+                                             const V* __restrict__ shift, const int64_t* __restrict__ parent,
+                                             int mode, const V* __restrict__ Et, V* __restrict__ out) {
+  extern __shared__ unsigned char xfer_smem[];
+  V* row = reinterpret_cast<V*>(xfer_smem);  // kXferRows x rl (rl >= nj)
+  V* tab = row + kXferRows * rl;             // nj x nm when TAB
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kXferRows + w;
+  const int64_t c = blockIdx.y;
+  if (TAB)
+    for (int i = threadIdx.x; i < nj * nm; i += 256) tab[i] = Et[i];
+  if (t < nt) {
+    const int64_t rowoff = (int64_t)t * nj;
+    V* rw = row + w * rl;
+    if (mode == 0) {
+      const V* src = in + c * (int64_t)nt * nj + rowoff;
+      for (int jj = lane; jj < nj; jj += 64) rw[jj] = src[jj];
+    } else {
+      const V* src = in + parent[c] * (int64_t)nt * nj + rowoff;
+      const V* sh = shift + c * (int64_t)nt * nj + rowoff;
+      for (int jj = lane; jj < nj; jj += 64) rw[jj] = cmulc(sh[jj], src[jj]);
+    }
+  }
+  __syncthreads();
+  if (t >= nt) return;  // no barrier below
+  const V* E = TAB ? tab : Et;
+  const V* rw = row + w * rl;
+  V* o = out + (c * nt + t) * (int64_t)nm;
+  for (int mi = lane; mi < nm; mi += 64) {
+    V acc = mk(T(0), T(0));
+    for (int jj = 0; jj < nj; ++jj) acc = cadd(acc, cmul(rw[jj], E[(int64_t)jj * nm + mi]));
+    o[mi] = acc;
+  }
+}
+
+// out[c][to][mi] = sum_ti M[to][ti][|m|] in[c][ti][mi], m = mi - mhalf; the
+// cluster's input rows are the staged table.
+template <typename T, typename V, bool TAB>
+__global__ __launch_bounds__(256) void k_theta(int nto, int nti, int nm, int mhalf, int nmh, const T* __restrict__ M,
+                                               const V* __restrict__ in, V* __restrict__ out) {
+  extern __shared__ unsigned char xfer_smem[];
+  V* tab = reinterpret_cast<V*>(xfer_smem);  // nti x nm when TAB
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int to = blockIdx.x * kXferRows + w;
+  const int64_t c = blockIdx.y;
+  const V* src = in + c * (int64_t)nti * nm;
+  if (TAB) {
+    for (int i = threadIdx.x; i < nti * nm; i += 256) tab[i] = src[i];
+    __syncthreads();
+  }
+  if (to >= nto) return;  // no barrier below
+  const V* S = TAB ? tab : src;
+  const T* Mr = M + (int64_t)to * nti * nmh;
+  V* o = out + (c * nto + to) * (int64_t)nm;
+  for (int mi = lane; mi < nm; mi += 64) {
+    int am = mi - mhalf;
+    if (am < 0) am = -am;
+    T ar = 0, ai = 0;
+    for (int ti = 0; ti < nti; ++ti) {
+      const V a = S[(int64_t)ti * nm + mi];
+      const T wv = Mr[(int64_t)ti * nmh + am];
+      ar += wv * a.x;
+      ai += wv * a.y;
+    }
+    o[mi] = mk(ar, ai);
+  }
+}
+
+// sigp[p][t][j] = sum_{c in children(p)} shift[c][t][j] sum_mi G[c][t][mi] E[mi][j];
+// one wavefront per row t, lanes over j (up to 4 per lane, nj <= 256).
+template <typename T, typename V, bool TAB>
+__global__ __launch_bounds__(256) void k_up_idft(const int64_t* __restrict__ cbeg, const int64_t* __restrict__ cend,
+                                                 int nt, int nj, int nm, int rl, const V* __restrict__ G,
+                                                 const V* __restrict__ E, const V* __restrict__ shift,
+                                                 V* __restrict__ sigp) {
+  extern __shared__ unsigned char xfer_smem[];
+  V* g = reinterpret_cast<V*>(xfer_smem);  // kXferRows x rl (rl >= nm)
+  V* tab = g + kXferRows * rl;             // nm x nj when TAB
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kXferRows + w;
+  const bool act = t < nt;
+  const int64_t p = blockIdx.y;
+  if (TAB)
+    for (int i = threadIdx.x; i < nm * nj; i += 256) tab[i] = E[i];
+  const V* Et = TAB ? tab : E;
+  V* gw = g + w * rl;
+  V acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = mk(T(0), T(0));
+  // every wavefront of the block walks the same children (uniform barriers)
+  for (int64_t c = cbeg[p]; c < cend[p]; ++c) {
+    __syncthreads();
+    if (act) {
+      const V* gc = G + (c * nt + t) * (int64_t)nm;
+      for (int mi = lane; mi < nm; mi += 64) gw[mi] = gc[mi];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int jj = lane + 64 * q;
+        if (jj < nj) {
+          V sacc = mk(T(0), T(0));
+          for (int mi = 0; mi < nm; ++mi) sacc = cadd(sacc, cmul(gw[mi], Et[(int64_t)mi * nj + jj]));
+          acc[q] = cadd(acc[q], cmul(shift[(c * nt + t) * (int64_t)nj + jj], sacc));
+        }
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jj = lane + 64 * q;
+      if (jj < nj) sigp[(p * nt + t) * (int64_t)nj + jj] = acc[q];
+    }
+  }
+}
+
+// locc[c][t][j] += sum_mi K[c][t][mi] E[mi][j]; one wavefront per row t.
+template <typename T, typename V, bool TAB>
+__global__ __launch_bounds__(256) void k_down_idft(int nt, int nj, int nm, int rl, const V* __restrict__ K,
+                                                   const V* __restrict__ E, V* __restrict__ locc) {
+  extern __shared__ unsigned char xfer_smem[];
+  V* kk = reinterpret_cast<V*>(xfer_smem);  // kXferRows x rl (rl >= nm)
+  V* tab = kk + kXferRows * rl;             // nm x nj when TAB
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kXferRows + w;
+  const int64_t c = blockIdx.y;
+  if (TAB)
+    for (int i = threadIdx.x; i < nm * nj; i += 256) tab[i] = E[i];
+  V* kw = kk + w * rl;
+  if (t < nt) {
+    const V* kr = K + (c * nt + t) * (int64_t)nm;
+    for (int mi = lane; mi < nm; mi += 64) kw[mi] = kr[mi];
+  }
+  __syncthreads();
+  if (t >= nt) return;  // no barrier below
+  const V* Et = TAB ? tab : E;
+  for (int jj = lane; jj < nj; jj += 64) {
+    V sacc = mk(T(0), T(0));
+    for (int mi = 0; mi < nm; ++mi) sacc = cadd(sacc, cmul(kw[mi], Et[(int64_t)mi * nj + jj]));
+    const int64_t o = (c * nt + t) * (int64_t)nj + jj;
+    locc[o] = cadd(locc[o], sacc);
+  }
+}
+
+// One-row-per-block forms (table read from L2), used where a level has too
+// few clusters for the row-blocked forms to fill the chip.
 // One 64-lane block per (cluster c, row t): out[c][t][mi] = sum_j val(j) Et[j][mi]
 // with Et the DFT table stored j-major (consecutive lanes read consecutive mi).
 // mode 0: val(j) = in[c][t][j]; mode 1: val(j) = conj(shift[c][t][j]) in[parent[c]][t][j].
 template <typename T, typename V>
-__global__ __launch_bounds__(64) void k_dft(int nt, int nj, int nm, const V* __restrict__ in,
+__global__ __launch_bounds__(64) void k_dft_row(int nt, int nj, int nm, const V* __restrict__ in,
                                             const V* __restrict__ shift, const int64_t* __restrict__ parent,
                                             int mode, const V* __restrict__ Et, V* __restrict__ out) {
   __shared__ V row[256];
@@ -356,34 +518,10 @@ __global__ __launch_bounds__(64) void k_dft(int nt, int nj, int nm, const V* __r
   }
 }
 
-// One 64-lane block per (cluster c, output row to):
-// out[c][to][mi] = sum_ti M[to][ti][|m|] in[c][ti][mi], m = mi - mhalf.
-template <typename T, typename V>
-__global__ __launch_bounds__(64) void k_theta(int nto, int nti, int nm, int mhalf, int nmh, const T* __restrict__ M,
-                                              const V* __restrict__ in, V* __restrict__ out) {
-  const int to = blockIdx.x;
-  const int64_t c = blockIdx.y;
-  const V* src = in + c * (int64_t)nti * nm;
-  const T* Mr = M + (int64_t)to * nti * nmh;
-  V* o = out + (c * nto + to) * (int64_t)nm;
-  for (int mi = threadIdx.x; mi < nm; mi += 64) {
-    int am = mi - mhalf;
-    if (am < 0) am = -am;
-    T ar = 0, ai = 0;
-    for (int ti = 0; ti < nti; ++ti) {
-      const V a = src[(int64_t)ti * nm + mi];
-      const T w = Mr[(int64_t)ti * nmh + am];
-      ar += w * a.x;
-      ai += w * a.y;
-    }
-    o[mi] = mk(ar, ai);
-  }
-}
-
 // One block per (parent p, row t), lanes over j:
 // sigp[p][t][j] = sum_{c in children(p)} shift[c][t][j] sum_mi G[c][t][mi] E[mi][j]
 template <typename T, typename V>
-__global__ __launch_bounds__(128) void k_up_idft(const int64_t* __restrict__ cbeg, const int64_t* __restrict__ cend,
+__global__ __launch_bounds__(128) void k_up_idft_row(const int64_t* __restrict__ cbeg, const int64_t* __restrict__ cend,
                                                  int nt, int nj, int nm, const V* __restrict__ G,
                                                  const V* __restrict__ E, const V* __restrict__ shift,
                                                  V* __restrict__ sigp) {
@@ -412,7 +550,7 @@ __global__ __launch_bounds__(128) void k_up_idft(const int64_t* __restrict__ cbe
 
 // One block per (cluster c, row t), lanes over j: locc[c][t][j] += sum_mi K[c][t][mi] E[mi][j]
 template <typename T, typename V>
-__global__ __launch_bounds__(128) void k_down_idft(int nt, int nj, int nm, const V* __restrict__ K,
+__global__ __launch_bounds__(128) void k_down_idft_row(int nt, int nj, int nm, const V* __restrict__ K,
                                                    const V* __restrict__ E, V* __restrict__ locc) {
   __shared__ V kk[256];
   const int t = blockIdx.x;
@@ -533,35 +671,61 @@ template <typename T, typename V>
 void launch_fmm_dft(int64_t nc, int nt, int nj, int nm, const V* in, const V* shift, const int64_t* parent,
                     int mode, const V* Et, V* out, hipStream_t st) {
   if (nc <= 0 || nt <= 0) return;
-  hipLaunchKernelGGL((k_dft<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(64), 0, st, nt, nj, nm, in, shift,
-                     parent, mode, Et, out);
+  const dim3 grid((unsigned)((nt + kXferRows - 1) / kXferRows), (unsigned)nc);
+  const int rl = (nj + 1) & ~1;
+  const size_t rows = kXferRows * (size_t)rl * sizeof(V), tab = (size_t)nj * nm * sizeof(V);
+  if (tab <= kXferTab && (int64_t)grid.x * nc >= kXferMinBlocks)
+    hipLaunchKernelGGL((k_dft<T, V, true>), grid, dim3(256), rows + tab, st, nt, nj, nm, rl, in, shift, parent, mode,
+                       Et, out);
+  else
+    hipLaunchKernelGGL((k_dft_row<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(64), 0, st, nt, nj, nm, in, shift,
+                       parent, mode, Et, out);
 }
 
 template <typename T, typename V>
 void launch_fmm_theta(int64_t nc, int nto, int nti, int nm, int mhalf, const T* M, const V* in, V* out,
                       hipStream_t st) {
   if (nc <= 0 || nto <= 0) return;
-  hipLaunchKernelGGL((k_theta<T, V>), dim3((unsigned)nto, (unsigned)nc), dim3(64), 0, st, nto, nti, nm, mhalf,
-                     mhalf + 1, M, in, out);
+  const dim3 grid((unsigned)((nto + kXferRows - 1) / kXferRows), (unsigned)nc);
+  const size_t tab = (size_t)nti * nm * sizeof(V);
+  if (tab <= kXferTab)
+    hipLaunchKernelGGL((k_theta<T, V, true>), grid, dim3(256), tab, st, nto, nti, nm, mhalf, mhalf + 1, M, in, out);
+  else
+    hipLaunchKernelGGL((k_theta<T, V, false>), grid, dim3(256), 0, st, nto, nti, nm, mhalf, mhalf + 1, M, in, out);
 }
 
 template <typename T, typename V>
 void launch_fmm_up_idft(int64_t np, const int64_t* cbeg, const int64_t* cend, int nt, int nj, int nm,
                         const V* G, const V* E, const V* shift, V* sigp, hipStream_t st) {
   if (np <= 0 || nt <= 0) return;
-  // one wavefront covers nj <= 64; the kernel walks two chunks of blockDim
-  const unsigned threads = nj <= 64 ? 64 : 128;
-  hipLaunchKernelGGL((k_up_idft<T, V>), dim3((unsigned)nt, (unsigned)np), dim3(threads), 0, st, cbeg, cend, nt, nj,
-                     nm, G, E, shift, sigp);
+  const dim3 grid((unsigned)((nt + kXferRows - 1) / kXferRows), (unsigned)np);
+  const int rl = (nm + 1) & ~1;
+  const size_t rows = kXferRows * (size_t)rl * sizeof(V), tab = (size_t)nm * nj * sizeof(V);
+  if (tab <= kXferTab) {  // each block also walks the children: few blocks suffice
+    hipLaunchKernelGGL((k_up_idft<T, V, true>), grid, dim3(256), rows + tab, st, cbeg, cend, nt, nj, nm, rl, G, E,
+                       shift, sigp);
+  } else {
+    // one wavefront covers nj <= 64; the kernel walks two chunks of blockDim
+    const unsigned threads = nj <= 64 ? 64 : 128;
+    hipLaunchKernelGGL((k_up_idft_row<T, V>), dim3((unsigned)nt, (unsigned)np), dim3(threads), 0, st, cbeg, cend, nt,
+                       nj, nm, G, E, shift, sigp);
+  }
 }
 
 template <typename T, typename V>
 void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const V* E, V* locc,
                           hipStream_t st) {
   if (nc <= 0 || nt <= 0) return;
-  const unsigned threads = nj <= 64 ? 64 : 128;
-  hipLaunchKernelGGL((k_down_idft<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(threads), 0, st, nt, nj, nm, K, E,
-                     locc);
+  const dim3 grid((unsigned)((nt + kXferRows - 1) / kXferRows), (unsigned)nc);
+  const int rl = (nm + 1) & ~1;
+  const size_t rows = kXferRows * (size_t)rl * sizeof(V), tab = (size_t)nm * nj * sizeof(V);
+  if (tab <= kXferTab && (int64_t)grid.x * nc >= kXferMinBlocks) {
+    hipLaunchKernelGGL((k_down_idft<T, V, true>), grid, dim3(256), rows + tab, st, nt, nj, nm, rl, K, E, locc);
+  } else {
+    const unsigned threads = nj <= 64 ? 64 : 128;
+    hipLaunchKernelGGL((k_down_idft_row<T, V>), dim3((unsigned)nt, (unsigned)nc), dim3(threads), 0, st, nt, nj, nm, K,
+                       E, locc);
+  }
 }
 
 #define BEM_FMM_INST(T, V)                                                                                    \
