@@ -221,6 +221,8 @@ __global__ __launch_bounds__(256) void k_aggregate(const int64_t* __restrict__ e
   const int64_t c = blockIdx.y;
   if (v >= nu) return;
   V acc = mk(T(0), T(0));
+  // unrolled so that several rows are in flight per lane
+#pragma unroll 8
   for (int64_t j = ebeg[c]; j < eend[c]; ++j) {
     V t = Tm[j * nu + v];
     if (CONJ) t = mk(t.x, -t.y);
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(256) void k_disaggregate(int64_t N, const int64_t* 
   if (i >= N) return;
   const int64_t c = ec[i];
   T ar = 0, ai = 0;
+#pragma unroll 4
   for (int v = lane; v < nu; v += 64) {
     V a = Sm[i * nu + v];
     if (FACTOR) a = cmul(a, source_factor<T, V>(F, i, v));
