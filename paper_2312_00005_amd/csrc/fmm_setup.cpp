@@ -55,6 +55,14 @@ struct FmmLevel {
   // EcT/EpT/EpcT node-major for the forward DFTs (c: conjugated)
   DevBuf<double2> Ec64, Ep64, Ecc64, EcT64, EpT64, EpcT64, tA64, tB64;
   DevBuf<float2> Ec32, Ep32, Ecc32, EcT32, EpT32, EpcT32, tA32, tB32;
+  // what depends only on the expansion lengths is kept across wavenumbers:
+  // the sphere grid (L it was built for, theta nodes and weights on the
+  // host) and the transfer tables (child and own L they were built for)
+  int grid_L = -1;
+  std::vector<double> xt_h, wt_h;
+  int xfer_Lc = -1, xfer_Lp = -1;
+  // tree-only: largest cluster radius, shortest interaction distance
+  double rmax = 0.0, xmin = -1.0;
 };
 
 }  // namespace
@@ -195,6 +203,15 @@ void upload_tree(bem_mesh* m, FmmState* F, hipStream_t s) {
     const Level& L = T.lv[l];
     FmmLevel& D = F->set[si].lv[l];
     D.nc = L.nc;
+    for (double r : L.r) D.rmax = std::max(D.rmax, r);
+    for (int64_t c = 0; c < L.nc; ++c)
+      for (int64_t q = L.il_off[c]; q < L.il_off[c + 1]; ++q) {
+        const int64_t n = L.il[q];
+        const double d0 = L.z[3 * c] - L.z[3 * n], d1 = L.z[3 * c + 1] - L.z[3 * n + 1],
+                     d2 = L.z[3 * c + 2] - L.z[3 * n + 2];
+        const double v = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        if (D.xmin < 0.0 || v < D.xmin) D.xmin = v;
+      }
     upload_vec(D.z, L.z, s);
     upload_vec(D.il_off, L.il_off, s);
     upload_vec(D.il, L.il, s);
@@ -466,7 +483,6 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
   const Tree& T = m->tree;
   const int nl = (int)T.lv.size();
   const double k = m->k;
-  std::vector<std::vector<double>> xt(nl), wt(nl);
   F->top = nl - 1;
   for (int l = 0; l < nl; ++l)
     if (F->lv[l].npairs > 0) {
@@ -479,29 +495,21 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     if (single) m->fmm_L32[l] = 0;
     else m->fmm_L[l] = 0;
   }
+  // (uploads are synchronous: DevBuf::upload waits for its copy)
   for (int l = F->top; l < nl; ++l) {
     FmmLevel& D = F->lv[l];
-    const Level& L = T.lv[l];
-    double rmax = 0.0;
-    for (double r : L.r) rmax = std::max(rmax, r);
-    double xmin = -1.0;
-    for (int64_t c = 0; c < L.nc; ++c)
-      for (int64_t q = L.il_off[c]; q < L.il_off[c + 1]; ++q) {
-        const int64_t n = L.il[q];
-        const double d0 = L.z[3 * c] - L.z[3 * n], d1 = L.z[3 * c + 1] - L.z[3 * n + 1],
-                     d2 = L.z[3 * c + 2] - L.z[3 * n + 2];
-        const double v = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        if (xmin < 0.0 || v < xmin) xmin = v;
-      }
-    D.L = truncation_length(k, rmax, o, xmin, single);
+    D.L = truncation_length(k, D.rmax, o, D.xmin, single);
     if (D.L > 120) throw Error(BEM_E_ARG, "expansion length " + std::to_string(D.L) + " above the supported 120");
     if (single) m->fmm_L32[l] = D.L;
     else m->fmm_L[l] = D.L;
     D.nu = 2 * D.L * D.L;
-    std::vector<double> sh, wh;
-    sphere_grid(D.L, sh, wh, xt[l], wt[l]);
-    D.s.upload(sh, s);
-    D.w.upload(wh, s);
+    if (D.grid_L != D.L) {
+      std::vector<double> sh, wh;
+      sphere_grid(D.L, sh, wh, D.xt_h, D.wt_h);
+      D.s.upload(sh, s);
+      D.w.upload(wh, s);
+      D.grid_L = D.L;
+    }
     const size_t nd = (size_t)std::max<int64_t>(1, D.npairs) * D.nu;
     if (single) {
       D.D32.alloc(nd);
@@ -528,10 +536,25 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     const int Lc = C.L, Lp = P.L;
     const int nm = 2 * Lc - 1;
     P.nm = nm;
+    const size_t tmp = (size_t)C.nc * std::max(Lc, Lp) * nm;
+    if (single) {
+      P.tA32.alloc(tmp);
+      P.tB32.alloc(tmp);
+    } else {
+      P.tA64.alloc(tmp);
+      P.tB64.alloc(tmp);
+    }
+    if (P.xfer_Lc == Lc && P.xfer_Lp == Lp) continue;  // tables of these lengths are in place
+    P.xfer_Lc = Lc;
+    P.xfer_Lp = Lp;
+    const std::vector<double>& xtp = P.xt_h;
+    const std::vector<double>& xtc = C.xt_h;
+    const std::vector<double>& wtp = P.wt_h;
+    const std::vector<double>& wtc = C.wt_h;
     // M'_m[tp][tc] = sum_{n=m}^{Lc-1} Pbar_n^m(x_tp) Pbar_n^m(x_tc)
     std::vector<std::vector<double>> Pp(Lp), Pc(Lc);
-    for (int t = 0; t < Lp; ++t) assoc_legendre(Lc, xt[l][t], Pp[t]);
-    for (int t = 0; t < Lc; ++t) assoc_legendre(Lc, xt[l + 1][t], Pc[t]);
+    for (int t = 0; t < Lp; ++t) assoc_legendre(Lc, xtp[t], Pp[t]);
+    for (int t = 0; t < Lc; ++t) assoc_legendre(Lc, xtc[t], Pc[t]);
     // theta matrices stored [row out][row in][|m|]:
     //   Mi [tp][tc][m] = (pi/Lc) M'_m[tp][tc] w_tc   (interpolation, child -> parent)
     //   Ma [tc][tp][m] = (pi/Lp) M'_m[tp][tc] w_tp   (anterpolation, parent -> child)
@@ -543,8 +566,8 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
         for (int tc = 0; tc < Lc; ++tc) {
           double acc = 0.0;
           for (int n = mm; n < Lc; ++n) acc += Pp[tp][(size_t)mm * Lc + n] * Pc[tc][(size_t)mm * Lc + n];
-          const double vi = (M_PI / Lc) * acc * wt[l + 1][tc];
-          const double va = (M_PI / Lp) * acc * wt[l][tp];
+          const double vi = (M_PI / Lc) * acc * wtc[tc];
+          const double va = (M_PI / Lp) * acc * wtp[tp];
           Mi[((size_t)tp * Lc + tc) * Lc + mm] = vi;
           MaT[((size_t)tp * Lc + tc) * Lc + mm] = va;
           Ma[((size_t)tc * Lp + tp) * Lc + mm] = va;
@@ -572,7 +595,6 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
         EpcT[(size_t)j * nm + mi] = make_double2(e.x, -e.y);
       }
     }
-    const size_t tmp = (size_t)C.nc * std::max(Lc, Lp) * nm;
     auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
     auto c32 = [](const std::vector<double2>& v) {
       std::vector<float2> o(v.size());
@@ -590,8 +612,6 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
       P.EcT32.upload(c32(EcT), s);
       P.EpT32.upload(c32(EpT), s);
       P.EpcT32.upload(c32(EpcT), s);
-      P.tA32.alloc(tmp);
-      P.tB32.alloc(tmp);
     } else {
       P.Mi64.upload(Mi, s);
       P.Ma64.upload(Ma, s);
@@ -603,11 +623,7 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
       P.EcT64.upload(EcT, s);
       P.EpT64.upload(EpT, s);
       P.EpcT64.upload(EpcT, s);
-      P.tA64.alloc(tmp);
-      P.tB64.alloc(tmp);
     }
-    // the uploads read host vectors that go out of scope: finish them first
-    BEM_HIP(hipStreamSynchronize(s));
   }
   if (o.level_rows) {
     // the paper's explicit element-to-cluster rows on every level with pairs
@@ -627,7 +643,6 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
                         single ? nullptr : L.S64.p, single ? L.S32.p : nullptr, s);
     }
     BEM_HIP(hipGetLastError());
-    BEM_HIP(hipStreamSynchronize(s));
     return;
   }
   FmmLevel& leaf = F->lv[nl - 1];
@@ -643,7 +658,6 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
   launch_fmm_leaf_S(m->N, m->d_geom.p, FS->elem_cluster.p, leaf.z.p, leaf.s.p, leaf.w.p, leaf.nu, k, m->gre,
                     m->gim, single ? nullptr : F->S64.p, single ? F->S32.p : nullptr, s);
   BEM_HIP(hipGetLastError());
-  BEM_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
