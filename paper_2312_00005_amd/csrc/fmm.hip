@@ -18,6 +18,7 @@
 //
 // Every output element has a single owner thread or wavefront and sums in a
 // fixed order (no atomics): results are bit-reproducible.
+#include "common.h"
 #include "fmm.h"
 #include "sincos_cw.h"
 
@@ -51,6 +52,7 @@ template <> __device__ inline float2 from_d2<float2>(double2 v) { return make_fl
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ------------------------------------------------------------ setup ---
+template <bool SINGLE>
 __global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t* __restrict__ ec,
                          const double* __restrict__ zc, const double* __restrict__ s, int nu,
                          const double2* __restrict__ cfac, double k, const double* __restrict__ ra,
@@ -72,17 +74,30 @@ __global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t*
   const double base = k * ((zc[3 * c] - P0[0]) * sx + (zc[3 * c + 1] - P0[1]) * sy + (zc[3 * c + 2] - P0[2]) * sz);
   const double pe1 = k * (e1[0] * sx + e1[1] * sy + e1[2] * sz);
   const double pe2 = k * (e2[0] * sx + e2[1] * sy + e2[2] * sz);
-  double ar = 0.0, ai = 0.0;
-  for (int q = 0; q < nq; ++q) {
-    double sn, cs;
-    sincos_cw_lit(base - ra[q] * pe1 - rb[q] * pe2, &sn, &cs);
-    ar += rw[q] * cs;
-    ai += rw[q] * sn;
-  }
   const double a2 = 2.0 * g[AREA * N + j];
-  const double tr = ar * a2, ti = ai * a2;
-  if (T64) T64[idx] = make_double2(tr, ti);
-  if (T32) T32[idx] = make_float2((float)tr, (float)ti);
+  if (SINGLE) {
+    // rows of the complex-FP32 operator: phases in revolutions (the hardware
+    // sine and cosine take revolutions), formed from FP64 per-row terms
+    constexpr double kRev = 0.15915494309189533577;  // 1 / (2 pi)
+    const float b0 = (float)(base * kRev), q1 = (float)(pe1 * kRev), q2 = (float)(pe2 * kRev);
+    float ar = 0.0f, ai = 0.0f;
+    for (int q = 0; q < nq; ++q) {
+      const float ph = fmaf(-(float)rb[q], q2, fmaf(-(float)ra[q], q1, b0));
+      const float w = (float)rw[q];
+      ar = fmaf(w, __builtin_amdgcn_cosf(ph), ar);
+      ai = fmaf(w, __builtin_amdgcn_sinf(ph), ai);
+    }
+    T32[idx] = make_float2((float)(ar * a2), (float)(ai * a2));
+  } else {
+    double ar = 0.0, ai = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      double sn, cs;
+      sincos_cw_lit(base - ra[q] * pe1 - rb[q] * pe2, &sn, &cs);
+      ar += rw[q] * cs;
+      ai += rw[q] * sn;
+    }
+    T64[idx] = make_double2(ar * a2, ai * a2);
+  }
 }
 
 __global__ void k_leaf_S(int64_t N, const double* __restrict__ g, const int64_t* __restrict__ ec,
@@ -111,14 +126,19 @@ __global__ void k_leaf_S(int64_t N, const double* __restrict__ g, const int64_t*
   if (S32) S32[idx] = make_float2((float)r, (float)im);
 }
 
+// Bonnet factors (2l+1)/(l+1) and l/(l+1), l < kLegMax (wavefront-uniform
+// scalar loads in the node loop of k_translation)
+constexpr int kLegMax = 128;
+__constant__ double c_leg_a[kLegMax];
+__constant__ double c_leg_b[kLegMax];
+
 // one block per interaction pair; h_l by upward recurrence in shared memory
 __global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64_t* __restrict__ pm,
                                                      const int64_t* __restrict__ pn,
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ s, int nu, int L, double k,
                                                      double2* __restrict__ D64, float2* __restrict__ D32) {
-  extern __shared__ double2 coef[];  // L + 1 values i^l (2l+1) h_l(k|X|), then the recurrence factors
-  double* rec = reinterpret_cast<double*>(coef + (L + 1));  // (2l+1)/(l+1) and l/(l+1), l < L
+  extern __shared__ double2 coef[];  // L + 1 values i^l (2l+1) h_l(k|X|)
   const int64_t q = blockIdx.x;
   if (q >= npairs) return;
   const int64_t a = pm[q], b = pn[q];
@@ -152,10 +172,6 @@ __global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64
       coef[l] = make_double2((2.0 * l + 1.0) * cr, (2.0 * l + 1.0) * ci);
     }
   }
-  for (int l = threadIdx.x; l < L; l += blockDim.x) {
-    rec[2 * l] = (2.0 * l + 1.0) / (l + 1.0);
-    rec[2 * l + 1] = (double)l / (l + 1.0);
-  }
   __syncthreads();
   const double u0 = X0 / r, u1 = X1 / r, u2 = X2 / r;
   for (int v = threadIdx.x; v < nu; v += blockDim.x) {
@@ -167,8 +183,8 @@ __global__ __launch_bounds__(256) void k_translation(int64_t npairs, const int64
       di += coef[1].y * ct;
     }
     for (int l = 1; l < L; ++l) {
-      // Bonnet: P_{l+1} = ((2l+1) x P_l - l P_{l-1}) / (l+1), factors from LDS
-      const double pn1 = fma(rec[2 * l] * ct, p, -rec[2 * l + 1] * pm1);
+      // Bonnet: P_{l+1} = ((2l+1) x P_l - l P_{l-1}) / (l+1)
+      const double pn1 = fma(c_leg_a[l] * ct, p, -c_leg_b[l] * pm1);
       pm1 = p;
       p = pn1;
       dr += coef[l + 1].x * p;
@@ -576,8 +592,12 @@ void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* ec, const d
                        int nu, const double2* cfac, double k, const double* ra, const double* rb,
                        const double* rw, int nq, double2* T64, float2* T32, hipStream_t st) {
   if (N <= 0 || nu <= 0) return;
-  hipLaunchKernelGGL(k_leaf_T, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac, k, ra, rb,
-                     rw, nq, T64, T32);
+  if (T64)
+    hipLaunchKernelGGL(k_leaf_T<false>, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac,
+                       k, ra, rb, rw, nq, T64, nullptr);
+  if (T32)
+    hipLaunchKernelGGL(k_leaf_T<true>, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac,
+                       k, ra, rb, rw, nq, nullptr, T32);
 }
 
 void launch_fmm_leaf_S(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
@@ -592,9 +612,23 @@ void launch_fmm_translation(int64_t npairs, const int64_t* pm, const int64_t* pn
                             const double* s, int nu, int L, double k, double2* D64, float2* D32,
                             hipStream_t st) {
   if (npairs <= 0) return;
-  hipLaunchKernelGGL(k_translation, dim3((unsigned)npairs), dim3(256), (L + 1) * sizeof(double2) + 2 * L * sizeof(double),
-                     st, npairs,
-                     pm, pn, z, s, nu, L, k, D64, D32);
+  // the factors do not depend on the problem: uploaded once per device
+  static bool leg_ready[64] = {};
+  int dev = 0;
+  BEM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(BEM_E_HIP, "device index out of range");
+  if (!leg_ready[dev]) {
+    double a[kLegMax], b[kLegMax];
+    for (int l = 0; l < kLegMax; ++l) {
+      a[l] = (2.0 * l + 1.0) / (l + 1.0);
+      b[l] = (double)l / (l + 1.0);
+    }
+    BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_leg_a), a, sizeof(a)));
+    BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_leg_b), b, sizeof(b)));
+    leg_ready[dev] = true;
+  }
+  hipLaunchKernelGGL(k_translation, dim3((unsigned)npairs), dim3(256), (L + 1) * sizeof(double2), st, npairs, pm, pn, z, s,
+                     nu, L, k, D64, D32);
 }
 
 void launch_fmm_shift(int64_t nchild, const int64_t* parent, const double* zp, const double* zc,
