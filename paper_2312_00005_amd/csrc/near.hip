@@ -673,7 +673,10 @@ __global__ __launch_bounds__(256) void k_records(int64_t N, const double* __rest
 // (Sec. 3.1.2); H_ii = H'_ii = 0.  Then
 // A_ii = (1 - gamma c_i)/2 + gamma E_ii + G_ii c_i.
 __global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict__ diag) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // one wavefront per element; lanes share the element's quadrature points
+  // (the six Duffy triangles' self_n^2 points each, then the edge points)
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (t >= L.N) return;
   const int64_t N = L.N;
   const double* g = L.geom;
@@ -691,60 +694,63 @@ __global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict_
     M[1][c] = 0.5 * (P[1][c] + P[2][c]);
     M[2][c] = 0.5 * (P[2][c] + P[0][c]);
   }
-  const double* Q1s[6] = {P[0], M[0], P[1], M[1], P[2], M[2]};
-  const double* Q2s[6] = {M[0], P[1], M[1], P[2], M[2], P[0]};
-  double Gr = 0, Gi = 0;
-  for (int sidx = 0; sidx < 6; ++sidx) {
-    const double* Q1 = Q1s[sidx];
-    const double* Q2 = Q2s[sidx];
+  // Duffy triangles (V[h], V[h + 1]) with V = P0, M01, P1, M12, P2, M20
+  const double* V[6] = {P[0], M[0], P[1], M[1], P[2], M[2]};
+  const int nn2 = L.self_n * L.self_n;
+  double Gr = 0, Gi = 0, Er = 0, Ei = 0;
+#pragma unroll
+  for (int h = 0; h < 6; ++h) {
+    const double* Q1 = V[h];
+    const double* Q2 = V[(h + 1) % 6];
     double a[3], b[3], d[3];
     for (int c = 0; c < 3; ++c) {
       a[c] = Q1[c] - x[c];
       b[c] = Q2[c] - x[c];
       d[c] = Q2[c] - Q1[c];
     }
-    double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    const double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
     const double As2 = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
-    for (int ia = 0; ia < L.self_n; ++ia) {
+    for (int pnt = lane; pnt < nn2; pnt += 64) {
+      const int ia = pnt / L.self_n, ib = pnt - ia * L.self_n;
       const double u = L.duffy_u[ia], wu = L.duffy_w[ia];
-      for (int ib = 0; ib < L.self_n; ++ib) {
-        const double v = L.duffy_u[ib], wv = L.duffy_w[ib];
-        double R[3];
-        for (int c = 0; c < 3; ++c) R[c] = u * (a[c] + v * d[c]);
-        const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
-        double sn, cs;
-        sincos(k * r, &sn, &cs);
-        const double wgt = As2 * u * wu * wv * kInv4Pi / r;
-        Gr += wgt * cs;
-        Gi += wgt * sn;
-      }
+      const double v = L.duffy_u[ib], wv = L.duffy_w[ib];
+      double R[3];
+      for (int c = 0; c < 3; ++c) R[c] = u * (a[c] + v * d[c]);
+      const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      const double wgt = As2 * u * wu * wv * kInv4Pi / r;
+      Gr += wgt * cs;
+      Gi += wgt * sn;
     }
   }
-  double Er = 0, Ei = 0;
+  // edges P_e -> P_(e+1): (n x R) . d with grad_y G = G (ik - 1/r) R / r
+#pragma unroll
   for (int e = 0; e < 3; ++e) {
     const double* Pa = P[e];
     const double* Pb = P[(e + 1) % 3];
     double d[3];
     for (int c = 0; c < 3; ++c) d[c] = Pb[c] - Pa[c];
-    // (n x R) . d
-    for (int q = 0; q < L.edge_pts; ++q) {
+    for (int q = lane; q < L.edge_pts; q += 64) {
       double R[3];
       for (int c = 0; c < 3; ++c) R[c] = Pa[c] + L.edge_t[q] * d[c] - x[c];
       const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
       const double rinv = 1.0 / r;
       double sn, cs;
       sincos(k * r, &sn, &cs);
-      double nxR[3] = {n[1] * R[2] - n[2] * R[1], n[2] * R[0] - n[0] * R[2], n[0] * R[1] - n[1] * R[0]};
+      const double nxR[3] = {n[1] * R[2] - n[2] * R[1], n[2] * R[0] - n[0] * R[2], n[0] * R[1] - n[1] * R[0]};
       const double proj = nxR[0] * d[0] + nxR[1] * d[1] + nxR[2] * d[2];
-      // grad_y G = G (ik - 1/r) R / r, G = exp(ikr)/(4 pi r)
       const double s = L.edge_w[q] * proj * kInv4Pi * rinv * rinv;
       // exp(ikr) (ik - 1/r) = (cs + i sn)(-1/r + i k)
-      const double fr = -cs * rinv - sn * k;
-      const double fi = cs * k - sn * rinv;
-      Er += s * fr;
-      Ei += s * fi;
+      Er += s * (-cs * rinv - sn * k);
+      Ei += s * (cs * k - sn * rinv);
     }
   }
+  Gr = wave_sum(Gr);
+  Gi = wave_sum(Gi);
+  Er = wave_sum(Er);
+  Ei = wave_sum(Ei);
+  if (lane != 0) return;
   Er += k * k * Gr;
   Ei += k * k * Gi;
   double cr = 0, ci = 0;
@@ -1303,7 +1309,7 @@ void launch_records(int64_t N, const double* geom, double kap, double kap32, dou
 
 void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s) {
   if (L.N <= 0) return;
-  hipLaunchKernelGGL(k_self, dim3(blocks_for(L.N, 256)), dim3(256), 0, s, L, diag);
+  hipLaunchKernelGGL(k_self, dim3(blocks_for(L.N, 4)), dim3(256), 0, s, L, diag);
 }
 
 void launch_rhs_plane(int64_t N, const double* geom, double k, double gre, double gim, const double* d,
