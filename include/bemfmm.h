@@ -153,6 +153,11 @@ typedef struct bem_options {
                                that the far-field kernels on the side stream
                                find free wavefront slots (a tuning choice;
                                results are identical) */
+  double quad_eps_mixed;    /* quadrature tolerance (Sec. 3.1.4 estimates) of
+                               the direct far field (far_direct = 1) in the
+                               complex-FP32 operator, whose pair orders are
+                               chosen on the fly; the FP64 operator and every
+                               near-field plan use quad_eps */
 } bem_options;
 
 typedef struct bem_solve_info {

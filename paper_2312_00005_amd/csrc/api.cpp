@@ -46,6 +46,7 @@ void set_paper(bem_options* o) {
   o->l_eps = 1e-3;
   o->t_order = 4;
   o->quad_eps = 1e-3;
+  o->quad_eps_mixed = 1e-3;
   o->quad_m_max = 6;
   o->quad_split_on_cap = 0;
   o->subdiv_ratio = 1.3;
@@ -102,6 +103,7 @@ void check_options(const bem_options* o) {
   if (!o) throw Error(BEM_E_ARG, "options is NULL");
   if (o->quad_m_max < 1 || o->quad_m_max > kMaxRuleOrder) throw Error(BEM_E_ARG, "quad_m_max must be in [1, 8]");
   if (!(o->quad_eps > 0.0)) throw Error(BEM_E_ARG, "quad_eps must be positive");
+  if (!(o->quad_eps_mixed > 0.0)) throw Error(BEM_E_ARG, "quad_eps_mixed must be positive");
   if (!(o->subdiv_ratio > 0.0)) throw Error(BEM_E_ARG, "subdiv_ratio must be positive");
   if (o->max_subdiv < 0 || o->max_subdiv > 15) throw Error(BEM_E_ARG, "max_subdiv must be in [0, 15]");
   if (o->self_n < 1 || o->self_n > 64) throw Error(BEM_E_ARG, "self_n must be in [1, 64]");
@@ -207,7 +209,10 @@ void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, dou
   F.far_off = m->d_far_off.p;
   F.far_beg = m->d_far_beg.p;
   F.far_end = m->d_far_end.p;
-  for (int q = 0; q < kMaxRuleOrder; ++q) F.rt2_min[q] = m->far_rt2_min[q];
+  for (int q = 0; q < kMaxRuleOrder; ++q) {
+    F.rt2_min[q] = m->far_rt2_min[q];
+    F.rt2_min32[q] = m->far_rt2_min32[q];
+  }
   F.ratio2 = m->opt.subdiv_ratio * m->opt.subdiv_ratio;
   F.m_max = m->opt.quad_m_max;
   F.split_on_cap = m->opt.quad_split_on_cap;
@@ -255,14 +260,16 @@ void build_far_direct(bem_mesh* m) {
   }
   for (int64_t e = 0; e < m->N; ++e)
     if (el[e] < 0) throw Error(BEM_E_MESH, "element outside every leaf cluster", m->tree.perm[e]);
-  const double eps = m->opt.quad_eps;
-  for (int mm = 1; mm <= kMaxRuleOrder; ++mm) {
-    const double q1 = std::pow(eps / 32.0, 1.0 / (2 * mm + 1));
-    const double q2 = std::pow(eps / (64.0 * (2 * mm + 1)), 1.0 / (2 * mm + 2));
-    const double q3 = std::pow(eps / (128.0 * (mm + 1) * (2 * mm + 1)), 1.0 / (2 * mm + 3));
-    const double qm = std::min(q1, std::min(q2, q3));
-    const double rt = 1.0 / (2.0 * qm);
-    m->far_rt2_min[mm - 1] = rt * rt;
+  for (int set = 0; set < 2; ++set) {
+    const double eps = set == 0 ? m->opt.quad_eps : m->opt.quad_eps_mixed;
+    for (int mm = 1; mm <= kMaxRuleOrder; ++mm) {
+      const double q1 = std::pow(eps / 32.0, 1.0 / (2 * mm + 1));
+      const double q2 = std::pow(eps / (64.0 * (2 * mm + 1)), 1.0 / (2 * mm + 2));
+      const double q3 = std::pow(eps / (128.0 * (mm + 1) * (2 * mm + 1)), 1.0 / (2 * mm + 3));
+      const double qm = std::min(q1, std::min(q2, q3));
+      const double rt = 1.0 / (2.0 * qm);
+      (set == 0 ? m->far_rt2_min : m->far_rt2_min32)[mm - 1] = rt * rt;
+    }
   }
   hipStream_t s = nullptr;
   m->d_elem_leaf.upload(el, s);
@@ -485,6 +492,8 @@ bem_status bem_options_default(bem_options* o, const char* preset) {
       o->edge_gauss = 6;
       o->gmres_tol = 1e-6;
       o->l_eps_mixed = 1e-4;
+      // complex-FP32 direct far field: rules for errors near FP32 rounding
+      o->quad_eps_mixed = 1e-6;
       // the other sign of the imaginary coupling: the discrete spectrum lies
       // in the right half-plane, where block Jacobi also pays off
       o->gamma_im_k = -1.0;

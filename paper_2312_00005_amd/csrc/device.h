@@ -53,7 +53,8 @@ struct FarLaunch {
   const int64_t* far_off;
   const int64_t* far_beg;
   const int64_t* far_end;
-  double rt2_min[kMaxRuleOrder];  // order m suffices iff r~^2 > rt2_min[m-1]
+  double rt2_min[kMaxRuleOrder];  // order m suffices iff r~^2 > rt2_min[m-1] (FP64 kernels)
+  double rt2_min32[kMaxRuleOrder];  // the same for the complex-FP32 kernels
   double ratio2;
   int m_max, split_on_cap, max_subdiv;
   double k, gre, gim;

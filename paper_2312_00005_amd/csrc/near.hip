@@ -785,11 +785,14 @@ template <> __device__ inline double far_kap<double>(const FarLaunch& F) { retur
 template <> __device__ inline double far_kap<float>(const FarLaunch& F) { return F.kap32; }
 
 // order for r~^2 (0: split)
-// r~^2 = d2 / area, compared as d2 against threshold * area (no division)
+// r~^2 = d2 / area, compared as d2 against threshold * area (no division);
+// the complex-FP32 kernels take their own thresholds
+template <typename T>
 __device__ inline int far_order(const FarLaunch& F, double d2, double area) {
+  const double* th = sizeof(T) == 4 ? F.rt2_min32 : F.rt2_min;
   if (d2 < F.ratio2 * area) return 0;
   for (int m = 1; m <= F.m_max; ++m)
-    if (d2 > F.rt2_min[m - 1] * area) return m;
+    if (d2 > th[m - 1] * area) return m;
   return F.split_on_cap ? 0 : F.m_max;
 }
 
@@ -814,7 +817,7 @@ __device__ void far_pair_split(const FarLaunch& F, const T* g, const T* rec, int
       d2 += dc * dc;
     }
     const double area = area0 * ldexp(1.0, -2 * depth);
-    int m = far_order(F, d2, area);
+    int m = far_order<T>(F, d2, area);
     if (m == 0 && depth < F.max_subdiv && depth < 15) {
       ++depth;
       continue;
@@ -891,7 +894,7 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
           const double dc = (double)xi[c] - (double)g[(CX + c) * N + j];
           d2 += dc * dc;
         }
-        m = far_order(F, d2, (double)g[AREA * N + j]);
+        m = far_order<T>(F, d2, (double)g[AREA * N + j]);
       }
       T s1r = 0, s1i = 0, s2r = 0, s2i = 0;
       // one uniform rule per pass

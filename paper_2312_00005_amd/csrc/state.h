@@ -71,7 +71,8 @@ struct bem_mesh {
   bool far_direct = false;
   bem::DevBuf<int32_t> d_elem_leaf;
   bem::DevBuf<int64_t> d_far_off, d_far_beg, d_far_end;
-  double far_rt2_min[8] = {0};
+  double far_rt2_min[8] = {0};    // r~^2 thresholds of the orders (quad_eps)
+  double far_rt2_min32[8] = {0};  // the same for the complex-FP32 operator (quad_eps_mixed)
 
   // block-Jacobi preconditioner (tree order)
   int64_t nblk = 0;
