@@ -284,7 +284,10 @@ __device__ inline PointConsts<T> point_consts(double k, double kap, double gre, 
 // midpoints M, have v0 = P0, P1, P2, M01 and edges that are halves of
 // +-e1, +-e2, e2 - e1.
 // integrate_loaded: the same with the source's record r already in registers.
-template <typename T, bool WANT_S1, bool WANT_S2>
+// ONEPT: evaluate one-point items at the point itself (the direct far field,
+// where they are common; elsewhere the general loop handles them and the
+// kernel keeps fewer registers)
+template <typename T, bool WANT_S1, bool WANT_S2, bool ONEPT = false>
 __device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, const T xs[3], const T ni[3],
                                         const PointConsts<T>& P, T& s1r, T& s1i, T& s2r, T& s2i) {
   const int depth = (int)((item >> 29) & 15u);
@@ -319,9 +322,9 @@ __device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, c
   T d0[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) d0[c] = v0[c] - xs[c];
-  if (m == 1) {
-    // one rule point (most far pairs): the integrand at y itself, without
-    // the quadratic-form coefficients
+  if (ONEPT && m == 1) {
+    // one rule point: the integrand at y itself, without the quadratic-form
+    // coefficients
     const auto rp = RuleTab<T>::pt(c_rule_off[0]);
     T d[3];
 #pragma unroll
@@ -423,7 +426,7 @@ __device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, c
   s2i = a2i * f2;
 }
 
-template <typename T, bool WANT_S1, bool WANT_S2>
+template <typename T, bool WANT_S1, bool WANT_S2, bool ONEPT = false>
 __device__ inline void integrate_item(const T* __restrict__ rec, uint64_t item, int m, const T xs[3],
                                       const T ni[3], const PointConsts<T>& P, T& s1r, T& s1i, T& s2r,
                                       T& s2i, int64_t& jout) {
@@ -431,7 +434,7 @@ __device__ inline void integrate_item(const T* __restrict__ rec, uint64_t item, 
   jout = j;
   T r[kRec];
   Rec<T>::load(rec, j, r);
-  integrate_loaded<T, WANT_S1, WANT_S2>(r, item, m, xs, ni, P, s1r, s1i, s2r, s2i);
+  integrate_loaded<T, WANT_S1, WANT_S2, ONEPT>(r, item, m, xs, ni, P, s1r, s1i, s2r, s2i);
 }
 
 template <typename T> __device__ inline const T* near_rec(const NearLaunch& L);
@@ -826,7 +829,7 @@ __device__ void far_pair_split(const FarLaunch& F, const T* g, const T* rec, int
     const uint64_t item = (uint64_t)j | ((uint64_t)depth << 29) | (path << 33);
     T a1r, a1i, a2r, a2i;
     int64_t jj;
-    integrate_item<T, WANT_S1, WANT_S2>(rec, item, m, xs, ni, P, a1r, a1i, a2r, a2i, jj);
+    integrate_item<T, WANT_S1, WANT_S2, true>(rec, item, m, xs, ni, P, a1r, a1i, a2r, a2i, jj);
     s1r += a1r;
     s1i += a1i;
     s2r += a2r;
@@ -902,7 +905,8 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
         if (__ballot(m == mc) == 0) continue;
         if (m == mc) {
           int64_t jj;
-          integrate_item<T, !VMODE, HAS_C || VMODE>(rec, (uint64_t)j, mc, xs, ni, P, s1r, s1i, s2r, s2i, jj);
+          integrate_item<T, !VMODE, HAS_C || VMODE, true>(rec, (uint64_t)j, mc, xs, ni, P, s1r, s1i, s2r, s2i,
+                                                         jj);
         }
       }
       if (__ballot(m == 0) != 0 && m == 0)
