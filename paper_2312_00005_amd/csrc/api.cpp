@@ -289,6 +289,8 @@ BlockArgs block_args(const bem_mesh* m) {
   B.beg = m->d_blk_beg.p;
   B.n = m->d_blk_n.p;
   B.off = m->d_blk_off.p;
+  B.items = m->d_blk_items.p;
+  B.seg = m->d_blk_seg.p;
   return B;
 }
 
@@ -329,9 +331,28 @@ void build_blocks(bem_mesh* m, int max_n) {
   }
   for (int64_t e = 0; e < m->N; ++e)
     if (eb[e] < 0) throw Error(BEM_E_MESH, "element outside every leaf cluster", m->tree.perm[e]);
+  // per row, the near items whose source lies in the row's block (order and
+  // rule segments as in the plan): the assembly integrates only these
+  std::vector<uint64_t> bitems;
+  std::vector<int64_t> bseg((size_t)m->N * (kMaxRuleOrder + 1));
+  for (int64_t t = 0; t < m->N; ++t) {
+    const int64_t b0 = beg[eb[t]], b1 = b0 + nn[eb[t]];
+    const int64_t* sg = m->plan.seg.data() + t * (kMaxRuleOrder + 1);
+    for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
+      bseg[t * (kMaxRuleOrder + 1) + mc] = (int64_t)bitems.size();
+      for (int64_t it = sg[mc]; it < sg[mc + 1]; ++it) {
+        const int64_t j = (int64_t)(m->plan.items[it] & ((uint64_t(1) << 26) - 1));
+        if (j >= b0 && j < b1) bitems.push_back(m->plan.items[it]);
+      }
+    }
+    bseg[t * (kMaxRuleOrder + 1) + kMaxRuleOrder] = (int64_t)bitems.size();
+  }
+  if (bitems.empty()) bitems.push_back(0);
   hipStream_t s = nullptr;
   m->nblk = (int64_t)beg.size();
   m->blk_entries = total;
+  m->d_blk_items.upload(bitems, s);
+  m->d_blk_seg.upload(bseg, s);
   m->d_elem_blk.upload(eb, s);
   m->d_blk_beg.upload(beg, s);
   m->d_blk_n.upload(nn, s);
@@ -996,7 +1017,7 @@ size_t bem_workspace_bytes(const bem_mesh* m) {
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
              m->d_partial.bytes() + m->d_h.bytes() + m->d_z.bytes() + m->d_elem_blk.bytes() +
              m->d_blk_n.bytes() + m->d_blk_sing.bytes() + m->d_blk_beg.bytes() + m->d_blk_off.bytes() +
-             m->d_blk_a.bytes() + m->d_blk_inv.bytes() + m->d_far.bytes();
+             m->d_blk_a.bytes() + m->d_blk_inv.bytes() + m->d_blk_items.bytes() + m->d_blk_seg.bytes() + m->d_far.bytes();
   return b + fmm_bytes(m);
 }
 

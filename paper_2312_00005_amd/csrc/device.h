@@ -95,6 +95,8 @@ struct BlockArgs {
   const int64_t* beg;       // nblk
   const int32_t* n;         // nblk
   const int64_t* off;       // nblk
+  const uint64_t* items;    // per row, the near items with their source in the row's block
+  const int64_t* seg;       // N * 9 rule segments of those items (as NearLaunch::seg)
 };
 // a[off + jl * n + il] = A_(beg + il, beg + jl): diagonal plus the near-field
 // entries inside the block, in FP64

@@ -947,8 +947,9 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
 
 // ------------------------------------------------ preconditioner blocks ---
 // One wavefront per row t: the row's near items whose source lies in t's block
-// are integrated (FP64) and summed per column in a fixed order (lane order of
-// the item chunks), so the assembly is deterministic; lane jl owns column jl.
+// (B.items: a compact per-row list built with the blocks) are integrated (FP64)
+// and summed per column in a fixed order (lane order of the item chunks), so
+// the assembly is deterministic; lane jl owns column jl.
 template <bool HAS_C>
 __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs B, double2* __restrict__ a) {
   const int lane = threadIdx.x & 63;
@@ -968,7 +969,7 @@ __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs 
     ni[c] = g[(NX + c) * N + t];
   }
   double accr = 0.0, acci = 0.0;
-  const int64_t* sg = L.seg + t * (kMaxRuleOrder + 1);
+  const int64_t* sg = B.seg + t * (kMaxRuleOrder + 1);
   for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
     const int64_t e = sg[mc + 1];
     for (int64_t base = sg[mc]; base < e; base += 64) {
@@ -976,14 +977,14 @@ __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs 
       int64_t j = -1;
       bool in = false;
       if (it < e) {
-        j = (int64_t)(L.items[it] & ((uint64_t(1) << 26) - 1));
+        j = (int64_t)(B.items[it] & ((uint64_t(1) << 26) - 1));
         in = j >= b0 && j < b0 + n;
       }
       double vr = 0.0, vi = 0.0;
       if (in) {
         double s1r, s1i, s2r, s2i;
         int64_t jj;
-        integrate_item<double, true, HAS_C>(L.rec, L.items[it], mc + 1, xs, ni, P, s1r, s1i, s2r,
+        integrate_item<double, true, HAS_C>(L.rec, B.items[it], mc + 1, xs, ni, P, s1r, s1i, s2r,
                                             s2i, jj);
         vr = s1r;
         vi = s1i;

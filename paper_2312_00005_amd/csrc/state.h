@@ -81,6 +81,8 @@ struct bem_mesh {
   int64_t singular_blocks = 0;
   bem::DevBuf<int32_t> d_elem_blk, d_blk_n, d_blk_sing;
   bem::DevBuf<int64_t> d_blk_beg, d_blk_off;
+  bem::DevBuf<uint64_t> d_blk_items;  // per row, the near items whose source is in the row's block
+  bem::DevBuf<int64_t> d_blk_seg;     // their rule segments (N x 9, as the plan's)
   bem::DevBuf<double2> d_blk_a, d_blk_inv;
 
   // work vectors (tree order)
