@@ -68,9 +68,13 @@ void set_paper(bem_options* o) {
   o->use_graphs = 1;
 }
 
+// rule tables live in each device's constant memory: uploaded once per device
 void upload_rules() {
-  static bool done = false;
-  if (done) return;
+  static bool done[64] = {};
+  int dev = 0;
+  BEM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(BEM_E_HIP, "device index out of range");
+  if (done[dev]) return;
   double a[kRulePoints], b[kRulePoints], w[kRulePoints];
   int off[kMaxRuleOrder + 1];
   int pos = 0;
@@ -90,7 +94,7 @@ void upload_rules() {
   off[kMaxRuleOrder] = pos;
   upload_rule_tables(a, b, w, off);
   BEM_HIP(hipGetLastError());
-  done = true;
+  done[dev] = true;
 }
 
 int default_levels(int64_t N) {

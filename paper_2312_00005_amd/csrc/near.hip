@@ -20,6 +20,7 @@
 // a shuffle reduction adds the lanes in a fixed order -- no atomics, so every
 // run is bit-identical.  The singular self term is not an item: it is folded
 // into the per-frequency diagonal A_ii (self-term kernel below).
+#include "common.h"
 #include "device.h"
 
 #include <cmath>
@@ -29,13 +30,7 @@ namespace bem {
 __constant__ double c_rule_a[kRulePoints];
 __constant__ double c_rule_b[kRulePoints];
 __constant__ double c_rule_w[kRulePoints];
-__constant__ float c_rule_a32[kRulePoints];
-__constant__ float c_rule_b32[kRulePoints];
-__constant__ float c_rule_w32[kRulePoints];
 __constant__ int c_rule_off[kMaxRuleOrder + 1];
-// weights divided by 4 pi (the Green's function's factor folded in)
-__constant__ double c_rule_ws[kRulePoints];
-__constant__ float c_rule_ws32[kRulePoints];
 // (a, b, w / 4 pi) of every rule point in one record, for one scalar load
 // per point
 struct alignas(16) RulePt32 { float a, b, w, pad; };
@@ -47,24 +42,16 @@ __constant__ RulePt64 c_rule_pt64[kRulePoints];
 __constant__ double c_sincos[4 + 8 + 8];
 
 void upload_rule_tables(const double* a, const double* b, const double* w, const int* off) {
-  float a32[kRulePoints], b32[kRulePoints], w32[kRulePoints], ws32[kRulePoints];
-  double ws[kRulePoints];
-  for (int i = 0; i < kRulePoints; ++i) {
-    a32[i] = (float)a[i];
-    b32[i] = (float)b[i];
-    w32[i] = (float)w[i];
-    ws[i] = w[i] * 0.079577471545947667884441881686257181;
-    ws32[i] = (float)ws[i];
-  }
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_ws), ws, sizeof(double) * kRulePoints);
+  // the point loops read (a, b, w / 4 pi) per point; the field kernels a, b, w
   RulePt32 pt32[kRulePoints];
   RulePt64 pt64[kRulePoints];
   for (int i = 0; i < kRulePoints; ++i) {
-    pt32[i] = RulePt32{a32[i], b32[i], ws32[i], 0.0f};
-    pt64[i] = RulePt64{a[i], b[i], ws[i], 0.0};
+    const double ws = w[i] * 0.079577471545947667884441881686257181;
+    pt32[i] = RulePt32{(float)a[i], (float)b[i], (float)ws, 0.0f};
+    pt64[i] = RulePt64{a[i], b[i], ws, 0.0};
   }
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt32), pt32, sizeof(pt32));
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt64), pt64, sizeof(pt64));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt32), pt32, sizeof(pt32)));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt64), pt64, sizeof(pt64)));
   // sin/cos reduction: pi/2 split into three parts, the first two with 20
   // significant bits so that n*C1 and n*C2 are exact; Taylor coefficients
   const double sc[20] = {0.6366197723675814, 1.5707950592041016, 1.2675900507019833e-06, 7.443547480486623e-13,
@@ -72,15 +59,11 @@ void upload_rule_tables(const double* a, const double* b, const double* w, const
                          -1.0 / 39916800.0, 1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,
                          1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
                          -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5};
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_sincos), sc, sizeof(sc));
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_ws32), ws32, sizeof(float) * kRulePoints);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a), a, sizeof(double) * kRulePoints);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b), b, sizeof(double) * kRulePoints);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_w), w, sizeof(double) * kRulePoints);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a32), a32, sizeof(float) * kRulePoints);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b32), b32, sizeof(float) * kRulePoints);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_w32), w32, sizeof(float) * kRulePoints);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_rule_off), off, sizeof(int) * (kMaxRuleOrder + 1));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sincos), sc, sizeof(sc)));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a), a, sizeof(double) * kRulePoints));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b), b, sizeof(double) * kRulePoints));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_w), w, sizeof(double) * kRulePoints));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_off), off, sizeof(int) * (kMaxRuleOrder + 1)));
 }
 
 namespace {
@@ -92,17 +75,9 @@ enum { P0X = 0, P1X = 3, P2X = 6, NX = 9, AREA = 12, CX = 13 };
 
 template <typename T> struct RuleTab;
 template <> struct RuleTab<double> {
-  __device__ static double a(int i) { return c_rule_a[i]; }
-  __device__ static double b(int i) { return c_rule_b[i]; }
-  __device__ static double w(int i) { return c_rule_w[i]; }
-  __device__ static double ws(int i) { return c_rule_ws[i]; }
   __device__ static RulePt64 pt(int i) { return c_rule_pt64[i]; }
 };
 template <> struct RuleTab<float> {
-  __device__ static float a(int i) { return c_rule_a32[i]; }
-  __device__ static float b(int i) { return c_rule_b32[i]; }
-  __device__ static float w(int i) { return c_rule_w32[i]; }
-  __device__ static float ws(int i) { return c_rule_ws32[i]; }
   __device__ static RulePt32 pt(int i) { return c_rule_pt32[i]; }
 };
 
@@ -138,19 +113,15 @@ __device__ inline void sincos_cw(double x, double* s, double* c) {
   *c = ((q + 1) & 2) ? -b : b;
 }
 
-__device__ inline void sincos_t(double x, double* s, double* c) { sincos_cw(x, s, c); }
-__device__ inline void sincos_t(float x, float* s, float* c) { __sincosf(x, s, c); }
 
 // Phase of exp(ikr) in the unit the sine/cosine below take: radians in FP64
 // (Cody-Waite reduction above), revolutions in FP32 (the hardware sine and
 // cosine take revolutions, so k/(2 pi) is folded into the per-item constant).
 template <typename T> struct Phase;
 template <> struct Phase<double> {
-  __device__ static double scale(double k) { return k; }
   __device__ static void sincos(double x, double* s, double* c) { sincos_cw(x, s, c); }
 };
 template <> struct Phase<float> {
-  __device__ static float scale(float k) { return k * 0.15915494309189535f; }
   __device__ static void sincos(float x, float* s, float* c) {
     *s = __builtin_amdgcn_sinf(x);
     *c = __builtin_amdgcn_cosf(x);
