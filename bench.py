@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--streams", type=int, default=1, help="concurrent frequencies in the sweep workload")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="concurrent frequencies in the sweep workload (only 1: concurrent host threads are disabled)")
     ap.add_argument("--profile-near-only", action="store_true",
                     help="run only complex-FP32 near-field applications, then a 512 MiB copy "
                          "that calibrates the HBM byte counters (for rocprofv3 --pmc runs)")

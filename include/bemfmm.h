@@ -38,7 +38,10 @@
  *   - Every function returns a bem_status; on failure bem_last_error() gives a
  *     thread-local message valid until the next call on the same thread.
  *     Nothing is thrown across this boundary.
- *   - A bem_mesh is not thread-safe: use one per host thread / stream.
+ *   - A bem_mesh is not thread-safe.  Calls from several host threads at
+ *     once, even on different meshes, are not supported: a run with two
+ *     threads solving on two meshes ended in a host crash whose cause is not
+ *     known.  Use the library from one host thread per device at a time.
  */
 #ifndef BEMFMM_H
 #define BEMFMM_H

@@ -7,11 +7,11 @@ large enough, Sec. 3.3.1), stay within the supported length and fit the
 memory budget runs the FMM; otherwise the far field is evaluated by direct
 quadrature (far_direct), which has no low-frequency breakdown and needs no
 translation memory.  Frequencies that share a method share one device plan
-(geometry, tree, near plan built once) and are solved back to back; with
-several streams, consecutive frequencies of a group run concurrently, each on
-its own HIP stream and mesh instance (one host thread per stream; the library
-calls release the interpreter lock).  This module only schedules calls into
-the library.
+(geometry, tree, near plan built once) and are solved back to back on the
+caller's stream.  Solving several frequencies concurrently from several host
+threads (one HIP stream and mesh instance each) is disabled: such a run ended
+once in a host segmentation fault inside the solve whose cause has not been
+found.  This module only schedules calls into the library.
 """
 
 import math
@@ -55,6 +55,9 @@ class FrequencySweep:
         self.leaf_size = leaf_size
         self.overrides = overrides
         self.streams = max(1, int(streams))
+        if self.streams > 1:
+            raise NotImplementedError("concurrent frequencies from several host threads are disabled "
+                                      "(a host crash was seen in that mode and its cause is not known)")
         t0 = time.perf_counter()
         trees = {d: bemfmm.HostTree(nodes, tris, preset, levels=d, leaf_size=leaf_size, **overrides)
                  for d in depths}
