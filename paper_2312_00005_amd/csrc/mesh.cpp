@@ -282,19 +282,46 @@ Tree build_tree(const Geometry& gc, int levels, double root_edge, int leaf_size,
 
 namespace {
 
-int estimator_order(double rt, double eps) {
-  double q = 1.0 / (2.0 * rt);
+// Rule order of a (sub-)element (Sec. 3.1.4): the smallest m whose three
+// a-priori estimates 32 q^(2m+1), 64 (2m+1) q^(2m+2), 128 (m+1)(2m+1) q^(2m+3),
+// q = 1/(2 r~), are all below eps.  Each estimate grows with q, so order m
+// holds iff q is below the smallest root of the three, i.e. iff r~ > th[m]:
+// the table gives the order without powers, and within 1e-12 (relative) of a
+// threshold the estimates themselves decide, so the choice is the
+// estimates', bit for bit.
+struct OrderTable {
+  double th[65];
+  explicit OrderTable(double eps) {
+    for (int m = 1; m <= 64; ++m) {
+      const double q1 = std::pow(eps / 32.0, 1.0 / (2 * m + 1));
+      const double q2 = std::pow(eps / (64.0 * (2 * m + 1)), 1.0 / (2 * m + 2));
+      const double q3 = std::pow(eps / (128.0 * (m + 1) * (2 * m + 1)), 1.0 / (2 * m + 3));
+      th[m] = 1.0 / (2.0 * std::min(q1, std::min(q2, q3)));
+    }
+    th[0] = 0.0;
+  }
+};
+
+bool order_holds(double rt, double eps, int m) {
+  const double q = 1.0 / (2.0 * rt);
+  const double eg = 32.0 * std::pow(q, double(2 * m + 1));
+  const double eh = 64.0 * double(2 * m + 1) * std::pow(q, double(2 * m + 2));
+  const double ee = 128.0 * double(m + 1) * double(2 * m + 1) * std::pow(q, double(2 * m + 3));
+  return eg < eps && eh < eps && ee < eps;
+}
+
+int estimator_order_fast(double rt, double eps, const OrderTable& T) {
   for (int m = 1; m <= 64; ++m) {
-    double eg = 32.0 * std::pow(q, double(2 * m + 1));
-    double eh = 64.0 * double(2 * m + 1) * std::pow(q, double(2 * m + 2));
-    double ee = 128.0 * double(m + 1) * double(2 * m + 1) * std::pow(q, double(2 * m + 3));
-    if (eg < eps && eh < eps && ee < eps) return m;
+    const double t = T.th[m];
+    if (rt > t * (1.0 + 1e-12)) return m;
+    if (rt >= t * (1.0 - 1e-12) && order_holds(rt, eps, m)) return m;
   }
   return 64;
 }
 
 struct PlanCtx {
   const QuadParams* q;
+  const OrderTable* ot;
   double x[3];
   int64_t j;
   std::vector<uint64_t>* out;
@@ -314,7 +341,7 @@ void plan_rec(PlanCtx& C, const double* v0, const double* v1, const double* v2, 
   bool split = rt < C.q->ratio;
   int m = 1;
   if (!split) {
-    m = estimator_order(rt, C.q->eps);
+    m = estimator_order_fast(rt, C.q->eps, *C.ot);
     if (m > C.q->m_max) {
       if (C.q->split_on_cap) split = true;
       else m = C.q->m_max;
@@ -358,10 +385,12 @@ NearPlan build_near_plan(const Geometry& g, const QuadParams& q,
   std::vector<std::vector<uint64_t>> per(N);
   std::vector<int64_t> pts(N, 0), npairs(N, 0), bad(N, -1);
   std::vector<int> mm(N, 1);
+  const OrderTable ot(q.eps);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t t = 0; t < N; ++t) {
     PlanCtx C;
     C.q = &q;
+    C.ot = &ot;
     for (int c = 0; c < 3; ++c) C.x[c] = g.at(G_CX + c, t);
     C.out = &per[t];
     C.points = 0;
