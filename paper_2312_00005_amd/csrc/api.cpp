@@ -146,6 +146,16 @@ void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, do
 
 void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
                      hipStream_t s, bool vmode) {
+  // a caller's own graph capture of s also counts as capturing (the far field
+  // then forks no third stream; see fmm_apply)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  BEM_HIP(hipStreamIsCapturing(s, &cs));
+  struct CaptureFlag {
+    bem_mesh* m;
+    bool was;
+    ~CaptureFlag() { m->capturing = was; }
+  } flag{m, m->capturing};
+  if (cs != hipStreamCaptureStatusNone) m->capturing = true;
   if (part == 2) {
     BEM_HIP(hipMemsetAsync(y, 0, m->N * sizeof(double2), s));
     far_apply(m, op, prec, x, y, s, vmode);
@@ -618,6 +628,9 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
       BEM_HIP(hipStreamCreateWithFlags(&m->side_stream, hipStreamNonBlocking));
       BEM_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
       BEM_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
+      BEM_HIP(hipStreamCreateWithFlags(&m->leaf_stream, hipStreamNonBlocking));
+      BEM_HIP(hipEventCreateWithFlags(&m->ev_leaf_fork, hipEventDisableTiming));
+      BEM_HIP(hipEventCreateWithFlags(&m->ev_leaf_join, hipEventDisableTiming));
       m->d_far.alloc(n_tri);
     }
     if (m->far_direct) build_far_direct(m.get());

@@ -226,6 +226,11 @@ __device__ inline V source_factor(const FactorArgs& F, int64_t j, int v) {
   return mk(fr, fi);
 }
 
+// The level-transfer kernels form a chain of short launches that runs beside
+// the near-field kernel and the leaf translation; a raised wave priority lets
+// their few instructions issue ahead of those long arithmetic and load streams.
+__device__ inline void chain_priority() { __builtin_amdgcn_s_setprio(2); }
+
 // sig_c(nu) = sum_{j in c} r_j(nu) x_j with r = Tm (CONJ: conj(Tm)) times the
 // source factor when FACTOR
 template <typename T, typename V, bool CONJ, bool FACTOR>
@@ -328,6 +333,7 @@ __global__ __launch_bounds__(256) void k_up_equal(const int64_t* __restrict__ cb
                                                   const int64_t* __restrict__ cend, int nu,
                                                   const V* __restrict__ shift, const V* __restrict__ sigc,
                                                   V* __restrict__ sigp) {
+  chain_priority();
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t p = blockIdx.y;
   if (v >= nu) return;
@@ -340,6 +346,7 @@ template <typename T, typename V>
 __global__ __launch_bounds__(256) void k_down_equal(const int64_t* __restrict__ parent, int nu,
                                                     const V* __restrict__ shift, const V* __restrict__ locp,
                                                     V* __restrict__ locc) {
+  chain_priority();
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = blockIdx.y;
   if (v >= nu) return;
@@ -364,6 +371,7 @@ template <typename T, typename V, bool TAB>
 __global__ __launch_bounds__(256) void k_dft(int nt, int nj, int nm, int rl, const V* __restrict__ in,
                                              const V* __restrict__ shift, const int64_t* __restrict__ parent,
                                              int mode, const V* __restrict__ Et, V* __restrict__ out) {
+  chain_priority();
   extern __shared__ unsigned char xfer_smem[];
   V* row = reinterpret_cast<V*>(xfer_smem);  // kXferRows x rl (rl >= nj)
   V* tab = row + kXferRows * rl;             // nj x nm when TAB
@@ -401,6 +409,7 @@ __global__ __launch_bounds__(256) void k_dft(int nt, int nj, int nm, int rl, con
 template <typename T, typename V, bool TAB>
 __global__ __launch_bounds__(256) void k_theta(int nto, int nti, int nm, int mhalf, int nmh, const T* __restrict__ M,
                                                const V* __restrict__ in, V* __restrict__ out) {
+  chain_priority();
   extern __shared__ unsigned char xfer_smem[];
   V* tab = reinterpret_cast<V*>(xfer_smem);  // nti x nm when TAB
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -436,6 +445,7 @@ __global__ __launch_bounds__(256) void k_up_idft(const int64_t* __restrict__ cbe
                                                  int nt, int nj, int nm, int rl, const V* __restrict__ G,
                                                  const V* __restrict__ E, const V* __restrict__ shift,
                                                  V* __restrict__ sigp) {
+  chain_priority();
   extern __shared__ unsigned char xfer_smem[];
   V* g = reinterpret_cast<V*>(xfer_smem);  // kXferRows x rl (rl >= nm)
   V* tab = g + kXferRows * rl;             // nm x nj when TAB
@@ -483,6 +493,7 @@ __global__ __launch_bounds__(256) void k_up_idft(const int64_t* __restrict__ cbe
 template <typename T, typename V, bool TAB>
 __global__ __launch_bounds__(256) void k_down_idft(int nt, int nj, int nm, int rl, const V* __restrict__ K,
                                                    const V* __restrict__ E, V* __restrict__ locc) {
+  chain_priority();
   extern __shared__ unsigned char xfer_smem[];
   V* kk = reinterpret_cast<V*>(xfer_smem);  // kXferRows x rl (rl >= nm)
   V* tab = kk + kXferRows * rl;             // nm x nj when TAB
@@ -516,6 +527,7 @@ template <typename T, typename V>
 __global__ __launch_bounds__(64) void k_dft_row(int nt, int nj, int nm, const V* __restrict__ in,
                                             const V* __restrict__ shift, const int64_t* __restrict__ parent,
                                             int mode, const V* __restrict__ Et, V* __restrict__ out) {
+  chain_priority();
   __shared__ V row[256];
   const int t = blockIdx.x;
   const int64_t c = blockIdx.y;
@@ -544,6 +556,7 @@ __global__ __launch_bounds__(128) void k_up_idft_row(const int64_t* __restrict__
                                                  int nt, int nj, int nm, const V* __restrict__ G,
                                                  const V* __restrict__ E, const V* __restrict__ shift,
                                                  V* __restrict__ sigp) {
+  chain_priority();
   __shared__ V g[256];
   const int t = blockIdx.x;
   const int64_t p = blockIdx.y;
@@ -571,6 +584,7 @@ __global__ __launch_bounds__(128) void k_up_idft_row(const int64_t* __restrict__
 template <typename T, typename V>
 __global__ __launch_bounds__(128) void k_down_idft_row(int nt, int nj, int nm, const V* __restrict__ K,
                                                    const V* __restrict__ E, V* __restrict__ locc) {
+  chain_priority();
   __shared__ V kk[256];
   const int t = blockIdx.x;
   const int64_t c = blockIdx.y;

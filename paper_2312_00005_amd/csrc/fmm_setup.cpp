@@ -374,8 +374,27 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
     BEM_HIP(hipGetLastError());
     return;
   }
+  const int tpb = m->tune_tpb[sizeof(T) == sizeof(float) ? 1 : 0];
   launch_fmm_aggregate<T, V>(leaf.nc, FS->leaf_ebeg.p, FS->leaf_eend.p, leaf.nu, P::T(F), vmode ? nullptr : &fa, x,
                              P::sig(leaf), false, s);
+  // The leaf translation needs only the leaf signatures and is the largest
+  // far-field kernel: with a tree of more than one level it runs on its own
+  // stream beside the upward pass, the upper translations and the downward
+  // pass, which joins it before adding into the leaf local expansions.  Not
+  // while s is being captured into a graph: a capture that forked a third
+  // stream this way ended in a host crash inside the solve, cause not found,
+  // so captured applications keep the single far-field stream.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  BEM_HIP(hipStreamIsCapturing(s, &cap));
+  const bool fork =
+      F->top < nl - 1 && m->leaf_stream != nullptr && !m->capturing && cap == hipStreamCaptureStatusNone;
+  if (fork) {
+    BEM_HIP(hipEventRecord(m->ev_leaf_fork, s));
+    BEM_HIP(hipStreamWaitEvent(m->leaf_stream, m->ev_leaf_fork, 0));
+    launch_fmm_translate<T, V>(leaf.nc, leaf.il_off.p, leaf.il.p, leaf.code.p, false, leaf.L, leaf.nu, P::D(leaf),
+                               P::sig(leaf), P::loc(leaf), tpb, m->leaf_stream);
+    BEM_HIP(hipEventRecord(m->ev_leaf_join, m->leaf_stream));
+  }
   for (int l = nl - 2; l >= F->top; --l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
@@ -388,20 +407,23 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
                                P::shift(Lp), P::sig(Lp), s);
     }
   }
-  for (int l = F->top; l < nl; ++l) {
+  for (int l = F->top; l < (fork ? nl - 1 : nl); ++l) {
     FmmLevel& L = F->lv[l];
     launch_fmm_translate<T, V>(L.nc, L.il_off.p, L.il.p, L.code.p, false, L.L, L.nu, P::D(L), P::sig(L), P::loc(L),
-                               m->tune_tpb[sizeof(T) == sizeof(float) ? 1 : 0], s);
+                               tpb, s);
   }
   for (int l = F->top; l + 1 < nl; ++l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
+    const bool into_leaf = fork && l + 2 == nl;
     if (!Lp.resample) {
+      if (into_leaf) BEM_HIP(hipStreamWaitEvent(s, m->ev_leaf_join, 0));
       launch_fmm_down_equal<T, V>(Lc.nc, Lc.parent.p, Lp.nu, P::shift(Lp), P::loc(Lp), P::loc(Lc), s);
     } else {
       launch_fmm_dft<T, V>(Lc.nc, Lp.L, 2 * Lp.L, Lp.nm, P::loc(Lp), P::shift(Lp), Lc.parent.p, 1, P::EpT(Lp),
                            P::tA(Lp), s);
       launch_fmm_theta<T, V>(Lc.nc, Lc.L, Lp.L, Lp.nm, Lc.L - 1, P::Ma(Lp), P::tA(Lp), P::tB(Lp), s);
+      if (into_leaf) BEM_HIP(hipStreamWaitEvent(s, m->ev_leaf_join, 0));
       launch_fmm_down_idft<T, V>(Lc.nc, Lc.L, 2 * Lc.L, Lp.nm, P::tB(Lp), P::Ec(Lp), P::loc(Lc), s);
     }
   }

@@ -41,13 +41,16 @@ void apply_iter(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, do
     if (!m->cap_stream) BEM_HIP(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     BEM_HIP(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+    m->capturing = true;
     try {
       apply_tree(m, op, prec, x, y, m->cap_stream);
     } catch (...) {
+      m->capturing = false;
       (void)hipStreamEndCapture(m->cap_stream, &g);
       if (g) (void)hipGraphDestroy(g);
       throw;
     }
+    m->capturing = false;
     BEM_HIP(hipStreamEndCapture(m->cap_stream, &g));
     const hipError_t e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);

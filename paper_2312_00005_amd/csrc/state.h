@@ -66,6 +66,11 @@ struct bem_mesh {
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bem::DevBuf<double2> d_far;
+  // inside the FMM, the leaf-level translation runs on a third stream beside
+  // the upward pass, the upper levels' translations and the downward pass
+  hipStream_t leaf_stream = nullptr;
+  hipEvent_t ev_leaf_fork = nullptr, ev_leaf_join = nullptr;
+  bool capturing = false;  // set while an application is captured into a graph
 
   // direct far field (far_direct option)
   bool far_direct = false;
@@ -101,6 +106,9 @@ struct bem_mesh {
     if (side_stream) (void)hipStreamDestroy(side_stream);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (leaf_stream) (void)hipStreamDestroy(leaf_stream);
+    if (ev_leaf_fork) (void)hipEventDestroy(ev_leaf_fork);
+    if (ev_leaf_join) (void)hipEventDestroy(ev_leaf_join);
     bem::fmm_destroy(fmm_state);
   }
 };
