@@ -242,8 +242,10 @@ def main():
             o.gmres_tol = 1e-6
             ms = bemfmm.Mesh(nodes, tris, o)
             # one problem at a nearby wavenumber first: the device buffers of the
-            # per-frequency state are allocated once per mesh, as in a sweep
+            # per-frequency state are allocated once per mesh, as in a sweep;
+            # the launch shapes are tuned once per mesh there too
             ms.set_problem(k * 1.01)
+            ms.autotune()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ms.set_problem(k)

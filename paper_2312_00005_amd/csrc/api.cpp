@@ -192,13 +192,16 @@ void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const
   if (part == 0 && m->fmm) {
     // fork: far field into d_far on the side stream, near field into y on s
     // (stream, events and buffer are made with the mesh: nothing here may
-    // allocate, so that the sequence can be captured)
+    // allocate, so that the sequence can be captured).  The near field is
+    // enqueued first: after an idle device (each Krylov step waits for its
+    // Gram-Schmidt values) it would otherwise start only once the host has
+    // submitted the whole far-field chain.
     BEM_HIP(hipEventRecord(m->ev_fork, s));
     BEM_HIP(hipStreamWaitEvent(m->side_stream, m->ev_fork, 0));
+    launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
     launch_zero(m->N, m->d_far.p, m->side_stream);
     far_apply(m, op, prec, x, m->d_far.p, m->side_stream, vmode);
     BEM_HIP(hipEventRecord(m->ev_join, m->side_stream));
-    launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
     BEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
     launch_axpby(m->N, make_double2(1, 0), y, make_double2(1, 0), m->d_far.p, y, s);
     BEM_HIP(hipGetLastError());
