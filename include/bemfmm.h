@@ -278,15 +278,16 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
                                void* stream);
 
 /* Choose launch shapes by timing them on this mesh and problem: near-field
- * targets per workgroup (1, 2, 4, 8), translation threads per workgroup
- * (64, 128, 256) and, with the cluster tree, the resident near-field
- * wavefronts per compute unit while the far field runs beside it (0, 8, 12,
- * 16, 24; see near_waves_per_cu), for the FP64 and the complex-FP32
- * operator.  Results are kept in the mesh and used by every later
- * application; near_wpb, translate_tpb and near_waves (host int32[2]: FP64,
- * FP32) receive them and may be NULL.  Runs about 50 operator parts on the
- * stream; results are unchanged by the choice (each output keeps its owner
- * and summation order). */
+ * targets per workgroup (1, 2, 4, 8) on the near field alone and, with the
+ * cluster tree, the resident near-field wavefronts per compute unit while the
+ * far field runs beside it (0, 8, 12, 16, 24; see near_waves_per_cu) jointly
+ * with the translation threads per workgroup (64, 128, 256; FMM only) on
+ * whole applications, for the FP64 and the complex-FP32 operator.  Results
+ * are kept in the mesh and used by every later application; near_wpb,
+ * translate_tpb and near_waves (host int32[2]: FP64, FP32) receive them and
+ * may be NULL.  Runs about 200 operator applications or parts on the stream;
+ * results are unchanged by the choice (each output keeps its owner and
+ * summation order). */
 bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb,
                         int32_t* near_waves, void* stream);
 

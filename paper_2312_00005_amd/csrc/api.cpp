@@ -745,7 +745,7 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
     auto timed = [&](auto&& fn) {
       fn();  // warm-up
       BEM_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) fn();
+      for (int r = 0; r < 5; ++r) fn();
       BEM_HIP(hipEventRecord(e1, s));
       BEM_HIP(hipEventSynchronize(e1));
       float ms = 0.0f;
@@ -767,33 +767,28 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           }
         }
         m->tune_wpb[pi] = pick;
-        if (m->fmm && !m->far_direct) {
-          best = -1.0f;
-          pick = 64;
-          for (int tpb : {64, 128, 256}) {
-            m->tune_tpb[pi] = tpb;
-            const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 2, m->d_x.p, m->d_y.p, s); });
-            if (best < 0.0f || t < best) {
-              best = t;
-              pick = tpb;
-            }
-          }
-          m->tune_tpb[pi] = pick;
-        }
         if (m->fmm) {
           // resident near-field wavefronts per compute unit while the far
-          // field runs beside it on the side stream (whole applications)
+          // field runs beside it, jointly with the translation block size:
+          // the kernels compete for the same slots, so both are timed on
+          // whole applications
           best = -1.0f;
-          pick = 0;
-          for (int nw : {0, 8, 12, 16, 24}) {
-            m->tune_nwaves[pi] = nw;
-            const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
-            if (best < 0.0f || t < best) {
-              best = t;
-              pick = nw;
+          int pick_nw = 0, pick_tpb = m->tune_tpb[pi];
+          const std::vector<int> tpbs = m->far_direct ? std::vector<int>{m->tune_tpb[pi]} : std::vector<int>{64, 128, 256};
+          for (int tpb : tpbs) {
+            for (int nw : {0, 8, 12, 16, 24}) {
+              m->tune_tpb[pi] = tpb;
+              m->tune_nwaves[pi] = nw;
+              const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
+              if (best < 0.0f || t < best) {
+                best = t;
+                pick_nw = nw;
+                pick_tpb = tpb;
+              }
             }
           }
-          m->tune_nwaves[pi] = pick;
+          m->tune_nwaves[pi] = pick_nw;
+          m->tune_tpb[pi] = pick_tpb;
         }
         if (near_wpb) near_wpb[pi] = m->tune_wpb[pi];
         if (translate_tpb) translate_tpb[pi] = m->tune_tpb[pi];
