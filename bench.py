@@ -116,6 +116,14 @@ def summarize_counters(fetch_csv, write_csv, out):
     cal_f = pick(fetch, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
     cal_w = pick(write, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
     avg = lambda v: sum(v) / len(v)
+
+    def rel(path):
+        # the command lines record where the counter runs wrote, relative to
+        # the repository when inside it
+        r = os.path.relpath(os.path.abspath(path), ROOT)
+        return path if r.startswith("..") else r
+
+    fdir, wdir = rel(os.path.dirname(fetch_csv) or "."), rel(os.path.dirname(write_csv) or ".")
     f_scale = max(fetch[cal_f]) / CAL_BYTES
     w_scale = max(write[cal_w]) / CAL_BYTES
     rec = {
@@ -130,12 +138,11 @@ def summarize_counters(fetch_csv, write_csv, out):
         "hbm_bytes_per_launch": avg(fetch[near_f]) / f_scale + avg(write[near_w]) / w_scale,
         "source_sha256": kernel_source_hash(),
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- "
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fdir} -o f -- "
             "python bench.py --profile-near-only --steps 3 --warmup 1",
-            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- "
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {wdir} -o w -- "
             "python bench.py --profile-near-only --steps 3 --warmup 1",
-            "python bench.py --summarize-counters gpurun_out/pmc_fetch/f_counter_collection.csv "
-            "gpurun_out/pmc_write/w_counter_collection.csv",
+            f"python bench.py --summarize-counters {rel(fetch_csv)} {rel(write_csv)}",
         ],
     }
     with open(out, "w") as fh:

@@ -2,7 +2,9 @@
 the eager path: GMRES solves with and without graphs agree bit for bit
 (every kernel is deterministic), for the FMM and the direct far field, A and
 A^H, FP64 and mixed precision, across a change of wavenumber (which forces a
-new capture) and with eager Krylov work between the replays."""
+new capture) and with eager Krylov work between the replays.  Eager FMM
+applications also run the leaf-level translation on a third stream, which
+captured ones do not, so the comparison covers that split as well."""
 
 import math
 
