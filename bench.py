@@ -64,6 +64,13 @@ def parse():
                     help="turn two rocprofv3 counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) "
                          "of --profile-near-only runs into the traffic record read by the bench")
     ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json"))
+    ap.add_argument("--profile-far-only", action="store_true",
+                    help="run only complex-FP32 far-field (FMM) applications, then the calibration copy")
+    ap.add_argument("--summarize-translate", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="per-launch HBM bytes of the translation kernel from two counter runs of "
+                         "--profile-far-only, written to --translate-out")
+    ap.add_argument("--translate-out",
+                    default=os.path.join(ROOT, "profiles", "k_translate_c2_sphere20480_traffic.json"))
     return ap.parse_args()
 
 
@@ -161,10 +168,56 @@ def measured_traffic():
     return rec["hbm_bytes_per_launch"]
 
 
+def summarize_translate(fetch_csv, write_csv, out):
+    """FETCH_SIZE / WRITE_SIZE per translation launch, grouped by grid (one
+    group per tree level), scaled by what the same counters read for the
+    calibration copy of known size."""
+    import csv
+
+    def per_dispatch(path, counter):
+        acc = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (r["Kernel_Name"], r.get("Grid_Size", r.get("Grid_Size_X", "")))
+                acc.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = per_dispatch(write_csv, "WRITE_SIZE")
+    cal = lambda d: max(max(v) for k, v in d.items() if "copy" in k[0].lower() or "elementwise" in k[0].lower())
+    f_scale, w_scale = cal(fetch) / CAL_BYTES, cal(write) / CAL_BYTES
+    avg = lambda v: sum(v) / len(v)
+    groups = []
+    for key in sorted(k for k in fetch if "k_translate<float" in k[0]):
+        fb = avg(fetch[key]) / f_scale
+        wb = avg(write.get(key, [0.0])) / w_scale
+        groups.append({"kernel": key[0].replace("bem::(anonymous namespace)::", "").split("(")[0],
+                       "grid": key[1], "launches": len(fetch[key]),
+                       "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb})
+    rel = lambda p: (lambda r: p if r.startswith("..") else r)(os.path.relpath(os.path.abspath(p), ROOT))
+    rec = {"workload": "c2: 20480-triangle sphere, 3-level FMM, tight preset, complex-FP32 far field",
+           "calibration": {"known_bytes": CAL_BYTES, "fetch_scale": f_scale, "write_scale": w_scale},
+           "groups": sorted(groups, key=lambda g: -g["fetch_bytes_per_launch"]),
+           "commands": [
+               f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {rel(os.path.dirname(fetch_csv) or '.')} -o f -- "
+               "python bench.py --profile-far-only --steps 3 --warmup 1",
+               f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {rel(os.path.dirname(write_csv) or '.')} -o w -- "
+               "python bench.py --profile-far-only --steps 3 --warmup 1",
+               f"python bench.py --summarize-translate {rel(fetch_csv)} {rel(write_csv)}"]}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.traffic_out)
+        return
+    if args.summarize_translate:
+        summarize_translate(args.summarize_translate[0], args.summarize_translate[1], args.translate_out)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -208,14 +261,15 @@ def main():
     stats = mesh.stats()
     x = torch.from_numpy(synth.complex_normal(N, seed=4)).to("cuda")
     y = torch.empty_like(x)
-    if args.profile_near_only:
+    if args.profile_near_only or args.profile_far_only:
         for _ in range(args.warmup + args.steps):
-            mesh.apply_part(x, 1, prec="mixed", out=y)
+            mesh.apply_part(x, 2 if args.profile_far_only else 1, prec="mixed", out=y)
         src = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"profiled {args.warmup + args.steps} near-field applications and one {CAL_BYTES} B copy")
+        log(f"profiled {args.warmup + args.steps} {'far' if args.profile_far_only else 'near'}-field "
+            f"applications and one {CAL_BYTES} B copy")
         return
 
     def timed(fn, steps):
