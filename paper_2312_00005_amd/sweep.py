@@ -11,14 +11,18 @@ translation memory.  Frequencies that share a method share one device plan
 caller's stream.  Solving several frequencies concurrently from several host
 threads (one HIP stream and mesh instance each) is disabled: such a run ended
 once in a host segmentation fault inside the solve whose cause has not been
-found.  This module only schedules calls into the library.
+found.  Frequencies may come from a frequency-defining curve
+(``FrequencySweep.from_curve``) and element groups may carry an admittance
+that follows curves of the frequency step (``admittance=``, see curves.py);
+each frequency is then solved with its own beta.  This module only schedules
+calls into the library.
 """
 
 import math
 import threading
 import time
 
-from . import bemfmm
+from . import bemfmm, curves
 
 
 def wavenumbers(freqs, c=343.0):
@@ -47,9 +51,17 @@ class FrequencySweep:
     """Solve the exterior problem at every frequency of ``freqs`` on one mesh."""
 
     def __init__(self, nodes, tris, freqs, c=343.0, preset="mixed", depths=(4, 3, 2), leaf_size=32,
-                 memory_budget=96e9, max_L=120, streams=1, **overrides):
+                 memory_budget=96e9, max_L=120, streams=1, steps=None, admittance=None, rho=1.21, **overrides):
+        """steps / admittance: the frequency step s of every frequency and a
+        list of curves.AdmittanceGroup; each frequency is then solved with
+        beta = rho c Y(s) per element (Y = 0, sound hard, outside the groups)."""
         self.nodes, self.tris = nodes, tris
         self.freqs = list(freqs)
+        self.admittance = list(admittance) if admittance else []
+        self.steps = None if steps is None else [float(v) for v in steps]
+        if self.admittance and (self.steps is None or len(self.steps) != len(self.freqs)):
+            raise ValueError("frequency-dependent admittance needs the frequency step of every frequency")
+        self.rho_c = float(rho) * float(c)
         self.ks = wavenumbers(self.freqs, c)
         self.preset = preset
         self.leaf_size = leaf_size
@@ -70,6 +82,20 @@ class FrequencySweep:
         kind, d = method
         return bemfmm.Mesh(self.nodes, self.tris, self.preset, use_fmm=1, levels=d, leaf_size=self.leaf_size,
                            far_direct=1 if kind == "direct" else 0, **self.overrides)
+
+    @classmethod
+    def from_curve(cls, nodes, tris, n_steps, stepsize, s0, freq_curve, **kw):
+        """Frequencies f_n = freq_curve(s0 + stepsize n), n = 1 .. n_steps."""
+        s = curves.steps(n_steps, stepsize, s0)
+        return cls(nodes, tris, [freq_curve(v) for v in s], steps=s, **kw)
+
+    def beta(self, i):
+        """Device beta = rho c Y of frequency i, or None (sound hard)."""
+        if not self.admittance:
+            return None
+        import torch
+        y = curves.element_admittance(self.admittance, len(self.tris), self.steps[i])
+        return torch.from_numpy(self.rho_c * y).to("cuda")
 
     def run(self, source=("plane", (0.0, 0.0, 1.0), 1.0), keep_solutions=True):
         """Returns a list of per-frequency dicts (k, method, info, seconds and
@@ -95,7 +121,7 @@ class FrequencySweep:
                         for i in idx[w::len(meshes)]:
                             k = self.ks[i]
                             t1 = time.perf_counter()
-                            mesh.set_problem(k)
+                            mesh.set_problem(k, self.beta(i))
                             kind, s, P0 = source
                             b = mesh.rhs_plane_wave(s, P0) if kind == "plane" else mesh.rhs_point_source(s, P0)
                             p, _, info = mesh.solve(b, allow_noconv=True)

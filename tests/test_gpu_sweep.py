@@ -52,6 +52,46 @@ def test_sweep_methods_and_solutions():
         assert err < (1e-9 if r["method"][0] == "direct" else 1e-6)
 
 
+def test_sweep_frequency_dependent_admittance():
+    """Frequencies from a frequency-defining curve and an admittance whose real
+    and imaginary parts follow two more curves of the frequency step, on the
+    upper half of the sphere (input description, appendix): every solution
+    against the oracle's LU solution with beta = rho c alpha(s) from the
+    oracle's own curves."""
+    from paper_2312_00005_amd import curves, sweep
+    from oracle import curves as ocurves
+    announce("sweep ico3 with admittance curves")
+    nodes, tris = synth.icosphere(3)
+    g = element_geometry(nodes, tris)
+    upper = np.nonzero(g["x"][:, 2] > 0.0)[0]
+    rho, c = 1.21, 343.0
+    v0 = complex(0.5, -0.2) / (rho * c)
+    fnodes = [(0.0, 0.0), (2.0, 200.0)]
+    re_nodes, im_nodes = [(0.0, 0.5), (2.0, 1.5)], [(0.0, 1.0), (2.0, 2.0)]
+    grp = curves.AdmittanceGroup(upper, v0, curves.Curve(re_nodes), curves.Curve(im_nodes))
+    S = sweep.FrequencySweep.from_curve(nodes, tris, 2, 1.0, 0.0, curves.Curve(fnodes), c=c, rho=rho,
+                                        preset="mixed", depths=(3, 2), leaf_size=16, admittance=[grp],
+                                        gmres_tol=1e-10)
+    assert S.freqs == pytest.approx(ocurves.frequencies(2, 1.0, 0.0, fnodes))
+    results, _ = S.run()
+    p_mixed = preset("mixed")
+    for n, r in enumerate(results, start=1):
+        s = ocurves.step_arguments(2, 1.0, 0.0)[n - 1]
+        beta = np.zeros(len(tris), dtype=np.complex128)
+        beta[upper] = rho * c * ocurves.admittance(s, v0, re_nodes, im_nodes)
+        k = r["k"]
+        b = op.rhs_plane_wave(g, k, (0.0, 0.0, 1.0), p=p_mixed)
+        ref = op.lu_solve(op.dense(g, k, beta=beta, p=p_mixed), b)
+        err = rel_l2(to_host(r["p"]), ref)
+        announce(f"  step {n} f={r['f']:.0f} {r['method']} it={r['info']['iterations']} err={err:.2e}")
+        assert r["method"][0] == "direct"
+        assert err < 1e-9
+    # the admittance changes the solution: against the sound-hard solve
+    rigid = op.lu_solve(op.dense(g, results[-1]["k"], p=p_mixed),
+                        op.rhs_plane_wave(g, results[-1]["k"], (0.0, 0.0, 1.0), p=p_mixed))
+    assert rel_l2(to_host(results[-1]["p"]), rigid) > 1e-3
+
+
 @pytest.mark.skip(reason="two host threads solving concurrently (two streams) ended once in a host "
                          "segmentation fault inside bem_solve; the cause is not found, so the mode is "
                          "disabled in the sweep and stays off the GPU")
