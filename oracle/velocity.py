@@ -1,0 +1,35 @@
+"""Prescribed normal velocity (VELO condition; oracle's own copy, test
+infrastructure only).
+
+Input appendix, boundary conditions: VELO fixes the normal particle velocity u
+of an element; it may be combined with ADMI (a vibrating source on an
+absorbing surface).  In Eq. (SystemI) the normal derivative of the pressure
+unknown is then v = c phi + v_bar with v_bar = i w rho u = i k rho c u (time
+factor exp(-i w t), normal pointing into the fluid), and the known part moves
+to the right-hand side:
+
+    A(c) phi = b - V v_bar,   V = dA/dc (G - gamma H' off the diagonal,
+                                         G_ii - gamma/2 on it).
+
+Pinned by tests/test_oracle_velocity.py against the pulsating sphere, whose
+surface pressure is rho c u (i k a)/(i k a - 1) for a uniform u.
+"""
+
+import numpy as np
+
+from .adjoint import dense_dc
+from .operator import dense, lu_solve
+
+
+def velocity_rhs(geom, k, u, rho_c, p=None, gamma=None):
+    """-V (i k rho c u): the right-hand-side term of prescribed velocities u."""
+    V = dense_dc(geom, k, p=p, gamma=gamma)
+    return -(V @ (1j * k * rho_c * np.asarray(u, dtype=np.complex128)))
+
+
+def solve_velocity(geom, k, u, rho_c, beta=None, b=None, p=None, gamma=None):
+    """Pressure with prescribed velocities u (and admittance beta, incident b)."""
+    rhs = velocity_rhs(geom, k, u, rho_c, p=p, gamma=gamma)
+    if b is not None:
+        rhs = rhs + b
+    return lu_solve(dense(geom, k, beta, p, gamma), rhs)
