@@ -232,6 +232,18 @@ bem_status bem_apply_part(bem_mesh* m, bem_op op, bem_precision prec, int part,
 bem_status bem_apply_dc(bem_mesh* m, bem_op op, bem_precision prec,
                         const bem_c128* x, bem_c128* y, void* stream);
 
+/* Prescribed normal particle velocities (VELO condition of the input
+ * description, appendix; may be combined with ADMI): with v = c phi + v_bar
+ * and v_bar = i k rho_c u in Eq. (SystemI), the known part moves to the
+ * right-hand side:  rhs <- rhs - i k rho_c V u,  V = dA/dc as in
+ * bem_apply_dc, applied with the FP64 operator.  u: device bem_c128[n_tri]
+ * (outward normal velocity, 0 where not prescribed), caller's element order;
+ * rhs: device bem_c128[n_tri], updated in place.  Uses k of the problem;
+ * rho_c > 0 or BEM_E_ARG.  The velocity that bem_solve reports (-Y p) does
+ * not include u. */
+bem_status bem_rhs_velocity(bem_mesh* m, const bem_c128* u, double rho_c, bem_c128* rhs,
+                            void* stream);
+
 /* Solve A^H x = rhs (the adjoint system of an admittance gradient) with the
  * same GMRES / refinement settings as bem_solve.  Blocking; info may be NULL. */
 bem_status bem_solve_adjoint(bem_mesh* m, const bem_c128* rhs, bem_c128* x_out,

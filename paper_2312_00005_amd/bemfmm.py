@@ -104,6 +104,7 @@ _SIGS = {
     "bem_apply_part": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
     "bem_solve": (_i32, [_vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(bem_solve_info), _vp]),
     "bem_apply_dc": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "bem_rhs_velocity": (_i32, [_vp, _vp, _dbl, _vp, _vp]),
     "bem_incident_field": (_i32, [_vp, _i32, _vp, bem_c128, _i64, _vp, _vp, _vp]),
     "bem_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "bem_field": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -184,6 +185,10 @@ def bem_apply_part(mesh, op, prec, part, x_ptr, y_ptr, stream):
 
 def bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream):
     _check(_lib.bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream))
+
+
+def bem_rhs_velocity(mesh, u_ptr, rho_c, rhs_ptr, stream):
+    _check(_lib.bem_rhs_velocity(mesh, u_ptr, float(rho_c), rhs_ptr, stream))
 
 
 def bem_autotune(mesh, stream):
@@ -457,6 +462,11 @@ class Mesh:
         out = self._empty() if out is None else out
         bem_apply_dc(self._h, _OPS[op], _PRECS[prec], xp, _dev_c128(out, self.n, "y"), _stream())
         return out
+
+    def rhs_add_velocity(self, rhs, u, rho_c):
+        """rhs -= i k rho_c V u in place: prescribed normal velocities u (VELO)."""
+        bem_rhs_velocity(self._h, _dev_c128(u, self.n, "u"), rho_c, _dev_c128(rhs, self.n, "rhs"), _stream())
+        return rhs
 
     def autotune(self):
         """Time the launch-shape candidates on this problem and keep the fastest."""

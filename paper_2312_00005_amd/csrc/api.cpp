@@ -855,6 +855,24 @@ bem_status bem_apply_dc(bem_mesh* m, bem_op op, bem_precision prec, const bem_c1
   });
 }
 
+bem_status bem_rhs_velocity(bem_mesh* m, const bem_c128* u, double rho_c, bem_c128* rhs, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !u || !rhs) return fail(BEM_E_ARG, "NULL argument");
+    if (!(rho_c > 0.0)) return fail(BEM_E_ARG, "rho_c must be positive");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    hipStream_t s = as_stream(stream);
+    // d_b = V u in the caller's order, then rhs = rhs - i k rho_c d_b (d_b is
+    // the solve's staging buffer, allocated with the mesh and free between calls)
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(u), m->d_x.p, s);
+    apply_tree_part(m, BEM_OP_A, BEM_PREC_FP64, 0, m->d_x.p, m->d_y.p, s, true);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, m->d_b.p, s);
+    double2* r = reinterpret_cast<double2*>(rhs);
+    launch_axpby(m->N, make_double2(1, 0), r, make_double2(0, -m->k * rho_c), m->d_b.p, r, s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
 namespace {
 
 FieldArgs field_args(bem_mesh* m, int64_t npts, int part) {

@@ -102,3 +102,9 @@ def test_subdivision_overflow_names_the_element(bem):
     with pytest.raises(bem.BemError) as e:
         bem.Mesh(nodes, tris, "paper", use_fmm=0, max_subdiv=2)
     assert e.value.status == bem.BEM_E_MESH
+
+
+def test_null_arguments_are_rejected_before_any_device_work(bem):
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_rhs_velocity(None, None, 415.0, None, None)
+    assert e.value.status == bem.BEM_E_ARG
