@@ -54,7 +54,9 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="target host time of the oracle sample (the one-row probe overestimates a row, "
+                         "so the sample usually takes about half of it)")
     ap.add_argument("--streams", type=int, default=1,
                     help="concurrent frequencies in the sweep workload (only 1: concurrent host threads are disabled)")
     ap.add_argument("--profile-near-only", action="store_true",
@@ -423,6 +425,11 @@ def cpu_baseline(nodes, tris, k, pre, budget):
     N = len(tris)
     x = synth.complex_normal(N, seed=4)
     rng = np.random.default_rng(7)
+    try:  # one host thread, as reported (numpy's BLAS would otherwise spread the product)
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)
+    except ImportError:
+        limit = None
     t0 = time.perf_counter()
     op.rows(g, rng.choice(N, 1, replace=False), k, p=preset(pre)) @ x
     t1 = time.perf_counter() - t0
@@ -431,6 +438,8 @@ def cpu_baseline(nodes, tris, k, pre, budget):
     t0 = time.perf_counter()
     y = op.rows(g, rows, k, p=preset(pre)) @ x
     dt = time.perf_counter() - t0
+    if limit is not None:
+        limit.unregister()
     return {"value": nrows * N / dt, "unit": "element-interactions/s", "cores": 1, "kind": "oracle",
             "sample": f"{nrows} random rows of the dense N={N} operator ({pre} preset) assembled by "
                       f"the numpy oracle and applied to x, {dt:.1f}s on one host core"}
