@@ -57,7 +57,8 @@ def frequencies(n_steps: int, stepsize: float, s0: float, curve: Curve) -> np.nd
 @dataclass
 class AdmittanceGroup:
     """Elements (indices into the mesh's triangles) with admittance v0, whose
-    real and imaginary parts follow curve_re and curve_im (None: constant)."""
+    real and imaginary parts follow curve_re and curve_im (None: constant).
+    The same scaling serves a source strength (elements unused)."""
     elements: np.ndarray
     v0: complex
     curve_re: Optional[Curve] = None

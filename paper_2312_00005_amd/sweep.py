@@ -97,9 +97,20 @@ class FrequencySweep:
         y = curves.element_admittance(self.admittance, len(self.tris), self.steps[i])
         return torch.from_numpy(self.rho_c * y).to("cuda")
 
-    def run(self, source=("plane", (0.0, 0.0, 1.0), 1.0), keep_solutions=True):
+    def source_strength(self, i, P0, curve_re=None, curve_im=None):
+        """P0 at frequency i: c1(s) Re P0 + i c2(s) Im P0 with the step's
+        curves (the input description scales source strengths like
+        admittances); without curves P0 itself."""
+        if curve_re is None and curve_im is None:
+            return complex(P0)
+        if self.steps is None:
+            raise ValueError("a frequency-dependent source strength needs the frequency step of every frequency")
+        return curves.AdmittanceGroup(None, P0, curve_re, curve_im).value(self.steps[i])
+
+    def run(self, source=("plane", (0.0, 0.0, 1.0), 1.0), keep_solutions=True, source_curves=(None, None)):
         """Returns a list of per-frequency dicts (k, method, info, seconds and
-        the device solution p) plus timing totals."""
+        the device solution p) plus timing totals.  source_curves: curves of
+        the frequency step for the real and imaginary part of P0."""
         import torch
         groups = {}
         for i, m in enumerate(self.methods):
@@ -123,6 +134,7 @@ class FrequencySweep:
                             t1 = time.perf_counter()
                             mesh.set_problem(k, self.beta(i))
                             kind, s, P0 = source
+                            P0 = self.source_strength(i, P0, *source_curves)
                             b = mesh.rhs_plane_wave(s, P0) if kind == "plane" else mesh.rhs_point_source(s, P0)
                             p, _, info = mesh.solve(b, allow_noconv=True)
                             streams[w].synchronize()

@@ -92,6 +92,30 @@ def test_sweep_frequency_dependent_admittance():
     assert rel_l2(to_host(results[-1]["p"]), rigid) > 1e-3
 
 
+def test_sweep_source_strength_curves():
+    """A plane wave whose strength follows curves of the frequency step: each
+    solution is the constant-strength one times P0(s) (the operator is linear;
+    GMRES is invariant to the scale of the right-hand side up to rounding)."""
+    from paper_2312_00005_amd import curves, sweep
+    from oracle import curves as ocurves
+    announce("sweep ico3 with source-strength curves")
+    nodes, tris = synth.icosphere(3)
+    fn = curves.Curve([(0.0, 0.0), (2.0, 200.0)])
+    re_nodes, im_nodes = [(0.0, 1.0), (2.0, 3.0)], [(0.0, 0.0), (2.0, -1.0)]
+    S = sweep.FrequencySweep.from_curve(nodes, tris, 2, 1.0, 0.0, fn, preset="mixed", depths=(3, 2),
+                                        leaf_size=16, gmres_tol=1e-11)
+    P0 = complex(2.0, 0.5)
+    src = ("plane", (0.0, 0.0, 1.0), P0)
+    scaled, _ = S.run(source=src, source_curves=(curves.Curve(re_nodes), curves.Curve(im_nodes)))
+    plain, _ = S.run(source=("plane", (0.0, 0.0, 1.0), 1.0))
+    for n, (a, b) in enumerate(zip(scaled, plain), start=1):
+        s = ocurves.step_arguments(2, 1.0, 0.0)[n - 1]
+        strength = ocurves.admittance(s, P0, re_nodes, im_nodes)  # same scaling rule
+        err = rel_l2(to_host(a["p"]), strength * to_host(b["p"]))
+        announce(f"  step {n}: P0(s) = {strength:.3f}, err {err:.1e}")
+        assert err < 1e-9
+
+
 @pytest.mark.skip(reason="two host threads solving concurrently (two streams) ended once in a host "
                          "segmentation fault inside bem_solve; the cause is not found, so the mode is "
                          "disabled in the sweep and stays off the GPU")
