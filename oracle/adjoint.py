@@ -31,8 +31,10 @@ from .integrals import offdiag_integrals, self_integrals
 from .operator import coupling, dense, lu_solve, rhs_plane_wave, rhs_point_source
 
 
-def dense_dc(geom, k, p=None, gamma=None):
-    """V = dA/dc (the matrix that multiplies diag(c)), shape (N, N)."""
+def dense_dc(geom, k, p=None, gamma=None, tau=1):
+    """V = dA/dc (the matrix that multiplies diag(c)), shape (N, N); tau = -1
+    negates the integral terms of the interior problem (the -gamma/2 of the
+    jump term stays)."""
     gamma = coupling(k, gamma, p)
     N = geom["x"].shape[0]
     V = np.zeros((N, N), dtype=np.complex128)
@@ -43,9 +45,9 @@ def dense_dc(geom, k, p=None, gamma=None):
         IG, _, IHp, _ = offdiag_integrals(geom["x"][ii[e]], geom["n"][ii[e]], geom["P0"][jj[e]],
                                           geom["P1"][jj[e]], geom["P2"][jj[e]], geom["n"][jj[e]],
                                           geom["A"][jj[e]], k, p)
-        V[ii[e], jj[e]] = IG - gamma * IHp
+        V[ii[e], jj[e]] = tau * (IG - gamma * IHp)
     Gs, _ = self_integrals(geom, k, p)
-    V[np.arange(N), np.arange(N)] = Gs - 0.5 * gamma
+    V[np.arange(N), np.arange(N)] = tau * Gs - 0.5 * gamma
     return V
 
 

@@ -51,8 +51,10 @@ def bc_factor(k, beta):
     return -1j * k * np.asarray(beta, dtype=np.complex128)
 
 
-def rows(geom, row_idx, k, beta=None, p=None, gamma=None, cols=None, stats=None):
-    """Rows ``row_idx`` of the dense operator A (optionally only ``cols``)."""
+def rows(geom, row_idx, k, beta=None, p=None, gamma=None, cols=None, stats=None, tau=1):
+    """Rows ``row_idx`` of the dense operator A (optionally only ``cols``).
+    tau = -1: the interior problem of Eq. (SystemI), every integral term
+    negated and the jump term (phi - gamma v)/2 kept."""
     gamma = coupling(k, gamma, p)
     N = geom["x"].shape[0]
     c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
@@ -71,7 +73,7 @@ def rows(geom, row_idx, k, beta=None, p=None, gamma=None, cols=None, stats=None)
                               geom["P1"][gj[e]], geom["P2"][gj[e]], geom["n"][gj[e]],
                               geom["A"][gj[e]], k, p, stats=stats)
         IG, IH, IHp, IE = I
-        out[ii[e], jj[e]] = -(IH - gamma * IE) + (IG - gamma * IHp) * c[gj[e]]
+        out[ii[e], jj[e]] = tau * (-(IH - gamma * IE) + (IG - gamma * IHp) * c[gj[e]])
     # diagonal entries present in this block
     pos = {int(j): t for t, j in enumerate(cols)}
     diag_rows = [(r, pos[int(g)]) for r, g in enumerate(row_idx) if int(g) in pos]
@@ -81,13 +83,13 @@ def rows(geom, row_idx, k, beta=None, p=None, gamma=None, cols=None, stats=None)
         Gs, Es = self_integrals(sub, k, p)
         for t, (r, cpos) in enumerate(diag_rows):
             ci = c[sel[t]]
-            out[r, cpos] = 0.5 * (1.0 - gamma * ci) + gamma * Es[t] + Gs[t] * ci
+            out[r, cpos] = 0.5 * (1.0 - gamma * ci) + tau * (gamma * Es[t] + Gs[t] * ci)
     return out
 
 
-def dense(geom, k, beta=None, p=None, gamma=None, stats=None):
+def dense(geom, k, beta=None, p=None, gamma=None, stats=None, tau=1):
     N = geom["x"].shape[0]
-    return rows(geom, np.arange(N), k, beta, p, gamma, stats=stats)
+    return rows(geom, np.arange(N), k, beta, p, gamma, stats=stats, tau=tau)
 
 
 def diagonal(geom, k, beta=None, p=None, gamma=None):

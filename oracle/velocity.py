@@ -21,15 +21,16 @@ from .adjoint import dense_dc
 from .operator import dense, lu_solve
 
 
-def velocity_rhs(geom, k, u, rho_c, p=None, gamma=None):
+def velocity_rhs(geom, k, u, rho_c, p=None, gamma=None, tau=1):
     """-V (i k rho c u): the right-hand-side term of prescribed velocities u."""
-    V = dense_dc(geom, k, p=p, gamma=gamma)
+    V = dense_dc(geom, k, p=p, gamma=gamma, tau=tau)
     return -(V @ (1j * k * rho_c * np.asarray(u, dtype=np.complex128)))
 
 
-def solve_velocity(geom, k, u, rho_c, beta=None, b=None, p=None, gamma=None):
-    """Pressure with prescribed velocities u (and admittance beta, incident b)."""
-    rhs = velocity_rhs(geom, k, u, rho_c, p=p, gamma=gamma)
+def solve_velocity(geom, k, u, rho_c, beta=None, b=None, p=None, gamma=None, tau=1):
+    """Pressure with prescribed velocities u (and admittance beta, incident b);
+    tau = -1 for the interior problem."""
+    rhs = velocity_rhs(geom, k, u, rho_c, p=p, gamma=gamma, tau=tau)
     if b is not None:
         rhs = rhs + b
-    return lu_solve(dense(geom, k, beta, p, gamma), rhs)
+    return lu_solve(dense(geom, k, beta, p, gamma, tau=tau), rhs)

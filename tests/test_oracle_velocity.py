@@ -25,3 +25,22 @@ def test_pulsating_sphere_converges():
     e2, e3 = _err(2, 2.0), _err(3, 2.0)
     assert e3 < 0.03
     assert e3 < 0.65 * e2
+
+
+def _cavity_err(level, k, rho_c=415.0, u0=1e-3):
+    nodes, tris = synth.icosphere(level)
+    g = element_geometry(nodes, tris)
+    p = velocity.solve_velocity(g, k, np.full(len(tris), u0 + 0j), rho_c, p=preset("tight"), tau=-1)
+    # inside a sphere of radius a (= 1) moving with normal velocity u: p = C sin(kr)/r,
+    # dp/dr(a) = i k rho c u, so p(a) = rho c u i ka sin(ka) / (ka cos(ka) - sin(ka))
+    exact = rho_c * u0 * 1j * k * np.sin(k) / (k * np.cos(k) - np.sin(k))
+    return np.max(np.abs(p - exact)) / abs(exact)
+
+
+def test_interior_cavity_converges():
+    """tau = -1 (interior problem, Eq. (SystemI)): the field inside a pulsating
+    spherical cavity; a wrong tau on the integral terms or on the jump term
+    leaves an O(1) error."""
+    e2, e3 = _cavity_err(2, 1.0), _cavity_err(3, 1.0)
+    assert e3 < 0.04
+    assert e3 < 0.65 * e2
