@@ -161,6 +161,14 @@ typedef struct bem_options {
                                complex-FP32 operator, whose pair orders are
                                chosen on the fly; the FP64 operator and every
                                near-field plan use quad_eps */
+  int32_t interior;         /* 0: exterior problem (tau = 1 in Eq. (SystemI));
+                               1: interior problem (tau = -1: every integral
+                               term negated, the jump term (phi - gamma v)/2
+                               kept; the mesh normals still point out of the
+                               object).  Interior meshes use no block-Jacobi
+                               preconditioner and refuse the field-point calls
+                               (bem_field, bem_field_adjoint), which evaluate
+                               the exterior representation formula. */
 } bem_options;
 
 typedef struct bem_solve_info {

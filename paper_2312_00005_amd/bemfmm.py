@@ -62,7 +62,7 @@ class bem_options(ctypes.Structure):
         ("gamma_re", ctypes.c_double), ("gamma_im_k", ctypes.c_double),
         ("far_direct", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("level_rows", ctypes.c_int32),
         ("solver", ctypes.c_int32), ("near_waves_per_cu", ctypes.c_int32),
-        ("quad_eps_mixed", ctypes.c_double),
+        ("quad_eps_mixed", ctypes.c_double), ("interior", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -65,6 +65,7 @@ void set_paper(bem_options* o) {
   o->gamma_re = 0.0;
   o->gamma_im_k = 1.0;
   o->far_direct = 0;
+  o->interior = 0;
   o->use_graphs = 1;
 }
 
@@ -126,6 +127,7 @@ void check_options(const bem_options* o) {
     throw Error(BEM_E_ARG, "unknown precision");
   if (o->precond < 0 || o->precond > 2) throw Error(BEM_E_ARG, "precond must be 0, 1 or 2");
   if (o->far_direct != 0 && o->far_direct != 1) throw Error(BEM_E_ARG, "far_direct must be 0 or 1");
+  if (o->interior != 0 && o->interior != 1) throw Error(BEM_E_ARG, "interior must be 0 or 1");
   if (o->use_graphs != 0 && o->use_graphs != 1) throw Error(BEM_E_ARG, "use_graphs must be 0 or 1");
   if (o->level_rows != 0 && o->level_rows != 1) throw Error(BEM_E_ARG, "level_rows must be 0 or 1");
   if (o->solver != 0 && o->solver != 1) throw Error(BEM_E_ARG, "solver must be 0 (GMRES) or 1 (CGS)");
@@ -144,8 +146,22 @@ void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, do
   apply_tree_part(m, op, prec, 0, x, y, s);
 }
 
+void apply_tree_part_ext(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
+                         hipStream_t s, bool vmode);
+
+// The exterior application, turned into the interior one when the mesh was
+// made for an interior problem.
 void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
                      hipStream_t s, bool vmode) {
+  apply_tree_part_ext(m, op, prec, part, x, y, s, vmode);
+  if (!m->opt.interior) return;
+  const bool adj = op != BEM_OP_A;
+  const int mode = part == 2 ? 4 : (vmode ? 2 : 0) + (adj ? 1 : 0);
+  launch_interior(m->N, mode, m->gre, m->gim, m->have_beta ? m->d_cfac.p : nullptr, x, y, s);
+}
+
+void apply_tree_part_ext(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
+                         hipStream_t s, bool vmode) {
   // a caller's own graph capture of s also counts as capturing (the far field
   // then forks no third stream; see fmm_apply)
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -626,7 +642,8 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_cfac.alloc(n_tri);
     m->d_diag.alloc(n_tri);
     m->d_vdiag.alloc(n_tri);
-    if (o->precond) build_blocks(m.get(), o->precond == 1 ? kMaxBlock : 1);
+    // the block-Jacobi factors hold blocks of the exterior operator
+    if (o->precond && !o->interior) build_blocks(m.get(), o->precond == 1 ? kMaxBlock : 1);
     if (m->fmm) {
       BEM_HIP(hipStreamCreateWithFlags(&m->side_stream, hipStreamNonBlocking));
       BEM_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
@@ -909,6 +926,8 @@ bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c1
   return guarded([&]() -> bem_status {
     if (!m || !p_surf || n_pts < 0 || (n_pts > 0 && (!pts || !p_out))) return fail(BEM_E_ARG, "NULL argument");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    if (m->opt.interior)
+      return fail(BEM_E_STATE, "field points use the exterior representation formula (interior mesh)");
     if (n_pts == 0) {
       if (energy) BEM_HIP(hipMemsetAsync(energy, 0, sizeof(double), as_stream(stream)));
       return BEM_OK;
@@ -932,6 +951,8 @@ bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts, cons
     if (!m || !y_surf || n_pts < 0 || (n_pts > 0 && (!pts || !g))) return fail(BEM_E_ARG, "NULL argument");
     if (part != 0 && part != 1) return fail(BEM_E_ARG, "part must be 0 or 1");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    if (m->opt.interior)
+      return fail(BEM_E_STATE, "field points use the exterior representation formula (interior mesh)");
     hipStream_t s = as_stream(stream);
     DevBuf<int64_t> err;
     err.upload(std::vector<int64_t>{-1}, s);

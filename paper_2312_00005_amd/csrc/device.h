@@ -154,6 +154,10 @@ void launch_scale_copy(int64_t N, const double2* w, double2 alpha, double2* out,
 void launch_zero(int64_t N, double2* out, hipStream_t s);
 void launch_axpby(int64_t N, double2 a, const double2* x, double2 b, const double2* y, double2* out,
                   hipStream_t s);
+// interior problem: turn an exterior application y (of x) into the interior
+// one, y = -y + 2 D x (mode: 0 A, 1 A^H, 2 V, 3 V^H, 4 integral part only)
+void launch_interior(int64_t N, int mode, double gre, double gim, const double2* cfac, const double2* x,
+                     double2* y, hipStream_t s);
 int multidot_blocks(int64_t N);
 
 }  // namespace bem

@@ -138,6 +138,40 @@ void launch_zero(int64_t N, double2* out, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, out);
 }
 
+// Interior problem (tau = -1 in Eq. (SystemI)): with the exterior operator
+// A = D + K (D = (1 - gamma c)/2 the jump term, K every integral term) the
+// interior one is D - K = 2 D - A, so y = A x becomes y = -y + 2 D x.
+// mode 0: A (2D = 1 - gamma c); 1: A^H (conj); 2: V = dA/dc, whose jump
+// part is -gamma/2 (2D = -gamma); 3: V^H; 4: an integral part alone (-y).
+__global__ void k_interior(int64_t N, int mode, double gre, double gim, const double2* __restrict__ cfac,
+                           const double2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double2 v = y[n];
+  if (mode == 4) {
+    y[n] = make_double2(-v.x, -v.y);
+    return;
+  }
+  double dr, di;  // 2 D_nn
+  if (mode <= 1) {
+    const double2 c = cfac ? cfac[n] : make_double2(0.0, 0.0);
+    dr = 1.0 - (gre * c.x - gim * c.y);
+    di = -(gre * c.y + gim * c.x);
+  } else {
+    dr = -gre;
+    di = -gim;
+  }
+  if (mode == 1 || mode == 3) di = -di;
+  const double2 u = x[n];
+  y[n] = make_double2(-v.x + dr * u.x - di * u.y, -v.y + dr * u.y + di * u.x);
+}
+
+void launch_interior(int64_t N, int mode, double gre, double gim, const double2* cfac, const double2* x,
+                     double2* y, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_interior, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, mode, gre, gim, cfac, x, y);
+}
+
 void launch_axpby(int64_t N, double2 a, const double2* x, double2 b, const double2* y, double2* out,
                   hipStream_t s) {
   if (N <= 0) return;
