@@ -34,3 +34,24 @@ def solve_velocity(geom, k, u, rho_c, beta=None, b=None, p=None, gamma=None, tau
     if b is not None:
         rhs = rhs + b
     return lu_solve(dense(geom, k, beta, p, gamma, tau=tau), rhs)
+
+
+def pressure_system(geom, k, pres, beta=None, p=None, gamma=None, tau=1):
+    """System matrix with prescribed pressure (PRES) on the elements ``pres``
+    (input appendix, boundary conditions): there the pressure is known and
+    the unknown is v = dp/dn, so those columns of A are replaced by the
+    columns of V = dA/dc; admittance on PRES elements is ignored."""
+    pres = np.asarray(pres, dtype=np.int64)
+    c_beta = None if beta is None else np.array(beta, dtype=np.complex128)
+    if c_beta is not None:
+        c_beta[pres] = 0.0
+    M = dense(geom, k, c_beta, p, gamma, tau=tau)
+    V = dense_dc(geom, k, p=p, gamma=gamma, tau=tau)
+    A0_pres = M[:, pres].copy()  # the pressure columns (c = 0 there)
+    M[:, pres] = V[:, pres]
+    return M, A0_pres
+
+
+def pressure_rhs(A0_pres, pres_values):
+    """-A0[:, pres] p_bar: the known pressures moved to the right-hand side."""
+    return -(A0_pres @ np.asarray(pres_values, dtype=np.complex128))
