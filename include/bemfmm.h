@@ -240,6 +240,23 @@ bem_status bem_apply_part(bem_mesh* m, bem_op op, bem_precision prec, int part,
 bem_status bem_apply_dc(bem_mesh* m, bem_op op, bem_precision prec,
                         const bem_c128* x, bem_c128* y, void* stream);
 
+/* Prescribed pressure (PRES condition of the input description, appendix;
+ * p = 0 makes an element sound soft).  elems: host int64[n] element indices
+ * (caller's order), n = 0 clears the set.  On these elements the pressure is
+ * known and the unknown of bem_solve becomes v = dp/dn: the system's columns
+ * there are those of V = dA/dc (see bem_apply_dc) instead of A, every
+ * application of A then runs A and V once each, admittance on these elements
+ * is ignored and no block-Jacobi factors are used.  Invalidates the problem:
+ * call bem_set_problem afterwards.  Errors: BEM_E_ARG for an index outside
+ * the mesh. */
+bem_status bem_set_pressure_elements(bem_mesh* m, int64_t n, const int64_t* elems, void* stream);
+
+/* rhs <- rhs - A p_bar over the PRES elements (their known pressures moved to
+ * the right-hand side; p_bar: device bem_c128[n_tri] in the caller's order,
+ * read only on PRES elements).  FP64 operator.  BEM_E_STATE without PRES
+ * elements or before bem_set_problem. */
+bem_status bem_rhs_pressure(bem_mesh* m, const bem_c128* pbar, bem_c128* rhs, void* stream);
+
 /* Prescribed normal particle velocities (VELO condition of the input
  * description, appendix; may be combined with ADMI): with v = c phi + v_bar
  * and v_bar = i k rho_c u in Eq. (SystemI), the known part moves to the

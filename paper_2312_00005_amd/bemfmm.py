@@ -105,6 +105,8 @@ _SIGS = {
     "bem_solve": (_i32, [_vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(bem_solve_info), _vp]),
     "bem_apply_dc": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "bem_rhs_velocity": (_i32, [_vp, _vp, _dbl, _vp, _vp]),
+    "bem_set_pressure_elements": (_i32, [_vp, _i64, _vp, _vp]),
+    "bem_rhs_pressure": (_i32, [_vp, _vp, _vp, _vp]),
     "bem_incident_field": (_i32, [_vp, _i32, _vp, bem_c128, _i64, _vp, _vp, _vp]),
     "bem_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "bem_field": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -189,6 +191,14 @@ def bem_apply_dc(mesh, op, prec, x_ptr, y_ptr, stream):
 
 def bem_rhs_velocity(mesh, u_ptr, rho_c, rhs_ptr, stream):
     _check(_lib.bem_rhs_velocity(mesh, u_ptr, float(rho_c), rhs_ptr, stream))
+
+
+def bem_set_pressure_elements(mesh, n, elems_ptr, stream):
+    _check(_lib.bem_set_pressure_elements(mesh, n, elems_ptr, stream))
+
+
+def bem_rhs_pressure(mesh, pbar_ptr, rhs_ptr, stream):
+    _check(_lib.bem_rhs_pressure(mesh, pbar_ptr, rhs_ptr, stream))
 
 
 def bem_autotune(mesh, stream):
@@ -462,6 +472,18 @@ class Mesh:
         out = self._empty() if out is None else out
         bem_apply_dc(self._h, _OPS[op], _PRECS[prec], xp, _dev_c128(out, self.n, "y"), _stream())
         return out
+
+    def set_pressure_elements(self, elems):
+        """PRES elements (host integer indices); their unknown becomes dp/dn.
+        Call set_problem afterwards."""
+        import numpy as np
+        idx = np.ascontiguousarray(np.asarray(elems, dtype=np.int64).ravel())
+        bem_set_pressure_elements(self._h, idx.size, idx.ctypes.data if idx.size else None, _stream())
+
+    def rhs_add_pressure(self, rhs, pbar):
+        """rhs -= A pbar over the PRES elements, in place."""
+        bem_rhs_pressure(self._h, _dev_c128(pbar, self.n, "pbar"), _dev_c128(rhs, self.n, "rhs"), _stream())
+        return rhs
 
     def rhs_add_velocity(self, rhs, u, rho_c):
         """rhs -= i k rho_c V u in place: prescribed normal velocities u (VELO)."""

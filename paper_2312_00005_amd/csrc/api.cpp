@@ -151,13 +151,34 @@ void apply_tree_part_ext(bem_mesh* m, bem_op op, bem_precision prec, int part, c
 
 // The exterior application, turned into the interior one when the mesh was
 // made for an interior problem.
-void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
-                     hipStream_t s, bool vmode) {
+void apply_one(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
+               hipStream_t s, bool vmode) {
   apply_tree_part_ext(m, op, prec, part, x, y, s, vmode);
   if (!m->opt.interior) return;
   const bool adj = op != BEM_OP_A;
   const int mode = part == 2 ? 4 : (vmode ? 2 : 0) + (adj ? 1 : 0);
   launch_interior(m->N, mode, m->gre, m->gim, m->have_beta ? m->d_cfac.p : nullptr, x, y, s);
+}
+
+void apply_tree_part(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
+                     hipStream_t s, bool vmode) {
+  if (!m->has_pres || vmode) {
+    apply_one(m, op, prec, part, x, y, s, vmode);
+    return;
+  }
+  // PRES columns are those of V: M x = A (x off PRES) + V (x on PRES);
+  // M^H y = A^H y off PRES, V^H y on PRES (rows of the transpose)
+  if (op == BEM_OP_A) {
+    launch_mask(m->N, m->d_pres.p, 0, x, m->d_px.p, s);
+    apply_one(m, op, prec, part, m->d_px.p, y, s, false);
+    launch_mask(m->N, m->d_pres.p, 1, x, m->d_px.p, s);
+    apply_one(m, op, prec, part, m->d_px.p, m->d_py.p, s, true);
+    launch_axpby(m->N, make_double2(1, 0), y, make_double2(1, 0), m->d_py.p, y, s);
+  } else {
+    apply_one(m, op, prec, part, x, y, s, false);
+    apply_one(m, op, prec, part, x, m->d_py.p, s, true);
+    launch_blend(m->N, m->d_pres.p, y, m->d_py.p, s);
+  }
 }
 
 void apply_tree_part_ext(bem_mesh* m, bem_op op, bem_precision prec, int part, const double2* x, double2* y,
@@ -398,7 +419,7 @@ void build_blocks(bem_mesh* m, int max_n) {
 // assemble and invert the blocks for the current problem
 void setup_preconditioner(bem_mesh* m, hipStream_t s) {
   m->precond_ready = false;
-  if (!m->opt.precond || m->nblk == 0) return;
+  if (!m->opt.precond || m->nblk == 0 || m->has_pres) return;
   NearLaunch L{};
   L.N = m->N;
   L.geom = m->d_geom.p;
@@ -676,6 +697,8 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
       m->d_beta.alloc(m->N);
       BEM_HIP(hipMemcpyAsync(m->d_beta.p, beta, m->N * sizeof(double2), hipMemcpyDeviceToDevice, s));
       launch_cfac(m->N, m->d_perm.p, m->d_beta.p, k, m->d_cfac.p, s);
+      // admittance is ignored on PRES elements (their pressure is given)
+      if (m->has_pres) launch_mask(m->N, m->d_pres.p, 0, m->d_cfac.p, m->d_cfac.p, s);
     }
     SelfLaunch L{};
     L.N = m->N;
@@ -867,6 +890,48 @@ bem_status bem_apply_dc(bem_mesh* m, bem_op op, bem_precision prec, const bem_c1
     launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(x), m->d_x.p, s);
     apply_tree_part(m, op, prec, 0, m->d_x.p, m->d_y.p, s, true);
     launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(y), s);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+  });
+}
+
+bem_status bem_set_pressure_elements(bem_mesh* m, int64_t n, const int64_t* elems, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || n < 0 || (n > 0 && !elems)) return fail(BEM_E_ARG, "NULL argument or negative count");
+    std::vector<double> mask(m->N, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+      if (elems[i] < 0 || elems[i] >= m->N) return fail(BEM_E_ARG, "PRES element index out of range");
+      mask[m->tree.inv[elems[i]]] = 1.0;
+    }
+    hipStream_t s = as_stream(stream);
+    m->has_pres = n > 0;
+    if (m->has_pres) {
+      m->d_pres.upload(mask, s);
+      m->d_px.alloc(m->N);
+      m->d_py.alloc(m->N);
+    }
+    // the factors of the problem (c, diagonal, preconditioner, captured
+    // graphs) depend on the PRES set: bem_set_problem must run again
+    m->have_problem = false;
+    m->precond_ready = false;
+    ++m->problem_stamp;
+    return BEM_OK;
+  });
+}
+
+bem_status bem_rhs_pressure(bem_mesh* m, const bem_c128* pbar, bem_c128* rhs, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !pbar || !rhs) return fail(BEM_E_ARG, "NULL argument");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    if (!m->has_pres) return fail(BEM_E_STATE, "no PRES elements (bem_set_pressure_elements)");
+    hipStream_t s = as_stream(stream);
+    // d_b = A (pbar on PRES elements) in the caller's order; rhs -= d_b
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(pbar), m->d_y.p, s);
+    launch_mask(m->N, m->d_pres.p, 1, m->d_y.p, m->d_x.p, s);
+    apply_one(m, BEM_OP_A, BEM_PREC_FP64, 0, m->d_x.p, m->d_y.p, s, false);
+    launch_scatter(m->N, m->d_perm.p, m->d_y.p, m->d_b.p, s);
+    double2* r = reinterpret_cast<double2*>(rhs);
+    launch_axpby(m->N, make_double2(1, 0), r, make_double2(-1, 0), m->d_b.p, r, s);
     BEM_HIP(hipGetLastError());
     return BEM_OK;
   });
@@ -1071,7 +1136,8 @@ size_t bem_workspace_bytes(const bem_mesh* m) {
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
              m->d_partial.bytes() + m->d_h.bytes() + m->d_z.bytes() + m->d_elem_blk.bytes() +
              m->d_blk_n.bytes() + m->d_blk_sing.bytes() + m->d_blk_beg.bytes() + m->d_blk_off.bytes() +
-             m->d_blk_a.bytes() + m->d_blk_inv.bytes() + m->d_blk_items.bytes() + m->d_blk_seg.bytes() + m->d_far.bytes();
+             m->d_blk_a.bytes() + m->d_blk_inv.bytes() + m->d_blk_items.bytes() + m->d_blk_seg.bytes() + m->d_far.bytes() +
+             m->d_pres.bytes() + m->d_px.bytes() + m->d_py.bytes();
   return b + fmm_bytes(m);
 }
 

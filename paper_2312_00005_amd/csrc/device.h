@@ -158,6 +158,9 @@ void launch_axpby(int64_t N, double2 a, const double2* x, double2 b, const doubl
 // one, y = -y + 2 D x (mode: 0 A, 1 A^H, 2 V, 3 V^H, 4 integral part only)
 void launch_interior(int64_t N, int mode, double gre, double gim, const double2* cfac, const double2* x,
                      double2* y, hipStream_t s);
+// out = x where mask m == keep, else 0; blend: y = z where m == 1 (PRES elements)
+void launch_mask(int64_t N, const double* m, int keep, const double2* x, double2* out, hipStream_t s);
+void launch_blend(int64_t N, const double* m, double2* y, const double2* z, hipStream_t s);
 int multidot_blocks(int64_t N);
 
 }  // namespace bem

@@ -166,6 +166,32 @@ __global__ void k_interior(int64_t N, int mode, double gre, double gim, const do
   y[n] = make_double2(-v.x + dr * u.x - di * u.y, -v.y + dr * u.y + di * u.x);
 }
 
+// out = x on the elements with mask m == keep, 0 elsewhere (m is 0 or 1)
+__global__ void k_mask(int64_t N, const double* __restrict__ m, int keep, const double2* __restrict__ x,
+                       double2* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  out[n] = (m[n] != 0.0) == (keep != 0) ? x[n] : make_double2(0.0, 0.0);
+}
+
+// y = y where m == 0, z where m == 1
+__global__ void k_blend(int64_t N, const double* __restrict__ m, double2* __restrict__ y,
+                        const double2* __restrict__ z) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  if (m[n] != 0.0) y[n] = z[n];
+}
+
+void launch_mask(int64_t N, const double* m, int keep, const double2* x, double2* out, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_mask, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, m, keep, x, out);
+}
+
+void launch_blend(int64_t N, const double* m, double2* y, const double2* z, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_blend, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, m, y, z);
+}
+
 void launch_interior(int64_t N, int mode, double gre, double gim, const double2* cfac, const double2* x,
                      double2* y, hipStream_t s) {
   if (N <= 0) return;

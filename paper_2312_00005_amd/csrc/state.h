@@ -71,6 +71,11 @@ struct bem_mesh {
   hipStream_t leaf_stream = nullptr;
   hipEvent_t ev_leaf_fork = nullptr, ev_leaf_join = nullptr;
   bool capturing = false;  // set while an application is captured into a graph
+  // prescribed-pressure (PRES) elements: their unknown is v = dp/dn, so the
+  // system's columns there are those of V = dA/dc instead of A
+  bem::DevBuf<double> d_pres;       // tree order: 1 on PRES elements, 0 elsewhere
+  bem::DevBuf<double2> d_px, d_py;  // masked input and second application
+  bool has_pres = false;
 
   // direct far field (far_direct option)
   bool far_direct = false;
