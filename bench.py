@@ -27,7 +27,14 @@ sys.path.insert(0, ROOT)
 # phase factor (4), the complex accumulation (8); 61 with the admittance terms
 FLOPS_PER_POINT = 46
 FLOPS_PER_POINT_BC = 61
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# the same integrand evaluated term by term (G, H, H', E from r, 1/r and
+# exp(ikr), then the Burton-Miller combination), the count of a direct
+# implementation: 66 flops per point
+FLOPS_PER_POINT_DIRECT = 66
+# MI355X vector peaks: FP64 78.6 TFLOP/s; FP32 157.3 TFLOP/s with packed
+# FP32 instructions, which this build does not emit (78.6 without them)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32_packed": 157.3, "fp32": 78.6}
+SOLVE_TOL = 1e-6
 
 WORKLOADS = {
     # config of the headline metric: 20480-triangle rigid sphere, 6 elements
@@ -81,6 +88,7 @@ def log(msg):
 
 
 NEAR_KERNEL = "k_near<float, false, false"
+NEAR_KERNEL64 = "k_near<double, false, false"
 CAL_BYTES = 512 * 2 ** 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json")
 
@@ -274,6 +282,9 @@ def main():
             f"applications and one {CAL_BYTES} B copy")
         return
 
+    # the stream every kernel of an application is enqueued on (near field,
+    # permutations and the final sum; the far field forks from and joins it),
+    # so events recorded on it bracket whole launches
     def timed(fn, steps):
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -286,13 +297,21 @@ def main():
         return ev0.elapsed_time(ev1) / 1e3 / steps
 
     res = {}
-    for prec in ("mixed", "fp64"):
+    for prec in ("fp64", "mixed"):
         for _ in range(args.warmup):
             mesh.apply(x, prec=prec, out=y)
         t_full = timed(lambda: mesh.apply(x, prec=prec, out=y), args.steps)
         t_near = timed(lambda: mesh.apply_part(x, 1, prec=prec, out=y), args.steps)
         res[prec] = dict(t_full=t_full, t_near=t_near)
         log(f"{prec}: matvec {t_full * 1e3:.3f} ms, near part {t_near * 1e3:.3f} ms")
+    golden = load_golden(args.workload, N, k)
+    acc = {}
+    if golden is not None:
+        acc["operator_rel_l2"] = {}
+        for prec in ("fp64", "mixed"):
+            yv = mesh.apply(x, prec=prec).cpu().numpy()
+            acc["operator_rel_l2"][prec] = rel_l2(yv, golden["y_ax"])
+        log(f"operator vs oracle (dense, converged quadrature): {acc['operator_rel_l2']}")
     solves = {}
     if not args.no_solve:
         for prec in ("mixed", "fp64"):
@@ -302,7 +321,7 @@ def main():
                 o.levels = wl["levels"]
                 o.leaf_size = wl["leaf_size"]
             o.precision = bemfmm.BEM_PREC_MIXED if prec == "mixed" else bemfmm.BEM_PREC_FP64
-            o.gmres_tol = 1e-6
+            o.gmres_tol = SOLVE_TOL
             ms = bemfmm.Mesh(nodes, tris, o)
             # one problem at a nearby wavenumber first: the device buffers of the
             # per-frequency state are allocated once per mesh, as in a sweep;
@@ -321,14 +340,28 @@ def main():
             solves[prec] = dict(seconds=time.perf_counter() - t0, iterations=info["iterations"],
                                 refinements=info["refinements"], rel_residual=info["rel_residual"],
                                 L=info["L"])
+            if golden is not None:
+                pv = p.cpu().numpy()
+                ref = golden["p_lu"]
+                solves[prec]["pressure_rel_l2_vs_oracle_lu"] = rel_l2(pv, ref)
+                solves[prec]["pressure_max_rel_vs_oracle_lu"] = float(np.max(np.abs(pv - ref)) / np.max(np.abs(ref)))
             log(f"{prec}: solve {solves[prec]}")
             ms.close()
+    if golden is not None and solves:
+        acc["pressure_rel_l2"] = {p_: solves[p_]["pressure_rel_l2_vs_oracle_lu"] for p_ in solves}
+        acc["pressure_max_rel"] = {p_: solves[p_]["pressure_max_rel_vs_oracle_lu"] for p_ in solves}
+        acc["tolerance"] = {"fp64": 1e-5, "mixed": 1e-3}
+        acc["oracle"] = ("dense N x N operator assembled by the CPU oracle with converged quadrature "
+                         "(order tolerance 1e-11), LU solution (tests/golden/c2_sphere20480.npz, written by "
+                         "tests/golden/make_c2_golden.py)")
 
-    t_step = res["mixed"]["t_full"]
+    # headline: the FP64 (complex128) whole-operator application
+    t_step = res["fp64"]["t_full"]
     value = N * N / t_step
     pts = stats["quad_points"]
     near_flops = pts * FLOPS_PER_POINT
-    achieved = near_flops / res["mixed"]["t_near"] / 1e12
+    achieved64 = near_flops / res["fp64"]["t_near"] / 1e12
+    achieved32 = near_flops / res["mixed"]["t_near"] / 1e12
     out = {
         "metric": "FMM matvec element-interactions/s and GMRES solve s/frequency, mixed vs FP64",
         "value": value,
@@ -340,34 +373,63 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (fp32 operator; fp64 diagonal, Krylov and refinement)",
+        "dtype": "complex128",
         "data": "synthetic (seeded mesh and complex-normal vector)",
         "config": {"workload": f"{args.workload}: "
                    + ("graded ellipsoid with bump" if src is not None else "rigid sphere")
                    + f" N={N}, k={k:.4f}, "
                    + (f"{wl['levels']}-level FMM leaf~{wl['leaf_size']}" if wl["use_fmm"] else "all pairs direct")
-                   + f", preset {wl['preset']}",
-                   "n_elements": N, "k": k, "preset": wl["preset"]},
-        "fp64": {"value": N * N / res["fp64"]["t_full"], "ms_per_step": res["fp64"]["t_full"] * 1e3},
-        "mixed_speedup_over_fp64": res["fp64"]["t_full"] / t_step,
-        "near_ms": {p: res[p]["t_near"] * 1e3 for p in res},
+                   + f", preset {wl['preset']} (coupling gamma = -i/k), FP64 operator",
+                   "n_elements": N, "k": k, "preset": wl["preset"], "coupling": "-i/k"},
+        "mixed": {"value": N * N / res["mixed"]["t_full"], "ms_per_step": res["mixed"]["t_full"] * 1e3,
+                  "dtype": "complex64 operator (FP64 self terms, Krylov vectors and refinement)",
+                  "roofline": {"bound": "alu", "kernel": NEAR_KERNEL, "achieved": achieved32,
+                               "peak": PEAK_TFLOPS["fp32_packed"], "unit": "TFLOP/s",
+                               "frac": achieved32 / PEAK_TFLOPS["fp32_packed"],
+                               "peak_unpacked": PEAK_TFLOPS["fp32"],
+                               "frac_unpacked": achieved32 / PEAK_TFLOPS["fp32"],
+                               "traffic": measured_traffic()}},
+        "mixed_speedup_over_fp64": res["fp64"]["t_full"] / res["mixed"]["t_full"],
+        "accuracy": acc,
+        "near_ms": {p_: res[p_]["t_near"] * 1e3 for p_ in res},
         "near_quad_points": pts,
         "setup_s": {"mesh": t_mesh, "per_frequency": t_setup},
         "launch_shapes": tune,
-        "solve_s_per_frequency": {p: solves[p]["seconds"] for p in solves},
+        "solve_s_per_frequency": {p_: solves[p_]["seconds"] for p_ in solves},
         "solve": solves,
-        "roofline": {"bound": "alu", "kernel": NEAR_KERNEL, "achieved": achieved,
-                     "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp32"],
-                     "traffic": measured_traffic(),
+        "roofline": {"bound": "alu", "kernel": NEAR_KERNEL64, "achieved": achieved64,
+                     "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s", "frac": achieved64 / PEAK_TFLOPS["fp64"],
+                     "traffic": None,
                      "flops_per_launch": near_flops, "flops_per_point": FLOPS_PER_POINT,
-                     "fp64_kernel": {"kernel": "k_near<double, false, false",
-                                     "achieved": near_flops / res["fp64"]["t_near"] / 1e12,
-                                     "peak": PEAK_TFLOPS["fp64"],
-                                     "frac": near_flops / res["fp64"]["t_near"] / 1e12 / PEAK_TFLOPS["fp64"]}},
+                     "flops_per_point_direct": FLOPS_PER_POINT_DIRECT,
+                     "frac_at_direct_count": achieved64 * FLOPS_PER_POINT_DIRECT / FLOPS_PER_POINT
+                     / PEAK_TFLOPS["fp64"]},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nodes, tris, k, wl["preset"], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(nodes, tris, k, wl["preset"], args.cpu_seconds,
+                                           mesh_spec=wl["mesh"])
     print(json.dumps(out), flush=True)
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+GOLDEN = {"c2": os.path.join(ROOT, "tests", "golden", "c2_sphere20480.npz")}
+
+
+def load_golden(workload, N, k):
+    """Stored oracle results for the workload (dense operator applied to the
+    seed-4 vector, LU solution of the plane-wave problem), or None."""
+    import numpy as np
+    path = GOLDEN.get(workload)
+    if path is None or not os.path.exists(path):
+        return None
+    z = np.load(path)
+    if int(z["N"]) != N or abs(float(z["k"]) - k) > 1e-12 * k:
+        raise SystemExit(f"{path} holds another workload (N={int(z['N'])}, k={float(z['k'])})")
+    return {"y_ax": z["y_ax"], "p_lu": z["p_lu"]}
 
 
 def run_sweep(args, wl):
@@ -413,36 +475,104 @@ def run_sweep(args, wl):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(nodes, tris, k, pre, budget):
-    """The oracle timed on the host: dense operator rows assembled by direct
-    quadrature and multiplied by the same vector (element-interactions/s)."""
+def _oracle_rows_worker(task):
+    """Worker process of the CPU baseline: assemble dense oracle rows (one
+    host thread per process) and return the time taken."""
+    subdiv, kind, k, pre, rows = task
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
     import numpy as np
     import synth
     from oracle import operator as op
     from oracle.geometry import element_geometry
     from oracle.presets import preset
+    if kind == "icosphere":
+        nodes, tris = synth.icosphere(subdiv)
+    elif kind == "geodesic":
+        nodes, tris = synth.geodesic_sphere(subdiv)
+    else:
+        nodes, tris = synth.graded_ellipsoid_bump()[:2]
     g = element_geometry(nodes, tris)
+    x = synth.complex_normal(len(tris), seed=4)
+    t0 = time.perf_counter()
+    y = op.rows(g, np.asarray(rows), k, p=preset(pre)) @ x
+    return time.perf_counter() - t0, len(rows), complex(y[0])
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(nodes, tris, k, pre, budget, mesh_spec=None):
+    """The oracle timed on the host's own cores:
+    (1) dense operator rows assembled by direct quadrature, one worker
+        process per core (the oracle's assembly rate, extrapolated to all N
+        rows);
+    (2) the dense matvec (zgemv, BLAS threads = cores) of an assembled-size
+        row block, extrapolated to N rows: N^2 / t_zgemv is the oracle's
+        element-interactions/s, the value reported;
+    (3) LU factor + solve (zgetrf / zgetrs) of an n x n complex block,
+        extrapolated to N as (N/n)^3.
+    Every extrapolation is labelled as such."""
+    import multiprocessing as mp
+    import numpy as np
+    import scipy.linalg
+    from threadpoolctl import threadpool_info, threadpool_limits
     N = len(tris)
-    x = synth.complex_normal(N, seed=4)
+    ncpu = os.cpu_count() or 1
+    cores = max(1, min(ncpu, int(os.environ.get("OMP_NUM_THREADS") or ncpu)))
     rng = np.random.default_rng(7)
-    try:  # one host thread, as reported (numpy's BLAS would otherwise spread the product)
-        from threadpoolctl import threadpool_limits
-        limit = threadpool_limits(limits=1)
-    except ImportError:
-        limit = None
-    t0 = time.perf_counter()
-    op.rows(g, rng.choice(N, 1, replace=False), k, p=preset(pre)) @ x
-    t1 = time.perf_counter() - t0
-    nrows = max(1, min(N, int(budget / max(t1, 1e-6))))
-    rows = rng.choice(N, nrows, replace=False)
-    t0 = time.perf_counter()
-    y = op.rows(g, rows, k, p=preset(pre)) @ x
-    dt = time.perf_counter() - t0
-    if limit is not None:
-        limit.unregister()
-    return {"value": nrows * N / dt, "unit": "element-interactions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nrows} random rows of the dense N={N} operator ({pre} preset) assembled by "
-                      f"the numpy oracle and applied to x, {dt:.1f}s on one host core"}
+    # (1) assembly: a one-row probe sizes the sample to about budget/2 seconds
+    ctx = mp.get_context("spawn")
+    spec = mesh_spec
+    with ctx.Pool(cores) as pool:
+        t1, _, _ = pool.apply(_oracle_rows_worker, ((spec[1], spec[0], k, pre, [0]),))
+        per = max(1, int(0.5 * budget / max(t1, 1e-4)))
+        rows = rng.choice(N, min(N, per * cores), replace=False)
+        chunks = [(spec[1], spec[0], k, pre, list(map(int, c))) for c in np.array_split(rows, cores) if len(c)]
+        t0 = time.perf_counter()
+        outs = pool.map(_oracle_rows_worker, chunks)
+        t_asm = time.perf_counter() - t0
+    asm_rate = len(rows) * N / t_asm
+    # (2) zgemv on a dense block with the BLAS on every core
+    nb = min(N, 4096)
+    with threadpool_limits(cores):
+        blas = [{k_: i.get(k_) for k_ in ("internal_api", "num_threads", "version")} for i in threadpool_info()]
+        M = (rng.standard_normal((nb, N)) + 1j * rng.standard_normal((nb, N))).astype(np.complex128)
+        xv = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            M @ xv
+            ts.append(time.perf_counter() - t0)
+        t_gemv = float(np.median(ts)) * N / nb
+        del M
+        # (3) LU on an n x n block
+        n = min(N, 3072)
+        B = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) + n * np.eye(n)
+        t0 = time.perf_counter()
+        lu = scipy.linalg.lu_factor(B, overwrite_a=True, check_finite=False)
+        scipy.linalg.lu_solve(lu, np.ones(n, dtype=np.complex128), check_finite=False)
+        t_lu = (time.perf_counter() - t0) * (N / n) ** 3
+        del B, lu
+    return {"value": N * N / t_gemv, "unit": "element-interactions/s", "cores": cores, "kind": "oracle",
+            "sample": (f"dense zgemv of a {nb} x {N} complex128 block (median of 5, {cores} BLAS threads), "
+                       f"extrapolated to the {N} x {N} matrix; assembly: {len(rows)} random rows of the {pre} "
+                       f"operator by the numpy oracle in {len(chunks)} processes, {t_asm:.1f} s"),
+            "cpu_model": _cpu_model(), "os_cpu_count": ncpu, "blas": blas,
+            "zgemv_s_extrapolated": t_gemv,
+            "assembly_element_interactions_per_s": asm_rate,
+            "assembly_s_extrapolated": N * N / asm_rate,
+            "lu_s_extrapolated": t_lu,
+            "lu_block": n,
+            "solve_s_per_frequency_extrapolated": N * N / asm_rate + t_lu}
 
 
 if __name__ == "__main__":

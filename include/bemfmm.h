@@ -78,7 +78,7 @@ typedef enum {
 
 /* Warning bits of bem_solve_info.warnings (computation continues). */
 #define BEM_WARN_COARSE_MESH 1u  /* fewer than 6 elements per wavelength (Sec. 2.2) */
-#define BEM_WARN_LARGE_L 2u      /* an expansion length above 30 (Sec. 3.4.2)      */
+#define BEM_WARN_LARGE_L 2u      /* an expansion length above 30 (Sec. 4.2)      */
 #define BEM_WARN_NOT_CONVERGED 4u/* iterative solver stopped at its cap (Sec. 3.2) */
 
 typedef struct bem_options {
@@ -98,7 +98,7 @@ typedef struct bem_options {
   int32_t t_order;          /* order of the triangle rule for aggregation    */
   double quad_eps;          /* a-priori quadrature tolerance (1e-3, Sec. 3.1.4) */
   int32_t quad_m_max;       /* maximum Gauss order (6, Sec. 3.1.4)           */
-  int32_t quad_split_on_cap;/* 1: split instead of capping the order (Sec. 4.1.2) */
+  int32_t quad_split_on_cap;/* 1: split instead of capping the order (Sec. 5.1.2) */
   double subdiv_ratio;      /* split while r~ < subdiv_ratio (1.3, Sec. 3.1.3) */
   int32_t max_subdiv;       /* nested split limit (15, Sec. 4.1)             */
   int32_t self_n;           /* Duffy rule order per direction (4, Sec. 3.1.1) */
@@ -210,7 +210,7 @@ int64_t bem_mesh_bad_element(const bem_mesh* m);
 /* Per-frequency setup: wavenumber k > 0 and per-element normalised
  * admittance beta (device bem_c128[n_tri], or NULL for sound-hard
  * everywhere).  Computes the singular self terms, expansion lengths, sphere
- * grids, interpolation and translation data (Sec. 3.3.1, Sec. 3.4.2). */
+ * grids, interpolation and translation data (Sec. 3.3.1, Sec. 4.2). */
 bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta,
                            void* stream);
 
@@ -292,14 +292,33 @@ bem_status bem_incident_field(bem_mesh* m, int kind, const double src[3],
  *   p_out  : device bem_c128[n_pts]
  *   energy : device double[1] receiving sum_f |p_out[f]|^2, or NULL
  * n_pts = 0 is allowed (pts, p_inc, p_out may then be NULL; energy = 0).
- * BEM_E_MESH if a point is so close to an element that subdivision overflows. */
+ * BEM_E_MESH if a point is so close to an element that subdivision overflows.
+ * The normal derivative is taken as c_j p_j (sound-hard or admittance
+ * elements): a mesh with PRES elements is BEM_E_STATE, and a prescribed
+ * velocity (bem_rhs_velocity) is not included -- use bem_field_pv for both. */
 bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts,
                      const bem_c128* p_surf, const bem_c128* p_inc,
                      bem_c128* p_out, double* energy, void* stream);
 
+/* Exterior pressure from the representation formula with the surface
+ * pressure and its normal derivative given separately (Eq. (BIE_I),
+ * lambda = 1, tau = 1; any boundary condition):
+ *   p_out[f] = p_inc[f] + sum_j (I^H(x_f, G_j) p_surf[j] - I^G(x_f, G_j) dpdn_surf[j])
+ *   dpdn_surf : device bem_c128[n_tri], dp/dn on the outward normal: c_j p_j
+ *               on admittance / sound-hard elements, plus i k rho_c u_j where a
+ *               normal velocity u is prescribed, and the solution of bem_solve
+ *               on PRES elements (whose p_surf is the prescribed pressure).
+ * Other arguments, rules and errors as bem_field; interior meshes are
+ * BEM_E_STATE. */
+bem_status bem_field_pv(bem_mesh* m, int64_t n_pts, const double* pts,
+                        const bem_c128* p_surf, const bem_c128* dpdn_surf,
+                        const bem_c128* p_inc, bem_c128* p_out, double* energy,
+                        void* stream);
+
 /* Conjugate transpose of the field map: y_surf[j] = sum_f conj(K_fj) g[f] with
  * K = I^H - c I^G (part 0) or K = I^G alone (part 1).  g: device
- * bem_c128[n_pts]; y_surf: device bem_c128[n_tri]. */
+ * bem_c128[n_pts]; y_surf: device bem_c128[n_tri].  BEM_E_STATE on a mesh
+ * with PRES elements (the map assumes dp/dn = c p). */
 bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts,
                              const bem_c128* g, int part, bem_c128* y_surf,
                              void* stream);
@@ -309,7 +328,8 @@ bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts,
  *   grad[e] = 2 Re{ -i k rho_c p_e ( -conj(w_e) - conj(h_e) ) }
  * where p solves A p = b, w = V^H mu (bem_apply_dc, op A^H) with
  * A^H mu = M^H p_field, and h = (I^G)^H p_field (bem_field_adjoint, part 1).
- * All inputs device bem_c128[n_tri]; grad: device double[n_tri]. */
+ * All inputs device bem_c128[n_tri]; grad: device double[n_tri].
+ * BEM_E_STATE on a mesh with PRES elements. */
 bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w,
                                const bem_c128* hg, double rho_c, double* grad,
                                void* stream);
@@ -331,7 +351,10 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb,
 /* Solve A p = rhs by GMRES (FP64 Krylov vectors and residuals; with
  * precision MIXED an FP64 outer refinement around a complex-FP32 inner
  * operator).  p_out: device bem_c128[n_tri]; v_out (may be NULL): normal
- * velocity v = -beta/(rho_c) p.  info: host, may be NULL.  Blocking.
+ * velocity v = -beta/(rho_c) p.  On PRES elements (bem_set_pressure_elements)
+ * p_out holds the unknown there, dp/dn, and v_out = dp/dn / (i k rho_c).
+ * A prescribed velocity u (bem_rhs_velocity) is not added to v_out.
+ * info: host, may be NULL.  Blocking.
  * BEM_E_NOCONV if the tolerance was not reached (outputs still written). */
 bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out,
                      bem_c128* v_out, double rho_c, bem_solve_info* info,

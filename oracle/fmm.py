@@ -37,7 +37,7 @@ Truncation length per level (Eq. (FMMTruncation)):
             L >= ceil(ln(eps) / ln(1/a)), digits = -log10(eps); then L is
             lowered (not below 4) while 2^-52 (2L+1) |h_L(k X_min)| > eps/10,
             X_min the smallest centre distance of the level's interaction
-            pairs -- the small-argument growth of h_L (Sec. 3.4.2) would
+            pairs -- the small-argument growth of h_L (Sec. 4.2) would
             otherwise amplify rounding beyond the target.
   The complex-FP32 operator of the mixed path has its own lengths: the same
   rule with eps = fmm_eps_mixed and the cap taken with 2^-23 in every mode.

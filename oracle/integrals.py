@@ -17,7 +17,7 @@ Follows Sec. 3.1 "Quadrature":
       32 q^(2m+1),  64 (2m+1) q^(2m+2),  128 (m+1)(2m+1) q^(2m+3),  q = 1/(2 r~)
   are all below ``quad_eps``; if m exceeds ``m_max`` it is capped (paper
   default) or T is split once more (``split_on_cap``, the higher-accuracy
-  variant of Sec. 4.1.2).  The conical rule of order m is then applied.
+  variant of Sec. 5.1.2).  The conical rule of order m is then applied.
 
 Children of T = (P0, P1, P2) with edge midpoints M01, M12, M20:
   (P0, M01, M20), (P1, M12, M01), (P2, M20, M12), (M01, M12, M20).

@@ -20,7 +20,7 @@ Right-hand sides (Sec. 2.4): plane wave P0 exp(i k d.x); point source
 P0 exp(i k R)/(4 pi R); b = p_inc - gamma dp_inc/dn at the centroids.
 
 Solve: LAPACK LU (zgetrf / zgetrs through scipy), the paper's direct
-reference solver (Sec. 3.2, Sec. 4.1.3).
+reference solver (Sec. 3.2, Sec. 5.1.3).
 
 Pinned by: tests/test_oracle_operator.py -- modal eigenvalues of the sphere
 (A P_n(cos theta) ~ lambda_n P_n(cos theta) with O(h) error), the analytic

@@ -7,7 +7,7 @@ order capped, split while r~ < 1.3, at most 15 splits, 4x4 Duffy rule,
 2/sqrt(3)).
 
 ``tight``: the same rules with a 1e-8 order tolerance, splitting instead of
-capping the order (the higher-accuracy variant of Sec. 4.1.2), finer
+capping the order (the higher-accuracy variant of Sec. 5.1.2), finer
 singular and edge rules, and a wider admissibility with an accuracy-driven
 expansion length so that the FMM agrees with the dense operator to ~1e-7.
 

@@ -1,7 +1,7 @@
 """Closed-form sphere results (oracle; test infrastructure only).
 
 The paper checks against the analytic solution for a plane wave on a
-sound-hard sphere (Sec. 4.1); its textbook formula is not reproduced in the
+sound-hard sphere (Sec. 5.1); its textbook formula is not reproduced in the
 paper, so the series is derived here from the plane-wave expansion
 exp(i k r cos t) = sum_n i^n (2n+1) j_n(k r) P_n(cos t) with exp(-i w t)
 time dependence and h_n = h_n^(1):

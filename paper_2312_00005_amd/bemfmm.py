@@ -110,6 +110,7 @@ _SIGS = {
     "bem_incident_field": (_i32, [_vp, _i32, _vp, bem_c128, _i64, _vp, _vp, _vp]),
     "bem_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "bem_field": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bem_field_pv": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_field_adjoint": (_i32, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
     "bem_grad_admittance": (_i32, [_vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
     "bem_solve_adjoint": (_i32, [_vp, _vp, _vp, ctypes.POINTER(bem_solve_info), _vp]),
@@ -218,6 +219,10 @@ def bem_incident_field(mesh, kind, src, P0, n_pts, pts_ptr, out_ptr, stream):
 
 def bem_field(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream):
     _check(_lib.bem_field(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream))
+
+
+def bem_field_pv(mesh, n_pts, pts_ptr, p_ptr, dpdn_ptr, pinc_ptr, out_ptr, energy_ptr, stream):
+    _check(_lib.bem_field_pv(mesh, n_pts, pts_ptr, p_ptr, dpdn_ptr, pinc_ptr, out_ptr, energy_ptr, stream))
 
 
 def bem_field_adjoint(mesh, n_pts, pts_ptr, g_ptr, part, y_ptr, stream):
@@ -517,6 +522,20 @@ class Mesh:
         en = torch.zeros((), dtype=torch.float64, device="cuda") if energy else None
         bem_field(self._h, npts, pts.data_ptr(), _dev_c128(p_surf, self.n, "p_surf"), pinc, out.data_ptr(),
                   en.data_ptr() if en is not None else None, _stream())
+        return (out, en) if energy else out
+
+    def field_pv(self, pts, p_surf, dpdn_surf, p_inc=None, energy=False):
+        """Exterior pressure from the surface pressure and its normal
+        derivative given separately (any boundary condition, PRES included)."""
+        torch = _torch()
+        pts = _dev_pts(pts)
+        npts = pts.shape[0]
+        out = self._empty(npts)
+        pinc = _dev_c128(p_inc, npts, "p_inc") if p_inc is not None else None
+        en = torch.zeros((), dtype=torch.float64, device="cuda") if energy else None
+        bem_field_pv(self._h, npts, pts.data_ptr(), _dev_c128(p_surf, self.n, "p_surf"),
+                     _dev_c128(dpdn_surf, self.n, "dpdn_surf"), pinc, out.data_ptr(),
+                     en.data_ptr() if en is not None else None, _stream())
         return (out, en) if energy else out
 
     def field_adjoint(self, pts, g, part=0):

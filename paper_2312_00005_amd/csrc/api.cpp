@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "state.h"
 
@@ -69,12 +70,16 @@ void set_paper(bem_options* o) {
   o->use_graphs = 1;
 }
 
-// rule tables live in each device's constant memory: uploaded once per device
+// rule tables live in each device's constant memory: uploaded once per
+// device; the flag and the upload are under one lock, so that threads setting
+// up meshes at the same time neither upload twice nor read a half-set flag
 void upload_rules() {
+  static std::mutex mu;
   static bool done[64] = {};
   int dev = 0;
   BEM_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) throw Error(BEM_E_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
   if (done[dev]) return;
   double a[kRulePoints], b[kRulePoints], w[kRulePoints];
   int off[kMaxRuleOrder + 1];
@@ -970,6 +975,7 @@ FieldArgs field_args(bem_mesh* m, int64_t npts, int part) {
   A.split_on_cap = m->opt.quad_split_on_cap;
   A.max_subdiv = m->opt.max_subdiv;
   A.part = part;
+  A.dpdn = nullptr;
   return A;
 }
 
@@ -993,6 +999,8 @@ bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c1
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
     if (m->opt.interior)
       return fail(BEM_E_STATE, "field points use the exterior representation formula (interior mesh)");
+    if (m->has_pres)
+      return fail(BEM_E_STATE, "the mesh has PRES elements, whose normal derivative is not c p: use bem_field_pv");
     if (n_pts == 0) {
       if (energy) BEM_HIP(hipMemsetAsync(energy, 0, sizeof(double), as_stream(stream)));
       return BEM_OK;
@@ -1010,6 +1018,36 @@ bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c1
   });
 }
 
+bem_status bem_field_pv(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c128* p_surf,
+                        const bem_c128* dpdn_surf, const bem_c128* p_inc, bem_c128* p_out, double* energy,
+                        void* stream) {
+  return guarded([&]() -> bem_status {
+    if (!m || !p_surf || !dpdn_surf || n_pts < 0 || (n_pts > 0 && (!pts || !p_out)))
+      return fail(BEM_E_ARG, "NULL argument");
+    if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    if (m->opt.interior)
+      return fail(BEM_E_STATE, "field points use the exterior representation formula (interior mesh)");
+    hipStream_t s = as_stream(stream);
+    if (n_pts == 0) {
+      if (energy) BEM_HIP(hipMemsetAsync(energy, 0, sizeof(double), s));
+      return BEM_OK;
+    }
+    DevBuf<int64_t> err;
+    err.upload(std::vector<int64_t>{-1}, s);
+    // both surface vectors into tree order (d_x: p, d_y: dp/dn; mesh staging)
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(p_surf), m->d_x.p, s);
+    launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(dpdn_surf), m->d_y.p, s);
+    FieldArgs A = field_args(m, n_pts, 0);
+    A.dpdn = m->d_y.p;
+    launch_field(A, pts, m->d_x.p, reinterpret_cast<const double2*>(p_inc), reinterpret_cast<double2*>(p_out),
+                 err.p, s);
+    if (energy) launch_energy(n_pts, reinterpret_cast<const double2*>(p_out), energy, s);
+    BEM_HIP(hipGetLastError());
+    check_field_error(m, err, s);
+    return BEM_OK;
+  });
+}
+
 bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c128* g, int part,
                              bem_c128* y_surf, void* stream) {
   return guarded([&]() -> bem_status {
@@ -1018,6 +1056,7 @@ bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts, cons
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
     if (m->opt.interior)
       return fail(BEM_E_STATE, "field points use the exterior representation formula (interior mesh)");
+    if (m->has_pres) return fail(BEM_E_STATE, "the adjoint field map assumes dp/dn = c p (mesh has PRES elements)");
     hipStream_t s = as_stream(stream);
     DevBuf<int64_t> err;
     err.upload(std::vector<int64_t>{-1}, s);
@@ -1035,6 +1074,7 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
     if (!m || !p || !w || !hg || !grad) return fail(BEM_E_ARG, "NULL argument");
     if (!(rho_c > 0.0)) return fail(BEM_E_ARG, "rho_c must be positive");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
+    if (m->has_pres) return fail(BEM_E_STATE, "admittance gradients assume dp/dn = c p (mesh has PRES elements)");
     hipStream_t s = as_stream(stream);
     launch_grad_admittance(m->N, m->k, rho_c, reinterpret_cast<const double2*>(p),
                            reinterpret_cast<const double2*>(w), reinterpret_cast<const double2*>(hg), grad, s);
@@ -1077,9 +1117,13 @@ bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out, bem_c128
     launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(rhs), m->d_b.p, s);
     SolveResult r = solve_tree(m, m->d_b.p, m->d_sol.p, s);
     launch_scatter(m->N, m->d_perm.p, m->d_sol.p, reinterpret_cast<double2*>(p_out), s);
-    if (v_out)
+    if (v_out) {
       launch_velocity(m->N, m->have_beta ? m->d_beta.p : nullptr, rho_c, reinterpret_cast<double2*>(p_out),
                       reinterpret_cast<double2*>(v_out), s);
+      if (m->has_pres)
+        launch_velocity_pres(m->N, m->d_perm.p, m->d_pres.p, m->k, rho_c, reinterpret_cast<double2*>(p_out),
+                             reinterpret_cast<double2*>(v_out), s);
+    }
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(s));
     if (info) {

@@ -118,6 +118,9 @@ struct FieldArgs {
   double eps, ratio;     // quadrature tolerance, subdivision ratio
   int m_max, split_on_cap, max_subdiv;
   int part;              // 0: K = I^H - c I^G; 1: K = I^G
+  const double2* dpdn;   // k_field only: if set, the scattered field is
+                         // sum_j I^H_j p_j - I^G_j dpdn_j (tree order) and
+                         // cfac and part are not used
 };
 // out[f] = pinc[f] + sum_j K_fj p[j] (p in tree order); err[0] receives the
 // tree position of an element whose subdivision overflowed
@@ -140,6 +143,10 @@ void launch_gather(int64_t N, const int64_t* perm, const double2* src, double2* 
 void launch_scatter(int64_t N, const int64_t* perm, const double2* src, double2* dst, hipStream_t s);
 void launch_cfac(int64_t N, const int64_t* perm, const double2* beta_caller, double k, double2* cfac,
                  hipStream_t s);
+// v[perm[t]] = -i p[perm[t]] / (k rho_c) where pres[t] != 0 (caller-order p, v;
+// tree-order mask): the velocity of PRES elements, whose solution is dp/dn
+void launch_velocity_pres(int64_t N, const int64_t* perm, const double* pres, double k, double rho_c,
+                          const double2* p, double2* v, hipStream_t s);
 void launch_velocity(int64_t N, const double2* beta_caller, double rho_c, const double2* p,
                      double2* v, hipStream_t s);
 

@@ -23,6 +23,7 @@
 #include "sincos_cw.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace bem {
 
@@ -626,11 +627,14 @@ void launch_fmm_translation(int64_t npairs, const int64_t* pm, const int64_t* pn
                             const double* s, int nu, int L, double k, double2* D64, float2* D32,
                             hipStream_t st) {
   if (npairs <= 0) return;
-  // the factors do not depend on the problem: uploaded once per device
+  // the factors do not depend on the problem: uploaded once per device,
+  // flag and upload under one lock (meshes may be set up from several threads)
+  static std::mutex mu;
   static bool leg_ready[64] = {};
   int dev = 0;
   BEM_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) throw Error(BEM_E_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
   if (!leg_ready[dev]) {
     double a[kLegMax], b[kLegMax];
     for (int l = 0; l < kLegMax; ++l) {

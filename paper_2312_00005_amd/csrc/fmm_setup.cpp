@@ -10,7 +10,7 @@
 // L >= ceil(ln(eps)/ln(1/a)), digits = -log10(eps), a the admissibility, and
 // L lowered (not below 4) while the rounding unit times (2L+1)|h_L(k X_min)|
 // exceeds eps/10 (X_min the smallest centre distance of the level's
-// interaction pairs): the growth of h_L at small arguments (Sec. 3.4.2) must
+// interaction pairs): the growth of h_L at small arguments (Sec. 4.2) must
 // not amplify rounding beyond the target.  The complex-FP32 operator of the
 // mixed path uses its own lengths (eps = l_eps_mixed, FP32 rounding unit,
 // cap applied in every mode).

@@ -1099,6 +1099,14 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs A, const double* __rest
       err[0] = j;
       continue;
     }
+    const double2 pj = p[j];
+    if (A.dpdn) {
+      // I^H p_j - I^G (dp/dn)_j with the normal derivative given
+      const double2 vj = A.dpdn[j];
+      ar += (IH.x * pj.x - IH.y * pj.y) - (IG.x * vj.x - IG.y * vj.y);
+      ai += (IH.x * pj.y + IH.y * pj.x) - (IG.x * vj.y + IG.y * vj.x);
+      continue;
+    }
     double kr = IH.x, ki = IH.y;
     if (A.cfac && A.part == 0) {
       const double2 c = A.cfac[j];
@@ -1109,7 +1117,6 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs A, const double* __rest
       kr = IG.x;
       ki = IG.y;
     }
-    const double2 pj = p[j];
     ar += kr * pj.x - ki * pj.y;
     ai += kr * pj.y + ki * pj.x;
   }
@@ -1270,6 +1277,18 @@ __global__ void k_velocity(int64_t N, const double2* __restrict__ beta, double i
   v[t] = make_double2(-inv_rc * (b.x * q.x - b.y * q.y), -inv_rc * (b.x * q.y + b.y * q.x));
 }
 
+// PRES elements (tree position t, caller index perm[t]): the solution holds
+// dp/dn there, so the normal particle velocity is dp/dn / (i w rho) =
+// -i (dp/dn) / (k rho_c)
+__global__ void k_velocity_pres(int64_t N, const int64_t* __restrict__ perm, const double* __restrict__ pres,
+                                double scale, const double2* __restrict__ p, double2* __restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N || pres[t] == 0.0) return;
+  const int64_t e = perm[t];
+  const double2 q = p[e];
+  v[e] = make_double2(scale * q.y, -scale * q.x);
+}
+
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -1389,6 +1408,13 @@ void launch_velocity(int64_t N, const double2* beta, double rho_c, const double2
                      hipStream_t s) {
   if (N <= 0) return;
   hipLaunchKernelGGL(k_velocity, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, beta, 1.0 / rho_c, p, v);
+}
+
+void launch_velocity_pres(int64_t N, const int64_t* perm, const double* pres, double k, double rho_c,
+                          const double2* p, double2* v, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_velocity_pres, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, perm, pres, 1.0 / (k * rho_c),
+                     p, v);
 }
 
 }  // namespace bem

@@ -110,6 +110,20 @@ def test_far_field_matches_oracle_fmm(bem, subdiv, levels, leaf, adm, pre, epw, 
         err = rel_l2(y_full[rows], Aref @ x)
         announce(f"  whole operator vs converged dense rows: {err:.2e}")
         assert err < 1e-6
+    else:
+        # the paper's preset against dense rows too: its far field (L from
+        # Eq. (FMMTruncation) alone) against converged far entries, and the
+        # whole operator against the converged dense operator, which differs
+        # from it by the paper's own 1e-3 quadrature tolerance (Sec. 3.1.4)
+        conv = preset(pre, admissibility=adm, quad_eps=1e-12, split_on_cap=True, self_n=12, edge_parts=8,
+                      edge_gauss=6)
+        Aref = op.rows(g, rows, k, beta=beta, p=conv)
+        far_ref = (Ar * mask) @ x + (Aref * ~mask) @ x
+        e_far = rel_l2(y_full[rows], far_ref)
+        e_all = rel_l2(y_full[rows], Aref @ x)
+        announce(f"  far field vs converged far entries {e_far:.2e}, whole operator vs converged dense {e_all:.2e}")
+        assert e_far < 1e-5
+        assert e_all < 1e-3
 
 
 def test_fmm_levels_reported(bem):
@@ -151,7 +165,7 @@ def test_full_size_operator_sampled_rows(bem, c2):
     y32 = to_host(m.apply(xd, prec="mixed"))
     err32 = rel_l2(y32[rows], Ar @ x)
     announce(f"  fp32 operator vs converged dense rows: {err32:.2e}")
-    assert err32 < 2e-4
+    assert err32 < 1e-4
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

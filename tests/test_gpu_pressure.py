@@ -4,12 +4,17 @@ pressure and velocity terms and the solution against the oracle's dense
 system (1280 triangles, every pair by the near-field kernels); and a sphere
 with the pulsating sphere's pressure on one half and its velocity on the other
 at 20480 triangles with the FMM, whose solution must hold dp/dn = i k rho c u
-on the PRES half and the analytic pressure on the VELO half."""
+on the PRES half and the analytic pressure on the VELO half.  Field points of
+a PRES mesh: bem_field refuses them (its normal derivative would be c p),
+bem_field_pv takes p and dp/dn and matches the oracle's representation
+formula and the pulsating sphere's outgoing field; the reported velocity on
+PRES elements is dp/dn / (i k rho c)."""
 
 import numpy as np
 import pytest
 
 import synth
+from oracle import field as ofield
 from oracle import operator as op
 from oracle import velocity as ovel
 from oracle.geometry import element_geometry
@@ -90,3 +95,46 @@ def test_half_pres_half_velo_pulsating_sphere_with_fmm(bem):
     # first-order discretisation errors; dp/dn is largest next to the line
     # where the condition switches from PRES to VELO (2.2 % there at this size)
     assert e_v < 0.04 and e_p < 0.02
+
+
+def test_field_points_and_velocity_of_pres_mesh(bem):
+    announce("PRES/VELO pulsating sphere ico3: field points and velocities")
+    torch = pytest.importorskip("torch")
+    nodes, tris = synth.icosphere(3)
+    g = element_geometry(nodes, tris)
+    N = len(tris)
+    k, u0 = 2.0, 1e-3
+    p_exact = RHO_C * u0 * (1j * k) / (1j * k - 1.0)
+    pres = np.nonzero(g["x"][:, 2] > 0.0)[0]
+    is_pres = np.isin(np.arange(N), pres)
+    u = np.where(is_pres, 0.0, u0).astype(np.complex128)
+    pt = preset("tight")
+    m = bem.Mesh(nodes, tris, "tight", use_fmm=0, gmres_tol=1e-12)
+    m.set_pressure_elements(pres)
+    m.set_problem(k)
+    rhs = to_dev(np.zeros(N, dtype=np.complex128))
+    m.rhs_add_pressure(rhs, to_dev(np.full(N, p_exact)))
+    m.rhs_add_velocity(rhs, to_dev(u), RHO_C)
+    sol, vel, _ = m.solve(rhs, rho_c=RHO_C)
+    sol, vel = to_host(sol), to_host(vel)
+    # reported velocity: dp/dn / (i k rho c) on PRES elements (= u0 there, up
+    # to the discretisation error of dp/dn), -Y p = 0 elsewhere (no admittance)
+    assert np.allclose(vel[is_pres], sol[is_pres] / (1j * k * RHO_C), rtol=1e-14, atol=0)
+    assert np.max(np.abs(vel[is_pres] - u0)) / u0 < 0.05
+    assert np.all(vel[~is_pres] == 0)
+    p_s = np.where(is_pres, p_exact, sol)
+    v_s = np.where(is_pres, sol, 1j * k * RHO_C * u)
+    pts = synth.points_on_sphere(16, 2.0, seed=3)
+    ptsd = torch.from_numpy(pts).to("cuda")
+    with pytest.raises(bem.BemError) as e:
+        m.field(ptsd, to_dev(p_s))
+    assert e.value.status == bem.BEM_E_STATE
+    f = to_host(m.field_pv(ptsd, to_dev(p_s), to_dev(v_s)))
+    ref = ofield.field_pv(g, pts, k, p_s, v_s, p=pt)
+    e_or = rel_l2(f, ref)
+    r = np.linalg.norm(pts, axis=1)
+    exact = p_exact * np.exp(1j * k * (r - 1.0)) / r
+    e_an = rel_l2(f, exact)
+    announce(f"  field vs oracle {e_or:.1e}, vs pulsating sphere {e_an:.1e}")
+    assert e_or < 1e-12
+    assert e_an < 0.03

@@ -53,7 +53,7 @@ def test_expansion_reproduces_green_function():
     # geometric convergence while L is moderate ...
     for L, tol in [(10, 1e-5), (14, 1e-8), (18, 1e-11)]:
         assert err(L) < tol, (L, err(L))
-    # ... and the small-argument growth of h_L (Sec. 3.4.2) takes over for
+    # ... and the small-argument growth of h_L (Sec. 4.2) takes over for
     # large L: rounding amplified by (2L+1)|h_L(k X)| dominates
     e28 = err(28)
     bound28 = 2.0 ** -52 * (2 * 28 + 1) * ofmm.hankel_abs(28, k * np.linalg.norm(z2 - z1))
@@ -116,12 +116,58 @@ def test_truncation_length_modes():
     p = preset("paper")
     # small clusters: the lower bound 8 of Eq. (FMMTruncation)
     assert ofmm.truncation_length(1.0, 0.1, p) == 8
-    kd = 2 * 0.5 * 30.0
-    assert ofmm.truncation_length(30.0, 0.5, p) == math.ceil(kd + 1.8 * math.log10(kd + math.pi))
     t = preset("tight")
     assert ofmm.truncation_length(30.0, 0.5, t) >= ofmm.truncation_length(30.0, 0.5, p)
     # the stability cap lowers L when the smallest separation is small
     assert ofmm.truncation_length(1.0, 0.3, t, x_min=0.5) < ofmm.truncation_length(1.0, 0.3, t)
+
+
+def test_truncation_length_paper_worked_example():
+    """Sec. 5.1.2: on the sphere at 200 Hz (k = 3.696) the default factor 1.8
+    gives L = 8, 8, 8 on the three levels and factor 15 gives 12, 10, 9.  The
+    paper does not print the cluster radii; with radii halving from level to
+    level (leaf r = 0.0473 m, so that kd = 2 r k = 0.35, 0.7, 1.4) Eq.
+    (FMMTruncation) as implemented reproduces both rows, and a natural
+    logarithm in place of log10, a missing ceiling or a missing minimum of 8
+    does not."""
+    k = 3.696
+    radii = [0.35 / (2 * k) * f for f in (4, 2, 1)]  # levels 1, 2, 3
+    assert [ofmm.truncation_length(k, r, preset("paper")) for r in radii] == [8, 8, 8]
+    assert [ofmm.truncation_length(k, r, preset("paper", l_factor=15.0)) for r in radii] == [12, 10, 9]
+
+
+@pytest.mark.parametrize("k,r", [(27.7, 0.05), (27.7, 0.1), (10.0, 0.2), (60.0, 0.03), (60.0, 0.08), (5.0, 0.3)])
+def test_truncation_length_reaches_target_on_worst_pair(k, r):
+    """At the L chosen for the tight preset (accuracy 1e-7, admissibility 3)
+    the discretised expansion reproduces G (relative to |G|) to within five
+    times the target for two clusters of radius r at the admissibility limit,
+    with x and y on the cluster spheres (facing each other, and at random
+    positions; the (1/a)^L rate holds up to a constant of a few); three terms
+    fewer miss it by more than twenty times, so the length is neither too
+    short nor needlessly long.  green_expansion is
+    pinned to G independently above."""
+    t = preset("tight")
+    X = t["admissibility"] * 2 * r * 1.0001
+    L = ofmm.truncation_length(k, r, t, x_min=X)
+    rng = np.random.default_rng(int(1000 * k * r))
+    e = rng.standard_normal(3)
+    e /= np.linalg.norm(e)
+    z1, z2 = np.zeros(3), X * e
+
+    def worst(LL):
+        pts = [(z1 + r * e, z2 - r * e)]
+        for _ in range(6):
+            u, v = rng.standard_normal(3), rng.standard_normal(3)
+            pts.append((z1 + r * u / np.linalg.norm(u), z2 + r * v / np.linalg.norm(v)))
+        out = 0.0
+        for x, y in pts:
+            d = np.linalg.norm(x - y)
+            gxy = np.exp(1j * k * d) / (4 * math.pi * d)
+            out = max(out, abs(ofmm.green_expansion(k, x, y, z1, z2, LL) - gxy) / abs(gxy))
+        return out
+
+    assert worst(L) < 5 * t["fmm_eps"]
+    assert worst(L - 3) > 20 * t["fmm_eps"]
 
 
 def test_fmm_matches_dense_operator():
