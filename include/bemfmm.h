@@ -188,6 +188,25 @@ typedef struct bem_solve_info {
 
 typedef struct bem_mesh bem_mesh;
 
+/* Device allocator of the library's own memory (plan, per-frequency state,
+ * work vectors).  alloc_fn(bytes, ctx) returns device memory on the current
+ * device (NULL on failure: the calling entry point then returns BEM_E_OOM);
+ * free_fn(ptr, bytes, ctx) takes back what alloc_fn returned, with the same
+ * byte count.  The memory is used on the streams the caller passes and on
+ * the library's internal streams; before a block is returned the library
+ * waits for the device (hipDeviceSynchronize), so free_fn may hand it out
+ * again at once.  A typical pair is PyTorch's caching allocator.
+ *
+ * bem_set_allocator sets the pair for the whole process (both NULL restores
+ * hipMalloc / hipFree; one NULL is BEM_E_ARG).  Every buffer keeps the pair it
+ * was allocated with, so the pair may change between meshes; it must stay
+ * callable until every buffer allocated through it is released
+ * (bem_mesh_destroy).  Not to be called while another thread is inside the
+ * library. */
+typedef void* (*bem_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*bem_free_fn)(void* ptr, size_t bytes, void* ctx);
+bem_status bem_set_allocator(bem_alloc_fn alloc_fn, bem_free_fn free_fn, void* ctx);
+
 /* Fill *o with a named preset: "paper" (the paper's defaults), "tight"
  * (higher-accuracy quadrature and expansion, FP64) or "mixed" ("tight" with
  * complex-FP32 inner operator and FP64 refinement).  Unknown name: BEM_E_ARG. */
@@ -199,10 +218,11 @@ bem_status bem_options_default(bem_options* o, const char* preset);
  *   xyz : host, double[n_nodes][3]
  *   tri : host, int32[n_tri][3], 0-based node indices, counter-clockwise seen
  *         from outside (the paper's mesh appendix)
- * Blocking.  BEM_E_MESH for a zero-area triangle or a subdivision overflow. */
+ * The uploads run on `stream`.  Blocking: returns when the plan is on the
+ * device.  BEM_E_MESH for a zero-area triangle or a subdivision overflow. */
 bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri,
                            const int32_t* tri, const bem_options* o,
-                           bem_mesh** out);
+                           void* stream, bem_mesh** out);
 
 /* Element index (caller order) that caused the last BEM_E_MESH, or -1. */
 int64_t bem_mesh_bad_element(const bem_mesh* m);
@@ -359,6 +379,27 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb,
 bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out,
                      bem_c128* v_out, double rho_c, bem_solve_info* info,
                      void* stream);
+
+/* Solve n independent systems A_i p_i = rhs_i, one per mesh (typically the
+ * frequencies of a sweep, each mesh set up with bem_set_problem at its own
+ * wavenumber), with the settings of bem_solve.  The GMRES iterations of all
+ * systems advance in lock-step, each system on an internal stream of its
+ * mesh forked from `stream` after the caller's prior work: while one
+ * system's Gram-Schmidt coefficients travel to the host, the kernels of the
+ * others run.  Arrays of n pointers (host arrays of device pointers):
+ *   meshes : distinct meshes (a mesh twice is BEM_E_ARG)
+ *   rhs, p_out : device bem_c128[n_tri of that mesh]
+ *   v_out  : NULL, or an array whose entries are NULL or device
+ *            bem_c128[n_tri] (velocity as in bem_solve; rho_c > 0 then)
+ *   infos  : host bem_solve_info[n] or NULL
+ * Blocking: returns when every system is solved and `stream` has joined the
+ * internal streams.  BEM_E_NOCONV if any system stopped before its tolerance
+ * (all outputs written); BEM_E_STATE if a mesh has no problem set.  With the
+ * CGS solver (solver = 1) the systems are solved one after another. */
+bem_status bem_solve_batch(int32_t n, bem_mesh* const* meshes,
+                           const bem_c128* const* rhs, bem_c128* const* p_out,
+                           bem_c128* const* v_out, double rho_c,
+                           bem_solve_info* infos, void* stream);
 
 /* Mesh statistics (host outputs; any pointer may be NULL). */
 bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,

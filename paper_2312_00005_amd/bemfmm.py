@@ -95,7 +95,8 @@ _dbl = ctypes.c_double
 
 _SIGS = {
     "bem_options_default": (_i32, [ctypes.POINTER(bem_options), ctypes.c_char_p]),
-    "bem_mesh_create": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), ctypes.POINTER(_vp)]),
+    "bem_mesh_create": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), _vp, ctypes.POINTER(_vp)]),
+    "bem_set_allocator": (_i32, [_vp, _vp, _vp]),
     "bem_mesh_bad_element": (_i64, [_vp]),
     "bem_set_problem": (_i32, [_vp, _dbl, _vp, _vp]),
     "bem_rhs_plane_wave": (_i32, [_vp, _vp, bem_c128, _vp, _vp]),
@@ -114,6 +115,7 @@ _SIGS = {
     "bem_field_adjoint": (_i32, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
     "bem_grad_admittance": (_i32, [_vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
     "bem_solve_adjoint": (_i32, [_vp, _vp, _vp, ctypes.POINTER(bem_solve_info), _vp]),
+    "bem_solve_batch": (_i32, [_i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
     "bem_mesh_stats": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "bem_mesh_destroy": (None, [_vp]),
@@ -153,11 +155,47 @@ def bem_options_default(preset="paper"):
     return o
 
 
-def bem_mesh_create(n_nodes, xyz_ptr, n_tri, tri_ptr, options):
+def bem_mesh_create(n_nodes, xyz_ptr, n_tri, tri_ptr, options, stream=None):
     out = _vp()
-    st = _lib.bem_mesh_create(n_nodes, xyz_ptr, n_tri, tri_ptr, ctypes.byref(options), ctypes.byref(out))
+    st = _lib.bem_mesh_create(n_nodes, xyz_ptr, n_tri, tri_ptr, ctypes.byref(options), stream, ctypes.byref(out))
     _check(st)
     return out.value
+
+
+BEM_ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp)
+BEM_FREE_FN = ctypes.CFUNCTYPE(None, _vp, ctypes.c_size_t, _vp)
+_allocator_refs = []  # the callbacks must outlive every buffer allocated through them
+
+
+def bem_set_allocator(alloc_fn, free_fn, ctx=None):
+    """alloc_fn / free_fn: BEM_ALLOC_FN / BEM_FREE_FN instances, or both None
+    (hipMalloc / hipFree)."""
+    _check(_lib.bem_set_allocator(ctypes.cast(alloc_fn, _vp) if alloc_fn else None,
+                                  ctypes.cast(free_fn, _vp) if free_fn else None, ctx))
+    if alloc_fn:
+        _allocator_refs.append((alloc_fn, free_fn))
+
+
+def use_torch_allocator():
+    """Back the library's device memory by PyTorch's caching allocator on the
+    current device (torch.cuda.caching_allocator_alloc / _delete)."""
+    torch = _torch()
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:  # out of memory: the library reports BEM_E_OOM
+            return None
+
+    def _free(ptr, nbytes, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    bem_set_allocator(BEM_ALLOC_FN(_alloc), BEM_FREE_FN(_free))
+
+
+def use_hip_allocator():
+    """Back the library's device memory by hipMalloc / hipFree again."""
+    bem_set_allocator(None, None)
 
 
 def bem_mesh_bad_element(mesh):
@@ -243,6 +281,18 @@ def bem_solve(mesh, rhs_ptr, p_ptr, v_ptr, rho_c, stream):
     info = bem_solve_info()
     st = _lib.bem_solve(mesh, rhs_ptr, p_ptr, v_ptr, rho_c, ctypes.byref(info), stream)
     return st, info
+
+
+def bem_solve_batch(meshes, rhs_ptrs, p_ptrs, v_ptrs, rho_c, stream):
+    """meshes: mesh handles; rhs_ptrs, p_ptrs: device pointers; v_ptrs: None
+    or a list of device pointers / None.  Returns (status, [bem_solve_info])."""
+    n = len(meshes)
+    arr = lambda vals: (_vp * max(n, 1))(*[v if v else None for v in vals]) if n else None
+    infos = (bem_solve_info * max(n, 1))()
+    st = _lib.bem_solve_batch(n, arr(meshes), arr(rhs_ptrs), arr(p_ptrs),
+                              arr(v_ptrs) if v_ptrs is not None else None, float(rho_c or 0.0),
+                              ctypes.cast(infos, _vp), stream)
+    return st, [infos[i] for i in range(n)]
 
 
 def bem_mesh_stats(mesh):
@@ -375,7 +425,12 @@ def _torch():
 
 
 def _stream():
+    """The current torch stream, or None (the default stream) where torch has
+    no device: the host-side checks of every entry point run before any
+    device work, so argument errors are reported without a GPU."""
     torch = _torch()
+    if not torch.cuda.is_available():
+        return None
     return torch.cuda.current_stream().cuda_stream
 
 
@@ -418,7 +473,7 @@ class Mesh:
         self.n = int(self._tris.shape[0])
         self._h = None
         self._h = bem_mesh_create(self._nodes.shape[0], self._nodes.ctypes.data, self.n,
-                                  self._tris.ctypes.data, options)
+                                  self._tris.ctypes.data, options, _stream())
         self._beta = None
 
     def close(self):
@@ -576,6 +631,19 @@ class Mesh:
 
     def stats(self):
         return bem_mesh_stats(self._h)
+
+    @staticmethod
+    def solve_batch(meshes, rhs_list, rho_c=None, allow_noconv=False):
+        """Solve one system per mesh with bem_solve_batch (lock-step GMRES);
+        returns [(p, v or None, info dict)]."""
+        ps = [m._empty() for m in meshes]
+        vs = [m._empty() for m in meshes] if rho_c is not None else None
+        rp = [_dev_c128(r, m.n, "rhs") for m, r in zip(meshes, rhs_list)]
+        st, infos = bem_solve_batch([m._h for m in meshes], rp, [p.data_ptr() for p in ps],
+                                    [v.data_ptr() for v in vs] if vs is not None else None, rho_c, _stream())
+        if st != BEM_OK and not (allow_noconv and st == BEM_E_NOCONV):
+            _check(st)
+        return [(ps[i], vs[i] if vs is not None else None, infos[i].as_dict()) for i in range(len(meshes))]
 
     def workspace_bytes(self):
         return bem_workspace_bytes(self._h)

@@ -147,6 +147,16 @@ void check_options(const bem_options* o) {
 
 namespace bem {
 
+namespace {
+std::mutex g_alloc_mu;
+AllocHook g_alloc_hook;
+}  // namespace
+
+AllocHook current_alloc_hook() {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  return g_alloc_hook;
+}
+
 void apply_tree(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s) {
   apply_tree_part(m, op, prec, 0, x, y, s);
 }
@@ -292,7 +302,7 @@ void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, dou
 // field: order m suffices iff all three a-priori estimates of Sec. 3.1.4 are
 // below eps, i.e. iff q = 1/(2 r~) < q_m with q_m the smallest of the three
 // roots.
-void build_far_direct(bem_mesh* m) {
+void build_far_direct(bem_mesh* m, hipStream_t s) {
   const Level& leaf = m->tree.lv.back();
   std::vector<int32_t> el(m->N, -1);
   std::vector<int64_t> off(leaf.nc + 1, 0), fb, fe;
@@ -330,7 +340,6 @@ void build_far_direct(bem_mesh* m) {
       (set == 0 ? m->far_rt2_min : m->far_rt2_min32)[mm - 1] = rt * rt;
     }
   }
-  hipStream_t s = nullptr;
   m->d_elem_leaf.upload(el, s);
   m->d_far_off.upload(off, s);
   if (fb.empty()) {
@@ -364,7 +373,7 @@ void precondition(bem_mesh* m, bem_op op, const double2* x, double2* y, hipStrea
 // Partition the elements (tree order) into the preconditioner's blocks: each
 // leaf cluster (the whole mesh without FMM) split evenly into pieces of at
 // most max_n (<= kMaxBlock) elements.
-void build_blocks(bem_mesh* m, int max_n) {
+void build_blocks(bem_mesh* m, int max_n, hipStream_t s) {
   std::vector<std::pair<int64_t, int64_t>> ranges;
   if (m->fmm) {
     const Level& leaf = m->tree.lv.back();
@@ -407,7 +416,6 @@ void build_blocks(bem_mesh* m, int max_n) {
     bseg[t * (kMaxRuleOrder + 1) + kMaxRuleOrder] = (int64_t)bitems.size();
   }
   if (bitems.empty()) bitems.push_back(0);
-  hipStream_t s = nullptr;
   m->nblk = (int64_t)beg.size();
   m->blk_entries = total;
   m->d_blk_items.upload(bitems, s);
@@ -553,6 +561,16 @@ extern "C" {
 
 const char* bem_last_error(void) { return g_last_error.c_str(); }
 
+bem_status bem_set_allocator(bem_alloc_fn alloc_fn, bem_free_fn free_fn, void* ctx) {
+  return guarded([&]() -> bem_status {
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+      return fail(BEM_E_ARG, "set both allocator functions, or neither (hipMalloc / hipFree)");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_alloc_hook = AllocHook{alloc_fn, free_fn, alloc_fn ? ctx : nullptr};
+    return BEM_OK;
+  });
+}
+
 bem_status bem_options_default(bem_options* o, const char* preset) {
   return guarded([&]() -> bem_status {
     if (!o || !preset) return fail(BEM_E_ARG, "NULL argument");
@@ -586,7 +604,7 @@ bem_status bem_options_default(bem_options* o, const char* preset) {
 }
 
 bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
-                           const bem_options* o, bem_mesh** out) {
+                           const bem_options* o, void* stream, bem_mesh** out) {
   return guarded([&]() -> bem_status {
     if (!out) return fail(BEM_E_ARG, "out is NULL");
     *out = nullptr;
@@ -606,7 +624,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
       if (ncu > 0) m->n_cu = ncu;
     }
     upload_rules();
-    hipStream_t s = nullptr;
+    hipStream_t s = as_stream(stream);
     m->d_geom.upload(m->g.f, s);
     std::vector<float> g32(m->g.f.begin(), m->g.f.end());
     m->d_geom32.upload(g32, s);
@@ -669,7 +687,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_diag.alloc(n_tri);
     m->d_vdiag.alloc(n_tri);
     // the block-Jacobi factors hold blocks of the exterior operator
-    if (o->precond && !o->interior) build_blocks(m.get(), o->precond == 1 ? kMaxBlock : 1);
+    if (o->precond && !o->interior) build_blocks(m.get(), o->precond == 1 ? kMaxBlock : 1, s);
     if (m->fmm) {
       BEM_HIP(hipStreamCreateWithFlags(&m->side_stream, hipStreamNonBlocking));
       BEM_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
@@ -679,7 +697,7 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
       BEM_HIP(hipEventCreateWithFlags(&m->ev_leaf_join, hipEventDisableTiming));
       m->d_far.alloc(n_tri);
     }
-    if (m->far_direct) build_far_direct(m.get());
+    if (m->far_direct) build_far_direct(m.get(), s);
     BEM_HIP(hipStreamSynchronize(s));
     *out = m.release();
     return BEM_OK;
@@ -1107,6 +1125,65 @@ bem_status bem_solve_adjoint(bem_mesh* m, const bem_c128* rhs, bem_c128* x_out, 
   });
 }
 
+namespace {
+
+// outputs of one solve: p (caller order) and the normal velocity
+void solve_outputs(bem_mesh* m, bem_c128* p_out, bem_c128* v_out, double rho_c, hipStream_t s) {
+  launch_scatter(m->N, m->d_perm.p, m->d_sol.p, reinterpret_cast<double2*>(p_out), s);
+  if (v_out) {
+    launch_velocity(m->N, m->have_beta ? m->d_beta.p : nullptr, rho_c, reinterpret_cast<double2*>(p_out),
+                    reinterpret_cast<double2*>(v_out), s);
+    if (m->has_pres)
+      launch_velocity_pres(m->N, m->d_perm.p, m->d_pres.p, m->k, rho_c, reinterpret_cast<double2*>(p_out),
+                           reinterpret_cast<double2*>(v_out), s);
+  }
+}
+
+void fill_info(const bem_mesh* m, const SolveResult& r, bem_solve_info* info);
+
+}  // namespace
+
+bem_status bem_solve_batch(int32_t n, bem_mesh* const* meshes, const bem_c128* const* rhs, bem_c128* const* p_out,
+                           bem_c128* const* v_out, double rho_c, bem_solve_info* infos, void* stream) {
+  return guarded([&]() -> bem_status {
+    if (n < 0 || (n > 0 && (!meshes || !rhs || !p_out))) return fail(BEM_E_ARG, "NULL argument");
+    for (int32_t i = 0; i < n; ++i) {
+      if (!meshes[i] || !rhs[i] || !p_out[i]) return fail(BEM_E_ARG, "NULL mesh or vector in the batch");
+      if (!meshes[i]->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called on a mesh");
+      for (int32_t q = 0; q < i; ++q)
+        if (meshes[q] == meshes[i]) return fail(BEM_E_ARG, "a mesh appears twice in the batch");
+      if (v_out && v_out[i] && !(rho_c > 0.0)) return fail(BEM_E_ARG, "rho_c must be positive when v_out is requested");
+    }
+    if (n == 0) return BEM_OK;
+    hipStream_t s = as_stream(stream);
+    // fork every system onto its mesh's stream after the caller's prior work
+    std::vector<BatchItem> items;
+    for (int32_t i = 0; i < n; ++i) {
+      bem_mesh* m = meshes[i];
+      if (!m->batch_stream) BEM_HIP(hipStreamCreateWithFlags(&m->batch_stream, hipStreamNonBlocking));
+      if (!m->ev_batch) BEM_HIP(hipEventCreateWithFlags(&m->ev_batch, hipEventDisableTiming));
+      BEM_HIP(hipEventRecord(m->ev_batch, s));
+      BEM_HIP(hipStreamWaitEvent(m->batch_stream, m->ev_batch, 0));
+      launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(rhs[i]), m->d_b.p, m->batch_stream);
+      items.push_back(BatchItem{m, m->d_b.p, m->d_sol.p, m->batch_stream});
+    }
+    const std::vector<SolveResult> res = solve_tree_batch(items);
+    bool all = true;
+    for (int32_t i = 0; i < n; ++i) {
+      bem_mesh* m = meshes[i];
+      solve_outputs(m, p_out[i], v_out ? v_out[i] : nullptr, rho_c, m->batch_stream);
+      BEM_HIP(hipEventRecord(m->ev_batch, m->batch_stream));
+      BEM_HIP(hipStreamWaitEvent(s, m->ev_batch, 0));
+      if (infos) fill_info(m, res[i], &infos[i]);
+      all = all && res[i].converged;
+    }
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(s));
+    if (!all) return fail(BEM_E_NOCONV, "a system of the batch stopped before its tolerance");
+    return BEM_OK;
+  });
+}
+
 bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out, bem_c128* v_out, double rho_c,
                      bem_solve_info* info, void* stream) {
   return guarded([&]() -> bem_status {
@@ -1116,17 +1193,21 @@ bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out, bem_c128
     hipStream_t s = as_stream(stream);
     launch_gather(m->N, m->d_perm.p, reinterpret_cast<const double2*>(rhs), m->d_b.p, s);
     SolveResult r = solve_tree(m, m->d_b.p, m->d_sol.p, s);
-    launch_scatter(m->N, m->d_perm.p, m->d_sol.p, reinterpret_cast<double2*>(p_out), s);
-    if (v_out) {
-      launch_velocity(m->N, m->have_beta ? m->d_beta.p : nullptr, rho_c, reinterpret_cast<double2*>(p_out),
-                      reinterpret_cast<double2*>(v_out), s);
-      if (m->has_pres)
-        launch_velocity_pres(m->N, m->d_perm.p, m->d_pres.p, m->k, rho_c, reinterpret_cast<double2*>(p_out),
-                             reinterpret_cast<double2*>(v_out), s);
-    }
+    solve_outputs(m, p_out, v_out, rho_c, s);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(s));
-    if (info) {
+    if (info) fill_info(m, r, info);
+    if (!r.converged)
+      return fail(BEM_E_NOCONV, "GMRES stopped at relative residual " + std::to_string(r.rel_residual));
+    return BEM_OK;
+  });
+}
+
+namespace {
+
+void fill_info(const bem_mesh* m, const SolveResult& r, bem_solve_info* info) {
+  {
+    {
       std::memset(info, 0, sizeof(*info));
       info->iterations = r.iterations;
       info->refinements = r.refinements;
@@ -1151,11 +1232,10 @@ bem_status bem_solve(bem_mesh* m, const bem_c128* rhs, bem_c128* p_out, bem_c128
       double lambda = 2.0 * M_PI / m->k;
       if (lambda / h < 6.0) info->warnings |= BEM_WARN_COARSE_MESH;
     }
-    if (!r.converged)
-      return fail(BEM_E_NOCONV, "GMRES stopped at relative residual " + std::to_string(r.rel_residual));
-    return BEM_OK;
-  });
+  }
 }
+
+}  // namespace
 
 bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters, int64_t* near_pairs,
                           int64_t* near_items, int64_t* quad_points) {

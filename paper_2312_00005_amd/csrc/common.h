@@ -29,6 +29,16 @@ struct Error : std::runtime_error {
                          std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Device allocator of the plan memory: hipMalloc / hipFree, or the caller's
+// pair set with bem_set_allocator (process-wide; a buffer keeps the pair it
+// was allocated with).
+struct AllocHook {
+  bem_alloc_fn alloc = nullptr;
+  bem_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+AllocHook current_alloc_hook();
+
 // Owning device buffer.  alloc() keeps the allocation when the new size fits
 // (capacity only grows), so per-frequency state re-sized for every wavenumber
 // of a sweep does not go back to the allocator each time.
@@ -37,16 +47,18 @@ struct DevBuf {
   T* p = nullptr;
   size_t n = 0;    // elements in use
   size_t cap = 0;  // elements allocated
+  AllocHook hook{};
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) { o.p = nullptr; o.n = o.cap = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap), hook(o.hook) { o.p = nullptr; o.n = o.cap = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       n = o.n;
       cap = o.cap;
+      hook = o.hook;
       o.p = nullptr;
       o.n = o.cap = 0;
     }
@@ -54,7 +66,16 @@ struct DevBuf {
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (hook.free) {
+        // hipFree waits for the device; a caller's allocator may hand the
+        // block out again at once, so wait here before returning it
+        (void)hipDeviceSynchronize();
+        hook.free(p, cap * sizeof(T), hook.ctx);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     n = cap = 0;
   }
@@ -65,7 +86,13 @@ struct DevBuf {
     }
     release();
     if (count == 0) return;
-    BEM_HIP(hipMalloc(&p, count * sizeof(T)));
+    hook = current_alloc_hook();
+    if (hook.alloc) {
+      p = static_cast<T*>(hook.alloc(count * sizeof(T), hook.ctx));
+      if (!p) throw Error(BEM_E_OOM, "the allocator set with bem_set_allocator returned NULL");
+    } else {
+      BEM_HIP(hipMalloc(&p, count * sizeof(T)));
+    }
     n = cap = count;
   }
   // Copy a host vector to the device and wait for the copy (setup paths only:

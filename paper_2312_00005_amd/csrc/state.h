@@ -60,6 +60,10 @@ struct bem_mesh {
   GraphSlot graphs[2][2];
   uint64_t problem_stamp = 0;   // bumped by every bem_set_problem
   hipStream_t cap_stream = nullptr;
+  // the mesh's stream inside bem_solve_batch (forked from and joined to the
+  // caller's stream)
+  hipStream_t batch_stream = nullptr;
+  hipEvent_t ev_batch = nullptr;
 
   // the far field runs on a second stream, concurrently with the near field
   // (into d_far), and is added after both finish
@@ -108,6 +112,8 @@ struct bem_mesh {
       for (auto& gs : row)
         if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (batch_stream) (void)hipStreamDestroy(batch_stream);
+    if (ev_batch) (void)hipEventDestroy(ev_batch);
     if (side_stream) (void)hipStreamDestroy(side_stream);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -164,6 +170,15 @@ struct SolveResult {
 };
 // solve op(A) x = b (op = A or A^H)
 SolveResult solve_tree(bem_mesh* m, const double2* b, double2* x, hipStream_t s, bem_op op = BEM_OP_A);
+// several independent systems (distinct meshes, each on its own stream),
+// their GMRES iterations advanced in lock-step
+struct BatchItem {
+  bem_mesh* m;
+  const double2* b;
+  double2* x;
+  hipStream_t s;
+};
+std::vector<SolveResult> solve_tree_batch(const std::vector<BatchItem>& items, bem_op op = BEM_OP_A);
 
 void ensure_transposed_plan(bem_mesh* m, hipStream_t s);
 

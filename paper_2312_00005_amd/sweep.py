@@ -7,11 +7,13 @@ large enough, Sec. 3.3.1), stay within the supported length and fit the
 memory budget runs the FMM; otherwise the far field is evaluated by direct
 quadrature (far_direct), which has no low-frequency breakdown and needs no
 translation memory.  Frequencies that share a method share one device plan
-(geometry, tree, near plan built once) and are solved back to back on the
-caller's stream.  Solving several frequencies concurrently from several host
-threads (one HIP stream and mesh instance each) is disabled: such a run ended
-once in a host segmentation fault inside the solve whose cause has not been
-found.  Frequencies may come from a frequency-defining curve
+(geometry, tree, near plan built once); with batch = B a group holds B
+mesh instances and solves B frequencies at a time with bem_solve_batch, whose
+lock-step GMRES keeps the device busy while each system's Gram-Schmidt
+coefficients travel to the host.  Solving several frequencies concurrently
+from several host threads (one HIP stream and mesh instance each) is
+disabled: such a run ended once in a host segmentation fault inside the solve
+whose cause has not been found.  Frequencies may come from a frequency-defining curve
 (``FrequencySweep.from_curve``) and element groups may carry an admittance
 that follows curves of the frequency step (``admittance=``, see curves.py);
 each frequency is then solved with its own beta.  This module only schedules
@@ -19,7 +21,6 @@ calls into the library.
 """
 
 import math
-import threading
 import time
 
 from . import bemfmm, curves
@@ -51,7 +52,8 @@ class FrequencySweep:
     """Solve the exterior problem at every frequency of ``freqs`` on one mesh."""
 
     def __init__(self, nodes, tris, freqs, c=343.0, preset="mixed", depths=(4, 3, 2), leaf_size=32,
-                 memory_budget=96e9, max_L=120, streams=1, steps=None, admittance=None, rho=1.21, **overrides):
+                 memory_budget=96e9, max_L=120, streams=1, steps=None, admittance=None, rho=1.21, batch=1,
+                 **overrides):
         """steps / admittance: the frequency step s of every frequency and a
         list of curves.AdmittanceGroup; each frequency is then solved with
         beta = rho c Y(s) per element (Y = 0, sound hard, outside the groups)."""
@@ -67,6 +69,7 @@ class FrequencySweep:
         self.leaf_size = leaf_size
         self.overrides = overrides
         self.streams = max(1, int(streams))
+        self.batch = max(1, int(batch))
         if self.streams > 1:
             raise NotImplementedError("concurrent frequencies from several host threads are disabled "
                                       "(a host crash was seen in that mode and its cause is not known)")
@@ -110,49 +113,41 @@ class FrequencySweep:
     def run(self, source=("plane", (0.0, 0.0, 1.0), 1.0), keep_solutions=True, source_curves=(None, None)):
         """Returns a list of per-frequency dicts (k, method, info, seconds and
         the device solution p) plus timing totals.  source_curves: curves of
-        the frequency step for the real and imaginary part of P0."""
+        the frequency step for the real and imaginary part of P0.  With
+        batch = B, each method group holds B mesh instances: B frequencies are
+        set up (one per mesh) and solved together by bem_solve_batch; a
+        frequency's seconds are then its share of the batch."""
         import torch
         groups = {}
         for i, m in enumerate(self.methods):
             groups.setdefault(m, []).append(i)
         results = [None] * len(self.ks)
-        errors = []
         t_setup = 0.0
         t0 = time.perf_counter()
         for method, idx in groups.items():
             ts = time.perf_counter()
-            meshes = [self._mesh(method) for _ in range(min(self.streams, len(idx)))]
+            meshes = [self._mesh(method) for _ in range(min(self.batch, len(idx)))]
             t_setup += time.perf_counter() - ts
-            streams = [torch.cuda.Stream() for _ in meshes]
-
-            def worker(w):
-                try:
-                    with torch.cuda.stream(streams[w]):
-                        mesh = meshes[w]
-                        for i in idx[w::len(meshes)]:
-                            k = self.ks[i]
-                            t1 = time.perf_counter()
-                            mesh.set_problem(k, self.beta(i))
-                            kind, s, P0 = source
-                            P0 = self.source_strength(i, P0, *source_curves)
-                            b = mesh.rhs_plane_wave(s, P0) if kind == "plane" else mesh.rhs_point_source(s, P0)
-                            p, _, info = mesh.solve(b, allow_noconv=True)
-                            streams[w].synchronize()
-                            results[i] = {"f": self.freqs[i], "k": k, "method": self.methods[i], "info": info,
-                                          "seconds": time.perf_counter() - t1,
-                                          "p": p if keep_solutions else None}
-                except Exception as e:  # reported after the join
-                    errors.append(e)
-
-            threads = [threading.Thread(target=worker, args=(w,)) for w in range(len(meshes))]
-            for t in threads:
-                t.start()
-            for t in threads:
-                t.join()
+            for c0 in range(0, len(idx), len(meshes)):
+                chunk = idx[c0:c0 + len(meshes)]
+                t1 = time.perf_counter()
+                rhs = []
+                for mesh, i in zip(meshes, chunk):
+                    mesh.set_problem(self.ks[i], self.beta(i))
+                    kind, src, P0 = source
+                    P0 = self.source_strength(i, P0, *source_curves)
+                    rhs.append(mesh.rhs_plane_wave(src, P0) if kind == "plane" else mesh.rhs_point_source(src, P0))
+                if len(chunk) == 1:
+                    out = [meshes[0].solve(rhs[0], allow_noconv=True)]
+                else:
+                    out = bemfmm.Mesh.solve_batch(meshes[:len(chunk)], rhs, allow_noconv=True)
+                torch.cuda.current_stream().synchronize()
+                dt = (time.perf_counter() - t1) / len(chunk)
+                for (p, _, info), i in zip(out, chunk):
+                    results[i] = {"f": self.freqs[i], "k": self.ks[i], "method": self.methods[i], "info": info,
+                                  "seconds": dt, "p": p if keep_solutions else None}
             for mesh in meshes:
                 mesh.close()
-            if errors:
-                raise errors[0]
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return results, {"wall_s": wall, "mesh_setup_s": t_setup, "plan_choice_s": self.plan_seconds,

@@ -108,3 +108,13 @@ def test_null_arguments_are_rejected_before_any_device_work(bem):
     with pytest.raises(bem.BemError) as e:
         bem.bem_rhs_velocity(None, None, 415.0, None, None)
     assert e.value.status == bem.BEM_E_ARG
+
+
+def test_allocator_hook_arguments(bem):
+    """bem_set_allocator: one function without the other is BEM_E_ARG; both
+    NULL restores hipMalloc / hipFree (no device work either way)."""
+    alloc = bem.BEM_ALLOC_FN(lambda n, ctx: None)
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_set_allocator(alloc, None)
+    assert e.value.status == bem.BEM_E_ARG
+    bem.bem_set_allocator(None, None)
