@@ -74,7 +74,9 @@ def parse():
                          "of --profile-near-only runs into the traffic record read by the bench")
     ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json"))
     ap.add_argument("--profile-far-only", action="store_true",
-                    help="run only complex-FP32 far-field (FMM) applications, then the calibration copy")
+                    help="run only far-field (FMM) applications, then the calibration copy")
+    ap.add_argument("--profile-prec", default="mixed", choices=("mixed", "fp64"),
+                    help="operator precision of the --profile-near-only / --profile-far-only applications")
     ap.add_argument("--summarize-translate", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="per-launch HBM bytes of the translation kernel from two counter runs of "
                          "--profile-far-only, written to --translate-out")
@@ -273,7 +275,7 @@ def main():
     y = torch.empty_like(x)
     if args.profile_near_only or args.profile_far_only:
         for _ in range(args.warmup + args.steps):
-            mesh.apply_part(x, 2 if args.profile_far_only else 1, prec="mixed", out=y)
+            mesh.apply_part(x, 2 if args.profile_far_only else 1, prec=args.profile_prec, out=y)
         src = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)

@@ -7,8 +7,9 @@ centroids (Sec. 2.3):
 
 gamma = i/k (Sec. 2.5).  Boundary conditions enter per element as v_j = c_j
 phi_j: sound-hard c = 0 (the default of the appendix "The Mesh"); admittance
-c = -i k beta with beta = rho c Y (reading: v = -Y p on an exterior surface,
-the absorbing sign that the duct's plane-wave solution of Sec. 5.3 fixes).
+c = -tau i k beta with beta = rho c Y (reading: v = -tau Y p along the
+outward normal, the absorbing sign on an exterior surface; the duct's
+plane-wave solution of Sec. 5.3 fixes it for the interior problem).
 Hence
 
     A_ij = (1 - gamma c_i)/2 delta_ij - (H_ij - gamma E_ij) + (G_ij - gamma H'_ij) c_j.
@@ -44,11 +45,16 @@ def coupling(k, gamma=None, p=None):
     return 1j / k
 
 
-def bc_factor(k, beta):
-    """c_j with v_j = c_j phi_j: 0 for sound-hard, -i k beta_j for admittance."""
+def bc_factor(k, beta, tau=1):
+    """c_j with v_j = c_j phi_j: 0 for sound-hard, -tau i k beta_j for
+    admittance.  The normal velocity is v = -tau Y p along the outward mesh
+    normal: absorbing on an exterior surface (tau = 1) and, on an interior
+    problem (tau = -1, normals pointing out of the fluid), the condition of
+    the duct of Sec. 5.3 whose closed-form solution p = -rho c exp(ikx)
+    carries v = +p/(rho c) at the admittance end."""
     if beta is None:
         return None
-    return -1j * k * np.asarray(beta, dtype=np.complex128)
+    return -tau * 1j * k * np.asarray(beta, dtype=np.complex128)
 
 
 def rows(geom, row_idx, k, beta=None, p=None, gamma=None, cols=None, stats=None, tau=1):
@@ -57,7 +63,7 @@ def rows(geom, row_idx, k, beta=None, p=None, gamma=None, cols=None, stats=None,
     negated and the jump term (phi - gamma v)/2 kept."""
     gamma = coupling(k, gamma, p)
     N = geom["x"].shape[0]
-    c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta)
+    c = np.zeros(N, dtype=np.complex128) if beta is None else bc_factor(k, beta, tau)
     row_idx = np.asarray(row_idx, dtype=np.int64)
     cols = np.arange(N) if cols is None else np.asarray(cols, dtype=np.int64)
     out = np.zeros((row_idx.size, cols.size), dtype=np.complex128)
@@ -133,9 +139,9 @@ def solve(nodes, tris, k, beta=None, p=None, rhs=None, gamma=None):
     return lu_solve(A, rhs), geom, A
 
 
-def velocity(pressure, beta, rho_c):
-    """Normal particle velocity v = -Y p (exterior admittance, Y = beta/(rho c));
-    zero on sound-hard elements."""
+def velocity(pressure, beta, rho_c, tau=1):
+    """Normal particle velocity v = -tau Y p (Y = beta/(rho c)) along the
+    outward normal; zero on sound-hard elements."""
     if beta is None:
         return np.zeros_like(pressure)
-    return -np.asarray(beta) / rho_c * pressure
+    return -tau * np.asarray(beta) / rho_c * pressure

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "guard.h"
 #include "state.h"
 
 using namespace bem;
@@ -12,25 +13,6 @@ using namespace bem;
 namespace {
 
 thread_local std::string g_last_error;
-
-bem_status fail(bem_status code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
-
-template <class F>
-bem_status guarded(F&& f) {
-  try {
-    g_last_error.clear();
-    return f();
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::bad_alloc&) {
-    return fail(BEM_E_OOM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return fail(BEM_E_ARG, e.what());
-  }
-}
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -146,6 +128,9 @@ void check_options(const bem_options* o) {
 }  // namespace
 
 namespace bem {
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+void clear_last_error() { g_last_error.clear(); }
 
 namespace {
 std::mutex g_alloc_mu;
@@ -719,7 +704,8 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     if (beta) {
       m->d_beta.alloc(m->N);
       BEM_HIP(hipMemcpyAsync(m->d_beta.p, beta, m->N * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      launch_cfac(m->N, m->d_perm.p, m->d_beta.p, k, m->d_cfac.p, s);
+      // c = -tau i k beta: the velocity -tau Y p along the outward normal
+      launch_cfac(m->N, m->d_perm.p, m->d_beta.p, m->opt.interior ? -k : k, m->d_cfac.p, s);
       // admittance is ignored on PRES elements (their pressure is given)
       if (m->has_pres) launch_mask(m->N, m->d_pres.p, 0, m->d_cfac.p, m->d_cfac.p, s);
     }
@@ -978,7 +964,9 @@ bem_status bem_rhs_velocity(bem_mesh* m, const bem_c128* u, double rho_c, bem_c1
   });
 }
 
-namespace {
+}  // extern "C"
+
+namespace bem {
 
 FieldArgs field_args(bem_mesh* m, int64_t npts, int part) {
   FieldArgs A{};
@@ -997,9 +985,9 @@ FieldArgs field_args(bem_mesh* m, int64_t npts, int part) {
   return A;
 }
 
-void check_field_error(bem_mesh* m, DevBuf<int64_t>& err, hipStream_t s) {
+void check_field_error(bem_mesh* m, const int64_t* err, hipStream_t s) {
   int64_t e = -1;
-  BEM_HIP(hipMemcpyAsync(&e, err.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BEM_HIP(hipMemcpyAsync(&e, err, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   BEM_HIP(hipStreamSynchronize(s));
   if (e >= 0) {
     m->bad_element = m->tree.perm[e];
@@ -1008,7 +996,9 @@ void check_field_error(bem_mesh* m, DevBuf<int64_t>& err, hipStream_t s) {
   }
 }
 
-}  // namespace
+}  // namespace bem
+
+extern "C" {
 
 bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c128* p_surf,
                      const bem_c128* p_inc, bem_c128* p_out, double* energy, void* stream) {
@@ -1031,7 +1021,7 @@ bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts, const bem_c1
                  reinterpret_cast<double2*>(p_out), err.p, s);
     if (energy) launch_energy(n_pts, reinterpret_cast<const double2*>(p_out), energy, s);
     BEM_HIP(hipGetLastError());
-    check_field_error(m, err, s);
+    check_field_error(m, err.p, s);
     return BEM_OK;
   });
 }
@@ -1061,7 +1051,7 @@ bem_status bem_field_pv(bem_mesh* m, int64_t n_pts, const double* pts, const bem
                  err.p, s);
     if (energy) launch_energy(n_pts, reinterpret_cast<const double2*>(p_out), energy, s);
     BEM_HIP(hipGetLastError());
-    check_field_error(m, err, s);
+    check_field_error(m, err.p, s);
     return BEM_OK;
   });
 }
@@ -1081,7 +1071,7 @@ bem_status bem_field_adjoint(bem_mesh* m, int64_t n_pts, const double* pts, cons
     launch_field_adj(field_args(m, n_pts, part), pts, reinterpret_cast<const double2*>(g), m->d_y.p, err.p, s);
     launch_scatter(m->N, m->d_perm.p, m->d_y.p, reinterpret_cast<double2*>(y_surf), s);
     BEM_HIP(hipGetLastError());
-    check_field_error(m, err, s);
+    check_field_error(m, err.p, s);
     return BEM_OK;
   });
 }
@@ -1093,6 +1083,7 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
     if (!(rho_c > 0.0)) return fail(BEM_E_ARG, "rho_c must be positive");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
     if (m->has_pres) return fail(BEM_E_STATE, "admittance gradients assume dp/dn = c p (mesh has PRES elements)");
+    if (m->opt.interior) return fail(BEM_E_STATE, "admittance gradients are made for exterior problems");
     hipStream_t s = as_stream(stream);
     launch_grad_admittance(m->N, m->k, rho_c, reinterpret_cast<const double2*>(p),
                            reinterpret_cast<const double2*>(w), reinterpret_cast<const double2*>(hg), grad, s);
@@ -1131,8 +1122,9 @@ namespace {
 void solve_outputs(bem_mesh* m, bem_c128* p_out, bem_c128* v_out, double rho_c, hipStream_t s) {
   launch_scatter(m->N, m->d_perm.p, m->d_sol.p, reinterpret_cast<double2*>(p_out), s);
   if (v_out) {
-    launch_velocity(m->N, m->have_beta ? m->d_beta.p : nullptr, rho_c, reinterpret_cast<double2*>(p_out),
-                    reinterpret_cast<double2*>(v_out), s);
+    // v = -tau Y p = -tau beta p / rho_c
+    launch_velocity(m->N, m->have_beta ? m->d_beta.p : nullptr, m->opt.interior ? -rho_c : rho_c,
+                    reinterpret_cast<double2*>(p_out), reinterpret_cast<double2*>(v_out), s);
     if (m->has_pres)
       launch_velocity_pres(m->N, m->d_perm.p, m->d_pres.p, m->k, rho_c, reinterpret_cast<double2*>(p_out),
                            reinterpret_cast<double2*>(v_out), s);

@@ -1264,7 +1264,7 @@ __global__ void k_cfac(int64_t N, const int64_t* __restrict__ perm, const double
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
   const double2 b = beta[perm[t]];
-  // c = -i k beta
+  // c = -i k beta (k carries the sign -tau: +i |k| beta on interior problems)
   cf[t] = make_double2(k * b.y, -k * b.x);
 }
 

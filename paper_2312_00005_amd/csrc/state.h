@@ -182,4 +182,11 @@ std::vector<SolveResult> solve_tree_batch(const std::vector<BatchItem>& items, b
 
 void ensure_transposed_plan(bem_mesh* m, hipStream_t s);
 
+// field-point kernels' arguments for the mesh's current problem (part 0:
+// K = I^H - c I^G, part 1: K = I^G), and the check of their error flag (the
+// tree position of an element whose subdivision overflowed, or -1), which
+// waits for the stream and throws BEM_E_MESH naming the element
+FieldArgs field_args(bem_mesh* m, int64_t npts, int part);
+void check_field_error(bem_mesh* m, const int64_t* err, hipStream_t s);
+
 }  // namespace bem

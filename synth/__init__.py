@@ -8,11 +8,11 @@ library can be fed from it without sharing any of the method's code.
 """
 
 from .meshes import (icosphere, geodesic_sphere, graded_ellipsoid_bump,
-                     flat_patch, octahedron, mean_edge_length)
+                     flat_patch, octahedron, box, mean_edge_length)
 from .vectors import complex_normal, uniform01, points_on_sphere
 
 __all__ = [
     "icosphere", "geodesic_sphere", "graded_ellipsoid_bump", "flat_patch",
-    "octahedron", "mean_edge_length", "complex_normal", "uniform01",
+    "octahedron", "box", "mean_edge_length", "complex_normal", "uniform01",
     "points_on_sphere",
 ]

@@ -165,6 +165,44 @@ def graded_ellipsoid_bump(freq=55, semi_axes=(0.075, 0.09, 0.11),
     return e, tris, apex, np.array([1.0, 0.0, 0.0])
 
 
+def box(lengths, h, origin=(0.0, 0.0, 0.0)):
+    """Closed surface of the axis-aligned box [o, o + lengths] with a structured
+    triangulation: each face cut into round(edge / h) (at least one) equal
+    divisions per side, every rectangle split into two triangles along the
+    same diagonal, vertices shared between faces, counter-clockwise seen from
+    outside (normals out of the box)."""
+    lx, ly, lz = (float(v) for v in lengths)
+    o = np.asarray(origin, dtype=np.float64)
+    n = [max(1, int(round(v / h))) for v in (lx, ly, lz)]
+    index = {}
+    nodes = []
+
+    def node(i, j, k):
+        key = (i, j, k)
+        if key not in index:
+            index[key] = len(nodes)
+            nodes.append(o + np.array([lx * i / n[0], ly * j / n[1], lz * k / n[2]]))
+        return index[key]
+
+    tris = []
+    # each face: the fixed axis, its side (0 or its division count), and the
+    # two in-face axes ordered so that their cross product points outward
+    faces = [(0, 0, 2, 1), (0, n[0], 1, 2), (1, 0, 0, 2), (1, n[1], 2, 0), (2, 0, 1, 0), (2, n[2], 0, 1)]
+    for ax, side, u, v in faces:
+        for a in range(n[u]):
+            for b in range(n[v]):
+                def at(da, db):
+                    idx = [0, 0, 0]
+                    idx[ax] = side
+                    idx[u] = a + da
+                    idx[v] = b + db
+                    return node(*idx)
+                p00, p10, p11, p01 = at(0, 0), at(1, 0), at(1, 1), at(0, 1)
+                tris.append([p00, p10, p11])
+                tris.append([p00, p11, p01])
+    return np.array(nodes, dtype=np.float64), np.array(tris, dtype=np.int32)
+
+
 def flat_patch(h=1.0):
     """Unit square in the z = 0 plane split into two triangles (normal +z)."""
     nodes = np.array([[0, 0, 0], [h, 0, 0], [h, h, 0], [0, h, 0]], dtype=np.float64)
