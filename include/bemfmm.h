@@ -11,9 +11,11 @@
  *
  * Per element j the boundary condition is v_j = c_j phi_j with c_j = 0 on a
  * sound-hard element (the default of the paper's mesh appendix) and
- * c_j = -i k beta_j for an admittance element, beta = rho c Y (exterior
- * reading v = -Y p).  The unknown may be read as surface pressure p; all
- * source amplitudes are pressure amplitudes.
+ * c_j = -tau i k beta_j for an admittance element, beta = rho c Y: the
+ * normal velocity along the outward mesh normal is v = -tau Y p (absorbing on
+ * an exterior surface, tau = 1; on an interior problem, tau = -1, the
+ * condition of the duct of Sec. 5.3).  The unknown may be read as surface
+ * pressure p; all source amplitudes are pressure amplitudes.
  *
  * The operator A is applied as the near field (direct singular,
  * hypersingular, quasi-singular and regular quadrature, Sec. 3.1, evaluated
@@ -165,10 +167,13 @@ typedef struct bem_options {
                                1: interior problem (tau = -1: every integral
                                term negated, the jump term (phi - gamma v)/2
                                kept; the mesh normals still point out of the
-                               object).  Interior meshes use no block-Jacobi
-                               preconditioner and refuse the field-point calls
-                               (bem_field, bem_field_adjoint), which evaluate
-                               the exterior representation formula. */
+                               object, i.e. out of the fluid; admittance then
+                               means v = +Y p, c = +i k beta).  Interior
+                               meshes use no block-Jacobi preconditioner and
+                               refuse bem_field, bem_field_adjoint and
+                               bem_grad_admittance (exterior representation
+                               formula); bem_field_pv evaluates points inside
+                               the fluid. */
 } bem_options;
 
 typedef struct bem_solve_info {
@@ -328,8 +333,9 @@ bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts,
  *               on admittance / sound-hard elements, plus i k rho_c u_j where a
  *               normal velocity u is prescribed, and the solution of bem_solve
  *               on PRES elements (whose p_surf is the prescribed pressure).
- * Other arguments, rules and errors as bem_field; interior meshes are
- * BEM_E_STATE. */
+ * On an interior mesh (option interior) the points lie inside the fluid and
+ * the sum is negated (tau = -1 in Eq. (BIE_I); the mesh normals point out of
+ * the fluid).  Other arguments, rules and errors as bem_field. */
 bem_status bem_field_pv(bem_mesh* m, int64_t n_pts, const double* pts,
                         const bem_c128* p_surf, const bem_c128* dpdn_surf,
                         const bem_c128* p_inc, bem_c128* p_out, double* energy,

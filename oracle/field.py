@@ -8,11 +8,13 @@ regular rules as the collocation rows (Sec. 3.1.3-3.1.4), r~ measured from x.
 With other boundary conditions (prescribed velocity, prescribed pressure)
 the normal derivative is not c_j phi_j, and the same representation formula
 takes the surface pressure and its normal derivative separately:
-    phi(x) = phi_inc(x) + sum_j ( I^H_j(x) phi_j - I^G_j(x) v_j ).
+    phi(x) = phi_inc(x) + tau sum_j ( I^H_j(x) phi_j - I^G_j(x) v_j ),
+with tau = -1 inside the fluid of an interior problem.
 
 Pinned by: tests/test_oracle_operator.py (reciprocity of two point sources,
 the analytic sphere field at r = 2); tests/test_oracle_velocity.py (the
-pulsating sphere's outgoing field from a half-PRES, half-VELO solution).
+pulsating sphere's outgoing field from a half-PRES, half-VELO solution);
+tests/test_oracle_duct.py (the plane wave inside the duct of Sec. 5.3).
 """
 
 import numpy as np
@@ -46,12 +48,13 @@ def field_matrix(geom, pts, k, beta=None, p=None):
     return IH - bc_factor(k, beta)[None, :] * IG
 
 
-def field_pv(geom, pts, k, p_surf, dpdn_surf, p=None):
-    """Scattered field sum_j (I^H_j p_j - I^G_j v_j) at the points, from the
-    surface pressure p_surf and its normal derivative dpdn_surf (outward
-    normal)."""
+def field_pv(geom, pts, k, p_surf, dpdn_surf, p=None, tau=1):
+    """Scattered field tau sum_j (I^H_j p_j - I^G_j v_j) at the points, from
+    the surface pressure p_surf and its normal derivative dpdn_surf (outward
+    mesh normal); tau = -1 for points inside the fluid of an interior problem
+    (Eq. (BIE_I) with the normals pointing out of the fluid)."""
     IG, IH = field_parts(geom, pts, k, p)
-    return IH @ np.asarray(p_surf, dtype=np.complex128) - IG @ np.asarray(dpdn_surf, dtype=np.complex128)
+    return tau * (IH @ np.asarray(p_surf, dtype=np.complex128) - IG @ np.asarray(dpdn_surf, dtype=np.complex128))
 
 
 def plane_wave(pts, k, d, P0=1.0):

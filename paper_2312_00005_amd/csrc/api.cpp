@@ -982,6 +982,7 @@ FieldArgs field_args(bem_mesh* m, int64_t npts, int part) {
   A.max_subdiv = m->opt.max_subdiv;
   A.part = part;
   A.dpdn = nullptr;
+  A.tau = m->opt.interior ? -1.0 : 1.0;
   return A;
 }
 
@@ -1033,8 +1034,6 @@ bem_status bem_field_pv(bem_mesh* m, int64_t n_pts, const double* pts, const bem
     if (!m || !p_surf || !dpdn_surf || n_pts < 0 || (n_pts > 0 && (!pts || !p_out)))
       return fail(BEM_E_ARG, "NULL argument");
     if (!m->have_problem) return fail(BEM_E_STATE, "bem_set_problem has not been called");
-    if (m->opt.interior)
-      return fail(BEM_E_STATE, "field points use the exterior representation formula (interior mesh)");
     hipStream_t s = as_stream(stream);
     if (n_pts == 0) {
       if (energy) BEM_HIP(hipMemsetAsync(energy, 0, sizeof(double), s));

@@ -119,8 +119,9 @@ struct FieldArgs {
   int m_max, split_on_cap, max_subdiv;
   int part;              // 0: K = I^H - c I^G; 1: K = I^G
   const double2* dpdn;   // k_field only: if set, the scattered field is
-                         // sum_j I^H_j p_j - I^G_j dpdn_j (tree order) and
+                         // tau sum_j I^H_j p_j - I^G_j dpdn_j (tree order) and
                          // cfac and part are not used
+  double tau;            // with dpdn: 1 exterior, -1 inside an interior problem
 };
 // out[f] = pinc[f] + sum_j K_fj p[j] (p in tree order); err[0] receives the
 // tree position of an element whose subdivision overflowed

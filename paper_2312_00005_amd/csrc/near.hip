@@ -1101,10 +1101,10 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs A, const double* __rest
     }
     const double2 pj = p[j];
     if (A.dpdn) {
-      // I^H p_j - I^G (dp/dn)_j with the normal derivative given
+      // tau (I^H p_j - I^G (dp/dn)_j) with the normal derivative given
       const double2 vj = A.dpdn[j];
-      ar += (IH.x * pj.x - IH.y * pj.y) - (IG.x * vj.x - IG.y * vj.y);
-      ai += (IH.x * pj.y + IH.y * pj.x) - (IG.x * vj.y + IG.y * vj.x);
+      ar += A.tau * ((IH.x * pj.x - IH.y * pj.y) - (IG.x * vj.x - IG.y * vj.y));
+      ai += A.tau * ((IH.x * pj.y + IH.y * pj.x) - (IG.x * vj.y + IG.y * vj.x));
       continue;
     }
     double kr = IH.x, ki = IH.y;
