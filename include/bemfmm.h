@@ -325,6 +325,19 @@ bem_status bem_field(bem_mesh* m, int64_t n_pts, const double* pts,
                      const bem_c128* p_surf, const bem_c128* p_inc,
                      bem_c128* p_out, double* energy, void* stream);
 
+/* bem_field for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and errors as bem_field (p_out identical bit for
+ * bit; the energy summed in a different, fixed order), but no hipMalloc,
+ * hipFree or other allocation.  Its error flag and the partial sums of the
+ * energy live in a fixed device array (8 KiB) that each GPU holds until the
+ * process ends; n_pts above 4194304 is BEM_E_ARG.  Every call on one GPU
+ * shares that array: calls that overlap in time on one GPU race.  Like
+ * bem_field it waits for `stream` before returning (the error check). */
+bem_status bem_field_noalloc(bem_mesh* m, int64_t n_pts, const double* pts,
+                             const bem_c128* p_surf, const bem_c128* p_inc,
+                             bem_c128* p_out, double* energy, void* stream);
+
 /* Exterior pressure from the representation formula with the surface
  * pressure and its normal derivative given separately (Eq. (BIE_I),
  * lambda = 1, tau = 1; any boundary condition):

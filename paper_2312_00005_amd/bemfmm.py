@@ -112,6 +112,7 @@ _SIGS = {
     "bem_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "bem_field": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_field_pv": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bem_field_noalloc": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bem_field_adjoint": (_i32, [_vp, _i64, _vp, _vp, _i32, _vp, _vp]),
     "bem_grad_admittance": (_i32, [_vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
     "bem_solve_adjoint": (_i32, [_vp, _vp, _vp, ctypes.POINTER(bem_solve_info), _vp]),
@@ -257,6 +258,10 @@ def bem_incident_field(mesh, kind, src, P0, n_pts, pts_ptr, out_ptr, stream):
 
 def bem_field(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream):
     _check(_lib.bem_field(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream))
+
+
+def bem_field_noalloc(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream):
+    _check(_lib.bem_field_noalloc(mesh, n_pts, pts_ptr, p_ptr, pinc_ptr, out_ptr, energy_ptr, stream))
 
 
 def bem_field_pv(mesh, n_pts, pts_ptr, p_ptr, dpdn_ptr, pinc_ptr, out_ptr, energy_ptr, stream):
