@@ -467,6 +467,29 @@ bem_status bem_tree_fmm_lengths(const bem_tree* t, double k, const bem_options* 
 
 void bem_tree_destroy(bem_tree* t);
 
+/* ---- the paper's automatic choice of method (Sec. 3.3.4, Fig. FMMChange) --
+ * Methods in the numbering of the paper's input description (FMM_type):
+ * conventional BEM without FMM, single-level FMM, multilevel FMM. */
+#define BEM_METHOD_BEM 0
+#define BEM_METHOD_SLFMM 1
+#define BEM_METHOD_MLFMM 4
+
+/* Largest distance between two of the mesh's nodes (the diameter D of the
+ * scatterer in the switching rules).  xyz: host double[n_nodes][3].  Host
+ * only, O(n_nodes^2) over the host's threads. */
+bem_status bem_mesh_diameter(int64_t n_nodes, const double* xyz, double* diameter);
+
+/* The method the paper's safeguards turn a requested method into, for a mesh
+ * of n_tri elements and diameter D at wavenumber k (lambda = 2 pi / k), the
+ * rules applied in this order:
+ *   requested BEM and n_tri > 20000            -> SLFMM
+ *   BEM or SLFMM (after the above), n_tri > 50000 -> MLFMM
+ *   an FMM and lambda >= 80 D                   -> BEM
+ *   MLFMM and lambda > D                        -> SLFMM
+ * *method receives BEM_METHOD_*.  Host only.  BEM_E_ARG for an unknown
+ * method or a non-positive size, diameter or wavenumber. */
+bem_status bem_auto_method(int32_t requested, int64_t n_tri, double diameter, double k, int32_t* method);
+
 const char* bem_last_error(void);
 
 #ifdef __cplusplus

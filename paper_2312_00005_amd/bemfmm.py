@@ -129,6 +129,8 @@ _SIGS = {
     "bem_tree_plan_stats": (_i32, [_vp, _vp, _vp, _vp]),
     "bem_tree_fmm_lengths": (_i32, [_vp, _dbl, ctypes.POINTER(bem_options), _vp, _vp, _vp, _vp]),
     "bem_tree_destroy": (None, [_vp]),
+    "bem_mesh_diameter": (_i32, [_i64, _vp, _vp]),
+    "bem_auto_method": (_i32, [_i32, _i64, _dbl, _dbl, _vp]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -369,6 +371,24 @@ def bem_tree_plan_stats(tree):
 
 def bem_tree_destroy(tree):
     _lib.bem_tree_destroy(tree)
+
+
+BEM_METHOD_BEM, BEM_METHOD_SLFMM, BEM_METHOD_MLFMM = 0, 1, 4
+
+
+def bem_mesh_diameter(nodes):
+    """Largest distance between two nodes (host array of shape (n, 3))."""
+    import numpy as np
+    xyz = np.ascontiguousarray(nodes, dtype=np.float64)
+    d = _dbl()
+    _check(_lib.bem_mesh_diameter(xyz.shape[0], xyz.ctypes.data, ctypes.byref(d)))
+    return d.value
+
+
+def bem_auto_method(requested, n_tri, diameter, k):
+    out = _i32()
+    _check(_lib.bem_auto_method(int(requested), int(n_tri), float(diameter), float(k), ctypes.byref(out)))
+    return out.value
 
 
 def bem_tree_fmm_lengths(tree, k, options):

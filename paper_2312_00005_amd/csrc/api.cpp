@@ -1256,6 +1256,51 @@ size_t bem_workspace_bytes(const bem_mesh* m) {
   return b + fmm_bytes(m);
 }
 
+bem_status bem_mesh_diameter(int64_t n_nodes, const double* xyz, double* diameter) {
+  return guarded([&]() -> bem_status {
+    if (!xyz || !diameter || n_nodes < 1) return fail(BEM_E_ARG, "NULL argument or no nodes");
+    for (int64_t i = 0; i < 3 * n_nodes; ++i)
+      if (!std::isfinite(xyz[i])) return fail(BEM_E_ARG, "non-finite node coordinate");
+    // largest squared distance over all node pairs (each pair once)
+    double best = 0.0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(max : best)
+    for (int64_t i = 0; i < n_nodes; ++i) {
+      const double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2];
+      double b = 0.0;
+      for (int64_t j = i + 1; j < n_nodes; ++j) {
+        const double dx = xyz[3 * j] - xi, dy = xyz[3 * j + 1] - yi, dz = xyz[3 * j + 2] - zi;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        b = d2 > b ? d2 : b;
+      }
+      best = b > best ? b : best;
+    }
+    *diameter = std::sqrt(best);
+    return BEM_OK;
+  });
+}
+
+bem_status bem_auto_method(int32_t requested, int64_t n_tri, double diameter, double k, int32_t* method) {
+  return guarded([&]() -> bem_status {
+    if (!method) return fail(BEM_E_ARG, "method is NULL");
+    if (requested != BEM_METHOD_BEM && requested != BEM_METHOD_SLFMM && requested != BEM_METHOD_MLFMM)
+      return fail(BEM_E_ARG, "requested must be BEM_METHOD_BEM, BEM_METHOD_SLFMM or BEM_METHOD_MLFMM");
+    if (n_tri < 1 || !(diameter > 0.0) || !std::isfinite(diameter) || !(k > 0.0) || !std::isfinite(k))
+      return fail(BEM_E_ARG, "n_tri, diameter and k must be positive");
+    int32_t m = requested;
+    // more elements than the conventional method (20000) or the single-level
+    // FMM (50000) is meant for: the faster method
+    if (m == BEM_METHOD_BEM && n_tri > 20000) m = BEM_METHOD_SLFMM;
+    if ((m == BEM_METHOD_BEM || m == BEM_METHOD_SLFMM) && n_tri > 50000) m = BEM_METHOD_MLFMM;
+    // wavelengths the expansion cannot resolve: at 80 or more diameters no
+    // FMM at all; longer than the diameter, one level only
+    const double lambda = 2.0 * M_PI / k;
+    if (m != BEM_METHOD_BEM && lambda >= 80.0 * diameter) m = BEM_METHOD_BEM;
+    if (m == BEM_METHOD_MLFMM && lambda > diameter) m = BEM_METHOD_SLFMM;
+    *method = m;
+    return BEM_OK;
+  });
+}
+
 bem_status bem_tree_build(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
                           const bem_options* o, bem_tree** out) {
   return guarded([&]() -> bem_status {

@@ -37,9 +37,10 @@ struct alignas(16) RulePt32 { float a, b, w, pad; };
 struct alignas(32) RulePt64 { double a, b, w, pad; };
 __constant__ RulePt32 c_rule_pt32[kRulePoints];
 __constant__ RulePt64 c_rule_pt64[kRulePoints];
-// 2/pi, C1, C2, C3 (pi/2 in three parts), the sin coefficients 1/17! ... -1/3!
-// (highest first), the cos coefficients 1/16! ... -1/2!
-__constant__ double c_sincos[4 + 8 + 8];
+// exp(2 pi i j / kExpTab), j = 0 .. kExpTab - 1: the table of the
+// table-driven exp(i theta) of the FP64 quadrature kernels (staged in LDS)
+constexpr int kExpTab = 512;
+__constant__ double2 c_exp_tab[kExpTab];
 
 void upload_rule_tables(const double* a, const double* b, const double* w, const int* off) {
   // the point loops read (a, b, w / 4 pi) per point; the field kernels a, b, w
@@ -52,14 +53,34 @@ void upload_rule_tables(const double* a, const double* b, const double* w, const
   }
   BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt32), pt32, sizeof(pt32)));
   BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_pt64), pt64, sizeof(pt64)));
-  // sin/cos reduction: pi/2 split into three parts, the first two with 20
-  // significant bits so that n*C1 and n*C2 are exact; Taylor coefficients
-  const double sc[20] = {0.6366197723675814, 1.5707950592041016, 1.2675900507019833e-06, 7.443547480486623e-13,
-                         1.0 / 355687428096000.0, -1.0 / 1307674368000.0, 1.0 / 6227020800.0,
-                         -1.0 / 39916800.0, 1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,
-                         1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
-                         -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5};
-  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sincos), sc, sizeof(sc)));
+  {
+    // exp(i j 2 pi / kExpTab) from angles of at most pi/4 (within an
+    // octant the argument r pi / (kExpTab / 4) carries only the rounding of
+    // pi), then the exact octant and quadrant symmetries
+    std::vector<double2> tab(kExpTab);
+    const int quarter = kExpTab / 4;
+    for (int j = 0; j < kExpTab; ++j) {
+      const int q = j / quarter, r = j % quarter;
+      double c, sn;
+      if (2 * r <= quarter) {
+        const double a = M_PI * (double)r / (double)(2 * quarter);
+        c = std::cos(a);
+        sn = std::sin(a);
+      } else {
+        const double a = M_PI * (double)(quarter - r) / (double)(2 * quarter);
+        c = std::sin(a);
+        sn = std::cos(a);
+      }
+      // rotate by q quarter turns
+      for (int t = 0; t < q; ++t) {
+        const double c2 = -sn;
+        sn = c;
+        c = c2;
+      }
+      tab[j] = make_double2(c, sn);
+    }
+    BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_exp_tab), tab.data(), sizeof(double2) * kExpTab));
+  }
   BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_a), a, sizeof(double) * kRulePoints));
   BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_b), b, sizeof(double) * kRulePoints));
   BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rule_w), w, sizeof(double) * kRulePoints));
@@ -81,53 +102,46 @@ template <> struct RuleTab<float> {
   __device__ static RulePt32 pt(int i) { return c_rule_pt32[i]; }
 };
 
-// sin and cos of x for |x| < 2^20: Cody & Waite reduction by pi/2 (pi/2 split
-// into three parts, the first two with 20 significant bits so that n*C1 and
-// n*C2 are exact), then the Taylor series of sin and cos on [-pi/4, pi/4]
-// truncated after the 1/17! and 1/16! terms (truncation error < 5e-17).  The
-// near-field phases kr are far below the range limit.
-// The constants of sincos_cw live in constant memory (c_sincos) rather than
-// as literals so that the compiler keeps them in scalar registers across the
-// point loop instead of re-materialising 64-bit immediates for every point.
-__device__ inline void sincos_cw(double x, double* s, double* c) {
-  const double* K = c_sincos;
-  const double n = rint(x * K[0]);
-  double y = fma(-n, K[1], x);
-  y = fma(-n, K[2], y);
-  y = fma(-n, K[3], y);
-  const double z = y * y;
-  // sin y = y (1 - z/3! + z^2/5! - ... - z^7/15! + z^8/17!)
-  double ps = K[4];
-#pragma unroll
-  for (int i = 5; i < 12; ++i) ps = fma(ps, z, K[i]);
-  const double sy = fma(y * z, ps, y);
-  // cos y = 1 - z/2! + z^2/4! - ... + z^8/16!
-  double pc = K[12];
-#pragma unroll
-  for (int i = 13; i < 20; ++i) pc = fma(pc, z, K[i]);
-  const double cy = fma(z, pc, 1.0);
-  const int q = ((int)n) & 3;
-  const double a = (q & 1) ? cy : sy;
-  const double b = (q & 1) ? sy : cy;
-  *s = (q & 2) ? -a : a;
-  *c = ((q + 1) & 2) ? -b : b;
+// exp(i x) for |x| < 2^20 by the table-driven method of Tang: x = j h + d
+// with h = 2 pi / kExpTab and j = rint(x / h) (Cody & Waite reduction, h in
+// three parts of which the first two have 26 significant bits, so that
+// j C1 and j C2 are exact for |j| < 2^27), |d| <= h / 2 = pi / 512; then
+// exp(i x) = T[j mod kExpTab] exp(i d) with the Taylor series of cos d to
+// d^6 / 6! and of sin d to d^5 / 5! (truncation below 1e-22 and 1e-20).  The
+// table T (exp(i j h), computed on the host) sits in LDS.
+__device__ inline void cis_table(double x, const double2* __restrict__ tab, double* s, double* c) {
+  constexpr double kInvH = 81.487330863050417;           // kExpTab / (2 pi)
+  constexpr double kC1 = 0x1.921fb58p-7;                  // 2 pi / kExpTab in three parts
+  constexpr double kC2 = -0x1.dde974p-34;
+  constexpr double kC3 = 0x1.1a62633145c07p-61;
+  const double j = rint(x * kInvH);
+  double d = fma(-j, kC1, x);
+  d = fma(-j, kC2, d);
+  d = fma(-j, kC3, d);
+  const double2 t = tab[((int)j) & (kExpTab - 1)];
+  const double z = d * d;
+  // cos d = 1 - z/2 + z^2/24 - z^3/720; sin d = d (1 - z/6 + z^2/120)
+  const double cd = fma(z, fma(z, fma(z, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  const double sd = fma(d * z, fma(z, 1.0 / 120.0, -1.0 / 6.0), d);
+  *c = fma(t.x, cd, -t.y * sd);
+  *s = fma(t.y, cd, t.x * sd);
 }
 
+// Per-block copy of the exp table into LDS (every thread of the block takes
+// part; the barrier makes it visible to all of them).
+__device__ inline void stage_exp_table(double2* __restrict__ lds) {
+  for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) lds[i] = c_exp_tab[i];
+  __syncthreads();
+}
 
-// Phase of exp(ikr) in the unit the sine/cosine below take: radians in FP64
-// (Cody-Waite reduction above), revolutions in FP32 (the hardware sine and
-// cosine take revolutions, so k/(2 pi) is folded into the per-item constant).
-template <typename T> struct Phase;
-template <> struct Phase<double> {
-  __device__ static void sincos(double x, double* s, double* c) { sincos_cw(x, s, c); }
-};
-template <> struct Phase<float> {
-  __device__ static void sincos(float x, float* s, float* c) {
-    *s = __builtin_amdgcn_sinf(x);
-    *c = __builtin_amdgcn_cosf(x);
-  }
-};
-__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
+// 1/sqrt(x) for positive normal x: the hardware estimate and one correction
+// y (1 + e/2 + 3 e^2/8), e = 1 - x y^2 (cubic convergence; the estimate's
+// relative error of order 2^-23 becomes rounding)
+__device__ inline double rsqrt_t(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
 __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
 
 __device__ inline double wave_sum(double v) {
@@ -210,7 +224,18 @@ template <typename T> struct PointConsts {
   T kgr, kgi;                // kap gamma
   T Q0r, Q0i, Q1r, Q1i, Q2r, Q2i;
   T ikap;                    // 1 / kap
+  const double2* ex;         // FP64: the exp table in LDS (see cis_table)
 };
+// exp of the phase in the unit the kernels use: radians in FP64 (table
+// driven), revolutions in FP32 (the hardware sine and cosine take
+// revolutions, so k/(2 pi) is folded into the per-item constants)
+__device__ inline void phase_cis(const PointConsts<double>& P, double x, double* s, double* c) {
+  cis_table(x, P.ex, s, c);
+}
+__device__ inline void phase_cis(const PointConsts<float>& P, float x, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(x);
+  *c = __builtin_amdgcn_cosf(x);
+}
 template <typename T>
 __device__ inline PointConsts<T> point_consts(double k, double kap, double gre, double gim) {
   PointConsts<T> P;
@@ -225,6 +250,20 @@ __device__ inline PointConsts<T> point_consts(double k, double kap, double gre, 
   P.Q2r = (T)(-gre * kap);  // -gamma kap
   P.Q2i = (T)(-gim * kap);
   P.ikap = (T)(1.0 / kap);
+  P.ex = nullptr;
+  return P;
+}
+
+// The constants and, for FP64, the exp table staged in the block's LDS
+// (lds: a __shared__ array of kExpTab entries, used only when T is double;
+// every thread of the block must call this)
+template <typename T>
+__device__ inline PointConsts<T> point_consts_staged(double k, double kap, double gre, double gim, double2* lds) {
+  PointConsts<T> P = point_consts<T>(k, kap, gre, gim);
+  if constexpr (sizeof(T) == sizeof(double)) {
+    stage_exp_table(lds);
+    P.ex = lds;
+  }
   return P;
 }
 
@@ -303,7 +342,7 @@ __device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, c
     const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     const T U = rsqrt_t(r2);
     T sn, cs;
-    Phase<T>::sincos(r2 * U, &sn, &cs);
+    phase_cis(P, r2 * U, &sn, &cs);
     const T hn = d[0] * nj[0] + d[1] * nj[1] + d[2] * nj[2];
     const T cx = d[0] * ni[0] + d[1] * ni[1] + d[2] * ni[2];
     const T Rr = fma(U, P.Q2r, P.Q1r), Ri = fma(U, P.Q2i, P.Q1i);
@@ -367,7 +406,7 @@ __device__ inline void integrate_loaded(const T r[kRec], uint64_t item, int m, c
     r2 = fma(qb, tb, r2);
     const T U = rsqrt_t(r2);
     T sn, cs;
-    Phase<T>::sincos(r2 * U, &sn, &cs);
+    phase_cis(P, r2 * U, &sn, &cs);
     // cx, or sigma when S2 is not wanted
     const T cx = fma(qb, c2, fma(qa, c1, c0));
     const T Rr = fma(U, P.Q2r, P.Q1r), Ri = fma(U, P.Q2i, P.Q1i);
@@ -464,7 +503,8 @@ __global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __rest
   const int64_t N = L.N;
   const double kap = near_kap<T>(L);
   const T* __restrict__ rec = near_rec<T>(L);
-  const PointConsts<T> P = point_consts<T>(L.k, kap, L.gre, L.gim);
+  __shared__ double2 s_ex[sizeof(T) == sizeof(double) ? kExpTab : 1];
+  const PointConsts<T> P = point_consts_staged<T>(L.k, kap, L.gre, L.gim, s_ex);
   constexpr bool NEED_C = HAS_C && !VMODE;
   const int64_t stride = (int64_t)gridDim.x * WPB;
   // the target is uniform across the wavefront: say so, so that its data go
@@ -520,11 +560,12 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
                                                   const double2* __restrict__ x, double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
   const int64_t jsrc = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double kap = near_kap<T>(L);
+  __shared__ double2 s_ex[sizeof(T) == sizeof(double) ? kExpTab : 1];
+  const PointConsts<T> P = point_consts_staged<T>(L.k, kap, L.gre, L.gim, s_ex);  // whole block, before any exit
   if (jsrc >= L.N) return;
   const int64_t N = L.N;
-  const double kap = near_kap<T>(L);
   const T* __restrict__ rec = near_rec<T>(L);
-  const PointConsts<T> P = point_consts<T>(L.k, kap, L.gre, L.gim);
   T cr = 0, ci = 0;
   if (HAS_C) {
     const double2 c = L.cfac[jsrc];
@@ -826,12 +867,13 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
                                                     double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double kap = far_kap<T>(F);
+  __shared__ double2 s_ex[sizeof(T) == sizeof(double) ? kExpTab : 1];
+  const PointConsts<T> P = point_consts_staged<T>(F.k, kap, F.gre, F.gim, s_ex);  // whole block, before any exit
   if (r >= F.N) return;
   const int64_t N = F.N;
   const T* g = far_geom<T>(F);
   const T* __restrict__ rec = far_rec<T>(F);
-  const double kap = far_kap<T>(F);
-  const PointConsts<T> P = point_consts<T>(F.k, kap, F.gre, F.gim);
   T xr[3], nr[3], xsr[3];
   for (int c = 0; c < 3; ++c) {
     xr[c] = g[(CX + c) * N + r];
@@ -925,6 +967,8 @@ template <bool HAS_C>
 __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs B, double2* __restrict__ a) {
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ double2 s_ex[kExpTab];
+  const PointConsts<double> P = point_consts_staged<double>(L.k, L.kap, L.gre, L.gim, s_ex);  // before any exit
   if (t >= L.N) return;
   const int64_t N = L.N;
   const double* g = L.geom;
@@ -933,7 +977,6 @@ __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs 
   const int n = B.n[blk];
   const int64_t off = B.off[blk];
   const int il = (int)(t - b0);
-  const PointConsts<double> P = point_consts<double>(L.k, L.kap, L.gre, L.gim);
   double xs[3], ni[3];
   for (int c = 0; c < 3; ++c) {
     xs[c] = L.kap * g[(CX + c) * N + t];

@@ -30,6 +30,19 @@ def wavenumbers(freqs, c=343.0):
     return [2.0 * math.pi * f / c for f in freqs]
 
 
+def paper_methods(nodes, tris, ks, requested=bemfmm.BEM_METHOD_MLFMM, depth=3):
+    """Per wavenumber the method of the paper's automatic switches
+    (bem_auto_method): ("dense", 0) for the conventional method, ("fmm", 1)
+    for the single-level FMM, ("fmm", depth) for the multilevel FMM."""
+    D = bemfmm.bem_mesh_diameter(nodes)
+    out = []
+    for k in ks:
+        m = bemfmm.bem_auto_method(requested, len(tris), D, k)
+        out.append(("dense", 0) if m == bemfmm.BEM_METHOD_BEM else
+                   ("fmm", 1) if m == bemfmm.BEM_METHOD_SLFMM else ("fmm", depth))
+    return out
+
+
 def choose_methods(trees, ks, max_L=120, memory_budget=96e9):
     """Per wavenumber ("fmm", depth) or ("direct", depth); trees: {depth: HostTree}."""
     out = []
@@ -53,7 +66,11 @@ class FrequencySweep:
 
     def __init__(self, nodes, tris, freqs, c=343.0, preset="mixed", depths=(4, 3, 2), leaf_size=32,
                  memory_budget=96e9, max_L=120, streams=1, steps=None, admittance=None, rho=1.21, batch=1,
-                 **overrides):
+                 policy="stability", requested=bemfmm.BEM_METHOD_MLFMM, **overrides):
+        """policy: "stability" (the deepest tree whose expansion the stability
+        cap leaves intact, else the direct far field) or "paper" (the paper's
+        automatic switches between the conventional method, the single-level
+        and the multilevel FMM, from the requested method)."""
         """steps / admittance: the frequency step s of every frequency and a
         list of curves.AdmittanceGroup; each frequency is then solved with
         beta = rho c Y(s) per element (Y = 0, sound hard, outside the groups)."""
@@ -74,15 +91,23 @@ class FrequencySweep:
             raise NotImplementedError("concurrent frequencies from several host threads are disabled "
                                       "(a host crash was seen in that mode and its cause is not known)")
         t0 = time.perf_counter()
-        trees = {d: bemfmm.HostTree(nodes, tris, preset, levels=d, leaf_size=leaf_size, **overrides)
-                 for d in depths}
-        self.methods = choose_methods(trees, self.ks, max_L=max_L, memory_budget=memory_budget)
+        if policy == "paper":
+            self.methods = paper_methods(nodes, tris, self.ks, requested, max(depths))
+            self.lengths = [None] * len(self.ks)
+        elif policy == "stability":
+            trees = {d: bemfmm.HostTree(nodes, tris, preset, levels=d, leaf_size=leaf_size, **overrides)
+                     for d in depths}
+            self.methods = choose_methods(trees, self.ks, max_L=max_L, memory_budget=memory_budget)
+            self.lengths = [trees[d].fmm_lengths(k) for (kind, d), k in zip(self.methods, self.ks)]
+            del trees
+        else:
+            raise ValueError(f"unknown policy {policy!r}")
         self.plan_seconds = time.perf_counter() - t0
-        self.lengths = [trees[d].fmm_lengths(k) for (kind, d), k in zip(self.methods, self.ks)]
-        del trees
 
     def _mesh(self, method):
         kind, d = method
+        if kind == "dense":
+            return bemfmm.Mesh(self.nodes, self.tris, self.preset, use_fmm=0, **self.overrides)
         return bemfmm.Mesh(self.nodes, self.tris, self.preset, use_fmm=1, levels=d, leaf_size=self.leaf_size,
                            far_direct=1 if kind == "direct" else 0, **self.overrides)
 
