@@ -377,11 +377,14 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
  * targets per workgroup (1, 2, 4, 8) on the near field alone and, with the
  * cluster tree, the resident near-field wavefronts per compute unit while the
  * far field runs beside it (0, 8, 12, 16, 24; see near_waves_per_cu) jointly
- * with the translation threads per workgroup (64, 128, 256; FMM only) on
- * whole applications, for the FP64 and the complex-FP32 operator.  Results
- * are kept in the mesh and used by every later application; near_wpb,
- * translate_tpb and near_waves (host int32[2]: FP64, FP32) receive them and
- * may be NULL.  Runs about 200 operator applications or parts on the stream;
+ * with the translation threads per workgroup (64, 128, 256; FMM only) and the
+ * point where the leaf-level translation leaves the level chain for a stream
+ * of its own (right after aggregation, or after the leaf level's transfer to
+ * the level above) on whole applications, for the FP64 and the complex-FP32
+ * operator.  Results are kept in the mesh and used by every later
+ * application; near_wpb, translate_tpb and near_waves (host int32[2]: FP64,
+ * FP32) receive them and may be NULL.  Runs about 400 operator applications
+ * or parts on the stream;
  * results are unchanged by the choice (each output keeps its owner and
  * summation order). */
 bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb,
@@ -466,6 +469,33 @@ bem_status bem_tree_fmm_lengths(const bem_tree* t, double k, const bem_options* 
                                 double* bytes);
 
 void bem_tree_destroy(bem_tree* t);
+
+/* ---- evaluation grid: pressure at many field points with the FMM ----------
+ * The paper's evaluation points (output appendix; the sphere benchmark of
+ * Sec. 5.1 uses 24874 of them): the points are grouped into clusters no
+ * larger than the mesh's leaf clusters; pairs of a point cluster and a leaf
+ * cluster that pass the admissibility test (and the stability test of the
+ * FP64 expansion lengths) are evaluated through the leaf signatures, the
+ * translation operator of Eq. (FMMBase) (evaluated on the fly from its
+ * Legendre series) and a local expansion about the point cluster; the other
+ * pairs by the element integrals of bem_field_pv.  Accuracy: that of the FP64
+ * far field (l_eps).  Needs a mesh built with use_fmm = 1 and far_direct = 0.
+ *   bem_grid_create: pts host double[n_pts][3] (copied); the grid keeps a
+ *     pointer to the mesh, which must outlive it.
+ *   bem_grid_eval: p_surf, dpdn_surf (NULL: c p, not allowed with PRES
+ *     elements), p_inc (NULL: no incident field) and p_out as in
+ *     bem_field_pv (device vectors, caller's element / point order); energy
+ *     as in bem_field.  Per wavenumber the split into far and near pairs is
+ *     rebuilt on the host at the first evaluation.  Blocking (error check).
+ *   bem_grid_stats: point clusters, far pairs, near elements summed over the
+ *     point clusters (of the last evaluated problem). */
+typedef struct bem_grid bem_grid;
+bem_status bem_grid_create(bem_mesh* m, int64_t n_pts, const double* pts, bem_grid** out);
+bem_status bem_grid_eval(bem_grid* g, const bem_c128* p_surf, const bem_c128* dpdn_surf, const bem_c128* p_inc,
+                         bem_c128* p_out, double* energy, void* stream);
+bem_status bem_grid_stats(const bem_grid* g, int64_t* point_clusters, int64_t* far_pairs,
+                          int64_t* near_elements);
+void bem_grid_destroy(bem_grid* g);
 
 /* ---- the paper's automatic choice of method (Sec. 3.3.4, Fig. FMMChange) --
  * Methods in the numbering of the paper's input description (FMM_type):

@@ -130,6 +130,10 @@ _SIGS = {
     "bem_tree_fmm_lengths": (_i32, [_vp, _dbl, ctypes.POINTER(bem_options), _vp, _vp, _vp, _vp]),
     "bem_tree_destroy": (None, [_vp]),
     "bem_mesh_diameter": (_i32, [_i64, _vp, _vp]),
+    "bem_grid_create": (_i32, [_vp, _i64, _vp, ctypes.POINTER(_vp)]),
+    "bem_grid_eval": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bem_grid_stats": (_i32, [_vp, _vp, _vp, _vp]),
+    "bem_grid_destroy": (None, [_vp]),
     "bem_auto_method": (_i32, [_i32, _i64, _dbl, _dbl, _vp]),
 }
 
@@ -400,6 +404,64 @@ def bem_tree_fmm_lengths(tree, k, options):
     _check(_lib.bem_tree_fmm_lengths(tree, float(k), ctypes.byref(options), L, L32, ctypes.byref(capped),
                                      ctypes.byref(nbytes)))
     return {"L": list(L[:nl]), "L_mixed": list(L32[:nl]), "capped": bool(capped.value), "bytes": nbytes.value}
+
+
+def bem_grid_create(mesh, pts):
+    import numpy as np
+    xyz = np.ascontiguousarray(pts, dtype=np.float64)
+    out = _vp()
+    _check(_lib.bem_grid_create(mesh, xyz.shape[0], xyz.ctypes.data, ctypes.byref(out)))
+    return out.value
+
+
+def bem_grid_eval(grid, p_ptr, dpdn_ptr, pinc_ptr, out_ptr, energy_ptr, stream):
+    _check(_lib.bem_grid_eval(grid, p_ptr, dpdn_ptr, pinc_ptr, out_ptr, energy_ptr, stream))
+
+
+def bem_grid_stats(grid):
+    a, b, c = _i64(), _i64(), _i64()
+    _check(_lib.bem_grid_stats(grid, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"point_clusters": a.value, "far_pairs": b.value, "near_elements": c.value}
+
+
+def bem_grid_destroy(grid):
+    _lib.bem_grid_destroy(grid)
+
+
+class Grid:
+    """Evaluation grid (bem_grid_*) of a Mesh: pressure at many field points
+    with the far part from the FMM."""
+
+    def __init__(self, mesh, pts):
+        import numpy as np
+        self.mesh = mesh  # the grid keeps a pointer to the mesh
+        self.n = int(np.asarray(pts).shape[0])
+        self._h = None
+        self._h = bem_grid_create(mesh.handle, pts)
+
+    def eval(self, p_surf, dpdn_surf=None, p_inc=None, energy=False):
+        torch = _torch()
+        out = self.mesh._empty(self.n)
+        en = torch.zeros((), dtype=torch.float64, device="cuda") if energy else None
+        bem_grid_eval(self._h, _dev_c128(p_surf, self.mesh.n, "p_surf"),
+                      _dev_c128(dpdn_surf, self.mesh.n, "dpdn_surf") if dpdn_surf is not None else None,
+                      _dev_c128(p_inc, self.n, "p_inc") if p_inc is not None else None, out.data_ptr(),
+                      en.data_ptr() if en is not None else None, _stream())
+        return (out, en) if energy else out
+
+    def stats(self):
+        return bem_grid_stats(self._h)
+
+    def close(self):
+        if self._h:
+            bem_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class HostTree:

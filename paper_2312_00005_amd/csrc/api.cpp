@@ -822,22 +822,27 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           // the kernels compete for the same slots, so both are timed on
           // whole applications
           best = -1.0f;
-          int pick_nw = 0, pick_tpb = m->tune_tpb[pi];
+          int pick_nw = 0, pick_tpb = m->tune_tpb[pi], pick_late = 0;
           const std::vector<int> tpbs = m->far_direct ? std::vector<int>{m->tune_tpb[pi]} : std::vector<int>{64, 128, 256};
-          for (int tpb : tpbs) {
-            for (int nw : {0, 8, 12, 16, 24}) {
-              m->tune_tpb[pi] = tpb;
-              m->tune_nwaves[pi] = nw;
-              const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
-              if (best < 0.0f || t < best) {
-                best = t;
-                pick_nw = nw;
-                pick_tpb = tpb;
+          const std::vector<int> lates = m->far_direct ? std::vector<int>{0} : std::vector<int>{0, 1};
+          for (int late : lates)
+            for (int tpb : tpbs) {
+              for (int nw : {0, 8, 12, 16, 24}) {
+                m->tune_tpb[pi] = tpb;
+                m->tune_nwaves[pi] = nw;
+                m->tune_fork_late[pi] = late;
+                const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
+                if (best < 0.0f || t < best) {
+                  best = t;
+                  pick_nw = nw;
+                  pick_tpb = tpb;
+                  pick_late = late;
+                }
               }
             }
-          }
           m->tune_nwaves[pi] = pick_nw;
           m->tune_tpb[pi] = pick_tpb;
+          m->tune_fork_late[pi] = pick_late;
         }
         if (near_wpb) near_wpb[pi] = m->tune_wpb[pi];
         if (translate_tpb) translate_tpb[pi] = m->tune_tpb[pi];

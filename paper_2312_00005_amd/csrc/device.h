@@ -128,6 +128,15 @@ struct FieldArgs {
 void launch_field(const FieldArgs& A, const double* pts, const double2* p, const double2* pinc, double2* out,
                   int64_t* err, hipStream_t s);
 void launch_energy(int64_t n, const double2* p, double* energy, hipStream_t s);
+// evaluation grid: near part by element integrals, far part from the point
+// clusters' local expansions (points and output in cluster order; A.tau
+// gives the sign of the scattered field)
+void launch_grid_eval(const FieldArgs& A, const double* pts, const int64_t* pc, const double* zp, int nu,
+                      const double* sn, const double* wn, const double2* loc, const int64_t* near_off,
+                      const int64_t* near_beg, const int64_t* near_end, const double2* p, const double2* v,
+                      const double2* pinc, double2* out, int64_t* err, hipStream_t s);
+// v = c p elementwise (c NULL: v = 0)
+void launch_cmul(int64_t N, const double2* c, const double2* p, double2* v, hipStream_t s);
 // y[j] = sum_f conj(K_fj) g[f] (y in tree order)
 void launch_field_adj(const FieldArgs& A, const double* pts, const double2* g, double2* y, int64_t* err,
                       hipStream_t s);
@@ -158,6 +167,8 @@ void launch_reduce_partials(int nv, int nblk, const double2* partial, double2* h
 void launch_multiaxpy(int64_t N, int nv, const double2* V, int64_t ldv, const double2* h,
                       double sign, double2* w, hipStream_t s);
 void launch_scale_copy(int64_t N, const double2* w, double2 alpha, double2* out, hipStream_t s);
+// out[0 .. n) = value (a kernel: no memset node in captured graphs)
+void launch_fill_i64(int64_t n, int64_t value, int64_t* out, hipStream_t s);
 // out = 0 (a kernel, so that it can sit in a captured graph)
 void launch_zero(int64_t N, double2* out, hipStream_t s);
 void launch_axpby(int64_t N, double2 a, const double2* x, double2 b, const double2* y, double2* out,

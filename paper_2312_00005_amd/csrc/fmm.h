@@ -79,4 +79,15 @@ template <typename T, typename V>
 void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const V* E, V* locc,
                           hipStream_t st);
 
+// ------------------------------------------------- evaluation grid (FP64) ---
+// Per far pair q = (point cluster P, leaf cluster C): X = zp[P] - zc[C],
+// coef[q][l] = i^l (2l+1) h_l(k|X|) (l = 0..L) and the unit vector dir[q] = X/|X|.
+void launch_grid_coef(int64_t npairs, const int64_t* pair_p, const int64_t* pair_c, const double* zp,
+                      const double* zc, double k, int L, double2* coef, double* dir, hipStream_t st);
+// loc[P][nu] = sum_{q in far(P)} D_q(nu) (sigA + sigB)[C(q)][nu] with
+// D_q(nu) = sum_l coef[q][l] P_l(s_nu . dir[q]) evaluated on the fly.
+void launch_grid_translate(int64_t npc, const int64_t* far_off, const int64_t* pair_c, const double2* coef,
+                           const double* dir, int L, int nu, const double* s, const double2* sigA,
+                           const double2* sigB, double2* loc, hipStream_t st);
+
 }  // namespace bem

@@ -603,6 +603,26 @@ __global__ __launch_bounds__(128) void k_down_idft_row(int nt, int nj, int nm, c
 }  // namespace
 
 // ------------------------------------------------------------ launchers ---
+// The Bonnet factors do not depend on the problem: uploaded once per device,
+// flag and upload under one lock (meshes may be set up from several threads).
+void ensure_legendre_factors() {
+  static std::mutex mu;
+  static bool leg_ready[64] = {};
+  int dev = 0;
+  BEM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(BEM_E_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!leg_ready[dev]) {
+    double a[kLegMax], b[kLegMax];
+    for (int l = 0; l < kLegMax; ++l) {
+      a[l] = (2.0 * l + 1.0) / (l + 1.0);
+      b[l] = (double)l / (l + 1.0);
+    }
+    BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_leg_a), a, sizeof(a)));
+    BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_leg_b), b, sizeof(b)));
+    leg_ready[dev] = true;
+  }
+}
 void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
                        int nu, const double2* cfac, double k, const double* ra, const double* rb,
                        const double* rw, int nq, double2* T64, float2* T32, hipStream_t st) {
@@ -627,24 +647,7 @@ void launch_fmm_translation(int64_t npairs, const int64_t* pm, const int64_t* pn
                             const double* s, int nu, int L, double k, double2* D64, float2* D32,
                             hipStream_t st) {
   if (npairs <= 0) return;
-  // the factors do not depend on the problem: uploaded once per device,
-  // flag and upload under one lock (meshes may be set up from several threads)
-  static std::mutex mu;
-  static bool leg_ready[64] = {};
-  int dev = 0;
-  BEM_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) throw Error(BEM_E_HIP, "device index out of range");
-  std::lock_guard<std::mutex> lock(mu);
-  if (!leg_ready[dev]) {
-    double a[kLegMax], b[kLegMax];
-    for (int l = 0; l < kLegMax; ++l) {
-      a[l] = (2.0 * l + 1.0) / (l + 1.0);
-      b[l] = (double)l / (l + 1.0);
-    }
-    BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_leg_a), a, sizeof(a)));
-    BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_leg_b), b, sizeof(b)));
-    leg_ready[dev] = true;
-  }
+  ensure_legendre_factors();
   hipLaunchKernelGGL(k_translation, dim3((unsigned)npairs), dim3(256), (L + 1) * sizeof(double2), st, npairs, pm, pn, z, s,
                      nu, L, k, D64, D32);
 }
@@ -803,5 +806,114 @@ void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const 
 
 BEM_FMM_INST(double, double2)
 BEM_FMM_INST(float, float2)
+
+namespace {
+
+// coefficients of the translation operator per (point cluster, leaf cluster)
+// pair; h_l by upward recurrence in FP64 (as k_translation)
+__global__ void k_grid_coef(int64_t npairs, const int64_t* __restrict__ pair_p, const int64_t* __restrict__ pair_c,
+                            const double* __restrict__ zp, const double* __restrict__ zc, double k, int L,
+                            double2* __restrict__ coef, double* __restrict__ dir) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= npairs) return;
+  const int64_t a = pair_p[q], b = pair_c[q];
+  const double X0 = zp[3 * a] - zc[3 * b], X1 = zp[3 * a + 1] - zc[3 * b + 1], X2 = zp[3 * a + 2] - zc[3 * b + 2];
+  const double r = sqrt(X0 * X0 + X1 * X1 + X2 * X2);
+  dir[3 * q] = X0 / r;
+  dir[3 * q + 1] = X1 / r;
+  dir[3 * q + 2] = X2 / r;
+  const double x = k * r;
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  double h0r = sn / x, h0i = -cs / x;
+  double h1r = (sn - x * cs) / (x * x), h1i = -(cs + x * sn) / (x * x);
+  double2* c = coef + q * (int64_t)(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    double hr, hi;
+    if (l == 0) {
+      hr = h0r;
+      hi = h0i;
+    } else if (l == 1) {
+      hr = h1r;
+      hi = h1i;
+    } else {
+      const double f = (2.0 * (l - 1) + 1.0) / x;
+      hr = f * h1r - h0r;
+      hi = f * h1i - h0i;
+      h0r = h1r;
+      h0i = h1i;
+      h1r = hr;
+      h1i = hi;
+    }
+    double cr, ci;  // i^l h_l
+    switch (l & 3) {
+      case 0: cr = hr; ci = hi; break;
+      case 1: cr = -hi; ci = hr; break;
+      case 2: cr = -hr; ci = -hi; break;
+      default: cr = hi; ci = -hr; break;
+    }
+    c[l] = make_double2((2.0 * l + 1.0) * cr, (2.0 * l + 1.0) * ci);
+  }
+}
+
+// one block per point cluster, threads over the sphere nodes; the far pairs
+// of the cluster in a fixed order (deterministic), the translation values
+// from the Legendre series (Bonnet recurrence) on the fly
+__global__ __launch_bounds__(256) void k_grid_translate(const int64_t* __restrict__ far_off,
+                                                        const int64_t* __restrict__ pair_c,
+                                                        const double2* __restrict__ coef,
+                                                        const double* __restrict__ dir, int L, int nu,
+                                                        const double* __restrict__ s,
+                                                        const double2* __restrict__ sigA,
+                                                        const double2* __restrict__ sigB,
+                                                        double2* __restrict__ loc) {
+  const int64_t P = blockIdx.x;
+  const int64_t q0 = far_off[P], q1 = far_off[P + 1];
+  for (int v = threadIdx.x; v < nu; v += blockDim.x) {
+    const double sx = s[3 * v], sy = s[3 * v + 1], sz = s[3 * v + 2];
+    double ar = 0.0, ai = 0.0;
+    for (int64_t q = q0; q < q1; ++q) {
+      const double mu = sx * dir[3 * q] + sy * dir[3 * q + 1] + sz * dir[3 * q + 2];
+      const double2* c = coef + q * (int64_t)(L + 1);
+      double pm1 = 1.0, p = mu;
+      double dr = c[0].x, di = c[0].y;
+      if (L >= 1) {
+        dr = fma(c[1].x, mu, dr);
+        di = fma(c[1].y, mu, di);
+      }
+      for (int l = 1; l < L; ++l) {
+        const double pn = fma(c_leg_a[l] * mu, p, -c_leg_b[l] * pm1);
+        pm1 = p;
+        p = pn;
+        dr = fma(c[l + 1].x, p, dr);
+        di = fma(c[l + 1].y, p, di);
+      }
+      const int64_t cidx = pair_c[q] * nu + v;
+      const double2 a = sigA[cidx], b = sigB[cidx];
+      const double gr = a.x + b.x, gi = a.y + b.y;
+      ar += dr * gr - di * gi;
+      ai += dr * gi + di * gr;
+    }
+    loc[P * nu + v] = make_double2(ar, ai);
+  }
+}
+
+}  // namespace
+
+void launch_grid_coef(int64_t npairs, const int64_t* pair_p, const int64_t* pair_c, const double* zp,
+                      const double* zc, double k, int L, double2* coef, double* dir, hipStream_t st) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_grid_coef, dim3(nblk(npairs, 128)), dim3(128), 0, st, npairs, pair_p, pair_c, zp, zc, k, L,
+                     coef, dir);
+}
+
+void launch_grid_translate(int64_t npc, const int64_t* far_off, const int64_t* pair_c, const double2* coef,
+                           const double* dir, int L, int nu, const double* s, const double2* sigA,
+                           const double2* sigB, double2* loc, hipStream_t st) {
+  if (npc <= 0) return;
+  ensure_legendre_factors();
+  hipLaunchKernelGGL(k_grid_translate, dim3((unsigned)npc), dim3(256), 0, st, far_off, pair_c, coef, dir, L, nu, s,
+                     sigA, sigB, loc);
+}
 
 }  // namespace bem

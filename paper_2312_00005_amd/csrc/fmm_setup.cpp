@@ -388,13 +388,18 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
   BEM_HIP(hipStreamIsCapturing(s, &cap));
   const bool fork =
       F->top < nl - 1 && m->leaf_stream != nullptr && !m->capturing && cap == hipStreamCaptureStatusNone;
-  if (fork) {
+  // the fork comes right after aggregation, or (tune_fork_late) after the
+  // leaf level's own transfer to the level above, whose many small blocks
+  // otherwise wait for wavefront slots behind the translation's
+  const bool late = fork && m->tune_fork_late[sizeof(T) == sizeof(float) ? 1 : 0] != 0;
+  auto fork_leaf = [&]() {
     BEM_HIP(hipEventRecord(m->ev_leaf_fork, s));
     BEM_HIP(hipStreamWaitEvent(m->leaf_stream, m->ev_leaf_fork, 0));
     launch_fmm_translate<T, V>(leaf.nc, leaf.il_off.p, leaf.il.p, leaf.code.p, false, leaf.L, leaf.nu, P::D(leaf),
                                P::sig(leaf), P::loc(leaf), tpb, m->leaf_stream);
     BEM_HIP(hipEventRecord(m->ev_leaf_join, m->leaf_stream));
-  }
+  };
+  if (fork && !late) fork_leaf();
   for (int l = nl - 2; l >= F->top; --l) {
     FmmLevel& Lp = F->lv[l];
     FmmLevel& Lc = F->lv[l + 1];
@@ -406,6 +411,7 @@ void fmm_apply_t(bem_mesh* m, FmmState* FS, const double2* x, double2* y, bool v
       launch_fmm_up_idft<T, V>(Lp.nc, Lp.cbeg.p, Lp.cend.p, Lp.L, 2 * Lp.L, Lp.nm, P::tB(Lp), P::Ep(Lp),
                                P::shift(Lp), P::sig(Lp), s);
     }
+    if (late && l == nl - 2) fork_leaf();
   }
   for (int l = F->top; l < (fork ? nl - 1 : nl); ++l) {
     FmmLevel& L = F->lv[l];
@@ -766,4 +772,34 @@ FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options&
   return I;
 }
 
+
+FmmLeafView fmm_leaf_view(bem_mesh* m) {
+  if (!m->fmm || m->far_direct || !m->fmm_state) throw Error(BEM_E_STATE, "the mesh has no FMM far field");
+  FmmSet* F = &m->fmm_state->set[0];
+  FmmLevel& leaf = F->lv.back();
+  FmmLeafView v;
+  v.L = leaf.L;
+  v.nu = leaf.nu;
+  v.s = leaf.s.p;
+  v.w = leaf.w.p;
+  v.T = F->T64.p;
+  v.ebeg = m->fmm_state->leaf_ebeg.p;
+  v.eend = m->fmm_state->leaf_eend.p;
+  v.nc = leaf.nc;
+  if (v.L <= 0) throw Error(BEM_E_STATE, "the FMM has no expansion on the leaf level");
+  return v;
+}
+
+void fmm_leaf_aggregate(bem_mesh* m, const double2* x, bool factor, double2* sig, hipStream_t s) {
+  const FmmLeafView v = fmm_leaf_view(m);
+  FmmLevel& leaf = m->fmm_state->set[0].lv.back();
+  FactorArgs fa = factor_args(m, leaf);
+  fa.cfac = nullptr;
+  launch_fmm_aggregate<double, double2>(v.nc, v.ebeg, v.eend, v.nu, v.T, factor ? &fa : nullptr, x, sig, false, s);
+}
+
+bool fmm_leaf_pair_stable(const bem_mesh* m, int L, double X) {
+  if (m->opt.l_mode != 1) return true;  // the paper's lengths carry no stability cap
+  return 2.220446049250313e-16 * (2 * L + 1) * hankel_abs(L, m->k * X) <= 0.1 * m->opt.l_eps;
+}
 }  // namespace bem

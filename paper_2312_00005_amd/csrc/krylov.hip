@@ -92,6 +92,11 @@ __global__ void k_scale_copy(int64_t N, const double2* __restrict__ w, double2 a
   out[n] = make_double2(a.x * v.x - a.y * v.y, a.x * v.y + a.y * v.x);
 }
 
+__global__ void k_fill_i64(int64_t n, int64_t value, int64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = value;
+}
+
 __global__ void k_zero(int64_t N, double2* __restrict__ out) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n < N) out[n] = make_double2(0.0, 0.0);
@@ -131,6 +136,11 @@ void launch_multiaxpy(int64_t N, int nv, const double2* V, int64_t ldv, const do
 void launch_scale_copy(int64_t N, const double2* w, double2 alpha, double2* out, hipStream_t s) {
   if (N <= 0) return;
   hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, w, alpha, out);
+}
+
+void launch_fill_i64(int64_t n, int64_t value, int64_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, value, out);
 }
 
 void launch_zero(int64_t N, double2* out, hipStream_t s) {

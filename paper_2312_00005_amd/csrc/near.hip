@@ -1171,6 +1171,67 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs A, const double* __rest
   }
 }
 
+// Evaluation grid, one wavefront per point f (points in cluster order, point
+// cluster pc[f] with centre zp):
+//   out[f] = pinc[f] + tau ( near + far ),
+//   near = sum over the elements j of the cluster's near leaf clusters of
+//          I^H_j(x) p_j - I^G_j(x) v_j (same rules as k_field),
+//   far  = -(ik / 16 pi^2) sum_nu w_nu exp(ik (x - zp).s_nu) loc[pc][nu].
+__global__ __launch_bounds__(256) void k_grid_eval(FieldArgs A, int64_t npts, const double* __restrict__ pts,
+                                                   const int64_t* __restrict__ pc, const double* __restrict__ zp,
+                                                   int nu, const double* __restrict__ sn, const double* __restrict__ wn,
+                                                   const double2* __restrict__ loc,
+                                                   const int64_t* __restrict__ near_off,
+                                                   const int64_t* __restrict__ near_beg,
+                                                   const int64_t* __restrict__ near_end,
+                                                   const double2* __restrict__ p, const double2* __restrict__ v,
+                                                   const double2* __restrict__ pinc, double2* __restrict__ out,
+                                                   int64_t* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (f >= npts) return;
+  const double x[3] = {pts[3 * f], pts[3 * f + 1], pts[3 * f + 2]};
+  const int64_t c = pc[f];
+  const double d0 = x[0] - zp[3 * c], d1 = x[1] - zp[3 * c + 1], d2 = x[2] - zp[3 * c + 2];
+  double fr = 0.0, fi = 0.0;
+  for (int q = lane; q < nu; q += 64) {
+    double snv, csv;
+    sincos(A.k * (d0 * sn[3 * q] + d1 * sn[3 * q + 1] + d2 * sn[3 * q + 2]), &snv, &csv);
+    const double2 l = loc[c * nu + q];
+    const double w = wn[q];
+    fr += w * (csv * l.x - snv * l.y);
+    fi += w * (csv * l.y + snv * l.x);
+  }
+  // -(ik / 16 pi^2) (fr + i fi)
+  constexpr double kInv16Pi2 = 0.0063325739776461107152;
+  double ar = A.k * kInv16Pi2 * fi, ai = -A.k * kInv16Pi2 * fr;
+  for (int64_t r = near_off[c]; r < near_off[c + 1]; ++r)
+    for (int64_t j = near_beg[r] + lane; j < near_end[r]; j += 64) {
+      double2 IG, IH;
+      if (!field_integrals(A, j, x, IG, IH)) {
+        err[0] = j;
+        continue;
+      }
+      const double2 pj = p[j], vj = v[j];
+      ar += (IH.x * pj.x - IH.y * pj.y) - (IG.x * vj.x - IG.y * vj.y);
+      ai += (IH.x * pj.y + IH.y * pj.x) - (IG.x * vj.y + IG.y * vj.x);
+    }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (lane == 0) {
+    const double2 b = pinc ? pinc[f] : make_double2(0.0, 0.0);
+    out[f] = make_double2(b.x + A.tau * ar, b.y + A.tau * ai);
+  }
+}
+
+// v = c p elementwise (the normal derivative of admittance / sound-hard elements)
+__global__ void k_cmul(int64_t N, const double2* __restrict__ c, const double2* __restrict__ p, double2* __restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double2 a = c ? c[t] : make_double2(0.0, 0.0), b = p[t];
+  v[t] = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
 // y[j] = sum_f conj(K_fj) g[f]  (one wavefront per element); part 1: K = I^G
 __global__ __launch_bounds__(256) void k_field_adj(FieldArgs A, const double* __restrict__ pts,
                                                    const double2* __restrict__ gv, double2* __restrict__ y,
@@ -1429,6 +1490,20 @@ void launch_block_assemble(const NearLaunch& L, const BlockArgs& B, double2* a, 
     hipLaunchKernelGGL(k_block_assemble<true>, dim3(blocks_for(L.N, 4)), dim3(256), 0, s, L, B, a);
   else
     hipLaunchKernelGGL(k_block_assemble<false>, dim3(blocks_for(L.N, 4)), dim3(256), 0, s, L, B, a);
+}
+
+void launch_grid_eval(const FieldArgs& A, const double* pts, const int64_t* pc, const double* zp, int nu,
+                      const double* sn, const double* wn, const double2* loc, const int64_t* near_off,
+                      const int64_t* near_beg, const int64_t* near_end, const double2* p, const double2* v,
+                      const double2* pinc, double2* out, int64_t* err, hipStream_t s) {
+  if (A.npts <= 0) return;
+  hipLaunchKernelGGL(k_grid_eval, dim3(blocks_for(A.npts, 4)), dim3(256), 0, s, A, A.npts, pts, pc, zp, nu, sn, wn,
+                     loc, near_off, near_beg, near_end, p, v, pinc, out, err);
+}
+
+void launch_cmul(int64_t N, const double2* c, const double2* p, double2* v, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_cmul, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, c, p, v);
 }
 
 void launch_energy(int64_t n, const double2* p, double* energy, hipStream_t s) {

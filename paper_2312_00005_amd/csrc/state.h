@@ -49,6 +49,7 @@ struct bem_mesh {
   int tune_wpb[2] = {4, 4};     // near-field targets per workgroup
   int tune_tpb[2] = {64, 64};   // translation threads per workgroup
   int tune_nwaves[2] = {0, 0};  // resident near-field wavefronts per CU beside the far field (0: one per target)
+  int tune_fork_late[2] = {0, 0};  // leaf translation forked after the leaf level's upward transfer (1) or before (0)
 
   // captured operator applications of the Krylov driver, [op][precision]
   struct GraphSlot {
@@ -181,6 +182,26 @@ struct BatchItem {
 std::vector<SolveResult> solve_tree_batch(const std::vector<BatchItem>& items, bem_op op = BEM_OP_A);
 
 void ensure_transposed_plan(bem_mesh* m, hipStream_t s);
+
+// The FP64 far-field set's leaf level as the evaluation grid reads it (after
+// bem_set_problem on a mesh with the FMM): expansion length and grid, plain
+// aggregation rows T[j][nu] (tree order), leaf clusters' element ranges.
+struct FmmLeafView {
+  int L = 0, nu = 0;
+  const double* s = nullptr;    // sphere nodes, 3 per node
+  const double* w = nullptr;    // weights
+  const double2* T = nullptr;   // N x nu
+  const int64_t* ebeg = nullptr;
+  const int64_t* eend = nullptr;
+  int64_t nc = 0;
+};
+FmmLeafView fmm_leaf_view(bem_mesh* m);
+// FP64 leaf aggregation into sig (nc x nu): factor = true multiplies the rows
+// by ik s.n_j (cfac not used), false uses the plain rows
+void fmm_leaf_aggregate(bem_mesh* m, const double2* x, bool factor, double2* sig, hipStream_t s);
+// truncation-stability test of one pair distance X at the FP64 set's leaf
+// length: rounding times (2L+1)|h_L(kX)| within l_eps / 10
+bool fmm_leaf_pair_stable(const bem_mesh* m, int L, double X);
 
 // field-point kernels' arguments for the mesh's current problem (part 0:
 // K = I^H - c I^G, part 1: K = I^G), and the check of their error flag (the
