@@ -203,6 +203,46 @@ def box(lengths, h, origin=(0.0, 0.0, 0.0)):
     return np.array(nodes, dtype=np.float64), np.array(tris, dtype=np.int32)
 
 
+def box_quads(lengths, h, origin=(0.0, 0.0, 0.0)):
+    """The surface of box(lengths, h, origin) with every face rectangle kept
+    whole: (n, 4) vertex indices, counter-clockwise seen from outside."""
+    nodes, tris = box(lengths, h, origin)
+    # box() emits each rectangle as (p00, p10, p11), (p00, p11, p01)
+    t = tris.reshape(-1, 2, 3)
+    quads = np.stack([t[:, 0, 0], t[:, 0, 1], t[:, 0, 2], t[:, 1, 2]], axis=1)
+    return nodes, quads.astype(np.int32)
+
+
+def uv_sphere(n_theta, n_phi, radius=1.0):
+    """Latitude-longitude sphere: n_theta bands of equal polar angle, n_phi
+    sectors.  Every cell between two latitude circles is a plane isosceles
+    trapezoid (its four vertices are symmetric about the cell's mid meridian
+    plane); the cells at the poles are triangles.  Elements: (n, 4) vertex
+    indices, -1 in the last column of triangles, counter-clockwise seen from
+    outside."""
+    th = np.pi * np.arange(1, n_theta) / n_theta
+    ph = 2.0 * np.pi * np.arange(n_phi) / n_phi
+    nodes = [[0.0, 0.0, radius]]
+    for t in th:
+        for f in ph:
+            nodes.append([radius * np.sin(t) * np.cos(f), radius * np.sin(t) * np.sin(f), radius * np.cos(t)])
+    nodes.append([0.0, 0.0, -radius])
+    south = len(nodes) - 1
+
+    def ring(i, j):  # i-th latitude circle (0 = nearest the north pole)
+        return 1 + i * n_phi + (j % n_phi)
+
+    el = []
+    for j in range(n_phi):
+        el.append([0, ring(0, j), ring(0, j + 1), -1])
+    for i in range(n_theta - 2):
+        for j in range(n_phi):
+            el.append([ring(i, j), ring(i + 1, j), ring(i + 1, j + 1), ring(i, j + 1)])
+    for j in range(n_phi):
+        el.append([south, ring(n_theta - 2, j + 1), ring(n_theta - 2, j), -1])
+    return np.array(nodes, dtype=np.float64), np.array(el, dtype=np.int32)
+
+
 def flat_patch(h=1.0):
     """Unit square in the z = 0 plane split into two triangles (normal +z)."""
     nodes = np.array([[0, 0, 0], [h, 0, 0], [h, h, 0], [0, h, 0]], dtype=np.float64)
