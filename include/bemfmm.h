@@ -229,6 +229,23 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri,
                            const int32_t* tri, const bem_options* o,
                            void* stream, bem_mesh** out);
 
+/* The same for a mesh of flat triangles and plane quadrilaterals (Sec. 2.2):
+ *   el : host, int32[n_el][4], 0-based node indices counter-clockwise seen
+ *        from outside; el[e][3] < 0 marks a triangle
+ * A quadrilateral's collocation node is the mean of its four vertices (Sec.
+ * 2.3) and its normal lies along (P2 - P0) x (P3 - P1); it is integrated as
+ * the two triangles (P0, P1, P2) and (P0, P2, P3), each with the rules of a
+ * triangle (the paper's m x m product rule gives the same integral to the
+ * quadrature tolerance), and its singular integral by eight Duffy
+ * sub-triangles around the node (Sec. 3.1.1) and its four edges (Sec.
+ * 3.1.2).  Every later call takes vectors of n_el values, one per element.
+ * BEM_E_MESH (bem_mesh_bad_element names it) for a quadrilateral whose
+ * vertices lie more than 1e-8 of its longer diagonal off their mean plane,
+ * one that is not convex, or a degenerate element. */
+bem_status bem_mesh_create_elements(int64_t n_nodes, const double* xyz, int64_t n_el,
+                                    const int32_t* el, const bem_options* o,
+                                    void* stream, bem_mesh** out);
+
 /* Element index (caller order) that caused the last BEM_E_MESH, or -1. */
 int64_t bem_mesh_bad_element(const bem_mesh* m);
 

@@ -96,6 +96,8 @@ _dbl = ctypes.c_double
 _SIGS = {
     "bem_options_default": (_i32, [ctypes.POINTER(bem_options), ctypes.c_char_p]),
     "bem_mesh_create": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), _vp, ctypes.POINTER(_vp)]),
+    "bem_mesh_create_elements": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), _vp,
+                                        ctypes.POINTER(_vp)]),
     "bem_set_allocator": (_i32, [_vp, _vp, _vp]),
     "bem_mesh_bad_element": (_i64, [_vp]),
     "bem_set_problem": (_i32, [_vp, _dbl, _vp, _vp]),
@@ -160,6 +162,14 @@ def bem_options_default(preset="paper"):
     o = bem_options()
     _check(_lib.bem_options_default(ctypes.byref(o), preset.encode()))
     return o
+
+
+def bem_mesh_create_elements(n_nodes, xyz_ptr, n_el, el_ptr, options, stream=None):
+    out = _vp()
+    st = _lib.bem_mesh_create_elements(n_nodes, xyz_ptr, n_el, el_ptr, ctypes.byref(options), stream,
+                                       ctypes.byref(out))
+    _check(st)
+    return out
 
 
 def bem_mesh_create(n_nodes, xyz_ptr, n_tri, tri_ptr, options, stream=None):
@@ -559,8 +569,12 @@ class Mesh:
         self._tris = np.ascontiguousarray(tris, dtype=np.int32)
         self.n = int(self._tris.shape[0])
         self._h = None
-        self._h = bem_mesh_create(self._nodes.shape[0], self._nodes.ctypes.data, self.n,
-                                  self._tris.ctypes.data, options, _stream())
+        if self._tris.ndim != 2 or self._tris.shape[1] not in (3, 4):
+            raise ValueError("elements must be an (n, 3) or (n, 4) index array")
+        # (n, 4): triangles and plane quadrilaterals (-1 in the last column of a triangle)
+        create = bem_mesh_create if self._tris.shape[1] == 3 else bem_mesh_create_elements
+        self._h = create(self._nodes.shape[0], self._nodes.ctypes.data, self.n, self._tris.ctypes.data, options,
+                         _stream())
         self._beta = None
 
     def close(self):

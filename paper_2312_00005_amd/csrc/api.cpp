@@ -200,6 +200,7 @@ void apply_tree_part_ext(bem_mesh* m, bem_op op, bem_precision prec, int part, c
   }
   NearLaunch L{};
   L.N = m->N;
+  L.Q = quad_recs(m);
   L.geom = m->d_geom.p;
   L.geom32 = m->d_geom32.p;
   L.cfac = m->have_beta ? m->d_cfac.p : nullptr;
@@ -256,6 +257,7 @@ void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, dou
   }
   FarLaunch F{};
   F.N = m->N;
+  F.Q = quad_recs(m);
   F.geom = m->d_geom.p;
   F.geom32 = m->d_geom32.p;
   F.cfac = m->have_beta ? m->d_cfac.p : nullptr;
@@ -394,7 +396,7 @@ void build_blocks(bem_mesh* m, int max_n, hipStream_t s) {
     for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
       bseg[t * (kMaxRuleOrder + 1) + mc] = (int64_t)bitems.size();
       for (int64_t it = sg[mc]; it < sg[mc + 1]; ++it) {
-        const int64_t j = (int64_t)(m->plan.items[it] & ((uint64_t(1) << 26) - 1));
+        const int64_t j = m->g.owner((int64_t)(m->plan.items[it] & ((uint64_t(1) << 26) - 1)));
         if (j >= b0 && j < b1) bitems.push_back(m->plan.items[it]);
       }
     }
@@ -420,6 +422,7 @@ void setup_preconditioner(bem_mesh* m, hipStream_t s) {
   if (!m->opt.precond || m->nblk == 0 || m->has_pres) return;
   NearLaunch L{};
   L.N = m->N;
+  L.Q = quad_recs(m);
   L.geom = m->d_geom.p;
   L.cfac = m->have_beta ? m->d_cfac.p : nullptr;
   L.diag = m->d_diag.p;
@@ -449,16 +452,21 @@ void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
   const int64_t N = m->N;
   NearPlan T;
   T.off.assign(N + 1, 0);
+  // items by the element of their source record; a quadrilateral's items
+  // carry the half (0, 1) in bit 63
   const uint64_t jmask = (uint64_t(1) << 26) - 1;
-  for (uint64_t it : P.items) T.off[(it & jmask) + 1]++;
+  const Geometry& g = m->g;
+  for (uint64_t it : P.items) T.off[g.owner((int64_t)(it & jmask)) + 1]++;
   for (int64_t j = 0; j < N; ++j) T.off[j + 1] += T.off[j];
   T.items.resize(P.items.size());
   std::vector<int64_t> pos(T.off.begin(), T.off.end() - 1);
   for (int64_t t = 0; t < N; ++t)
     for (int64_t q = P.off[t]; q < P.off[t + 1]; ++q) {
       uint64_t it = P.items[q];
-      int64_t j = (int64_t)(it & jmask);
-      T.items[pos[j]++] = (it & ~jmask) | (uint64_t)t;
+      const int64_t r = (int64_t)(it & jmask);
+      const int64_t j = g.owner(r);
+      const uint64_t half = r >= N ? (uint64_t)((r - N) & 1) << 63 : 0;
+      T.items[pos[j]++] = (it & ~jmask) | (uint64_t)t | half;
     }
   // sort each source's list by rule order for uniform wavefront work
   for (int64_t j = 0; j < N; ++j)
@@ -481,6 +489,7 @@ void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
 namespace {
 
 // Geometry, cluster tree and near-field plan on the host (no device work).
+// el: n_tri x 4 vertex indices (el[4 e + 3] < 0: triangle)
 void build_host(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri, const bem_options& o,
                 Tree& tree, Geometry& g, NearPlan& plan, int64_t& bad_element) {
   std::vector<int64_t> ident(n_tri);
@@ -530,6 +539,16 @@ void validate_mesh_args(int64_t n_nodes, const double* xyz, int64_t n_tri, const
   if (!xyz || !tri || n_nodes < 3 || n_tri < 1) throw Error(BEM_E_ARG, "empty or NULL mesh");
   for (int64_t i = 0; i < 3 * n_nodes; ++i)
     if (!std::isfinite(xyz[i])) throw Error(BEM_E_ARG, "non-finite node coordinate");
+}
+
+// triangles (n x 3) as the n x 4 element array of build_host
+std::vector<int32_t> as_elements(int64_t n_tri, const int32_t* tri) {
+  std::vector<int32_t> el((size_t)4 * n_tri);
+  for (int64_t e = 0; e < n_tri; ++e) {
+    for (int c = 0; c < 3; ++c) el[4 * e + c] = tri[3 * e + c];
+    el[4 * e + 3] = -1;
+  }
+  return el;
 }
 
 }  // namespace
@@ -588,12 +607,37 @@ bem_status bem_options_default(bem_options* o, const char* preset) {
   });
 }
 
+namespace {
+bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
+                       const bem_options* o, void* stream, bem_mesh** out);
+}
+
 bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
                            const bem_options* o, void* stream, bem_mesh** out) {
   return guarded([&]() -> bem_status {
     if (!out) return fail(BEM_E_ARG, "out is NULL");
     *out = nullptr;
     validate_mesh_args(n_nodes, xyz, n_tri, tri);
+    const std::vector<int32_t> el = as_elements(n_tri, tri);
+    return create_mesh(n_nodes, xyz, n_tri, el.data(), o, stream, out);
+  });
+}
+
+bem_status bem_mesh_create_elements(int64_t n_nodes, const double* xyz, int64_t n_el, const int32_t* el,
+                                    const bem_options* o, void* stream, bem_mesh** out) {
+  return guarded([&]() -> bem_status {
+    if (!out) return fail(BEM_E_ARG, "out is NULL");
+    *out = nullptr;
+    validate_mesh_args(n_nodes, xyz, n_el, el);
+    return create_mesh(n_nodes, xyz, n_el, el, o, stream, out);
+  });
+}
+
+namespace {
+// el: n_tri x 4 (validated by the caller); runs inside the caller's guard
+bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
+                       const bem_options* o, void* stream, bem_mesh** out) {
+  {
     check_options(o);
     auto m = std::make_unique<bem_mesh>();
     m->opt = *o;
@@ -613,8 +657,16 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     m->d_geom.upload(m->g.f, s);
     std::vector<float> g32(m->g.f.begin(), m->g.f.end());
     m->d_geom32.upload(g32, s);
-    m->d_rec.alloc((size_t)n_tri * 16);
-    m->d_rec32.alloc((size_t)n_tri * 16);
+    if (m->g.nq > 0) {
+      m->d_qidx.upload(m->g.qidx, s);
+      m->d_hown.upload(m->g.hown, s);
+      m->d_hq.upload(m->g.hq, s);
+      std::vector<float> hq32(m->g.hq.begin(), m->g.hq.end());
+      m->d_hq32.upload(hq32, s);
+    }
+    // integration records: the elements, then the quadrilaterals' halves
+    m->d_rec.alloc((size_t)(n_tri + 2 * m->g.nq) * 16);
+    m->d_rec32.alloc((size_t)(n_tri + 2 * m->g.nq) * 16);
     m->d_perm.upload(m->tree.perm, s);
     m->d_off.upload(m->plan.off, s);
     m->d_seg.upload(m->plan.seg, s);
@@ -686,8 +738,9 @@ bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, co
     BEM_HIP(hipStreamSynchronize(s));
     *out = m.release();
     return BEM_OK;
-  });
+  }
 }
+}  // namespace
 
 int64_t bem_mesh_bad_element(const bem_mesh* m) { return m ? m->bad_element : -1; }
 
@@ -711,6 +764,7 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     }
     SelfLaunch L{};
     L.N = m->N;
+    L.Q = quad_recs(m);
     L.geom = m->d_geom.p;
     L.cfac = m->have_beta ? m->d_cfac.p : nullptr;
     L.duffy_u = m->d_duffy_u.p;
@@ -728,6 +782,8 @@ bem_status bem_set_problem(bem_mesh* m, double k, const bem_c128* beta, void* st
     m->kap = k;
     m->kap32 = (double)(float)(k / (2.0 * M_PI));
     launch_records(m->N, m->d_geom.p, m->kap, m->kap32, m->d_rec.p, m->d_rec32.p, s);
+    // the quadrilaterals' halves: records N .. N + 2 nq
+    launch_records_at(2 * m->g.nq, m->d_hq.p, m->N, m->kap, m->kap32, m->d_rec.p, m->d_rec32.p, s);
     BEM_HIP(hipGetLastError());
     setup_preconditioner(m, s);
     if (m->fmm && !m->far_direct) fmm_setup_problem(m, s);
@@ -973,9 +1029,22 @@ bem_status bem_rhs_velocity(bem_mesh* m, const bem_c128* u, double rho_c, bem_c1
 
 namespace bem {
 
+QuadRecs quad_recs(const bem_mesh* m) {
+  QuadRecs Q;
+  if (m->g.nq > 0) {
+    Q.nh = 2 * m->g.nq;
+    Q.qidx = m->d_qidx.p;
+    Q.hown = m->d_hown.p;
+    Q.hq = m->d_hq.p;
+    Q.hq32 = m->d_hq32.p;
+  }
+  return Q;
+}
+
 FieldArgs field_args(bem_mesh* m, int64_t npts, int part) {
   FieldArgs A{};
   A.N = m->N;
+  A.Q = quad_recs(m);
   A.npts = npts;
   A.geom = m->d_geom.p;
   A.cfac = m->have_beta ? m->d_cfac.p : nullptr;
@@ -1250,7 +1319,8 @@ bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,
 
 size_t bem_workspace_bytes(const bem_mesh* m) {
   if (!m) return 0;
-  size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_rec.bytes() + m->d_rec32.bytes() + m->d_perm.bytes() + m->d_off.bytes() + m->d_order.bytes() +
+  size_t b = m->d_geom.bytes() + m->d_geom32.bytes() + m->d_qidx.bytes() + m->d_hown.bytes() + m->d_hq.bytes() +
+             m->d_hq32.bytes() + m->d_rec.bytes() + m->d_rec32.bytes() + m->d_perm.bytes() + m->d_off.bytes() + m->d_order.bytes() +
              m->d_items.bytes() + m->d_seg.bytes() + m->d_seg_t.bytes() + m->d_off_t.bytes() + m->d_items_t.bytes() + m->d_beta.bytes() +
              m->d_cfac.bytes() + m->d_diag.bytes() + m->d_vdiag.bytes() + m->d_x.bytes() + m->d_y.bytes() + m->d_r.bytes() +
              m->d_b.bytes() + m->d_sol.bytes() + m->d_tmp.bytes() + m->d_V.bytes() + m->d_w.bytes() +
@@ -1317,7 +1387,8 @@ bem_status bem_tree_build(int64_t n_nodes, const double* xyz, int64_t n_tri, con
     t->N = n_tri;
     t->fmm = o->use_fmm != 0;
     int64_t bad = -1;
-    build_host(n_nodes, xyz, n_tri, tri, *o, t->tree, t->g, t->plan, bad);
+    const std::vector<int32_t> el = as_elements(n_tri, tri);
+    build_host(n_nodes, xyz, n_tri, el.data(), *o, t->tree, t->g, t->plan, bad);
     *out = t.release();
     return BEM_OK;
   });

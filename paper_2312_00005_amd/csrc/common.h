@@ -119,17 +119,39 @@ enum GeomField {
   G_NX, G_NY, G_NZ, G_AREA, G_CX, G_CY, G_CZ, G_NFIELDS
 };
 
+// Elements are flat triangles or plane quadrilaterals (Sec. 2.2).  A
+// quadrilateral P0 P1 P2 P3 keeps P0, P1, P2 in its own fields, its vertex
+// mean as collocation node, the normal along (P2 - P0) x (P3 - P1) and its
+// whole area; it is integrated as the two triangles (P0, P1, P2) and
+// (P0, P2, P3), the integration records N + 2q and N + 2q + 1 (q its
+// quadrilateral index), whose geometry is held in hq with the GeomField
+// layout and stride 2 nq.  Integration records j < N are the triangles.
 struct Geometry {
   int64_t N = 0;
   std::vector<double> f;  // G_NFIELDS * N
+  int64_t nq = 0;               // quadrilaterals
+  std::vector<int64_t> qidx;    // element -> quadrilateral index, or -1 (empty: triangles only)
+  std::vector<int64_t> hown;    // half record r (record N + r) -> element
+  std::vector<double> hq;       // G_NFIELDS * 2 nq: the halves (P0, P1, P2, normal, area, centroid)
   double& at(int field, int64_t e) { return f[field * N + e]; }
   double at(int field, int64_t e) const { return f[field * N + e]; }
+  bool is_quad(int64_t e) const { return !qidx.empty() && qidx[e] >= 0; }
+  int nv(int64_t e) const { return is_quad(e) ? 4 : 3; }
+  // vertex v (0..3) coordinate d of element e; P3 of a quadrilateral is the
+  // third vertex of its second half
+  double vtx(int v, int d, int64_t e) const {
+    return v < 3 ? at(G_P0X + 3 * v + d, e) : hq[(G_P2X + d) * 2 * nq + 2 * qidx[e] + 1];
+  }
+  // element of integration record j
+  int64_t owner(int64_t j) const { return j < N ? j : hown[j - N]; }
 };
 
 // Build geometry in the order given by perm (perm[t] = caller index of the
-// element at position t).  Throws BEM_E_MESH on a zero-area triangle.
-Geometry build_geometry(const double* xyz, int64_t n_nodes, const int32_t* tri,
-                        int64_t n_tri, const std::vector<int64_t>& perm);
+// element at position t).  el: n_el x 4 vertex indices, el[4 e + 3] < 0 for a
+// triangle.  Throws BEM_E_MESH on a degenerate element, a quadrilateral that
+// is not plane or not convex.
+Geometry build_geometry(const double* xyz, int64_t n_nodes, const int32_t* el,
+                        int64_t n_el, const std::vector<int64_t>& perm);
 
 // ----------------------------------------------------------------- tree ---
 struct Level {

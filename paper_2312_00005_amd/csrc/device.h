@@ -12,8 +12,22 @@ constexpr int kRulePoints = 204;                       // sum of m*m for m = 1..
 // Launch helpers (host-callable, defined in the .hip files).
 void upload_rule_tables(const double* a, const double* b, const double* w, const int* off);
 
+// Plane quadrilaterals: element j with qidx[j] = q >= 0 is integrated as the
+// records N + 2q and N + 2q + 1 (triangles (P0, P1, P2) and (P0, P2, P3));
+// hown[r] is the element of record N + r; hq / hq32 hold the halves'
+// geometry with the GeomField layout and stride nh = 2 nq.  nh = 0: the mesh
+// has triangles only and the arrays are not read.
+struct QuadRecs {
+  int64_t nh = 0;
+  const int64_t* qidx = nullptr;
+  const int64_t* hown = nullptr;
+  const double* hq = nullptr;
+  const float* hq32 = nullptr;
+};
+
 struct NearLaunch {
   int64_t N;
+  QuadRecs Q;             // integration records of quadrilaterals (items name records)
   const double* geom;     // G_NFIELDS * N, tree order
   const float* geom32;    // same fields in float (mixed path)
   const int64_t* off;     // N + 1
@@ -46,6 +60,7 @@ void launch_near(const NearLaunch& L, bool fp64, bool adjoint, bool vmode, const
 // intervals (tree order) outside its near clusters.
 struct FarLaunch {
   int64_t N;
+  QuadRecs Q;
   const double* geom;
   const float* geom32;
   const double2* cfac;
@@ -68,6 +83,7 @@ void launch_far_direct(const FarLaunch& F, bool fp64, bool adjoint, bool vmode, 
 
 struct SelfLaunch {
   int64_t N;
+  QuadRecs Q;
   const double* geom;
   const double2* cfac;
   double2* vdiag;         // optional output: G_ii - gamma/2
@@ -83,6 +99,10 @@ void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s);
 // (FP64), rec32: scale kap32 (FP32).
 void launch_records(int64_t N, const double* geom, double kap, double kap32, double* rec, float* rec32,
                     hipStream_t s);
+// the same for the n records whose geometry is geom (stride n), written at
+// rec + 16 first, rec32 + 16 first (the quadrilaterals' halves)
+void launch_records_at(int64_t n, const double* geom, int64_t first, double kap, double kap32, double* rec,
+                       float* rec32, hipStream_t s);
 
 // Block-Jacobi preconditioner: the elements (tree order) are partitioned into
 // contiguous blocks of at most kMaxBlock elements; block b covers
@@ -111,6 +131,7 @@ void launch_block_apply(int64_t N, const BlockArgs& B, const double2* inv, bool 
 
 struct FieldArgs {
   int64_t N;             // elements
+  QuadRecs Q;
   int64_t npts;          // field points
   const double* geom;    // tree order
   const double2* cfac;   // c_j (tree order) or NULL

@@ -20,10 +20,12 @@ struct FactorArgs {
 // pointer skips that copy).
 // Leaf aggregation rows T[j][nu] = int_Gj exp(ik (z_c(j) - y).s) dy (the source
 // factor is applied when the rows are used)
-// (conical rule with nq points: rule_a, rule_b, rule_w in device memory).
-void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* elem_cluster, const double* zc,
-                       const double* s, int nu, const double2* cfac, double k, const double* ra,
-                       const double* rb, const double* rw, int nq, double2* T64, float2* T32, hipStream_t st);
+// (conical rule with nq points: rule_a, rule_b, rule_w in device memory; a
+// quadrilateral, qidx[j] >= 0, integrated over its two halves in hq, stride nh).
+void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* qidx, const double* hq, int64_t nh,
+                       const int64_t* elem_cluster, const double* zc, const double* s, int nu, const double2* cfac,
+                       double k, const double* ra, const double* rb, const double* rw, int nq, double2* T64,
+                       float2* T32, hipStream_t st);
 // Leaf disaggregation rows S'[i][nu] = ik/(16 pi^2) w_nu (1 - gamma ik s.n_i) exp(ik (x_i - z).s)
 void launch_fmm_leaf_S(int64_t N, const double* geom, const int64_t* elem_cluster, const double* zc,
                        const double* s, const double* w, int nu, double k, double gre, double gim,

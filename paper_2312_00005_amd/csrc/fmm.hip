@@ -53,8 +53,11 @@ template <> __device__ inline float2 from_d2<float2>(double2 v) { return make_fl
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ------------------------------------------------------------ setup ---
+// A quadrilateral's row is the sum over its two integration triangles (qidx
+// >= 0: geometry in hq, stride nh).
 template <bool SINGLE>
-__global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t* __restrict__ ec,
+__global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t* __restrict__ qidx,
+                         const double* __restrict__ hq, int64_t nh, const int64_t* __restrict__ ec,
                          const double* __restrict__ zc, const double* __restrict__ s, int nu,
                          const double2* __restrict__ cfac, double k, const double* __restrict__ ra,
                          const double* __restrict__ rb, const double* __restrict__ rw, int nq,
@@ -65,40 +68,54 @@ __global__ void k_leaf_T(int64_t N, const double* __restrict__ g, const int64_t*
   const int64_t idx = j * nu + v;
   const int64_t c = ec[j];
   const double sx = s[3 * v], sy = s[3 * v + 1], sz = s[3 * v + 2];
-  double P0[3], e1[3], e2[3];
-  for (int d = 0; d < 3; ++d) {
-    P0[d] = g[(P0X + d) * N + j];
-    e1[d] = g[(P1X + d) * N + j] - P0[d];
-    e2[d] = g[(P2X + d) * N + j] - P0[d];
-  }
-  // exp(ik (z - y).s) = exp(ik (z - P0).s) exp(-ik (a e1 + b e2).s)
-  const double base = k * ((zc[3 * c] - P0[0]) * sx + (zc[3 * c + 1] - P0[1]) * sy + (zc[3 * c + 2] - P0[2]) * sz);
-  const double pe1 = k * (e1[0] * sx + e1[1] * sy + e1[2] * sz);
-  const double pe2 = k * (e2[0] * sx + e2[1] * sy + e2[2] * sz);
-  const double a2 = 2.0 * g[AREA * N + j];
-  if (SINGLE) {
-    // rows of the complex-FP32 operator: phases in revolutions (the hardware
-    // sine and cosine take revolutions), formed from FP64 per-row terms
-    constexpr double kRev = 0.15915494309189533577;  // 1 / (2 pi)
-    const float b0 = (float)(base * kRev), q1 = (float)(pe1 * kRev), q2 = (float)(pe2 * kRev);
-    float ar = 0.0f, ai = 0.0f;
-    for (int q = 0; q < nq; ++q) {
-      const float ph = fmaf(-(float)rb[q], q2, fmaf(-(float)ra[q], q1, b0));
-      const float w = (float)rw[q];
-      ar = fmaf(w, __builtin_amdgcn_cosf(ph), ar);
-      ai = fmaf(w, __builtin_amdgcn_sinf(ph), ai);
+  const int64_t qj = qidx ? qidx[j] : -1;
+  const int nrec = qj >= 0 ? 2 : 1;
+  double sr = 0.0, si = 0.0;
+  for (int h = 0; h < nrec; ++h) {
+    const double* gg = qj >= 0 ? hq : g;
+    const int64_t st = qj >= 0 ? nh : N, r = qj >= 0 ? 2 * qj + h : j;
+    double P0[3], e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) {
+      P0[d] = gg[(P0X + d) * st + r];
+      e1[d] = gg[(P1X + d) * st + r] - P0[d];
+      e2[d] = gg[(P2X + d) * st + r] - P0[d];
     }
-    T32[idx] = make_float2((float)(ar * a2), (float)(ai * a2));
-  } else {
-    double ar = 0.0, ai = 0.0;
-    for (int q = 0; q < nq; ++q) {
-      double sn, cs;
-      sincos_cw_lit(base - ra[q] * pe1 - rb[q] * pe2, &sn, &cs);
-      ar += rw[q] * cs;
-      ai += rw[q] * sn;
+    // exp(ik (z - y).s) = exp(ik (z - P0).s) exp(-ik (a e1 + b e2).s)
+    const double base =
+        k * ((zc[3 * c] - P0[0]) * sx + (zc[3 * c + 1] - P0[1]) * sy + (zc[3 * c + 2] - P0[2]) * sz);
+    const double pe1 = k * (e1[0] * sx + e1[1] * sy + e1[2] * sz);
+    const double pe2 = k * (e2[0] * sx + e2[1] * sy + e2[2] * sz);
+    const double a2 = 2.0 * gg[AREA * st + r];
+    if (SINGLE) {
+      // rows of the complex-FP32 operator: phases in revolutions (the hardware
+      // sine and cosine take revolutions), formed from FP64 per-row terms
+      constexpr double kRev = 0.15915494309189533577;  // 1 / (2 pi)
+      const float b0 = (float)(base * kRev), q1 = (float)(pe1 * kRev), q2 = (float)(pe2 * kRev);
+      float ar = 0.0f, ai = 0.0f;
+      for (int q = 0; q < nq; ++q) {
+        const float ph = fmaf(-(float)rb[q], q2, fmaf(-(float)ra[q], q1, b0));
+        const float w = (float)rw[q];
+        ar = fmaf(w, __builtin_amdgcn_cosf(ph), ar);
+        ai = fmaf(w, __builtin_amdgcn_sinf(ph), ai);
+      }
+      sr += (double)ar * a2;
+      si += (double)ai * a2;
+    } else {
+      double ar = 0.0, ai = 0.0;
+      for (int q = 0; q < nq; ++q) {
+        double sn, cs;
+        sincos_cw_lit(base - ra[q] * pe1 - rb[q] * pe2, &sn, &cs);
+        ar += rw[q] * cs;
+        ai += rw[q] * sn;
+      }
+      sr += ar * a2;
+      si += ai * a2;
     }
-    T64[idx] = make_double2(ar * a2, ai * a2);
   }
+  if (SINGLE)
+    T32[idx] = make_float2((float)sr, (float)si);
+  else
+    T64[idx] = make_double2(sr, si);
 }
 
 __global__ void k_leaf_S(int64_t N, const double* __restrict__ g, const int64_t* __restrict__ ec,
@@ -600,6 +617,108 @@ __global__ __launch_bounds__(128) void k_down_idft_row(int nt, int nj, int nm, c
   }
 }
 
+// ---- level transfer on the matrix cores ------------------------------------
+// The azimuthal DFTs of the resampling are products of a level's rows (R =
+// clusters x theta rows, K complex values each) with one K x N complex table
+// shared by all rows.  Written on interleaved reals, the complex product is
+// one real product: row (2K reals) times the 2K x 2N table
+//   B'[2k + a][2n + b] = Re B[k][n] (a = b),  Im B[k][n] (a = 0, b = 1),  -Im B[k][n] (a = 1, b = 0),
+// whose interleaved output is the complex result.  One wavefront computes a
+// 16-row x 16-real-column tile with 16 x 16 x 4 MFMA steps
+// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64): operand A[i][k] in lane
+// i + 16k, B[k][j] in lane j + 16k; result D[i][j] in lane j + 16 (i / 4),
+// element i % 4 (FP32) and in lane j + 16 (i % 4), element i / 4 (FP64).
+// Consecutive wavefronts take the column tiles of one row tile, so the rows
+// are read from L2 once per block; the table (a few tens of KB) stays in L2.
+// Used where the table is too large for the LDS-staged VALU form (the
+// row-per-block VALU fallback then reads it from L2 per row): measured alone
+// at c2, FP64 upward DFT 152 x 34 rows (K = 68, N = 67) 27.1 -> 16.4 us and
+// downward inverse DFT (K = 67, N = 68) 26.2 -> 19.5 us; where the table
+// fits LDS the VALU forms are as fast or faster (these products are bound
+// by memory latency, not arithmetic), and the shifted-parent form (conj(shift)
+// times the parent row, formed per operand) lost everywhere.
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = mf_f4;
+  __device__ static acc op(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lq, int v) { return 4 * lq + v; }  // row of result element v in lane group lq
+};
+template <> struct Mfma<double> {
+  using acc = mf_d4;
+  __device__ static acc op(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lq, int v) { return lq + 4 * v; }
+};
+
+constexpr int kMfmaWaves = 4;  // wavefronts per block
+
+// ACC false: out[r][0..N) = in[r][0..K) B;  ACC true: out[r][n] += (in[r] B)[n].
+// The K steps run in chunks of CH whose operands are loaded together.
+template <typename T, typename V, bool ACC, int CH>
+__global__ __launch_bounds__(64 * kMfmaWaves) void k_xfer_mfma(int64_t R, int K, int N, const V* __restrict__ in,
+                                                              const V* __restrict__ B, V* __restrict__ out) {
+  chain_priority();
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int K2 = 2 * K, N2 = 2 * N;
+  const int nut = (N2 + 15) >> 4;
+  const int64_t g = (int64_t)blockIdx.x * kMfmaWaves + (threadIdx.x >> 6);
+  const int64_t row0 = (g / nut) * 16;
+  const int u = (int)(g % nut);
+  if (row0 >= R) return;  // wavefront-uniform
+  const int ks = (K2 + 3) >> 2;
+  const int64_t r = row0 + li;
+  const bool rok = r < R;
+  const T* src = reinterpret_cast<const T*>(in);
+  const int nn = 16 * u + li;  // this lane's B' column and result column
+  const bool nok = nn < N2;
+  const int n = nn >> 1, bpart = nn & 1;
+  const T* Bs = reinterpret_cast<const T*>(B);
+  typename Mfma<T>::acc acc = {T(0), T(0), T(0), T(0)};
+  for (int s0 = 0; s0 < ks; s0 += CH) {
+    T a[CH], b[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      a[q] = T(0);
+      b[q] = T(0);
+      const int kk = 4 * (s0 + q) + lq;
+      if (kk < K2) {
+        if (rok) a[q] = src[r * K2 + kk];
+        if (nok) {
+          const int apart = kk & 1;
+          const T e = Bs[2 * ((kk >> 1) * N + n) + (apart != bpart)];
+          b[q] = (apart && !bpart) ? -e : e;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      if (s0 + q < ks) acc = Mfma<T>::op(a[q], b[q], acc);  // uniform condition
+  }
+  if (nok) {
+    T* o = reinterpret_cast<T*>(out);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t rr = row0 + Mfma<T>::row(lq, v);
+      if (rr < R) {
+        if (ACC)
+          o[rr * N2 + nn] += acc[v];
+        else
+          o[rr * N2 + nn] = acc[v];
+      }
+    }
+  }
+}
+
+// Host side: the matrix-core form of a rows-times-table transfer product.
+template <typename T, typename V, bool ACC>
+void xfer_mfma(int64_t R, int K, int N, const V* in, const V* B, V* out, hipStream_t st) {
+  const int64_t waves = ((R + 15) / 16) * ((2 * N + 15) / 16);
+  const dim3 grid((unsigned)((waves + kMfmaWaves - 1) / kMfmaWaves));
+  hipLaunchKernelGGL((k_xfer_mfma<T, V, ACC, 16>), grid, dim3(64 * kMfmaWaves), 0, st, R, K, N, in, B, out);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers ---
@@ -623,16 +742,18 @@ void ensure_legendre_factors() {
     leg_ready[dev] = true;
   }
 }
-void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
-                       int nu, const double2* cfac, double k, const double* ra, const double* rb,
-                       const double* rw, int nq, double2* T64, float2* T32, hipStream_t st) {
+void launch_fmm_leaf_T(int64_t N, const double* geom, const int64_t* qidx, const double* hq, int64_t nh,
+                       const int64_t* ec, const double* zc, const double* s, int nu, const double2* cfac, double k,
+                       const double* ra, const double* rb, const double* rw, int nq, double2* T64, float2* T32,
+                       hipStream_t st) {
   if (N <= 0 || nu <= 0) return;
+  if (nh == 0) qidx = nullptr;
   if (T64)
-    hipLaunchKernelGGL(k_leaf_T<false>, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac,
-                       k, ra, rb, rw, nq, T64, nullptr);
+    hipLaunchKernelGGL(k_leaf_T<false>, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, qidx, hq, nh,
+                       ec, zc, s, nu, cfac, k, ra, rb, rw, nq, T64, nullptr);
   if (T32)
-    hipLaunchKernelGGL(k_leaf_T<true>, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, ec, zc, s, nu, cfac,
-                       k, ra, rb, rw, nq, nullptr, T32);
+    hipLaunchKernelGGL(k_leaf_T<true>, dim3(nblk(nu, 256), (unsigned)N), dim3(256), 0, st, N, geom, qidx, hq, nh,
+                       ec, zc, s, nu, cfac, k, ra, rb, rw, nq, nullptr, T32);
 }
 
 void launch_fmm_leaf_S(int64_t N, const double* geom, const int64_t* ec, const double* zc, const double* s,
@@ -732,6 +853,10 @@ void launch_fmm_dft(int64_t nc, int nt, int nj, int nm, const V* in, const V* sh
   const dim3 grid((unsigned)((nt + kXferRows - 1) / kXferRows), (unsigned)nc);
   const int rl = (nj + 1) & ~1;
   const size_t rows = kXferRows * (size_t)rl * sizeof(V), tab = (size_t)nj * nm * sizeof(V);
+  if (mode == 0 && tab > kXferTab) {  // matrix cores where the table cannot be staged
+    xfer_mfma<T, V, false>(nc * nt, nj, nm, in, Et, out, st);
+    return;
+  }
   if (tab <= kXferTab && (int64_t)grid.x * nc >= kXferMinBlocks)
     hipLaunchKernelGGL((k_dft<T, V, true>), grid, dim3(256), rows + tab, st, nt, nj, nm, rl, in, shift, parent, mode,
                        Et, out);
@@ -777,6 +902,10 @@ void launch_fmm_down_idft(int64_t nc, int nt, int nj, int nm, const V* K, const 
   const dim3 grid((unsigned)((nt + kXferRows - 1) / kXferRows), (unsigned)nc);
   const int rl = (nm + 1) & ~1;
   const size_t rows = kXferRows * (size_t)rl * sizeof(V), tab = (size_t)nm * nj * sizeof(V);
+  if (tab > kXferTab) {  // matrix cores where the table cannot be staged
+    xfer_mfma<T, V, true>(nc * nt, nm, nj, K, E, locc, st);
+    return;
+  }
   if (tab <= kXferTab && (int64_t)grid.x * nc >= kXferMinBlocks) {
     hipLaunchKernelGGL((k_down_idft<T, V, true>), grid, dim3(256), rows + tab, st, nt, nj, nm, rl, K, E, locc);
   } else {

@@ -665,7 +665,7 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
         L.T64.alloc(m->N * L.nu);
         L.S64.alloc(m->N * L.nu);
       }
-      launch_fmm_leaf_T(m->N, m->d_geom.p, L.ec.p, L.z.p, L.s.p, L.nu, nullptr, k, FS->ra.p, FS->rb.p, FS->rw.p,
+      launch_fmm_leaf_T(m->N, m->d_geom.p, m->d_qidx.p, m->d_hq.p, 2 * m->g.nq, L.ec.p, L.z.p, L.s.p, L.nu, nullptr, k, FS->ra.p, FS->rb.p, FS->rw.p,
                         FS->nq, single ? nullptr : L.T64.p, single ? L.T32.p : nullptr, s);
       launch_fmm_leaf_S(m->N, m->d_geom.p, L.ec.p, L.z.p, L.s.p, L.w.p, L.nu, k, m->gre, m->gim,
                         single ? nullptr : L.S64.p, single ? L.S32.p : nullptr, s);
@@ -681,7 +681,7 @@ void setup_set(bem_mesh* m, FmmState* FS, int si, hipStream_t s) {
     F->T64.alloc(m->N * leaf.nu);
     F->S64.alloc(m->N * leaf.nu);
   }
-  launch_fmm_leaf_T(m->N, m->d_geom.p, FS->elem_cluster.p, leaf.z.p, leaf.s.p, leaf.nu, nullptr, k, FS->ra.p, FS->rb.p,
+  launch_fmm_leaf_T(m->N, m->d_geom.p, m->d_qidx.p, m->d_hq.p, 2 * m->g.nq, FS->elem_cluster.p, leaf.z.p, leaf.s.p, leaf.nu, nullptr, k, FS->ra.p, FS->rb.p,
                     FS->rw.p, FS->nq, single ? nullptr : F->T64.p, single ? F->T32.p : nullptr, s);
   launch_fmm_leaf_S(m->N, m->d_geom.p, FS->elem_cluster.p, leaf.z.p, leaf.s.p, leaf.w.p, leaf.nu, k, m->gre,
                     m->gim, single ? nullptr : F->S64.p, single ? F->S32.p : nullptr, s);

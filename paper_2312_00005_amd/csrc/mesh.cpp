@@ -1,8 +1,9 @@
 // Host-side, frequency-independent setup: element geometry, the cluster tree
 // with near and interaction lists, and the near-field quadrature plan.
 //
-// Geometry (Sec. 2.2-2.3, mesh appendix): flat triangles, centroid = vertex
-// mean, unit normal from the counter-clockwise vertex order, area.
+// Geometry (Sec. 2.2-2.3, mesh appendix): flat triangles and plane
+// quadrilaterals, collocation node = vertex mean, unit normal from the
+// counter-clockwise vertex order, area.
 //
 // Cluster tree (Sec. 3.3.2-3.3.4), as read here:
 //  * A group of elements is split by putting a box around its vertices and
@@ -24,9 +25,11 @@
 //    children of its parent's near clusters, far ones form its interaction
 //    list and the rest its near list.  Near pairs exist on the leaf level.
 //
-// Near-field plan (Sec. 3.1.3-3.1.4): for every near pair (i, j), i != j, the
-// element is split into four through its edge midpoints while
-// r~ = |x_i - mid| / sqrt(A) < ratio; otherwise the order m is the smallest
+// Near-field plan (Sec. 3.1.3-3.1.4): for every near pair (i, j), i != j, and
+// every integration triangle of j (the element itself, or the two halves of
+// a quadrilateral, each with its own midpoint and area), the triangle is
+// split into four through its edge midpoints while r~ = |x_i - mid| / sqrt(A)
+// < ratio; otherwise the order m is the smallest
 // with the three a-priori estimates below eps; an order above m_max is capped
 // or, with split_on_cap, split once more.  More than max_subdiv nested splits
 // is an error naming the element.
@@ -38,34 +41,108 @@
 
 namespace bem {
 
-Geometry build_geometry(const double* xyz, int64_t n_nodes, const int32_t* tri,
-                        int64_t n_tri, const std::vector<int64_t>& perm) {
+Geometry build_geometry(const double* xyz, int64_t n_nodes, const int32_t* el,
+                        int64_t n_el, const std::vector<int64_t>& perm) {
   Geometry g;
-  g.N = n_tri;
-  g.f.assign(size_t(G_NFIELDS) * n_tri, 0.0);
-  for (int64_t t = 0; t < n_tri; ++t) {
+  g.N = n_el;
+  g.f.assign(size_t(G_NFIELDS) * n_el, 0.0);
+  std::vector<int64_t> quads;  // tree positions of the quadrilaterals
+  for (int64_t t = 0; t < n_el; ++t) {
     int64_t e = perm[t];
-    const int32_t* v = tri + 3 * e;
-    for (int c = 0; c < 3; ++c)
+    const int32_t* v = el + 4 * e;
+    const int nv = v[3] >= 0 ? 4 : 3;
+    for (int c = 0; c < nv; ++c)
       if (v[c] < 0 || v[c] >= n_nodes)
-        throw Error(BEM_E_ARG, "triangle " + std::to_string(e) + " has a node index out of range", e);
+        throw Error(BEM_E_ARG, "element " + std::to_string(e) + " has a node index out of range", e);
     const double* a = xyz + 3 * v[0];
     const double* b = xyz + 3 * v[1];
     const double* c = xyz + 3 * v[2];
-    double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-    double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
-    double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    if (nv == 3) {
+      double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+      double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+      double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+      double nrm = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      if (!(nrm > 0.0) || !std::isfinite(nrm))
+        throw Error(BEM_E_MESH, "triangle " + std::to_string(e) + " has zero or invalid area", e);
+      for (int d = 0; d < 3; ++d) {
+        g.at(G_P0X + d, t) = a[d];
+        g.at(G_P1X + d, t) = b[d];
+        g.at(G_P2X + d, t) = c[d];
+        g.at(G_NX + d, t) = cr[d] / nrm;
+        g.at(G_CX + d, t) = (a[d] + b[d] + c[d]) / 3.0;
+      }
+      g.at(G_AREA, t) = 0.5 * nrm;
+      continue;
+    }
+    const double* q = xyz + 3 * v[3];
+    double d1[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double d2[3] = {q[0] - b[0], q[1] - b[1], q[2] - b[2]};
+    double cr[3] = {d1[1] * d2[2] - d1[2] * d2[1], d1[2] * d2[0] - d1[0] * d2[2], d1[0] * d2[1] - d1[1] * d2[0]};
     double nrm = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
     if (!(nrm > 0.0) || !std::isfinite(nrm))
-      throw Error(BEM_E_MESH, "triangle " + std::to_string(e) + " has zero or invalid area", e);
+      throw Error(BEM_E_MESH, "quadrilateral " + std::to_string(e) + " has zero or invalid area", e);
+    double n[3] = {cr[0] / nrm, cr[1] / nrm, cr[2] / nrm}, mid[3];
+    for (int d = 0; d < 3; ++d) mid[d] = 0.25 * (a[d] + b[d] + c[d] + q[d]);
+    // plane: every vertex within 1e-8 of the longer diagonal from the mean plane
+    const double diag = std::sqrt(std::max(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2],
+                                           d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]));
+    for (const double* p : {a, b, c, q}) {
+      const double off = (p[0] - mid[0]) * n[0] + (p[1] - mid[1]) * n[1] + (p[2] - mid[2]) * n[2];
+      if (std::fabs(off) > 1e-8 * diag)
+        throw Error(BEM_E_MESH, "quadrilateral " + std::to_string(e) + " is not plane", e);
+    }
+    // convex and counter-clockwise about n: every corner turns the same way
+    const double* P[4] = {a, b, c, q};
+    for (int k = 0; k < 4; ++k) {
+      const double* p0 = P[k];
+      const double* p1 = P[(k + 1) % 4];
+      const double* p2 = P[(k + 2) % 4];
+      double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+      double w[3] = {p2[0] - p1[0], p2[1] - p1[1], p2[2] - p1[2]};
+      double x[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+      if (!(x[0] * n[0] + x[1] * n[1] + x[2] * n[2] > 0.0))
+        throw Error(BEM_E_MESH, "quadrilateral " + std::to_string(e) + " is not convex", e);
+    }
     for (int d = 0; d < 3; ++d) {
       g.at(G_P0X + d, t) = a[d];
       g.at(G_P1X + d, t) = b[d];
       g.at(G_P2X + d, t) = c[d];
-      g.at(G_NX + d, t) = cr[d] / nrm;
-      g.at(G_CX + d, t) = (a[d] + b[d] + c[d]) / 3.0;
+      g.at(G_NX + d, t) = n[d];
+      g.at(G_CX + d, t) = mid[d];
     }
     g.at(G_AREA, t) = 0.5 * nrm;
+    quads.push_back(t);
+  }
+  if (quads.empty()) return g;
+  g.nq = (int64_t)quads.size();
+  const int64_t nh = 2 * g.nq;
+  g.qidx.assign(n_el, -1);
+  g.hown.resize(nh);
+  g.hq.assign(size_t(G_NFIELDS) * nh, 0.0);
+  for (int64_t qi = 0; qi < g.nq; ++qi) {
+    const int64_t t = quads[qi];
+    g.qidx[t] = qi;
+    const int32_t* v = el + 4 * perm[t];
+    const int32_t tri[2][3] = {{v[0], v[1], v[2]}, {v[0], v[2], v[3]}};
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r = 2 * qi + h;
+      g.hown[r] = t;
+      const double* a = xyz + 3 * tri[h][0];
+      const double* b = xyz + 3 * tri[h][1];
+      const double* c = xyz + 3 * tri[h][2];
+      double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+      double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+      double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+      const double nrm = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      for (int d = 0; d < 3; ++d) {
+        g.hq[(G_P0X + d) * nh + r] = a[d];
+        g.hq[(G_P1X + d) * nh + r] = b[d];
+        g.hq[(G_P2X + d) * nh + r] = c[d];
+        g.hq[(G_NX + d) * nh + r] = g.at(G_NX + d, t);
+        g.hq[(G_CX + d) * nh + r] = (a[d] + b[d] + c[d]) / 3.0;
+      }
+      g.hq[G_AREA * nh + r] = 0.5 * nrm;
+    }
   }
   return g;
 }
@@ -80,17 +157,20 @@ struct Group {
 
 void group_stats(const Geometry& g, Group& G) {
   double s[3] = {0, 0, 0};
-  for (int64_t e : G.e)
-    for (int v = 0; v < 3; ++v)
-      for (int d = 0; d < 3; ++d) s[d] += g.at(G_P0X + 3 * v + d, e);
-  double cnt = 3.0 * double(G.e.size());
+  double cnt = 0.0;
+  for (int64_t e : G.e) {
+    const int nv = g.nv(e);
+    for (int v = 0; v < nv; ++v)
+      for (int d = 0; d < 3; ++d) s[d] += g.vtx(v, d, e);
+    cnt += nv;
+  }
   for (int d = 0; d < 3; ++d) G.z[d] = s[d] / cnt;
   double r2 = 0.0;
   for (int64_t e : G.e)
-    for (int v = 0; v < 3; ++v) {
-      double dx = g.at(G_P0X + 3 * v, e) - G.z[0];
-      double dy = g.at(G_P0X + 3 * v + 1, e) - G.z[1];
-      double dz = g.at(G_P0X + 3 * v + 2, e) - G.z[2];
+    for (int v = 0; v < g.nv(e); ++v) {
+      double dx = g.vtx(v, 0, e) - G.z[0];
+      double dy = g.vtx(v, 1, e) - G.z[1];
+      double dz = g.vtx(v, 2, e) - G.z[2];
       double q = dx * dx + dy * dy + dz * dz;
       if (q > r2) r2 = q;
     }
@@ -100,9 +180,9 @@ void group_stats(const Geometry& g, Group& G) {
 std::vector<Group> split_group(const Geometry& g, const std::vector<int64_t>& elems, double edge) {
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t e : elems)
-    for (int v = 0; v < 3; ++v)
+    for (int v = 0; v < g.nv(e); ++v)
       for (int d = 0; d < 3; ++d) {
-        double c = g.at(G_P0X + 3 * v + d, e);
+        double c = g.vtx(v, d, e);
         lo[d] = std::min(lo[d], c);
         hi[d] = std::max(hi[d], c);
       }
@@ -381,7 +461,8 @@ NearPlan build_near_plan(const Geometry& g, const QuadParams& q,
   if (q.max_subdiv > 15) throw Error(BEM_E_ARG, "max_subdiv above 15 is not supported");
   if (q.m_max > 8 || q.m_max < 1) throw Error(BEM_E_ARG, "quad_m_max must be in [1, 8]");
   int64_t N = g.N;
-  if (N >= (int64_t(1) << 26)) throw Error(BEM_E_ARG, "too many elements for the packed plan");
+  const int64_t nh = 2 * g.nq;
+  if (N + nh >= (int64_t(1) << 26)) throw Error(BEM_E_ARG, "too many elements for the packed plan");
   std::vector<std::vector<uint64_t>> per(N);
   std::vector<int64_t> pts(N, 0), npairs(N, 0), bad(N, -1);
   std::vector<int> mm(N, 1);
@@ -401,11 +482,23 @@ NearPlan build_near_plan(const Geometry& g, const QuadParams& q,
       for (int64_t j = src_beg[s]; j < src_end[s]; ++j) {
         ++npairs[t];
         if (j == t) continue;
-        C.j = j;
-        double v0[3] = {g.at(G_P0X, j), g.at(G_P0Y, j), g.at(G_P0Z, j)};
-        double v1[3] = {g.at(G_P1X, j), g.at(G_P1Y, j), g.at(G_P1Z, j)};
-        double v2[3] = {g.at(G_P2X, j), g.at(G_P2Y, j), g.at(G_P2Z, j)};
-        plan_rec(C, v0, v1, v2, g.at(G_AREA, j), 0, 0);
+        if (!g.is_quad(j)) {
+          C.j = j;
+          double v0[3] = {g.at(G_P0X, j), g.at(G_P0Y, j), g.at(G_P0Z, j)};
+          double v1[3] = {g.at(G_P1X, j), g.at(G_P1Y, j), g.at(G_P1Z, j)};
+          double v2[3] = {g.at(G_P2X, j), g.at(G_P2Y, j), g.at(G_P2Z, j)};
+          plan_rec(C, v0, v1, v2, g.at(G_AREA, j), 0, 0);
+          continue;
+        }
+        // a quadrilateral: its two integration triangles, each with its own r~
+        for (int h = 0; h < 2; ++h) {
+          const int64_t r = 2 * g.qidx[j] + h;
+          C.j = N + r;
+          double v[3][3];
+          for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) v[a][d] = g.hq[(G_P0X + 3 * a + d) * nh + r];
+          plan_rec(C, v[0], v[1], v[2], g.hq[G_AREA * nh + r], 0, 0);
+        }
       }
     }
     // group items by order so that a wavefront mostly runs one rule
@@ -417,9 +510,11 @@ NearPlan build_near_plan(const Geometry& g, const QuadParams& q,
     bad[t] = C.bad;
   }
   for (int64_t t = 0; t < N; ++t)
-    if (bad[t] >= 0)
+    if (bad[t] >= 0) {
+      const int64_t e = g.owner(bad[t]);
       throw Error(BEM_E_MESH, "more than max_subdiv nested subdivisions (element at tree position " +
-                                  std::to_string(bad[t]) + ")", bad[t]);
+                                  std::to_string(e) + ")", e);
+    }
   NearPlan P;
   P.off.assign(N + 1, 0);
   for (int64_t t = 0; t < N; ++t) {

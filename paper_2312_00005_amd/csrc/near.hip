@@ -183,6 +183,23 @@ __device__ inline void item_triangle(const T* __restrict__ g, int64_t N, int64_t
   }
 }
 
+// The same for integration record j: the elements' own triangles (j < N) or
+// the halves of the quadrilaterals (geometry hq, stride nh).
+template <typename T>
+__device__ inline void rec_triangle(const T* __restrict__ g, int64_t N, const T* __restrict__ hq, int64_t nh,
+                                    int64_t j, int depth, uint64_t path, T v0[3], T v1[3], T v2[3]) {
+  if (j < N) item_triangle<T>(g, N, j, depth, path, v0, v1, v2);
+  else item_triangle<T>(hq, nh, j - N, depth, path, v0, v1, v2);
+}
+// field f of integration record j
+template <typename T>
+__device__ inline T rec_field(const T* __restrict__ g, int64_t N, const T* __restrict__ hq, int64_t nh, int f,
+                              int64_t j) {
+  return j < N ? g[f * N + j] : hq[f * nh + (j - N)];
+}
+// element of integration record j
+__device__ inline int64_t rec_owner(const QuadRecs& Q, int64_t N, int64_t j) { return j < N ? j : Q.hown[j - N]; }
+
 // Source-element records (built per wavenumber by k_records): 16 values per
 // element, all lengths multiplied by kap, the phase unit per length (k for
 // radians in FP64, k/(2 pi) for revolutions in FP32):
@@ -467,8 +484,9 @@ __device__ inline void load_slot(const NearLaunch& L, const T* __restrict__ rec,
   const int64_t j = (int64_t)(item & ((uint64_t(1) << 26) - 1));
   S.item = item;
   Rec<T>::load(rec, j, S.r);
-  S.x = x[j];
-  if (NEED_C) S.c = L.cfac[j];
+  const int64_t o = rec_owner(L.Q, L.N, j);  // the element whose unknown the record carries
+  S.x = x[o];
+  if (NEED_C) S.c = L.cfac[o];
 }
 // acc += K_ij x_j (VMODE: the dA/dc entry) for the slot's item
 template <typename T, bool HAS_C, bool VMODE>
@@ -573,6 +591,8 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
     ci = (T)c.y;
   }
   T accr = 0, acci = 0;
+  // a quadrilateral's items name their half in bit 63
+  const int64_t qj = L.Q.nh ? L.Q.qidx[jsrc] : -1;
   const int64_t* sg = L.seg + jsrc * (kMaxRuleOrder + 1);
   for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
     const int64_t b = sg[mc], e = sg[mc + 1];
@@ -580,8 +600,9 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
     for (int64_t it = b + lane; it < e; it += 64) {
       const uint64_t raw = L.items[it];
       const int64_t i = (int64_t)(raw & ((uint64_t(1) << 26) - 1));
-      // rebuild the forward item (source jsrc) and integrate from target i
-      const uint64_t item = (raw & ~((uint64_t(1) << 26) - 1)) | (uint64_t)jsrc;
+      // rebuild the forward item (source record of jsrc) and integrate from target i
+      const int64_t recj = qj >= 0 ? N + 2 * qj + (int64_t)(raw >> 63) : jsrc;
+      const uint64_t item = (raw & ~((uint64_t(1) << 26) - 1) & ~(uint64_t(1) << 63)) | (uint64_t)recj;
       T xs[3], ni[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -647,8 +668,8 @@ void near_dispatch(const NearLaunch& L, const T* g, const double2* x, double2* y
 // ------------------------------------------------------ element records ---
 // Records of the integration kernels (layout at Rec above), FP64 with scale
 // kap and FP32 with scale kap32; the scaled quantities are formed in FP64.
-__global__ __launch_bounds__(256) void k_records(int64_t N, const double* __restrict__ g, double kap,
-                                                 double kap32, double* __restrict__ rec,
+__global__ __launch_bounds__(256) void k_records(int64_t N, const double* __restrict__ g, int64_t first,
+                                                 double kap, double kap32, double* __restrict__ rec,
                                                  float* __restrict__ rec32) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
@@ -676,47 +697,39 @@ __global__ __launch_bounds__(256) void k_records(int64_t N, const double* __rest
     r[14] = 2.0 * (f1[0] * f2[0] + f1[1] * f2[1] + f1[2] * f2[2]);
     r[15] = 2.0 * area * s * s;
     for (int q = 0; q < kRec; ++q) {
-      if (p == 0) rec[kRec * t + q] = r[q];
-      else rec32[kRec * t + q] = (float)r[q];
+      if (p == 0) rec[kRec * (first + t) + q] = r[q];
+      else rec32[kRec * (first + t) + q] = (float)r[q];
     }
   }
 }
 
 // ------------------------------------------------------------ self terms ---
-// G_ii by the six-triangle Duffy rule (Sec. 3.1.1); E_ii = sum over the
-// counter-clockwise edges of int (n x grad_y G) . dy plus k^2 G_ii
-// (Sec. 3.1.2); H_ii = H'_ii = 0.  Then
+// G_ii by the Duffy rule on the sub-triangles that join the collocation node
+// to the vertices and edge midpoints (Sec. 3.1.1: six on a triangle, eight on
+// a quadrilateral); E_ii = sum over the counter-clockwise edges of
+// int (n x grad_y G) . dy plus k^2 G_ii (Sec. 3.1.2); H_ii = H'_ii = 0.  Then
 // A_ii = (1 - gamma c_i)/2 + gamma E_ii + G_ii c_i.
-__global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict__ diag) {
-  // one wavefront per element; lanes share the element's quadrature points
-  // (the six Duffy triangles' self_n^2 points each, then the edge points)
-  const int lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (t >= L.N) return;
-  const int64_t N = L.N;
-  const double* g = L.geom;
-  double P[3][3], x[3], n[3];
-  for (int v = 0; v < 3; ++v)
-    for (int c = 0; c < 3; ++c) P[v][c] = g[(P0X + 3 * v + c) * N + t];
-  for (int c = 0; c < 3; ++c) {
-    x[c] = g[(CX + c) * N + t];
-    n[c] = g[(NX + c) * N + t];
-  }
+// Duffy and edge sums of one element with NV vertices P (lanes share the points)
+template <int NV>
+__device__ inline void self_sums(const SelfLaunch& L, const double (&P)[4][3], const double x[3], const double n[3],
+                                 int lane, double& Gr, double& Gi, double& Er, double& Ei) {
   const double k = L.k;
-  double M[3][3];
-  for (int c = 0; c < 3; ++c) {
-    M[0][c] = 0.5 * (P[0][c] + P[1][c]);
-    M[1][c] = 0.5 * (P[1][c] + P[2][c]);
-    M[2][c] = 0.5 * (P[2][c] + P[0][c]);
-  }
-  // Duffy triangles (V[h], V[h + 1]) with V = P0, M01, P1, M12, P2, M20
-  const double* V[6] = {P[0], M[0], P[1], M[1], P[2], M[2]};
-  const int nn2 = L.self_n * L.self_n;
-  double Gr = 0, Gi = 0, Er = 0, Ei = 0;
+  double M[NV][3];
 #pragma unroll
-  for (int h = 0; h < 6; ++h) {
+  for (int e = 0; e < NV; ++e)
+    for (int c = 0; c < 3; ++c) M[e][c] = 0.5 * (P[e][c] + P[(e + 1) % NV][c]);
+  // Duffy triangles (V[h], V[h + 1]) with V = P0, M01, P1, M12, P2, ...
+  const double* V[2 * NV];
+#pragma unroll
+  for (int e = 0; e < NV; ++e) {
+    V[2 * e] = P[e];
+    V[2 * e + 1] = M[e];
+  }
+  const int nn2 = L.self_n * L.self_n;
+#pragma unroll
+  for (int h = 0; h < 2 * NV; ++h) {
     const double* Q1 = V[h];
-    const double* Q2 = V[(h + 1) % 6];
+    const double* Q2 = V[(h + 1) % (2 * NV)];
     double a[3], b[3], d[3];
     for (int c = 0; c < 3; ++c) {
       a[c] = Q1[c] - x[c];
@@ -741,9 +754,9 @@ __global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict_
   }
   // edges P_e -> P_(e+1): (n x R) . d with grad_y G = G (ik - 1/r) R / r
 #pragma unroll
-  for (int e = 0; e < 3; ++e) {
+  for (int e = 0; e < NV; ++e) {
     const double* Pa = P[e];
-    const double* Pb = P[(e + 1) % 3];
+    const double* Pb = P[(e + 1) % NV];
     double d[3];
     for (int c = 0; c < 3; ++c) d[c] = Pb[c] - Pa[c];
     for (int q = lane; q < L.edge_pts; q += 64) {
@@ -761,6 +774,32 @@ __global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict_
       Ei += s * (cs * k - sn * rinv);
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_self(SelfLaunch L, double2* __restrict__ diag) {
+  // one wavefront per element; lanes share the element's quadrature points
+  // (the Duffy triangles' self_n^2 points each, then the edge points)
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (t >= L.N) return;
+  const int64_t N = L.N;
+  const double* g = L.geom;
+  const int64_t q = L.Q.nh ? L.Q.qidx[t] : -1;
+  double P[4][3], x[3], n[3];
+  for (int v = 0; v < 3; ++v)
+    for (int c = 0; c < 3; ++c) P[v][c] = g[(P0X + 3 * v + c) * N + t];
+  // a quadrilateral's P3 is the last vertex of its second half
+  for (int c = 0; c < 3; ++c) P[3][c] = q >= 0 ? L.Q.hq[(P2X + c) * L.Q.nh + 2 * q + 1] : P[2][c];
+  for (int c = 0; c < 3; ++c) {
+    x[c] = g[(CX + c) * N + t];
+    n[c] = g[(NX + c) * N + t];
+  }
+  const double k = L.k;
+  double Gr = 0, Gi = 0, Er = 0, Ei = 0;
+  if (q >= 0)  // wavefront-uniform
+    self_sums<4>(L, P, x, n, lane, Gr, Gi, Er, Ei);
+  else
+    self_sums<3>(L, P, x, n, lane, Gr, Gi, Er, Ei);
   Gr = wave_sum(Gr);
   Gi = wave_sum(Gi);
   Er = wave_sum(Er);
@@ -795,6 +834,9 @@ __device__ inline const float* far_geom<float>(const FarLaunch& F) { return F.ge
 template <typename T> __device__ inline const T* far_rec(const FarLaunch& F);
 template <> __device__ inline const double* far_rec<double>(const FarLaunch& F) { return F.rec; }
 template <> __device__ inline const float* far_rec<float>(const FarLaunch& F) { return F.rec32; }
+template <typename T> __device__ inline const T* far_hq(const FarLaunch& F);
+template <> __device__ inline const double* far_hq<double>(const FarLaunch& F) { return F.Q.hq; }
+template <> __device__ inline const float* far_hq<float>(const FarLaunch& F) { return F.Q.hq32; }
 template <typename T> __device__ inline double far_kap(const FarLaunch& F);
 template <> __device__ inline double far_kap<double>(const FarLaunch& F) { return F.kap; }
 template <> __device__ inline double far_kap<float>(const FarLaunch& F) { return F.kap32; }
@@ -811,21 +853,23 @@ __device__ inline int far_order(const FarLaunch& F, double d2, double area) {
   return F.split_on_cap ? 0 : F.m_max;
 }
 
-// One (collocation i, element j) pair that needs subdivision: depth-first walk
-// over (depth, path) without a stack, per-sub-triangle rule as in the plan.
-// The rule choice uses the unscaled geometry g, the integration the records.
+// One (collocation i, integration record j) pair that needs subdivision:
+// depth-first walk over (depth, path) without a stack, per-sub-triangle rule
+// as in the plan.  The rule choice uses the unscaled geometry (g, or the
+// quadrilaterals' halves), the integration the records.
 template <typename T, bool WANT_S1, bool WANT_S2>
 __device__ void far_pair_split(const FarLaunch& F, const T* g, const T* rec, int64_t j, const T xi[3],
                                const T xs[3], const T ni[3], const PointConsts<T>& P, T& s1r, T& s1i, T& s2r,
                                T& s2i) {
   const int64_t N = F.N;
-  const double area0 = (double)g[AREA * N + j];
+  const T* hq = far_hq<T>(F);
+  const double area0 = (double)rec_field<T>(g, N, hq, F.Q.nh, AREA, j);
   int depth = 0;
   uint64_t path = 0;
   s1r = s1i = s2r = s2i = T(0);
   for (;;) {
     T v0[3], v1[3], v2[3];
-    item_triangle<T>(g, N, j, depth, path, v0, v1, v2);
+    rec_triangle<T>(g, N, hq, F.Q.nh, j, depth, path, v0, v1, v2);
     double d2 = 0.0;
     for (int c = 0; c < 3; ++c) {
       const double dc = (double)xi[c] - ((double)v0[c] + (double)v1[c] + (double)v2[c]) / 3.0;
@@ -903,27 +947,39 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
         ni[c] = ADJ ? g[(NX + c) * N + i] : nr[c];
         xs[c] = ADJ ? (T)(kap * F.geom[(CX + c) * N + i]) : xsr[c];
       }
-      int m = -1;
-      if (valid) {
-        double d2 = 0.0;
-        for (int c = 0; c < 3; ++c) {
-          const double dc = (double)xi[c] - (double)g[(CX + c) * N + j];
-          d2 += dc * dc;
-        }
-        m = far_order<T>(F, d2, (double)g[AREA * N + j]);
-      }
+      // the element's integration records: itself, or a quadrilateral's halves
+      const int64_t qj = (valid && F.Q.nh) ? F.Q.qidx[j] : -1;
       T s1r = 0, s1i = 0, s2r = 0, s2i = 0;
-      // one uniform rule per pass
-      for (int mc = 1; mc <= kMaxRuleOrder; ++mc) {
-        if (__ballot(m == mc) == 0) continue;
-        if (m == mc) {
-          int64_t jj;
-          integrate_item<T, !VMODE, HAS_C || VMODE, true>(rec, (uint64_t)j, mc, xs, ni, P, s1r, s1i, s2r, s2i,
-                                                         jj);
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && __ballot(qj >= 0) == 0) break;
+        const int64_t rj = qj >= 0 ? F.N + 2 * qj + h : j;
+        const bool act = valid && (h == 0 || qj >= 0);
+        int m = -1;
+        if (act) {
+          double d2 = 0.0;
+          for (int c = 0; c < 3; ++c) {
+            const double dc = (double)xi[c] - (double)rec_field<T>(g, N, far_hq<T>(F), F.Q.nh, CX + c, rj);
+            d2 += dc * dc;
+          }
+          m = far_order<T>(F, d2, (double)rec_field<T>(g, N, far_hq<T>(F), F.Q.nh, AREA, rj));
         }
+        T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+        // one uniform rule per pass
+        for (int mc = 1; mc <= kMaxRuleOrder; ++mc) {
+          if (__ballot(m == mc) == 0) continue;
+          if (m == mc) {
+            int64_t jj;
+            integrate_item<T, !VMODE, HAS_C || VMODE, true>(rec, (uint64_t)rj, mc, xs, ni, P, a1r, a1i, a2r, a2i,
+                                                           jj);
+          }
+        }
+        if (__ballot(m == 0) != 0 && m == 0)
+          far_pair_split<T, !VMODE, HAS_C || VMODE>(F, g, rec, rj, xi, xs, ni, P, a1r, a1i, a2r, a2i);
+        s1r += a1r;
+        s1i += a1i;
+        s2r += a2r;
+        s2i += a2i;
       }
-      if (__ballot(m == 0) != 0 && m == 0)
-        far_pair_split<T, !VMODE, HAS_C || VMODE>(F, g, rec, j, xi, xs, ni, P, s1r, s1i, s2r, s2i);
       if (!valid) continue;
       T vr = s1r, vi = s1i;
       if (VMODE) {
@@ -991,7 +1047,7 @@ __global__ __launch_bounds__(256) void k_block_assemble(NearLaunch L, BlockArgs 
       int64_t j = -1;
       bool in = false;
       if (it < e) {
-        j = (int64_t)(B.items[it] & ((uint64_t(1) << 26) - 1));
+        j = rec_owner(L.Q, N, (int64_t)(B.items[it] & ((uint64_t(1) << 26) - 1)));
         in = j >= b0 && j < b0 + n;
       }
       double vr = 0.0, vi = 0.0;
@@ -1047,19 +1103,19 @@ __device__ inline int field_order(double rt, double eps) {
   return 64;
 }
 
-// integrals (I^G, I^H) of element j seen from x; false on a subdivision overflow
-__device__ bool field_integrals(const FieldArgs& A, int64_t j, const double x[3], double2& IG, double2& IH) {
+// integrals (I^G, I^H) of integration record j (normal nj) seen from x,
+// added to gr, gi, hr, hi; false on a subdivision overflow
+__device__ bool field_record(const FieldArgs& A, int64_t j, const double nj[3], const double x[3], double& gr,
+                             double& gi, double& hr, double& hi) {
   const int64_t N = A.N;
   const double* g = A.geom;
-  const double nj[3] = {g[(NX + 0) * N + j], g[(NX + 1) * N + j], g[(NX + 2) * N + j]};
-  const double area0 = g[AREA * N + j];
+  const double area0 = rec_field<double>(g, N, A.Q.hq, A.Q.nh, AREA, j);
   const int max_depth = A.max_subdiv < 15 ? A.max_subdiv : 15;
   int depth = 0;
   uint64_t path = 0;
-  double gr = 0, gi = 0, hr = 0, hi = 0;
   for (;;) {
     double v0[3], v1[3], v2[3];
-    item_triangle<double>(g, N, j, depth, path, v0, v1, v2);
+    rec_triangle<double>(g, N, A.Q.hq, A.Q.nh, j, depth, path, v0, v1, v2);
     const double area = area0 * ldexp(1.0, -2 * depth);
     double d2 = 0.0;
     for (int c = 0; c < 3; ++c) {
@@ -1121,6 +1177,23 @@ __device__ bool field_integrals(const FieldArgs& A, int64_t j, const double x[3]
       --depth;
     }
     if (depth == 0) break;
+  }
+  return true;
+}
+
+// integrals (I^G, I^H) of element j seen from x (both halves of a
+// quadrilateral); false on a subdivision overflow
+__device__ bool field_integrals(const FieldArgs& A, int64_t j, const double x[3], double2& IG, double2& IH) {
+  const int64_t N = A.N;
+  const double* g = A.geom;
+  const double nj[3] = {g[(NX + 0) * N + j], g[(NX + 1) * N + j], g[(NX + 2) * N + j]};
+  double gr = 0, gi = 0, hr = 0, hi = 0;
+  const int64_t q = A.Q.nh ? A.Q.qidx[j] : -1;
+  if (q < 0) {
+    if (!field_record(A, j, nj, x, gr, gi, hr, hi)) return false;
+  } else {
+    for (int h = 0; h < 2; ++h)
+      if (!field_record(A, N + 2 * q + h, nj, x, gr, gi, hr, hi)) return false;
   }
   IG = make_double2(gr, gi);
   IH = make_double2(hr, hi);
@@ -1405,8 +1478,14 @@ void launch_near(const NearLaunch& L, bool fp64, bool adjoint, bool vmode, const
 
 void launch_records(int64_t N, const double* geom, double kap, double kap32, double* rec, float* rec32,
                     hipStream_t s) {
-  if (N <= 0) return;
-  hipLaunchKernelGGL(k_records, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, geom, kap, kap32, rec, rec32);
+  launch_records_at(N, geom, 0, kap, kap32, rec, rec32, s);
+}
+
+void launch_records_at(int64_t n, const double* geom, int64_t first, double kap, double kap32, double* rec,
+                       float* rec32, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, geom, first, kap, kap32, rec,
+                     rec32);
 }
 
 void launch_self_terms(const SelfLaunch& L, double2* diag, hipStream_t s) {

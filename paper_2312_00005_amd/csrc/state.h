@@ -12,6 +12,12 @@ struct FmmState;                                     // fmm_setup.cpp
 void fmm_destroy(FmmState* f);
 }  // namespace bem
 
+struct bem_mesh;
+namespace bem {
+// the quadrilateral records of a mesh as the kernels take them
+QuadRecs quad_recs(const bem_mesh* m);
+}  // namespace bem
+
 struct bem_mesh {
   bem_options opt{};
   int64_t N = 0;
@@ -25,6 +31,11 @@ struct bem_mesh {
 
   bem::DevBuf<double> d_geom;
   bem::DevBuf<float> d_geom32;
+  // plane quadrilaterals: element -> quadrilateral index, half -> element,
+  // halves' geometry (FP64, FP32); empty on triangle meshes
+  bem::DevBuf<int64_t> d_qidx, d_hown;
+  bem::DevBuf<double> d_hq;
+  bem::DevBuf<float> d_hq32;
   bem::DevBuf<int64_t> d_perm;
   bem::DevBuf<int64_t> d_off, d_off_t, d_seg, d_seg_t;
   bem::DevBuf<int32_t> d_order;    // targets by decreasing near-field work
