@@ -4,9 +4,11 @@ field) and GMRES solve on one MI355X.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1]
 
 A step is one application of the whole operator (near field, FMM far field,
-diagonal) to a seeded complex vector already resident in HBM, in the mixed
-(complex-FP32) path; the FP64 path is timed the same way and reported beside
-it, with one GMRES solve per precision.  Prints one JSON line.
+diagonal) to a seeded complex vector already resident in HBM, in FP64 (the
+paper's arithmetic: the headline value); the mixed path (complex-FP32
+operator) is timed the same way and reported beside it, with one GMRES solve
+per precision and the surface pressure's error against the oracle's LU
+solution.  Prints one JSON line.
 """
 
 import argparse
@@ -67,12 +69,16 @@ def parse():
     ap.add_argument("--streams", type=int, default=1,
                     help="concurrent frequencies in the sweep workload (only 1: concurrent host threads are disabled)")
     ap.add_argument("--profile-near-only", action="store_true",
-                    help="run only complex-FP32 near-field applications, then a 512 MiB copy "
-                         "that calibrates the HBM byte counters (for rocprofv3 --pmc runs)")
+                    help="run only near-field applications (precision --profile-prec), then a 512 MiB "
+                         "copy that calibrates the HBM byte counters (for rocprofv3 --pmc runs)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) "
                          "of --profile-near-only runs into the traffic record read by the bench")
-    ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json"))
+    ap.add_argument("--traffic-out", default=None,
+                    help="traffic record to write (default: the one of --profile-prec)")
+    ap.add_argument("--summarize-valu", nargs=2, metavar=("PMC_CSV", "OUT_MD"),
+                    help="per-kernel VALU instruction counts from a rocprofv3 --pmc run (SQ_INSTS_VALU, "
+                         "SQ_ACTIVE_INST_VALU, SQ_WAVES, GRBM_GUI_ACTIVE) as a markdown summary")
     ap.add_argument("--profile-far-only", action="store_true",
                     help="run only far-field (FMM) applications, then the calibration copy")
     ap.add_argument("--profile-prec", default="mixed", choices=("mixed", "fp64"),
@@ -92,7 +98,9 @@ def log(msg):
 NEAR_KERNEL = "k_near<float, false, false"
 NEAR_KERNEL64 = "k_near<double, false, false"
 CAL_BYTES = 512 * 2 ** 20
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json")
+# near-field traffic records per precision (complex FP32, FP64)
+TRAFFIC_FILES = {"mixed": os.path.join(ROOT, "profiles", "k_near_c2_sphere20480_traffic.json"),
+                 "fp64": os.path.join(ROOT, "profiles", "k_near_fp64_c2_sphere20480_traffic.json")}
 
 
 def kernel_source_hash():
@@ -106,11 +114,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def summarize_counters(fetch_csv, write_csv, out):
+def summarize_counters(fetch_csv, write_csv, out, prec="mixed"):
     """Per-dispatch averages of FETCH_SIZE / WRITE_SIZE (KiB) for the
-    near-field kernel and for the calibration copy, and the HBM bytes per
-    near-field launch scaled by the copy's measured/known ratio."""
+    near-field kernel of precision prec and for the calibration copy, and the
+    HBM bytes per near-field launch scaled by the copy's measured/known ratio."""
     import csv
+    kernel = NEAR_KERNEL if prec == "mixed" else NEAR_KERNEL64
+    out = out or TRAFFIC_FILES[prec]
 
     def per_kernel(path, counter):
         acc = {}
@@ -130,8 +140,8 @@ def summarize_counters(fetch_csv, write_csv, out):
             raise SystemExit(f"no dispatch matched in {sorted(d)[:8]}")
         return max(keys, key=lambda k: max(d[k]))
 
-    near_f = pick(fetch, lambda k: NEAR_KERNEL in k)
-    near_w = pick(write, lambda k: NEAR_KERNEL in k)
+    near_f = pick(fetch, lambda k: kernel in k)
+    near_w = pick(write, lambda k: kernel in k)
     cal_f = pick(fetch, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
     cal_w = pick(write, lambda k: "copy" in k.lower() or "elementwise" in k.lower())
     avg = lambda v: sum(v) / len(v)
@@ -145,9 +155,11 @@ def summarize_counters(fetch_csv, write_csv, out):
     fdir, wdir = rel(os.path.dirname(fetch_csv) or "."), rel(os.path.dirname(write_csv) or ".")
     f_scale = max(fetch[cal_f]) / CAL_BYTES
     w_scale = max(write[cal_w]) / CAL_BYTES
+    pflag = "" if prec == "mixed" else " --profile-prec fp64"
     rec = {
-        "kernel": NEAR_KERNEL,
-        "workload": "c2: 20480-triangle sphere, 3-level FMM, tight quadrature, complex-FP32 near field",
+        "kernel": kernel,
+        "workload": "c2: 20480-triangle sphere, 3-level FMM, tight quadrature, "
+                    + ("complex-FP32" if prec == "mixed" else "FP64") + " near field",
         "fetch_bytes_per_launch_raw": avg(fetch[near_f]),
         "write_bytes_per_launch_raw": avg(write[near_w]),
         "launches": len(fetch[near_f]),
@@ -158,10 +170,10 @@ def summarize_counters(fetch_csv, write_csv, out):
         "source_sha256": kernel_source_hash(),
         "commands": [
             f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fdir} -o f -- "
-            "python bench.py --profile-near-only --steps 3 --warmup 1",
+            f"python bench.py --profile-near-only --steps 3 --warmup 1{pflag}",
             f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {wdir} -o w -- "
-            "python bench.py --profile-near-only --steps 3 --warmup 1",
-            f"python bench.py --summarize-counters {rel(fetch_csv)} {rel(write_csv)}",
+            f"python bench.py --profile-near-only --steps 3 --warmup 1{pflag}",
+            f"python bench.py --summarize-counters {rel(fetch_csv)} {rel(write_csv)}{pflag}",
         ],
     }
     with open(out, "w") as fh:
@@ -169,9 +181,9 @@ def summarize_counters(fetch_csv, write_csv, out):
     print(json.dumps(rec))
 
 
-def measured_traffic():
+def measured_traffic(prec="mixed"):
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[prec]) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -223,10 +235,62 @@ def summarize_translate(fetch_csv, write_csv, out):
     print(json.dumps(rec))
 
 
+def summarize_valu(pmc_csv, out_md):
+    """Per kernel (name, grid): dispatches, average duration (the dispatch's
+    timestamps; counter runs serialise dispatches, so each ran alone), and
+    per-dispatch averages of SQ_INSTS_VALU (wavefront VALU instructions),
+    SQ_ACTIVE_INST_VALU, SQ_WAVES and GRBM_GUI_ACTIVE.  GRBM_GUI_ACTIVE is
+    summed over the 8 XCDs, so GRBM_GUI_ACTIVE / 8 / duration is the clock the
+    dispatch ran at.  A wave64 VALU instruction occupies its 16-lane SIMD for
+    4 cycles and the chip has 1024 SIMDs, so the share of SIMD cycles that
+    full-rate issue of the counted instructions needs is
+    4 SQ_INSTS_VALU / (1024 x clock x duration) (quarter-rate transcendentals
+    count once: a lower bound of the VALU pipe's occupancy)."""
+    import csv
+    acc = {}
+    with open(pmc_csv) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].replace("bem::(anonymous namespace)::", "").split("(")[0]
+            key = (name, r.get("Grid_Size", r.get("Grid_Size_X", "")))
+            d = acc.setdefault(key, {}).setdefault(r["Dispatch_Id"], {})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+            d["dur"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    rows = []
+    for (name, grid), ds in acc.items():
+        n = len(ds)
+        avg = lambda c: sum(v.get(c, 0.0) for v in ds.values()) / n
+        dur, ins, gui = avg("dur"), avg("SQ_INSTS_VALU"), avg("GRBM_GUI_ACTIVE")
+        if dur <= 0 or gui <= 0:
+            continue
+        clk = gui / 8.0 / dur
+        rows.append((dur * n, name, grid, n, dur, ins, avg("SQ_ACTIVE_INST_VALU"), avg("SQ_WAVES"), clk,
+                     4.0 * ins / (1024.0 * clk * dur)))
+    rows.sort(reverse=True)
+    rel = lambda p: (lambda r: p if r.startswith("..") else r)(os.path.relpath(os.path.abspath(p), ROOT))
+    with open(out_md, "w") as fh:
+        fh.write("# VALU instruction counts per kernel\n\n")
+        fh.write(f"From `{rel(pmc_csv)}`; summary by `python bench.py --summarize-valu {rel(pmc_csv)} "
+                 f"{rel(out_md)}`.  Dispatches ran one at a time (counter collection); clock = "
+                 "GRBM_GUI_ACTIVE / 8 XCDs / duration; VALU share = 4 SQ_INSTS_VALU / (1024 SIMDs x clock x "
+                 "duration), the fraction of SIMD cycles that full-rate issue of the counted VALU instructions "
+                 "needs.  The largest 25 kernels by total time (the run includes the autotuner's launch-shape "
+                 "candidates).\n\n")
+        fh.write("| kernel | grid | dispatches | avg duration (us) | SQ_INSTS_VALU | SQ_ACTIVE_INST_VALU | SQ_WAVES "
+                 "| clock (GHz) | VALU share |\n|---|---:|---:|---:|---:|---:|---:|---:|---:|\n")
+        for _, name, grid, n, dur, ins, act, waves, clk, share in rows[:25]:
+            fh.write(f"| `{name}` | {grid} | {n} | {dur * 1e6:.1f} | {ins:.4g} | {act:.4g} | {waves:.4g} | "
+                     f"{clk / 1e9:.2f} | {share:.2f} |\n")
+    print(open(out_md).read())
+
+
 def main():
     args = parse()
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.traffic_out)
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.traffic_out,
+                           args.profile_prec)
+        return
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu[0], args.summarize_valu[1])
         return
     if args.summarize_translate:
         summarize_translate(args.summarize_translate[0], args.summarize_translate[1], args.translate_out)
@@ -390,7 +454,7 @@ def main():
                                "frac": achieved32 / PEAK_TFLOPS["fp32_packed"],
                                "peak_unpacked": PEAK_TFLOPS["fp32"],
                                "frac_unpacked": achieved32 / PEAK_TFLOPS["fp32"],
-                               "traffic": measured_traffic()}},
+                               "traffic": measured_traffic("mixed")}},
         "mixed_speedup_over_fp64": res["fp64"]["t_full"] / res["mixed"]["t_full"],
         "accuracy": acc,
         "near_ms": {p_: res[p_]["t_near"] * 1e3 for p_ in res},
@@ -401,7 +465,7 @@ def main():
         "solve": solves,
         "roofline": {"bound": "alu", "kernel": NEAR_KERNEL64, "achieved": achieved64,
                      "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s", "frac": achieved64 / PEAK_TFLOPS["fp64"],
-                     "traffic": None,
+                     "traffic": measured_traffic("fp64"),
                      "flops_per_launch": near_flops, "flops_per_point": FLOPS_PER_POINT,
                      "flops_per_point_direct": FLOPS_PER_POINT_DIRECT,
                      "frac_at_direct_count": achieved64 * FLOPS_PER_POINT_DIRECT / FLOPS_PER_POINT
