@@ -174,6 +174,12 @@ typedef struct bem_options {
                                bem_grad_admittance (exterior representation
                                formula); bem_field_pv evaluates points inside
                                the fluid. */
+  int32_t translate_shape;  /* far-field translation launch: threads per
+                               block 64, 128 or 256 (0: 64), plus 4096 for the
+                               XCD slab order of the blocks (each of the 8 XCDs
+                               serving an eighth of a level's targets in tree
+                               order); a tuning choice, results are identical;
+                               bem_autotune replaces it */
 } bem_options;
 
 typedef struct bem_solve_info {
@@ -397,9 +403,11 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
  * with the translation threads per workgroup (64, 128, 256; FMM only) and the
  * point where the leaf-level translation leaves the level chain for a stream
  * of its own (right after aggregation, or after the leaf level's transfer to
- * the level above) on whole applications, for the FP64 and the complex-FP32
- * operator.  Results are kept in the mesh and used by every later
- * application; near_wpb, translate_tpb and near_waves (host int32[2]: FP64,
+ * the level above) on whole applications, then the translation blocks in XCD
+ * slab order (each of the 8 XCDs serving an eighth of the targets in tree
+ * order, so that the source signatures neighbouring targets share stay in
+ * one L2), for the FP64 and the complex-FP32 operator.  Results are kept in the mesh and used by every later
+ * application; near_wpb, translate_tpb (+ 4096 for the slab order) and near_waves (host int32[2]: FP64,
  * FP32) receive them and may be NULL.  Runs about 400 operator applications
  * or parts on the stream;
  * results are unchanged by the choice (each output keeps its owner and

@@ -63,6 +63,7 @@ class bem_options(ctypes.Structure):
         ("far_direct", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("level_rows", ctypes.c_int32),
         ("solver", ctypes.c_int32), ("near_waves_per_cu", ctypes.c_int32),
         ("quad_eps_mixed", ctypes.c_double), ("interior", ctypes.c_int32),
+        ("translate_shape", ctypes.c_int32),
     ]
 
     def as_dict(self):

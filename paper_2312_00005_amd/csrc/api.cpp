@@ -6,6 +6,7 @@
 #include <mutex>
 
 #include "guard.h"
+#include "fmm.h"
 #include "state.h"
 
 using namespace bem;
@@ -49,6 +50,7 @@ void set_paper(bem_options* o) {
   o->gamma_im_k = 1.0;
   o->far_direct = 0;
   o->interior = 0;
+  o->translate_shape = 0;
   o->use_graphs = 1;
 }
 
@@ -115,6 +117,11 @@ void check_options(const bem_options* o) {
   if (o->precond < 0 || o->precond > 2) throw Error(BEM_E_ARG, "precond must be 0, 1 or 2");
   if (o->far_direct != 0 && o->far_direct != 1) throw Error(BEM_E_ARG, "far_direct must be 0 or 1");
   if (o->interior != 0 && o->interior != 1) throw Error(BEM_E_ARG, "interior must be 0 or 1");
+  {
+    const int t = o->translate_shape & ~kTranslateSlab;
+    if (o->translate_shape < 0 || (t != 0 && t != 64 && t != 128 && t != 256))
+      throw Error(BEM_E_ARG, "translate_shape must be 0, 64, 128 or 256, plus 4096 for the slab order");
+  }
   if (o->use_graphs != 0 && o->use_graphs != 1) throw Error(BEM_E_ARG, "use_graphs must be 0 or 1");
   if (o->level_rows != 0 && o->level_rows != 1) throw Error(BEM_E_ARG, "level_rows must be 0 or 1");
   if (o->solver != 0 && o->solver != 1) throw Error(BEM_E_ARG, "solver must be 0 (GMRES) or 1 (CGS)");
@@ -643,6 +650,10 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
     m->opt = *o;
     m->N = n_tri;
     m->tune_nwaves[0] = m->tune_nwaves[1] = o->near_waves_per_cu;
+    {
+      const int t = o->translate_shape & ~kTranslateSlab;
+      m->tune_tpb[0] = m->tune_tpb[1] = (t == 0 ? 64 : t) | (o->translate_shape & kTranslateSlab);
+    }
     m->fmm = o->use_fmm != 0;
     m->far_direct = o->far_direct != 0;
     build_host(n_nodes, xyz, n_tri, tri, *o, m->tree, m->g, m->plan, m->bad_element);
@@ -899,6 +910,12 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           m->tune_nwaves[pi] = pick_nw;
           m->tune_tpb[pi] = pick_tpb;
           m->tune_fork_late[pi] = pick_late;
+          if (!m->far_direct) {
+            // the same shape with the translation blocks in XCD slab order
+            m->tune_tpb[pi] = pick_tpb | kTranslateSlab;
+            const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
+            if (!(t < best)) m->tune_tpb[pi] = pick_tpb;
+          }
         }
         if (near_wpb) near_wpb[pi] = m->tune_wpb[pi];
         if (translate_tpb) translate_tpb[pi] = m->tune_tpb[pi];
