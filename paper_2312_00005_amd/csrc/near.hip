@@ -857,19 +857,22 @@ __device__ inline int far_order(const FarLaunch& F, double d2, double area) {
 // depth-first walk over (depth, path) without a stack, per-sub-triangle rule
 // as in the plan.  The rule choice uses the unscaled geometry (g, or the
 // quadrilaterals' halves), the integration the records.
-template <typename T, bool WANT_S1, bool WANT_S2>
+template <typename T, bool WANT_S1, bool WANT_S2, bool QUADS>
 __device__ void far_pair_split(const FarLaunch& F, const T* g, const T* rec, int64_t j, const T xi[3],
                                const T xs[3], const T ni[3], const PointConsts<T>& P, T& s1r, T& s1i, T& s2r,
                                T& s2i) {
   const int64_t N = F.N;
   const T* hq = far_hq<T>(F);
-  const double area0 = (double)rec_field<T>(g, N, hq, F.Q.nh, AREA, j);
+  const double area0 = QUADS ? (double)rec_field<T>(g, N, hq, F.Q.nh, AREA, j) : (double)g[AREA * N + j];
   int depth = 0;
   uint64_t path = 0;
   s1r = s1i = s2r = s2i = T(0);
   for (;;) {
     T v0[3], v1[3], v2[3];
-    rec_triangle<T>(g, N, hq, F.Q.nh, j, depth, path, v0, v1, v2);
+    if (QUADS)
+      rec_triangle<T>(g, N, hq, F.Q.nh, j, depth, path, v0, v1, v2);
+    else
+      item_triangle<T>(g, N, j, depth, path, v0, v1, v2);
     double d2 = 0.0;
     for (int c = 0; c < 3; ++c) {
       const double dc = (double)xi[c] - ((double)v0[c] + (double)v1[c] + (double)v2[c]) / 3.0;
@@ -905,8 +908,11 @@ __device__ void far_pair_split(const FarLaunch& F, const T* g, const T* rec, int
 
 // One wavefront per row r: forward r = collocation point i, lanes over far
 // source elements j; adjoint r = source element j, lanes over far collocation
-// points i (the far relation of leaf clusters is symmetric).
-template <typename T, bool HAS_C, bool VMODE, bool ADJ>
+// points i (the far relation of leaf clusters is symmetric).  QUADS: the mesh
+// has quadrilaterals, whose two integration records are taken in turn (a
+// separate instantiation, so that triangle meshes keep the smaller register
+// footprint of one record per pair).
+template <typename T, bool HAS_C, bool VMODE, bool ADJ, bool QUADS>
 __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* __restrict__ x,
                                                     double2* __restrict__ y) {
   const int lane = threadIdx.x & 63;
@@ -947,38 +953,61 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
         ni[c] = ADJ ? g[(NX + c) * N + i] : nr[c];
         xs[c] = ADJ ? (T)(kap * F.geom[(CX + c) * N + i]) : xsr[c];
       }
-      // the element's integration records: itself, or a quadrilateral's halves
-      const int64_t qj = (valid && F.Q.nh) ? F.Q.qidx[j] : -1;
       T s1r = 0, s1i = 0, s2r = 0, s2i = 0;
-      for (int h = 0; h < 2; ++h) {
-        if (h == 1 && __ballot(qj >= 0) == 0) break;
-        const int64_t rj = qj >= 0 ? F.N + 2 * qj + h : j;
-        const bool act = valid && (h == 0 || qj >= 0);
+      if constexpr (QUADS) {
+        // the element's integration records: itself, or a quadrilateral's halves
+        const int64_t qj = valid ? F.Q.qidx[j] : -1;
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1 && __ballot(qj >= 0) == 0) break;
+          const int64_t rj = qj >= 0 ? F.N + 2 * qj + h : j;
+          const bool act = valid && (h == 0 || qj >= 0);
+          int m = -1;
+          if (act) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+              const double dc = (double)xi[c] - (double)rec_field<T>(g, N, far_hq<T>(F), F.Q.nh, CX + c, rj);
+              d2 += dc * dc;
+            }
+            m = far_order<T>(F, d2, (double)rec_field<T>(g, N, far_hq<T>(F), F.Q.nh, AREA, rj));
+          }
+          T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+          // one uniform rule per pass
+          for (int mc = 1; mc <= kMaxRuleOrder; ++mc) {
+            if (__ballot(m == mc) == 0) continue;
+            if (m == mc) {
+              int64_t jj;
+              integrate_item<T, !VMODE, HAS_C || VMODE, true>(rec, (uint64_t)rj, mc, xs, ni, P, a1r, a1i, a2r, a2i,
+                                                             jj);
+            }
+          }
+          if (__ballot(m == 0) != 0 && m == 0)
+            far_pair_split<T, !VMODE, HAS_C || VMODE, true>(F, g, rec, rj, xi, xs, ni, P, a1r, a1i, a2r, a2i);
+          s1r += a1r;
+          s1i += a1i;
+          s2r += a2r;
+          s2i += a2i;
+        }
+      } else {
         int m = -1;
-        if (act) {
+        if (valid) {
           double d2 = 0.0;
           for (int c = 0; c < 3; ++c) {
-            const double dc = (double)xi[c] - (double)rec_field<T>(g, N, far_hq<T>(F), F.Q.nh, CX + c, rj);
+            const double dc = (double)xi[c] - (double)g[(CX + c) * N + j];
             d2 += dc * dc;
           }
-          m = far_order<T>(F, d2, (double)rec_field<T>(g, N, far_hq<T>(F), F.Q.nh, AREA, rj));
+          m = far_order<T>(F, d2, (double)g[AREA * N + j]);
         }
-        T a1r = 0, a1i = 0, a2r = 0, a2i = 0;
         // one uniform rule per pass
         for (int mc = 1; mc <= kMaxRuleOrder; ++mc) {
           if (__ballot(m == mc) == 0) continue;
           if (m == mc) {
             int64_t jj;
-            integrate_item<T, !VMODE, HAS_C || VMODE, true>(rec, (uint64_t)rj, mc, xs, ni, P, a1r, a1i, a2r, a2i,
+            integrate_item<T, !VMODE, HAS_C || VMODE, true>(rec, (uint64_t)j, mc, xs, ni, P, s1r, s1i, s2r, s2i,
                                                            jj);
           }
         }
         if (__ballot(m == 0) != 0 && m == 0)
-          far_pair_split<T, !VMODE, HAS_C || VMODE>(F, g, rec, rj, xi, xs, ni, P, a1r, a1i, a2r, a2i);
-        s1r += a1r;
-        s1i += a1i;
-        s2r += a2r;
-        s2i += a2i;
+          far_pair_split<T, !VMODE, HAS_C || VMODE, false>(F, g, rec, j, xi, xs, ni, P, s1r, s1i, s2r, s2i);
       }
       if (!valid) continue;
       T vr = s1r, vi = s1i;
@@ -1538,7 +1567,11 @@ void launch_field(const FieldArgs& A, const double* pts, const double2* p, const
 
 template <typename T, bool HAS_C, bool VMODE, bool ADJ>
 void far_launch_t(const FarLaunch& F, const double2* x, double2* y, hipStream_t s) {
-  hipLaunchKernelGGL((k_far_direct<T, HAS_C, VMODE, ADJ>), dim3(blocks_for(F.N, 4)), dim3(256), 0, s, F, x, y);
+  if (F.Q.nh)
+    hipLaunchKernelGGL((k_far_direct<T, HAS_C, VMODE, ADJ, true>), dim3(blocks_for(F.N, 4)), dim3(256), 0, s, F, x, y);
+  else
+    hipLaunchKernelGGL((k_far_direct<T, HAS_C, VMODE, ADJ, false>), dim3(blocks_for(F.N, 4)), dim3(256), 0, s, F, x,
+                       y);
 }
 
 template <typename T>
