@@ -180,6 +180,13 @@ typedef struct bem_options {
                                serving an eighth of a level's targets in tree
                                order); a tuning choice, results are identical;
                                bem_autotune replaces it */
+  int32_t near_split;       /* with near_waves_per_cu > 0: percent (1-99) of the
+                               collocation points whose near field runs in the
+                               resident grid beside the far field; the rest run
+                               one wavefront each on the far field's stream
+                               after it, at full occupancy (0 or 100: all in
+                               the resident grid).  A tuning choice, results
+                               are identical; bem_autotune replaces it */
 } bem_options;
 
 typedef struct bem_solve_info {
@@ -403,8 +410,9 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
  * with the translation threads per workgroup (64, 128, 256; FMM only) and the
  * point where the leaf-level translation leaves the level chain for a stream
  * of its own (right after aggregation, or after the leaf level's transfer to
- * the level above) on whole applications, then the translation blocks in XCD
- * slab order (each of the 8 XCDs serving an eighth of the targets in tree
+ * the level above) on whole applications, then the share of near-field
+ * targets kept beside the far field (see near_split), then the translation
+ * blocks in XCD slab order (each of the 8 XCDs serving an eighth of the targets in tree
  * order, so that the source signatures neighbouring targets share stay in
  * one L2), for the FP64 and the complex-FP32 operator.  Results are kept in the mesh and used by every later
  * application; near_wpb, translate_tpb (+ 4096 for the slab order) and near_waves (host int32[2]: FP64,
@@ -447,6 +455,13 @@ bem_status bem_solve_batch(int32_t n, bem_mesh* const* meshes,
                            const bem_c128* const* rhs, bem_c128* const* p_out,
                            bem_c128* const* v_out, double rho_c,
                            bem_solve_info* infos, void* stream);
+
+/* Launch shapes in use (host int32[2] each: FP64, complex FP32; any pointer
+ * may be NULL): near-field targets per workgroup, translation shape (as
+ * translate_shape), resident near-field wavefronts per compute unit and the
+ * near-field split (as near_split).  Host only. */
+bem_status bem_mesh_launch_shapes(const bem_mesh* m, int32_t* near_wpb, int32_t* translate_shape,
+                                  int32_t* near_waves, int32_t* near_split);
 
 /* Mesh statistics (host outputs; any pointer may be NULL). */
 bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,

@@ -63,7 +63,7 @@ class bem_options(ctypes.Structure):
         ("far_direct", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("level_rows", ctypes.c_int32),
         ("solver", ctypes.c_int32), ("near_waves_per_cu", ctypes.c_int32),
         ("quad_eps_mixed", ctypes.c_double), ("interior", ctypes.c_int32),
-        ("translate_shape", ctypes.c_int32),
+        ("translate_shape", ctypes.c_int32), ("near_split", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -121,6 +121,7 @@ _SIGS = {
     "bem_solve_adjoint": (_i32, [_vp, _vp, _vp, ctypes.POINTER(bem_solve_info), _vp]),
     "bem_solve_batch": (_i32, [_i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp]),
     "bem_mesh_stats": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "bem_mesh_launch_shapes": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "bem_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "bem_mesh_destroy": (None, [_vp]),
     "bem_last_error": (ctypes.c_char_p, []),
@@ -258,13 +259,19 @@ def bem_rhs_pressure(mesh, pbar_ptr, rhs_ptr, stream):
     _check(_lib.bem_rhs_pressure(mesh, pbar_ptr, rhs_ptr, stream))
 
 
+def bem_mesh_launch_shapes(mesh):
+    w, t, nw, sp = ((_i32 * 2)() for _ in range(4))
+    _check(_lib.bem_mesh_launch_shapes(mesh, w, t, nw, sp))
+    return {"near_wpb": {"fp64": w[0], "mixed": w[1]}, "translate_tpb": {"fp64": t[0], "mixed": t[1]},
+            "near_waves_per_cu": {"fp64": nw[0], "mixed": nw[1]}, "near_split": {"fp64": sp[0], "mixed": sp[1]}}
+
+
 def bem_autotune(mesh, stream):
     w = (_i32 * 2)()
     t = (_i32 * 2)()
     nw = (_i32 * 2)()
     _check(_lib.bem_autotune(mesh, w, t, nw, stream))
-    return {"near_wpb": {"fp64": w[0], "mixed": w[1]}, "translate_tpb": {"fp64": t[0], "mixed": t[1]},
-            "near_waves_per_cu": {"fp64": nw[0], "mixed": nw[1]}}
+    return bem_mesh_launch_shapes(mesh)
 
 
 def bem_incident_field(mesh, kind, src, P0, n_pts, pts_ptr, out_ptr, stream):

@@ -51,6 +51,7 @@ void set_paper(bem_options* o) {
   o->far_direct = 0;
   o->interior = 0;
   o->translate_shape = 0;
+  o->near_split = 0;
   o->use_graphs = 1;
 }
 
@@ -122,6 +123,7 @@ void check_options(const bem_options* o) {
     if (o->translate_shape < 0 || (t != 0 && t != 64 && t != 128 && t != 256))
       throw Error(BEM_E_ARG, "translate_shape must be 0, 64, 128 or 256, plus 4096 for the slab order");
   }
+  if (o->near_split < 0 || o->near_split > 100) throw Error(BEM_E_ARG, "near_split must be in [0, 100]");
   if (o->use_graphs != 0 && o->use_graphs != 1) throw Error(BEM_E_ARG, "use_graphs must be 0 or 1");
   if (o->level_rows != 0 && o->level_rows != 1) throw Error(BEM_E_ARG, "level_rows must be 0 or 1");
   if (o->solver != 0 && o->solver != 1) throw Error(BEM_E_ARG, "solver must be 0 (GMRES) or 1 (CGS)");
@@ -243,9 +245,23 @@ void apply_tree_part_ext(bem_mesh* m, bem_op op, bem_precision prec, int part, c
     // submitted the whole far-field chain.
     BEM_HIP(hipEventRecord(m->ev_fork, s));
     BEM_HIP(hipStreamWaitEvent(m->side_stream, m->ev_fork, 0));
-    launch_near(L, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
+    // With a resident near-field grid the targets may be split: the first
+    // share (in visiting order) runs beside the far field, the rest one
+    // wavefront each on the far field's stream once it is done, at full
+    // occupancy.  Every target keeps one owner: results are identical.
+    const int split = m->tune_split[prec == BEM_PREC_FP64 ? 0 : 1];
+    const bool halves = op == BEM_OP_A && !vmode && L.nwaves > 0 && split > 0 && split < 100 && m->N >= 2;
+    NearLaunch L1 = L, L2 = L;
+    if (halves) {
+      L1.count = std::max<int64_t>(1, std::min<int64_t>(m->N - 1, m->N * split / 100));
+      L2.first = L1.count;
+      L2.count = m->N - L1.count;
+      L2.nwaves = 0;
+    }
+    launch_near(L1, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
     launch_zero(m->N, m->d_far.p, m->side_stream);
     far_apply(m, op, prec, x, m->d_far.p, m->side_stream, vmode);
+    if (halves) launch_near(L2, prec == BEM_PREC_FP64, false, false, x, y, m->side_stream);
     BEM_HIP(hipEventRecord(m->ev_join, m->side_stream));
     BEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
     launch_axpby(m->N, make_double2(1, 0), y, make_double2(1, 0), m->d_far.p, y, s);
@@ -653,6 +669,7 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
     {
       const int t = o->translate_shape & ~kTranslateSlab;
       m->tune_tpb[0] = m->tune_tpb[1] = (t == 0 ? 64 : t) | (o->translate_shape & kTranslateSlab);
+      m->tune_split[0] = m->tune_split[1] = o->near_split == 0 ? 100 : o->near_split;
     }
     m->fmm = o->use_fmm != 0;
     m->far_direct = o->far_direct != 0;
@@ -890,6 +907,7 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           // whole applications
           best = -1.0f;
           int pick_nw = 0, pick_tpb = m->tune_tpb[pi], pick_late = 0;
+          m->tune_split[pi] = 100;
           const std::vector<int> tpbs = m->far_direct ? std::vector<int>{m->tune_tpb[pi]} : std::vector<int>{64, 128, 256};
           const std::vector<int> lates = m->far_direct ? std::vector<int>{0} : std::vector<int>{0, 1};
           for (int late : lates)
@@ -915,6 +933,22 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
             m->tune_tpb[pi] = pick_tpb | kTranslateSlab;
             const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
             if (!(t < best)) m->tune_tpb[pi] = pick_tpb;
+            else best = t;
+          }
+          // a resident near-field grid: the share of targets it keeps beside
+          // the far field (the rest run after it at full occupancy)
+          m->tune_split[pi] = 100;
+          if (pick_nw > 0) {
+            int pick_split = 100;
+            for (int split : {90, 80, 70, 60, 50}) {
+              m->tune_split[pi] = split;
+              const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
+              if (t < best) {
+                best = t;
+                pick_split = split;
+              }
+            }
+            m->tune_split[pi] = pick_split;
           }
         }
         if (near_wpb) near_wpb[pi] = m->tune_wpb[pi];
@@ -1318,6 +1352,20 @@ void fill_info(const bem_mesh* m, const SolveResult& r, bem_solve_info* info) {
 }
 
 }  // namespace
+
+bem_status bem_mesh_launch_shapes(const bem_mesh* m, int32_t* near_wpb, int32_t* translate_shape,
+                                  int32_t* near_waves, int32_t* near_split) {
+  return guarded([&]() -> bem_status {
+    if (!m) return fail(BEM_E_ARG, "mesh is NULL");
+    for (int p = 0; p < 2; ++p) {
+      if (near_wpb) near_wpb[p] = m->tune_wpb[p];
+      if (translate_shape) translate_shape[p] = m->tune_tpb[p];
+      if (near_waves) near_waves[p] = m->tune_nwaves[p];
+      if (near_split) near_split[p] = m->tune_split[p];
+    }
+    return BEM_OK;
+  });
+}
 
 bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters, int64_t* near_pairs,
                           int64_t* near_items, int64_t* quad_points) {

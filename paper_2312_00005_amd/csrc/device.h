@@ -44,6 +44,8 @@ struct NearLaunch {
   const float* rec32;     // element records for the FP32 kernels, scale kap32
   double kap, kap32;      // k (phase in radians) and k / (2 pi) rounded to float (phase in revolutions)
   int64_t nwaves;         // forward kernel: wavefronts launched (0: one per target)
+  int64_t first, count;   // forward kernel: the targets at positions first .. first + count - 1 of
+                          // the visiting order (count 0: all N)
 };
 
 // y = diag x + sum over near items (tree-order vectors), in FP64 or complex

@@ -528,9 +528,12 @@ __global__ __launch_bounds__(64 * WPB) void k_near(NearLaunch L, const T* __rest
   // the target is uniform across the wavefront: say so, so that its data go
   // through scalar loads and registers.  Targets are visited in L.order
   // (groups of decreasing work), so the last wavefronts to start are short ones.
-  for (int64_t w = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); w < N;
+  // this launch's share of the targets: positions first .. first + count of
+  // the visiting order (count 0: all)
+  const int64_t cnt = L.count > 0 ? L.count : N;
+  for (int64_t w = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); w < cnt;
        w += stride) {
-    const int64_t t = L.order ? (int64_t)L.order[w] : w;
+    const int64_t t = L.order ? (int64_t)L.order[L.first + w] : L.first + w;
     T xs[3], ni[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -638,7 +641,8 @@ __global__ __launch_bounds__(256) void k_near_adj(NearLaunch L, const T* __restr
 
 template <typename T, int WPB>
 void near_forward(const NearLaunch& L, const T* g, const double2* x, double2* y, hipStream_t s) {
-  const int64_t waves = L.nwaves > 0 && L.nwaves < L.N ? L.nwaves : L.N;
+  const int64_t cnt = L.count > 0 ? L.count : L.N;
+  const int64_t waves = L.nwaves > 0 && L.nwaves < cnt ? L.nwaves : cnt;
   dim3 grid((unsigned)((waves + WPB - 1) / WPB)), block(64 * WPB);
   if (L.cfac) hipLaunchKernelGGL((k_near<T, true, false, WPB>), grid, block, 0, s, L, g, x, y);
   else hipLaunchKernelGGL((k_near<T, false, false, WPB>), grid, block, 0, s, L, g, x, y);

@@ -60,6 +60,8 @@ struct bem_mesh {
   int tune_wpb[2] = {4, 4};     // near-field targets per workgroup
   int tune_tpb[2] = {64, 64};   // translation threads per workgroup
   int tune_nwaves[2] = {0, 0};  // resident near-field wavefronts per CU beside the far field (0: one per target)
+  int tune_split[2] = {100, 100};  // percent of the near-field targets in the resident launch beside the far
+                                   // field; the rest run one wavefront each after the far field, on its stream
   int tune_fork_late[2] = {0, 0};  // leaf translation forked after the leaf level's upward transfer (1) or before (0)
 
   // captured operator applications of the Krylov driver, [op][precision]

@@ -61,6 +61,7 @@ def test_autotune_keeps_results(bem):
     assert set(picks["near_wpb"].values()) <= {1, 2, 4, 8}
     assert {t & ~4096 for t in picks["translate_tpb"].values()} <= {64, 128, 256}
     assert set(picks["near_waves_per_cu"].values()) <= {0, 8, 12, 16, 24}
+    assert set(picks["near_split"].values()) <= {50, 60, 70, 80, 90, 100}
     for p in ("fp64", "mixed"):
         assert np.array_equal(to_host(m.apply(x, prec=p)), before[p])
     # a resident near-field grid (each wavefront looping over targets) changes
@@ -69,6 +70,13 @@ def test_autotune_keeps_results(bem):
     m8.set_problem(k)
     for p in ("fp64", "mixed"):
         assert np.array_equal(to_host(m8.apply(x, prec=p)), before[p])
+    # nor does splitting the near field around the far field
+    for split in (50, 80):
+        ms = bem.Mesh(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=32, near_waves_per_cu=8, near_split=split)
+        ms.set_problem(k)
+        for p in ("fp64", "mixed"):
+            assert np.array_equal(to_host(ms.apply(x, prec=p)), before[p])
+        ms.close()
     # nor do the translation blocks in XCD slab order
     for shape in (4096 + 64, 4096 + 256):
         ms = bem.Mesh(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=32, translate_shape=shape)
