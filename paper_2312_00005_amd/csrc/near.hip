@@ -104,24 +104,28 @@ template <> struct RuleTab<float> {
 
 // exp(i x) for |x| < 2^20 by the table-driven method of Tang: x = j h + d
 // with h = 2 pi / kExpTab and j = rint(x / h) (Cody & Waite reduction, h in
-// three parts of which the first two have 26 significant bits, so that
-// j C1 and j C2 are exact for |j| < 2^27), |d| <= h / 2 = pi / 512; then
-// exp(i x) = T[j mod kExpTab] exp(i d) with the Taylor series of cos d to
-// d^6 / 6! and of sin d to d^5 / 5! (truncation below 1e-22 and 1e-20).  The
-// table T (exp(i j h), computed on the host) sits in LDS.
+// two parts), |d| <= h / 2 = pi / 512; then exp(i x) = T[j mod kExpTab]
+// exp(i d) with the Taylor series of cos d to d^4 / 4! and of sin d to
+// d^5 / 5! (truncation below 7.5e-17 and 1e-20).  The table T (exp(i j h),
+// computed on the host) sits in LDS.  The phases here are k r >= 0 over
+// distances within a mesh, far below 2^20.
 __device__ inline void cis_table(double x, const double2* __restrict__ tab, double* s, double* c) {
-  constexpr double kInvH = 81.487330863050417;           // kExpTab / (2 pi)
-  constexpr double kC1 = 0x1.921fb58p-7;                  // 2 pi / kExpTab in three parts
-  constexpr double kC2 = -0x1.dde974p-34;
-  constexpr double kC3 = 0x1.1a62633145c07p-61;
-  const double j = rint(x * kInvH);
+  constexpr double kInvH = 81.487330863050417;    // kExpTab / (2 pi)
+  constexpr double kC1 = 0x1.921fb58p-7;           // 2 pi / kExpTab in two parts: kC1 has 26 significant
+  constexpr double kC2 = -0x1.dde973dcb3b3ap-34;   // bits, so j kC1 is exact for |j| < 2^27; kC1 + kC2
+                                                   // is within 5e-27 of 2 pi / kExpTab
+  // j = nearest integer to x kInvH, read off the low word of x kInvH + 1.5 2^52
+  constexpr double kRound = 0x1.8p52;
+  const double jr = fma(x, kInvH, kRound);
+  const double j = jr - kRound;
+  const int ji = (int)(uint32_t)__builtin_bit_cast(uint64_t, jr);
   double d = fma(-j, kC1, x);
   d = fma(-j, kC2, d);
-  d = fma(-j, kC3, d);
-  const double2 t = tab[((int)j) & (kExpTab - 1)];
+  const double2 t = tab[ji & (kExpTab - 1)];
   const double z = d * d;
-  // cos d = 1 - z/2 + z^2/24 - z^3/720; sin d = d (1 - z/6 + z^2/120)
-  const double cd = fma(z, fma(z, fma(z, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  // |d| <= pi / kExpTab: cos d = 1 - z/2 + z^2/24 (the z^3 / 720 term is below
+  // 7.5e-17), sin d = d (1 - z/6 + z^2/120)
+  const double cd = fma(z, fma(z, 1.0 / 24.0, -0.5), 1.0);
   const double sd = fma(d * z, fma(z, 1.0 / 120.0, -1.0 / 6.0), d);
   *c = fma(t.x, cd, -t.y * sd);
   *s = fma(t.y, cd, t.x * sd);
