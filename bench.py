@@ -524,6 +524,7 @@ def run_sweep(args, wl):
             "it": r["info"]["iterations"], "res": r["info"]["rel_residual"], "s": round(r["seconds"], 4)}
            for r in results]
     n_direct = sum(1 for r in results if r["method"][0] == "direct")
+    n_fmm32 = sum(1 for r in results if r["method"][0] == "fmm32")
     out = {
         "metric": "FMM matvec element-interactions/s and GMRES solve s/frequency, mixed vs FP64",
         "value": N * N * matvecs / solve_time,
@@ -534,13 +535,15 @@ def run_sweep(args, wl):
         "dtype": "c64 (fp32 operator; fp64 diagonal, Krylov and refinement)",
         "data": "synthetic (seeded geodesic sphere mesh)",
         "config": {"workload": f"c4: frequency sweep, rigid sphere N={N}, 64 frequencies 100 Hz - 20 kHz, "
-                               f"per-frequency FMM depth 2-4 or direct far field, {args.streams} streams",
+                               f"per-frequency FMM depth 2-4, FP32 FMM with FP64 direct far field, or direct "
+                               f"far field, {args.streams} streams",
                    "n_elements": N, "frequencies": len(freqs)},
         "solve_s_per_frequency": tot["wall_s"] / len(freqs),
         "solve_s_per_frequency_excluding_plans": solve_time / len(freqs),
         "sweep": {"wall_s": tot["wall_s"], "mesh_setup_s": tot["mesh_setup_s"],
                   "plan_choice_s": tot["plan_choice_s"], "operator_applications": matvecs,
-                  "direct_far_field_frequencies": n_direct, "per_frequency": per},
+                  "direct_far_field_frequencies": n_direct,
+                  "fp32_fmm_fp64_direct_frequencies": n_fmm32, "per_frequency": per},
     }
     print(json.dumps(out), flush=True)
 

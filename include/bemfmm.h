@@ -136,7 +136,14 @@ typedef struct bem_options {
                                plan, chosen per pair on the fly; nothing
                                stored) instead of the FMM -- for frequencies
                                where the expansion is unstable (k X_min small,
-                               Sec. 3.3.1) or too long.  Needs use_fmm = 1. */
+                               Sec. 3.3.1) or too long.  2: the FP64 operator
+                               integrates the far field directly and the
+                               complex-FP32 operator keeps the FMM -- for the
+                               mixed path at frequencies where only the FP64
+                               expansion lengths are capped (the FP64
+                               refinement residuals then hold the solution's
+                               accuracy, the FP32 inner solves only need a good
+                               operator).  Needs use_fmm = 1. */
   int32_t use_graphs;       /* 1: bem_solve / bem_solve_adjoint replay the
                                operator application (near field and far field
                                kernels) of each GMRES iteration as a captured
@@ -499,9 +506,10 @@ bem_status bem_tree_plan_stats(const bem_tree* t, int64_t* pairs, int64_t* items
 /* Expansion lengths the tree would get at wavenumber k under options o (the
  * admissibility and length rule of o; Eq. (FMMTruncation) and the stability
  * cap): L[level] for the FP64 operator, L32[level] for the complex-FP32 one
- * (both host int32[levels]), *capped = 1 if the cap lowered any length below
- * the accuracy-driven one (the expansion is then less accurate than asked:
- * k X_min too small, Sec. 3.3.1), *bytes = estimated far-field device memory
+ * (both host int32[levels]), *capped: bit 0 set if the cap lowered any FP64
+ * length below the accuracy-driven one, bit 1 the same for the complex-FP32
+ * lengths (the expansion is then less accurate than asked: k X_min too
+ * small, Sec. 3.3.1), *bytes = estimated far-field device memory
  * of bem_set_problem.  Any output may be NULL.  BEM_E_STATE for a tree built
  * without use_fmm. */
 bem_status bem_tree_fmm_lengths(const bem_tree* t, double k, const bem_options* o,

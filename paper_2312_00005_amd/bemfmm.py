@@ -421,7 +421,8 @@ def bem_tree_fmm_lengths(tree, k, options):
     nbytes = _dbl()
     _check(_lib.bem_tree_fmm_lengths(tree, float(k), ctypes.byref(options), L, L32, ctypes.byref(capped),
                                      ctypes.byref(nbytes)))
-    return {"L": list(L[:nl]), "L_mixed": list(L32[:nl]), "capped": bool(capped.value), "bytes": nbytes.value}
+    return {"L": list(L[:nl]), "L_mixed": list(L32[:nl]), "capped": bool(capped.value),
+            "capped_fp64": bool(capped.value & 1), "capped_mixed": bool(capped.value & 2), "bytes": nbytes.value}
 
 
 def bem_grid_create(mesh, pts):

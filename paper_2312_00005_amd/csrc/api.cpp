@@ -116,7 +116,7 @@ void check_options(const bem_options* o) {
   if (o->precision != BEM_PREC_FP64 && o->precision != BEM_PREC_MIXED)
     throw Error(BEM_E_ARG, "unknown precision");
   if (o->precond < 0 || o->precond > 2) throw Error(BEM_E_ARG, "precond must be 0, 1 or 2");
-  if (o->far_direct != 0 && o->far_direct != 1) throw Error(BEM_E_ARG, "far_direct must be 0 or 1");
+  if (o->far_direct < 0 || o->far_direct > 2) throw Error(BEM_E_ARG, "far_direct must be 0, 1 or 2");
   if (o->interior != 0 && o->interior != 1) throw Error(BEM_E_ARG, "interior must be 0 or 1");
   {
     const int t = o->translate_shape & ~kTranslateSlab;
@@ -274,7 +274,7 @@ void apply_tree_part_ext(bem_mesh* m, bem_op op, bem_precision prec, int part, c
 
 void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, double2* y, hipStream_t s, bool vmode) {
   if (!m->fmm) return;
-  if (!m->far_direct) {
+  if (!m->far_direct && !(m->far_direct64 && prec == BEM_PREC_FP64)) {
     fmm_apply(m, op, prec, x, y, s, vmode);
     return;
   }
@@ -672,7 +672,8 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
       m->tune_split[0] = m->tune_split[1] = o->near_split == 0 ? 100 : o->near_split;
     }
     m->fmm = o->use_fmm != 0;
-    m->far_direct = o->far_direct != 0;
+    m->far_direct = o->far_direct == 1;
+    m->far_direct64 = o->far_direct == 2;
     build_host(n_nodes, xyz, n_tri, tri, *o, m->tree, m->g, m->plan, m->bad_element);
     {
       int dev = 0, ncu = 0;
@@ -762,7 +763,7 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
       BEM_HIP(hipEventCreateWithFlags(&m->ev_leaf_join, hipEventDisableTiming));
       m->d_far.alloc(n_tri);
     }
-    if (m->far_direct) build_far_direct(m.get(), s);
+    if (m->far_direct || m->far_direct64) build_far_direct(m.get(), s);
     BEM_HIP(hipStreamSynchronize(s));
     *out = m.release();
     return BEM_OK;
@@ -908,8 +909,9 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           best = -1.0f;
           int pick_nw = 0, pick_tpb = m->tune_tpb[pi], pick_late = 0;
           m->tune_split[pi] = 100;
-          const std::vector<int> tpbs = m->far_direct ? std::vector<int>{m->tune_tpb[pi]} : std::vector<int>{64, 128, 256};
-          const std::vector<int> lates = m->far_direct ? std::vector<int>{0} : std::vector<int>{0, 1};
+          const bool direct = m->far_direct || (m->far_direct64 && pi == 0);
+          const std::vector<int> tpbs = direct ? std::vector<int>{m->tune_tpb[pi]} : std::vector<int>{64, 128, 256};
+          const std::vector<int> lates = direct ? std::vector<int>{0} : std::vector<int>{0, 1};
           for (int late : lates)
             for (int tpb : tpbs) {
               for (int nw : {0, 8, 12, 16, 24}) {
@@ -928,7 +930,7 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           m->tune_nwaves[pi] = pick_nw;
           m->tune_tpb[pi] = pick_tpb;
           m->tune_fork_late[pi] = pick_late;
-          if (!m->far_direct) {
+          if (!direct) {
             // the same shape with the translation blocks in XCD slab order
             m->tune_tpb[pi] = pick_tpb | kTranslateSlab;
             const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
@@ -1524,7 +1526,7 @@ bem_status bem_tree_fmm_lengths(const bem_tree* t, double k, const bem_options* 
       if (L) L[l] = I.L[l];
       if (L32) L32[l] = I.L32[l];
     }
-    if (capped) *capped = I.capped ? 1 : 0;
+    if (capped) *capped = (I.capped64 ? 1 : 0) | (I.capped32 ? 2 : 0);
     if (bytes) *bytes = I.bytes;
     return BEM_OK;
   });

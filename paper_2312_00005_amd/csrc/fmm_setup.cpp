@@ -703,7 +703,7 @@ void fmm_setup_problem(bem_mesh* m, hipStream_t s) {
   F->gre_setup = m->gre;
   F->gim_setup = m->gim;
   upload_rule(F, m->opt.t_order, s);
-  setup_set(m, F, 0, s);
+  if (!m->far_direct64) setup_set(m, F, 0, s);  // the FP64 far field is direct otherwise
   setup_set(m, F, 1, s);
 }
 
@@ -762,7 +762,10 @@ FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options&
       const int la = truncation_length(k, rmax, o, -1.0, single != 0);
       const int lc = truncation_length(k, rmax, o, xmin, single != 0);
       (single ? I.L32 : I.L)[l] = lc;
-      if (xmin >= 0.0 && lc < la) I.capped = true;
+      if (xmin >= 0.0 && lc < la) {
+        I.capped = true;
+        (single ? I.capped32 : I.capped64) = true;
+      }
       const double nu = 2.0 * lc * lc;
       const double b = single ? 8.0 : 16.0;
       I.bytes += b * nu * (0.5 * (double)L.il.size() + 2.0 * (double)L.nc);
@@ -774,7 +777,8 @@ FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options&
 
 
 FmmLeafView fmm_leaf_view(bem_mesh* m) {
-  if (!m->fmm || m->far_direct || !m->fmm_state) throw Error(BEM_E_STATE, "the mesh has no FMM far field");
+  if (!m->fmm || m->far_direct || m->far_direct64 || !m->fmm_state)
+    throw Error(BEM_E_STATE, "the mesh has no FP64 FMM far field");
   FmmSet* F = &m->fmm_state->set[0];
   FmmLevel& leaf = F->lv.back();
   FmmLeafView v;

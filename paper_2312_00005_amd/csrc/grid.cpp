@@ -154,7 +154,8 @@ bem_status bem_grid_create(bem_mesh* m, int64_t n_pts, const double* pts, bem_gr
   return guarded([&]() -> bem_status {
     if (!m || !out || n_pts < 1 || !pts) return fail(BEM_E_ARG, "NULL argument or no points");
     *out = nullptr;
-    if (!m->fmm || m->far_direct) return fail(BEM_E_STATE, "the evaluation grid needs a mesh with the FMM");
+    if (!m->fmm || m->far_direct || m->far_direct64)
+      return fail(BEM_E_STATE, "the evaluation grid needs a mesh with the FP64 FMM (far_direct = 0)");
     for (int64_t i = 0; i < 3 * n_pts; ++i)
       if (!std::isfinite(pts[i])) return fail(BEM_E_ARG, "non-finite point coordinate");
     auto g = std::make_unique<bem_grid>();

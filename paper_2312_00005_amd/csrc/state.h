@@ -95,8 +95,11 @@ struct bem_mesh {
   bem::DevBuf<double2> d_px, d_py;  // masked input and second application
   bool has_pres = false;
 
-  // direct far field (far_direct option)
+  // direct far field (far_direct option): for every operator (far_direct),
+  // or for the FP64 operator only, the complex-FP32 one keeping the FMM
+  // (far_direct64)
   bool far_direct = false;
+  bool far_direct64 = false;
   bem::DevBuf<int32_t> d_elem_leaf;
   bem::DevBuf<int64_t> d_far_off, d_far_beg, d_far_end;
   double far_rt2_min[8] = {0};    // r~^2 thresholds of the orders (quad_eps)
@@ -171,7 +174,8 @@ struct FmmPlanInfo {
   int levels = 0;
   int L[16] = {0};
   int L32[16] = {0};
-  bool capped = false;
+  bool capped = false;            // either set
+  bool capped64 = false, capped32 = false;
   double bytes = 0.0;
 };
 FmmPlanInfo fmm_plan_info(const Tree& T, int64_t N, double k, const bem_options& o);
