@@ -521,7 +521,9 @@ def run_sweep(args, wl):
     matvecs = sum(r["info"]["iterations"] + 2 * r["info"]["refinements"] + 1 for r in results)
     solve_time = tot["wall_s"] - tot["mesh_setup_s"]
     per = [{"f": round(r["f"], 1), "method": f"{r['method'][0]}{r['method'][1]}",
-            "it": r["info"]["iterations"], "res": r["info"]["rel_residual"], "s": round(r["seconds"], 4)}
+            "it": r["info"]["iterations"], "ref": r["info"]["refinements"], "res": r["info"]["rel_residual"],
+            "s": round(r["seconds"], 4),
+            "setup_s": round(r["setup_seconds"], 4)}
            for r in results]
     n_direct = sum(1 for r in results if r["method"][0] == "direct")
     n_fmm32 = sum(1 for r in results if r["method"][0] == "fmm32")

@@ -152,7 +152,8 @@ class FrequencySweep:
         return curves.AdmittanceGroup(None, P0, curve_re, curve_im).value(self.steps[i])
 
     def run(self, source=("plane", (0.0, 0.0, 1.0), 1.0), keep_solutions=True, source_curves=(None, None)):
-        """Returns a list of per-frequency dicts (k, method, info, seconds and
+        """Returns a list of per-frequency dicts (k, method, info, seconds, of
+        which setup_seconds set up the frequency and solve_seconds solve it, and
         the device solution p) plus timing totals.  source_curves: curves of
         the frequency step for the real and imaginary part of P0.  With
         batch = B, each method group holds B mesh instances: B frequencies are
@@ -166,6 +167,12 @@ class FrequencySweep:
         t_setup = 0.0
         t0 = time.perf_counter()
         for method, idx in groups.items():
+            # the expansion tables grow with k and a buffer is only reallocated
+            # when it grows: from the highest k down, every frequency of the
+            # group reuses the first one's device memory (allocating anew at
+            # every step of an ascending sweep has cost up to 2 s a frequency
+            # at ~40 GB, after earlier groups had freed theirs)
+            idx = sorted(idx, key=lambda i: -self.ks[i])
             ts = time.perf_counter()
             meshes = [self._mesh(method) for _ in range(min(self.batch, len(idx)))]
             t_setup += time.perf_counter() - ts
@@ -178,15 +185,19 @@ class FrequencySweep:
                     kind, src, P0 = source
                     P0 = self.source_strength(i, P0, *source_curves)
                     rhs.append(mesh.rhs_plane_wave(src, P0) if kind == "plane" else mesh.rhs_point_source(src, P0))
+                torch.cuda.current_stream().synchronize()
+                t2 = time.perf_counter()
                 if len(chunk) == 1:
                     out = [meshes[0].solve(rhs[0], allow_noconv=True)]
                 else:
                     out = bemfmm.Mesh.solve_batch(meshes[:len(chunk)], rhs, allow_noconv=True)
                 torch.cuda.current_stream().synchronize()
-                dt = (time.perf_counter() - t1) / len(chunk)
+                t3 = time.perf_counter()
+                dt = (t3 - t1) / len(chunk)
                 for (p, _, info), i in zip(out, chunk):
                     results[i] = {"f": self.freqs[i], "k": self.ks[i], "method": self.methods[i], "info": info,
-                                  "seconds": dt, "p": p if keep_solutions else None}
+                                  "seconds": dt, "setup_seconds": (t2 - t1) / len(chunk),
+                                  "solve_seconds": (t3 - t2) / len(chunk), "p": p if keep_solutions else None}
             for mesh in meshes:
                 mesh.close()
         torch.cuda.synchronize()
