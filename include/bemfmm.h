@@ -111,7 +111,9 @@ typedef struct bem_options {
   int32_t gmres_maxit;      /* iteration cap (250 as in Sec. 3.2)             */
   double gmres_tol;         /* relative residual target                       */
   int32_t refine_maxit;     /* outer refinement steps (mixed precision)      */
-  double inner_tol;         /* inner GMRES tolerance (mixed precision)       */
+  double inner_tol;         /* inner GMRES tolerance (mixed precision),
+                               relative to the current FP64 residual; an inner
+                               solve never goes below half of gmres_tol |b| */
   double l_eps_mixed;       /* expansion accuracy of the complex-FP32 operator;
                                its L is also capped so that FP32 rounding times
                                (2L+1)|h_L(k X_min)| stays below l_eps_mixed/10 */

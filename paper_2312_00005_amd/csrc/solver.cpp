@@ -5,7 +5,10 @@
 // its residual is the residual of the unpreconditioned system.  With the
 // mixed precision option the inner solves run on the complex-FP32 operator
 // inside an FP64 iterative-refinement loop: r = b - A x with the FP64
-// operator, inner GMRES on A d = r, x += d.
+// operator, inner GMRES on A d = r, x += d.  An inner solve reduces its
+// residual by inner_tol, but never below half the outer target: the step
+// that only has to close a small gap to the target stops after a few
+// iterations instead of running the full inner reduction.
 #include <algorithm>
 #include <complex>
 #include <memory>
@@ -17,6 +20,12 @@ namespace bem {
 namespace {
 
 using cd = std::complex<double>;
+
+// absolute residual target of the inner solve of one refinement step: rn the
+// current FP64 residual norm, target the outer one (tol |b|)
+inline double inner_target(const bem_options& o, double rn, double target) {
+  return std::max(o.inner_tol * rn, 0.5 * target);
+}
 
 struct Work {
   int64_t N;
@@ -467,7 +476,7 @@ class SolveTask {
       finish_refinement();
       return;
     }
-    begin_gmres(m_->d_tmp.p, m_->d_y.p, BEM_PREC_MIXED, m_->opt.inner_tol * rn_, kRefine);
+    begin_gmres(m_->d_tmp.p, m_->d_y.p, BEM_PREC_MIXED, inner_target(m_->opt, rn_, tol_ * bnorm_), kRefine);
   }
 
   void finish_refinement() {
@@ -533,8 +542,8 @@ SolveResult solve_tree_cgs(bem_mesh* m, const double2* b, double2* x, hipStream_
     for (int it = 0; it < std::max(1, m->opt.refine_maxit); ++it) {
       if (rn <= tol * bnorm) break;
       bool conv = false;
-      out.iterations += cgs(m, op, BEM_PREC_MIXED, rr, d, true, m->opt.inner_tol * rn, m->opt.gmres_maxit, W, s,
-                            &conv);
+      out.iterations += cgs(m, op, BEM_PREC_MIXED, rr, d, true, inner_target(m->opt, rn, tol * bnorm),
+                            m->opt.gmres_maxit, W, s, &conv);
       ++out.refinements;
       launch_axpby(N, make_double2(1, 0), x, make_double2(1, 0), d, x, s);
       apply_tree(m, op, BEM_PREC_FP64, x, m->d_w.p, s);
