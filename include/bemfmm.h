@@ -196,6 +196,13 @@ typedef struct bem_options {
                                after it, at full occupancy (0 or 100: all in
                                the resident grid).  A tuning choice, results
                                are identical; bem_autotune replaces it */
+  int32_t far_rows;         /* direct far field (far_direct), forward operator
+                               on triangle meshes: collocation points per
+                               wavefront, 1 or 4 (0: 4 in the FP64 operator, 1
+                               in the complex-FP32 one).  With 4, consecutive
+                               points of one leaf cluster share every source
+                               element's loads.  A tuning choice: the same
+                               sums in the same order, equal to rounding */
 } bem_options;
 
 typedef struct bem_solve_info {

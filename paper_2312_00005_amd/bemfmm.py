@@ -64,6 +64,7 @@ class bem_options(ctypes.Structure):
         ("solver", ctypes.c_int32), ("near_waves_per_cu", ctypes.c_int32),
         ("quad_eps_mixed", ctypes.c_double), ("interior", ctypes.c_int32),
         ("translate_shape", ctypes.c_int32), ("near_split", ctypes.c_int32),
+        ("far_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -52,6 +52,7 @@ void set_paper(bem_options* o) {
   o->interior = 0;
   o->translate_shape = 0;
   o->near_split = 0;
+  o->far_rows = 0;
   o->use_graphs = 1;
 }
 
@@ -124,6 +125,8 @@ void check_options(const bem_options* o) {
       throw Error(BEM_E_ARG, "translate_shape must be 0, 64, 128 or 256, plus 4096 for the slab order");
   }
   if (o->near_split < 0 || o->near_split > 100) throw Error(BEM_E_ARG, "near_split must be in [0, 100]");
+  if (o->far_rows != 0 && o->far_rows != 1 && o->far_rows != kFarRows)
+    throw Error(BEM_E_ARG, "far_rows must be 0, 1 or " + std::to_string(kFarRows));
   if (o->use_graphs != 0 && o->use_graphs != 1) throw Error(BEM_E_ARG, "use_graphs must be 0 or 1");
   if (o->level_rows != 0 && o->level_rows != 1) throw Error(BEM_E_ARG, "level_rows must be 0 or 1");
   if (o->solver != 0 && o->solver != 1) throw Error(BEM_E_ARG, "solver must be 0 (GMRES) or 1 (CGS)");
@@ -303,6 +306,15 @@ void far_apply(bem_mesh* m, bem_op op, bem_precision prec, const double2* x, dou
   F.rec32 = m->d_rec32.p;
   F.kap = m->kap;
   F.kap32 = m->kap32;
+  // several points per wavefront pay in FP64, where the one-point kernel is
+  // bound by the L2 traffic of its loads (35.1 -> 30.9 ms on a 40500-element
+  // sphere); the FP32 kernel is bound by VALU issue and loses occupancy to
+  // the larger register set (11.1 -> 14.6 ms)
+  const bool rows = m->far_rows == kFarRows || (m->far_rows == 0 && prec == BEM_PREC_FP64);
+  if (rows && m->d_far_grp.n > 0) {
+    F.grp = m->d_far_grp.p;
+    F.ngrp = (int64_t)m->d_far_grp.n;
+  }
   launch_far_direct(F, prec == BEM_PREC_FP64, op != BEM_OP_A, vmode, x, y, s);
   BEM_HIP(hipGetLastError());
 }
@@ -350,6 +362,11 @@ void build_far_direct(bem_mesh* m, hipStream_t s) {
       (set == 0 ? m->far_rt2_min : m->far_rt2_min32)[mm - 1] = rt * rt;
     }
   }
+  std::vector<int64_t> grp;
+  for (int64_t c = 0; c < leaf.nc; ++c)
+    for (int64_t e = leaf.ebeg[c]; e < leaf.eend[c]; e += kFarRows)
+      grp.push_back(e * 8 + (std::min<int64_t>(kFarRows, leaf.eend[c] - e) - 1));
+  if (!grp.empty()) m->d_far_grp.upload(grp, s);
   m->d_elem_leaf.upload(el, s);
   m->d_far_off.upload(off, s);
   if (fb.empty()) {
@@ -670,6 +687,7 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
       const int t = o->translate_shape & ~kTranslateSlab;
       m->tune_tpb[0] = m->tune_tpb[1] = (t == 0 ? 64 : t) | (o->translate_shape & kTranslateSlab);
       m->tune_split[0] = m->tune_split[1] = o->near_split == 0 ? 100 : o->near_split;
+      m->far_rows = o->far_rows;
     }
     m->fmm = o->use_fmm != 0;
     m->far_direct = o->far_direct == 1;

@@ -78,7 +78,13 @@ struct FarLaunch {
   const double* rec;      // as in NearLaunch
   const float* rec32;
   double kap, kap32;
+  // forward operator on triangle meshes: groups of up to kFarRows
+  // consecutive collocation points of one leaf, one wavefront each, coded
+  // first * 8 + (count - 1); nullptr: one point per wavefront
+  const int64_t* grp;
+  int64_t ngrp;
 };
+constexpr int kFarRows = 4;
 // y += far(x) (adjoint: y += far^H x; vmode: the dA/dc part), tree order
 void launch_far_direct(const FarLaunch& F, bool fp64, bool adjoint, bool vmode, const double2* x, double2* y,
                        hipStream_t s);

@@ -24,6 +24,7 @@
 #include "device.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace bem {
 
@@ -1051,6 +1052,113 @@ __global__ __launch_bounds__(256) void k_far_direct(FarLaunch F, const double2* 
   }
 }
 
+// The forward direct far field on triangle meshes with several collocation
+// points per wavefront: the points of one group (up to G consecutive points
+// of one leaf cluster, F.grp) share the far list of their leaf, so each
+// source element's record, centre, area and x_j are loaded once per pass and
+// integrated against every point of the group.  Each point's contributions
+// arrive in the same order as in k_far_direct (the results agree to
+// rounding: the compiler may contract the two kernels differently); the
+// loads per pair drop G-fold (the one-point-per-wavefront kernel is bound by
+// the L2 traffic of these loads in FP64).
+template <typename T, bool HAS_C, bool VMODE, int G>
+__global__ __launch_bounds__(256) void k_far_rows(FarLaunch F, const double2* __restrict__ x,
+                                                  double2* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double kap = far_kap<T>(F);
+  __shared__ double2 s_ex[sizeof(T) == sizeof(double) ? kExpTab : 1];
+  const PointConsts<T> P = point_consts_staged<T>(F.k, kap, F.gre, F.gim, s_ex);  // whole block, before any exit
+  if (w >= F.ngrp) return;
+  const int64_t N = F.N;
+  const T* g = far_geom<T>(F);
+  const T* __restrict__ rec = far_rec<T>(F);
+  const int64_t code = F.grp[w];
+  const int64_t r0 = code >> 3;
+  const int nr = (int)(code & 7) + 1;  // points in the group, 1..G
+  const int leaf = F.elem_leaf[r0];
+  // per-lane partial sums of the group's points, lane-private in LDS (the
+  // point loop then needs no unrolling and the kernel no register array)
+  using V2 = typename std::conditional<sizeof(T) == sizeof(double), double2, float2>::type;
+  __shared__ V2 s_acc[4][G][64];
+  V2* acc = &s_acc[threadIdx.x >> 6][0][lane];
+  for (int u = 0; u < G; ++u) {
+    acc[64 * u].x = T(0);
+    acc[64 * u].y = T(0);
+  }
+  for (int64_t q = F.far_off[leaf]; q < F.far_off[leaf + 1]; ++q) {
+    const int64_t e = F.far_end[q];
+    for (int64_t base = F.far_beg[q]; base < e; base += 64) {
+      const int64_t o = base + lane;
+      const bool valid = o < e;
+      const int64_t j = valid ? o : r0;
+      T rj[kRec];
+      Rec<T>::load(rec, j, rj);
+      const double cj0 = (double)g[CX * N + j], cj1 = (double)g[(CX + 1) * N + j], cj2 = (double)g[(CX + 2) * N + j];
+      const double aj = (double)g[AREA * N + j];
+      const double2 xv = x[j];
+      T ccr = 0, cci = 0;
+      if (HAS_C && !VMODE) {
+        const double2 c = F.cfac[j];
+        ccr = (T)c.x;
+        cci = (T)c.y;
+      }
+#pragma unroll 1
+      for (int u = 0; u < nr; ++u) {
+        const int64_t r = r0 + u;
+        T xi[3], ni[3], xs[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xi[c] = g[(CX + c) * N + r];
+          ni[c] = g[(NX + c) * N + r];
+          xs[c] = (T)(kap * F.geom[(CX + c) * N + r]);
+        }
+        int m = -1;
+        if (valid) {
+          const double d0 = (double)xi[0] - cj0, d1 = (double)xi[1] - cj1, d2c = (double)xi[2] - cj2;
+          double d2 = 0.0;
+          d2 += d0 * d0;
+          d2 += d1 * d1;
+          d2 += d2c * d2c;
+          m = far_order<T>(F, d2, aj);
+        }
+        T s1r = 0, s1i = 0, s2r = 0, s2i = 0;
+        for (int mc = 1; mc <= kMaxRuleOrder; ++mc) {
+          if (__ballot(m == mc) == 0) continue;
+          if (m == mc)
+            integrate_loaded<T, !VMODE, HAS_C || VMODE, true>(rj, (uint64_t)j, mc, xs, ni, P, s1r, s1i, s2r, s2i);
+        }
+        if (__ballot(m == 0) != 0 && m == 0)
+          far_pair_split<T, !VMODE, HAS_C || VMODE, false>(F, g, rec, j, xi, xs, ni, P, s1r, s1i, s2r, s2i);
+        if (valid) {
+          T vr = s1r, vi = s1i;
+          if (VMODE) {
+            vr = s2r;
+            vi = s2i;
+          } else if (HAS_C) {
+            vr += ccr * s2r - cci * s2i;
+            vi += ccr * s2i + cci * s2r;
+          }
+          const T xa = (T)xv.x, xb = (T)xv.y;
+          T ar = acc[64 * u].x, ai = acc[64 * u].y;
+          ar += vr * xa - vi * xb;
+          ai += vr * xb + vi * xa;
+          acc[64 * u].x = ar;
+          acc[64 * u].y = ai;
+        }
+      }
+    }
+  }
+  for (int u = 0; u < nr; ++u) {
+    const double sr = wave_sum((double)acc[64 * u].x);
+    const double si = wave_sum((double)acc[64 * u].y);
+    if (lane == 0) {
+      const double2 yo = y[r0 + u];
+      y[r0 + u] = make_double2(yo.x + sr, yo.y + si);
+    }
+  }
+}
+
 // ------------------------------------------------ preconditioner blocks ---
 // One wavefront per row t: the row's near items whose source lies in t's block
 // (B.items: a compact per-row list built with the blocks) are integrated (FP64)
@@ -1575,6 +1683,11 @@ void launch_field(const FieldArgs& A, const double* pts, const double2* p, const
 
 template <typename T, bool HAS_C, bool VMODE, bool ADJ>
 void far_launch_t(const FarLaunch& F, const double2* x, double2* y, hipStream_t s) {
+  if (!ADJ && !F.Q.nh && F.grp && F.ngrp > 0) {
+    hipLaunchKernelGGL((k_far_rows<T, HAS_C, VMODE, kFarRows>), dim3(blocks_for(F.ngrp, 4)), dim3(256), 0, s, F, x,
+                       y);
+    return;
+  }
   if (F.Q.nh)
     hipLaunchKernelGGL((k_far_direct<T, HAS_C, VMODE, ADJ, true>), dim3(blocks_for(F.N, 4)), dim3(256), 0, s, F, x, y);
   else

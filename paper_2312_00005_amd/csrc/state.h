@@ -102,6 +102,10 @@ struct bem_mesh {
   bool far_direct64 = false;
   bem::DevBuf<int32_t> d_elem_leaf;
   bem::DevBuf<int64_t> d_far_off, d_far_beg, d_far_end;
+  // groups of up to kFarRows collocation points of one leaf for the forward
+  // direct far field (first * 8 + count - 1); far_rows as in bem_options
+  bem::DevBuf<int64_t> d_far_grp;
+  int far_rows = 0;
   double far_rt2_min[8] = {0};    // r~^2 thresholds of the orders (quad_eps)
   double far_rt2_min32[8] = {0};  // the same for the complex-FP32 operator (quad_eps_mixed)
 

@@ -67,3 +67,32 @@ def test_far_direct_solve_matches_lu(bem):
     p, _, info = m.solve(m.rhs_plane_wave((0.0, 0.0, 1.0)))
     assert info["rel_residual"] < 1e-12
     assert rel_max(to_host(p), op.lu_solve(A, b)) < 1e-10
+
+
+@pytest.mark.parametrize("pre,adm,levels,leaf,k,with_beta", CASES)
+def test_far_rows_match_one_point_per_wavefront(bem, pre, adm, levels, leaf, k, with_beta):
+    """The forward direct far field with four collocation points of a leaf
+    per wavefront (far_rows = 4, the default) sums every point's pairs in the
+    order of the one-point-per-wavefront kernel; the compiler may contract
+    the two kernels' arithmetic differently, so they agree to rounding:
+    1e-13 (FP64) and 1e-6 (complex FP32) relative to max|y|, with admittance
+    and for dA/dc."""
+    announce(f"far rows ico3 {pre} adm={adm:.3f} levels={levels} leaf={leaf} k={k} beta={with_beta}")
+    nodes, tris = synth.icosphere(3)
+    N = len(tris)
+    beta = (1.0 + 0.5 * synth.uniform01(N, seed=1)) + 0.3j if with_beta else None
+    meshes = [bem.Mesh(nodes, tris, pre, use_fmm=1, levels=levels, leaf_size=leaf, admissibility=adm, far_direct=1,
+                       far_rows=r) for r in (1, 4)]
+    for m in meshes:
+        m.set_problem(k, None if beta is None else to_dev(beta))
+    xd = to_dev(synth.complex_normal(N, seed=4))
+    for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):
+        a, b = (to_host(m.apply_part(xd, 2, prec=prec)) for m in meshes)
+        e = rel_max(b, a)
+        announce(f"  {prec}: far_rows 4 vs 1 {e:.1e}")
+        assert e < tol
+    if with_beta:
+        a, b = (to_host(m.apply_dc(xd)) for m in meshes)
+        assert rel_max(b, a) < 1e-13
+    for m in meshes:
+        m.close()
