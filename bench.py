@@ -81,6 +81,12 @@ def parse():
                          "SQ_ACTIVE_INST_VALU, SQ_WAVES, GRBM_GUI_ACTIVE) as a markdown summary")
     ap.add_argument("--profile-far-only", action="store_true",
                     help="run only far-field (FMM) applications, then the calibration copy")
+    ap.add_argument("--profile-far-direct", action="store_true",
+                    help="c4 mesh (40500 elements, depth 4) at 9382.3 Hz, the sweep's first direct-far-field "
+                         "frequency: only direct far-field applications (precision --profile-prec, "
+                         "--far-rows points per wavefront), then the calibration copy")
+    ap.add_argument("--far-rows", type=int, default=0, choices=(0, 1, 4),
+                    help="bem_options.far_rows of the --profile-far-direct mesh")
     ap.add_argument("--profile-prec", default="mixed", choices=("mixed", "fp64"),
                     help="operator precision of the --profile-near-only / --profile-far-only applications")
     ap.add_argument("--summarize-translate", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -309,6 +315,8 @@ def main():
     from paper_2312_00005_amd import bemfmm
 
     wl = WORKLOADS[args.workload]
+    if args.profile_far_direct:
+        return profile_far_direct(args)
     if wl.get("sweep"):
         return run_sweep(args, wl)
     src = None
@@ -500,6 +508,31 @@ def load_golden(workload, N, k):
     if int(z["N"]) != N or abs(float(z["k"]) - k) > 1e-12 * k:
         raise SystemExit(f"{path} holds another workload (N={int(z['N'])}, k={float(z['k'])})")
     return {"y_ax": z["y_ax"], "p_lu": z["p_lu"]}
+
+
+def profile_far_direct(args):
+    """Direct far-field applications alone on the c4 mesh, for counter runs."""
+    import torch
+    import synth
+    from paper_2312_00005_amd import bemfmm
+    from paper_2312_00005_amd.sweep import wavenumbers
+
+    nodes, tris = synth.geodesic_sphere(WORKLOADS["c4"]["mesh"][1])
+    torch.cuda.set_device(0)
+    m = bemfmm.Mesh(nodes, tris, WORKLOADS["c4"]["preset"], use_fmm=1, levels=4, leaf_size=32, far_direct=1,
+                    far_rows=args.far_rows)
+    m.set_problem(wavenumbers([9382.3])[0])
+    x = torch.from_numpy(synth.complex_normal(len(tris), seed=4)).to("cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup + args.steps):
+        m.apply_part(x, 2, prec=args.profile_prec, out=y)
+    src = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"profiled {args.warmup + args.steps} direct far-field applications ({args.profile_prec}, far_rows "
+        f"{args.far_rows}) and one {CAL_BYTES} B copy")
+    m.close()
 
 
 def run_sweep(args, wl):
