@@ -89,6 +89,10 @@ def test_invalid_arguments(bem):
         with pytest.raises(bem.BemError) as e:
             bem.Mesh(nodes, tris, "paper", use_fmm=0, near_waves_per_cu=nw)
         assert e.value.status == bem.BEM_E_ARG
+    for fr in (-1, 2, 8):
+        with pytest.raises(bem.BemError) as e:
+            bem.Mesh(nodes, tris, "paper", use_fmm=0, far_rows=fr)
+        assert e.value.status == bem.BEM_E_ARG
     with pytest.raises(bem.BemError):
         bem.bem_mesh_create(3, None, 1, None, bem.bem_options_default("paper"))
 
