@@ -492,7 +492,10 @@ void bem_mesh_destroy(bem_mesh* m);
 /* ---- host-only inspection of the frequency-independent plan -------------
  * bem_tree_build runs the same geometry, cluster-tree and near-field-plan
  * construction as bem_mesh_create but touches no device; it exists so that
- * the tree and plan can be inspected and tested without a GPU.  Levels are
+ * the tree and plan can be inspected and tested without a GPU.  The near
+ * plan is built on the first bem_tree_plan_stats call (which then reports
+ * its errors, e.g. BEM_E_MESH for too many nested subdivisions); the tree
+ * queries and bem_tree_fmm_lengths need only the tree.  Levels are
  * numbered from the root (0).  Arrays are written by the caller-sized output
  * pointers (any may be NULL): z[3 nc], r[nc], ebeg/eend/parent[nc] (element
  * ranges in tree order; parent index on the level above, -1 at the root),
@@ -526,6 +529,18 @@ bem_status bem_tree_fmm_lengths(const bem_tree* t, double k, const bem_options* 
                                 double* bytes);
 
 void bem_tree_destroy(bem_tree* t);
+
+/* A mesh on a host tree's geometry, cluster tree and near plan (the plan is
+ * built here if bem_tree_plan_stats has not built it yet), equal to
+ * bem_mesh_create on the tree's mesh and options but without building the
+ * plan again: for several meshes of one tree that differ in their far-field
+ * method, precision, solver or launch options (a frequency sweep).  The
+ * options' tree and plan fields (use_fmm, levels, leaf_size, root_box_edge,
+ * admissibility, quad_eps, quad_m_max, quad_split_on_cap, subdiv_ratio,
+ * max_subdiv) must equal the tree's, else BEM_E_ARG.  The mesh copies what it
+ * needs; the tree may be destroyed afterwards. */
+bem_status bem_mesh_create_from_tree(const bem_tree* t, const bem_options* o, void* stream,
+                                     bem_mesh** out);
 
 /* ---- evaluation grid: pressure at many field points with the FMM ----------
  * The paper's evaluation points (output appendix; the sphere benchmark of

@@ -98,6 +98,7 @@ _dbl = ctypes.c_double
 _SIGS = {
     "bem_options_default": (_i32, [ctypes.POINTER(bem_options), ctypes.c_char_p]),
     "bem_mesh_create": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), _vp, ctypes.POINTER(_vp)]),
+    "bem_mesh_create_from_tree": (_i32, [_vp, ctypes.POINTER(bem_options), _vp, ctypes.POINTER(_vp)]),
     "bem_mesh_create_elements": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(bem_options), _vp,
                                         ctypes.POINTER(_vp)]),
     "bem_set_allocator": (_i32, [_vp, _vp, _vp]),
@@ -171,6 +172,13 @@ def bem_mesh_create_elements(n_nodes, xyz_ptr, n_el, el_ptr, options, stream=Non
     out = _vp()
     st = _lib.bem_mesh_create_elements(n_nodes, xyz_ptr, n_el, el_ptr, ctypes.byref(options), stream,
                                        ctypes.byref(out))
+    _check(st)
+    return out
+
+
+def bem_mesh_create_from_tree(tree, options, stream=None):
+    out = _vp()
+    st = _lib.bem_mesh_create_from_tree(tree, ctypes.byref(options), stream, ctypes.byref(out))
     _check(st)
     return out
 
@@ -586,6 +594,25 @@ class Mesh:
         self._h = create(self._nodes.shape[0], self._nodes.ctypes.data, self.n, self._tris.ctypes.data, options,
                          _stream())
         self._beta = None
+
+    @classmethod
+    def from_tree(cls, tree, options=None, **overrides):
+        """A mesh on a HostTree's geometry, tree and near plan (built once in
+        the tree and copied): options default to the tree's, with overrides;
+        the tree and plan fields must stay the tree's."""
+        m = cls.__new__(cls)
+        m._h = None
+        if options is None:
+            options = bem_options.from_buffer_copy(tree.options)
+        elif isinstance(options, str):
+            options = bem_options_default(options)
+        for key, val in overrides.items():
+            setattr(options, key, val)
+        m.options = options
+        m._nodes, m._tris, m.n = tree._nodes, tree._tris, tree.n
+        m._beta = None
+        m._h = bem_mesh_create_from_tree(tree._h, options, _stream())
+        return m
 
     def close(self):
         if self._h:

@@ -432,12 +432,12 @@ void build_blocks(bem_mesh* m, int max_n, hipStream_t s) {
   std::vector<int64_t> bseg((size_t)m->N * (kMaxRuleOrder + 1));
   for (int64_t t = 0; t < m->N; ++t) {
     const int64_t b0 = beg[eb[t]], b1 = b0 + nn[eb[t]];
-    const int64_t* sg = m->plan.seg.data() + t * (kMaxRuleOrder + 1);
+    const int64_t* sg = m->plan->seg.data() + t * (kMaxRuleOrder + 1);
     for (int mc = 0; mc < kMaxRuleOrder; ++mc) {
       bseg[t * (kMaxRuleOrder + 1) + mc] = (int64_t)bitems.size();
       for (int64_t it = sg[mc]; it < sg[mc + 1]; ++it) {
-        const int64_t j = m->g.owner((int64_t)(m->plan.items[it] & ((uint64_t(1) << 26) - 1)));
-        if (j >= b0 && j < b1) bitems.push_back(m->plan.items[it]);
+        const int64_t j = m->g.owner((int64_t)(m->plan->items[it] & ((uint64_t(1) << 26) - 1)));
+        if (j >= b0 && j < b1) bitems.push_back(m->plan->items[it]);
       }
     }
     bseg[t * (kMaxRuleOrder + 1) + kMaxRuleOrder] = (int64_t)bitems.size();
@@ -488,7 +488,7 @@ void setup_preconditioner(bem_mesh* m, hipStream_t s) {
 
 void ensure_transposed_plan(bem_mesh* m, hipStream_t s) {
   if (m->have_plan_t) return;
-  const NearPlan& P = m->plan;
+  const NearPlan& P = *m->plan;
   const int64_t N = m->N;
   NearPlan T;
   T.off.assign(N + 1, 0);
@@ -530,8 +530,10 @@ namespace {
 
 // Geometry, cluster tree and near-field plan on the host (no device work).
 // el: n_tri x 4 vertex indices (el[4 e + 3] < 0: triangle)
-void build_host(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri, const bem_options& o,
-                Tree& tree, Geometry& g, NearPlan& plan, int64_t& bad_element) {
+// Geometry and cluster tree (the tree-order geometry g; without use_fmm the
+// caller order and no tree).
+void build_host_tree(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri, const bem_options& o,
+                     Tree& tree, Geometry& g, int64_t& bad_element) {
   std::vector<int64_t> ident(n_tri);
   for (int64_t i = 0; i < n_tri; ++i) ident[i] = i;
   Geometry gc;
@@ -541,11 +543,23 @@ void build_host(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t
     bad_element = e.element;
     throw;
   }
-  std::vector<int64_t> src_off, src_beg, src_end, tgt_group(n_tri, 0);
   if (o.use_fmm) {
     int levels = o.levels > 0 ? o.levels : default_levels(n_tri);
     tree = build_tree(gc, levels, o.root_box_edge, o.leaf_size, o.admissibility);
     g = build_geometry(xyz, n_nodes, tri, n_tri, tree.perm);
+  } else {
+    tree.perm = ident;
+    tree.inv = ident;
+    g = std::move(gc);
+  }
+}
+
+// The near-field quadrature plan of a tree (all pairs without use_fmm).
+void build_host_plan(const Tree& tree, const Geometry& g, const bem_options& o, NearPlan& plan,
+                     int64_t& bad_element) {
+  const int64_t n_tri = g.N;
+  std::vector<int64_t> src_off, src_beg, src_end, tgt_group(n_tri, 0);
+  if (o.use_fmm) {
     const Level& leaf = tree.lv.back();
     src_off.assign(leaf.nc + 1, 0);
     for (int64_t c = 0; c < leaf.nc; ++c) {
@@ -558,9 +572,6 @@ void build_host(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t
       src_off[c + 1] = (int64_t)src_beg.size();
     }
   } else {
-    tree.perm = ident;
-    tree.inv = ident;
-    g = std::move(gc);
     src_off = {0, 1};
     src_beg = {0};
     src_end = {n_tri};
@@ -573,6 +584,12 @@ void build_host(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t
     throw Error(e.code, "more than max_subdiv nested subdivisions for element " + std::to_string(bad_element),
                 bad_element);
   }
+}
+
+void build_host(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri, const bem_options& o,
+                Tree& tree, Geometry& g, NearPlan& plan, int64_t& bad_element) {
+  build_host_tree(n_nodes, xyz, n_tri, tri, o, tree, g, bad_element);
+  build_host_plan(tree, g, o, plan, bad_element);
 }
 
 void validate_mesh_args(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri) {
@@ -598,7 +615,20 @@ struct bem_tree {
   bool fmm = false;
   Tree tree;
   Geometry g;
-  NearPlan plan;
+  bem_options opt{};
+  // the near plan is built on first use (bem_tree_plan_stats, or a mesh made
+  // from the tree, which shares it): the tree alone serves
+  // bem_tree_fmm_lengths and the level queries
+  mutable std::shared_ptr<NearPlan> plan;
+  const NearPlan& ensure_plan() const {
+    if (!plan) {
+      auto p = std::make_shared<NearPlan>();
+      int64_t bad = -1;
+      build_host_plan(tree, g, opt, *p, bad);
+      plan = std::move(p);
+    }
+    return *plan;
+  }
 };
 
 extern "C" {
@@ -649,7 +679,7 @@ bem_status bem_options_default(bem_options* o, const char* preset) {
 
 namespace {
 bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
-                       const bem_options* o, void* stream, bem_mesh** out);
+                       const bem_options* o, void* stream, bem_mesh** out, const bem_tree* src = nullptr);
 }
 
 bem_status bem_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
@@ -676,7 +706,7 @@ bem_status bem_mesh_create_elements(int64_t n_nodes, const double* xyz, int64_t 
 namespace {
 // el: n_tri x 4 (validated by the caller); runs inside the caller's guard
 bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const int32_t* tri,
-                       const bem_options* o, void* stream, bem_mesh** out) {
+                       const bem_options* o, void* stream, bem_mesh** out, const bem_tree* src) {
   {
     check_options(o);
     auto m = std::make_unique<bem_mesh>();
@@ -692,7 +722,16 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
     m->fmm = o->use_fmm != 0;
     m->far_direct = o->far_direct == 1;
     m->far_direct64 = o->far_direct == 2;
-    build_host(n_nodes, xyz, n_tri, tri, *o, m->tree, m->g, m->plan, m->bad_element);
+    if (src) {
+      // the host tree's geometry, tree and near plan (built there once)
+      src->ensure_plan();
+      m->tree = src->tree;
+      m->g = src->g;
+      m->plan = src->plan;
+    } else {
+      m->plan = std::make_shared<NearPlan>();
+      build_host(n_nodes, xyz, n_tri, tri, *o, m->tree, m->g, *m->plan, m->bad_element);
+    }
     {
       int dev = 0, ncu = 0;
       BEM_HIP(hipGetDevice(&dev));
@@ -715,9 +754,9 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
     m->d_rec.alloc((size_t)(n_tri + 2 * m->g.nq) * 16);
     m->d_rec32.alloc((size_t)(n_tri + 2 * m->g.nq) * 16);
     m->d_perm.upload(m->tree.perm, s);
-    m->d_off.upload(m->plan.off, s);
-    m->d_seg.upload(m->plan.seg, s);
-    m->d_items.upload(m->plan.items, s);
+    m->d_off.upload(m->plan->off, s);
+    m->d_seg.upload(m->plan->seg, s);
+    m->d_items.upload(m->plan->items, s);
     {
       // forward near-field schedule: groups of targets by decreasing work, the
       // work of a target being its wavefront passes (64 items each) weighted
@@ -725,7 +764,7 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
       std::vector<double> work(n_tri, 0.0);
       for (int64_t t = 0; t < n_tri; ++t)
         for (int mm = 1; mm <= kMaxRuleOrder; ++mm) {
-          const int64_t cnt = m->plan.seg[t * (kMaxRuleOrder + 1) + mm] - m->plan.seg[t * (kMaxRuleOrder + 1) + mm - 1];
+          const int64_t cnt = m->plan->seg[t * (kMaxRuleOrder + 1) + mm] - m->plan->seg[t * (kMaxRuleOrder + 1) + mm - 1];
           work[t] += (double)((cnt + 63) / 64) * (mm * mm + 2);
         }
       // whole leaf clusters move together (their targets share sources, so
@@ -1348,9 +1387,9 @@ void fill_info(const bem_mesh* m, const SolveResult& r, bem_solve_info* info) {
       info->iterations = r.iterations;
       info->refinements = r.refinements;
       info->rel_residual = r.rel_residual;
-      info->near_pairs = m->plan.pairs;
-      info->near_items = (int64_t)m->plan.items.size();
-      info->quad_points = m->plan.points;
+      info->near_pairs = m->plan->pairs;
+      info->near_items = (int64_t)m->plan->items.size();
+      info->quad_points = m->plan->points;
       if (m->fmm) {
         info->levels = (int)m->tree.lv.size();
         for (int l = 0; l < info->levels && l < 16; ++l) {
@@ -1395,9 +1434,9 @@ bem_status bem_mesh_stats(const bem_mesh* m, int32_t* levels, int32_t* clusters,
     if (levels) *levels = nl;
     if (clusters)
       for (int l = 0; l < nl; ++l) clusters[l] = (int32_t)m->tree.lv[l].nc;
-    if (near_pairs) *near_pairs = m->plan.pairs;
-    if (near_items) *near_items = (int64_t)m->plan.items.size();
-    if (quad_points) *quad_points = m->plan.points;
+    if (near_pairs) *near_pairs = m->plan->pairs;
+    if (near_items) *near_items = (int64_t)m->plan->items.size();
+    if (quad_points) *quad_points = m->plan->points;
     return BEM_OK;
   });
 }
@@ -1471,11 +1510,31 @@ bem_status bem_tree_build(int64_t n_nodes, const double* xyz, int64_t n_tri, con
     auto t = std::make_unique<bem_tree>();
     t->N = n_tri;
     t->fmm = o->use_fmm != 0;
+    t->opt = *o;
     int64_t bad = -1;
     const std::vector<int32_t> el = as_elements(n_tri, tri);
-    build_host(n_nodes, xyz, n_tri, el.data(), *o, t->tree, t->g, t->plan, bad);
+    build_host_tree(n_nodes, xyz, n_tri, el.data(), *o, t->tree, t->g, bad);
     *out = t.release();
     return BEM_OK;
+  });
+}
+
+bem_status bem_mesh_create_from_tree(const bem_tree* t, const bem_options* o, void* stream, bem_mesh** out) {
+  return guarded([&]() -> bem_status {
+    if (!out) return fail(BEM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!t || !o) return fail(BEM_E_ARG, "NULL argument");
+    const bem_options& a = t->opt;
+    const bool same = a.use_fmm == o->use_fmm && a.levels == o->levels && a.leaf_size == o->leaf_size &&
+                      a.root_box_edge == o->root_box_edge && a.admissibility == o->admissibility &&
+                      a.quad_eps == o->quad_eps && a.quad_m_max == o->quad_m_max &&
+                      a.quad_split_on_cap == o->quad_split_on_cap && a.subdiv_ratio == o->subdiv_ratio &&
+                      a.max_subdiv == o->max_subdiv;
+    if (!same)
+      return fail(BEM_E_ARG, "the options' tree and near-plan fields (use_fmm, levels, leaf_size, root_box_edge, "
+                             "admissibility, quad_eps, quad_m_max, quad_split_on_cap, subdiv_ratio, max_subdiv) "
+                             "differ from the tree's");
+    return create_mesh(0, nullptr, t->N, nullptr, o, stream, out, t);
   });
 }
 
@@ -1525,9 +1584,10 @@ bem_status bem_tree_perm(const bem_tree* t, int64_t* perm) {
 bem_status bem_tree_plan_stats(const bem_tree* t, int64_t* pairs, int64_t* items, int64_t* points) {
   return guarded([&]() -> bem_status {
     if (!t) return fail(BEM_E_ARG, "NULL argument");
-    if (pairs) *pairs = t->plan.pairs;
-    if (items) *items = (int64_t)t->plan.items.size();
-    if (points) *points = t->plan.points;
+    const NearPlan& P = t->ensure_plan();
+    if (pairs) *pairs = P.pairs;
+    if (items) *items = (int64_t)P.items.size();
+    if (points) *points = P.points;
     return BEM_OK;
   });
 }

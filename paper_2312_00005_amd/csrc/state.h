@@ -24,7 +24,7 @@ struct bem_mesh {
   bool fmm = false;
   bem::Tree tree;
   bem::Geometry g;                 // tree order
-  bem::NearPlan plan;              // items by target
+  std::shared_ptr<bem::NearPlan> plan;  // items by target (shared with the host tree it came from)
   bool have_plan_t = false;
   bem::NearPlan plan_t;            // items by source (conjugate transpose)
   int64_t bad_element = -1;

@@ -103,19 +103,23 @@ class FrequencySweep:
             raise NotImplementedError("concurrent frequencies from several host threads are disabled "
                                       "(a host crash was seen in that mode and its cause is not known)")
         t0 = time.perf_counter()
+        # host trees by depth (their near plans are built when a mesh of that
+        # depth is first made from them, and shared by its method groups)
+        self.trees = {}
         if policy == "paper":
             self.methods = paper_methods(nodes, tris, self.ks, requested, max(depths))
             self.lengths = [None] * len(self.ks)
         elif policy == "stability":
-            trees = {d: bemfmm.HostTree(nodes, tris, preset, levels=d, leaf_size=leaf_size, **overrides)
-                     for d in depths}
+            self.trees = {d: bemfmm.HostTree(nodes, tris, preset, levels=d, leaf_size=leaf_size, **overrides)
+                          for d in depths}
             opts = bemfmm.bem_options_default(preset)
             for key, val in overrides.items():
                 setattr(opts, key, val)
             mixed = opts.precision != 0
-            self.methods = choose_methods(trees, self.ks, max_L=max_L, memory_budget=memory_budget, mixed=mixed)
-            self.lengths = [trees[d].fmm_lengths(k) for (kind, d), k in zip(self.methods, self.ks)]
-            del trees
+            self.methods = choose_methods(self.trees, self.ks, max_L=max_L, memory_budget=memory_budget, mixed=mixed)
+            self.lengths = [self.trees[d].fmm_lengths(k) for (kind, d), k in zip(self.methods, self.ks)]
+            used = {d for _, d in self.methods}
+            self.trees = {d: t for d, t in self.trees.items() if d in used}
         else:
             raise ValueError(f"unknown policy {policy!r}")
         self.plan_seconds = time.perf_counter() - t0
@@ -124,8 +128,11 @@ class FrequencySweep:
         kind, d = method
         if kind == "dense":
             return bemfmm.Mesh(self.nodes, self.tris, self.preset, use_fmm=0, **self.overrides)
+        far = {"direct": 1, "fmm32": 2}.get(kind, 0)
+        if d in self.trees:
+            return bemfmm.Mesh.from_tree(self.trees[d], far_direct=far)
         return bemfmm.Mesh(self.nodes, self.tris, self.preset, use_fmm=1, levels=d, leaf_size=self.leaf_size,
-                           far_direct={"direct": 1, "fmm32": 2}.get(kind, 0), **self.overrides)
+                           far_direct=far, **self.overrides)
 
     @classmethod
     def from_curve(cls, nodes, tris, n_steps, stepsize, s0, freq_curve, **kw):

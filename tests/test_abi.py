@@ -122,3 +122,17 @@ def test_allocator_hook_arguments(bem):
         bem.bem_set_allocator(alloc, None)
     assert e.value.status == bem.BEM_E_ARG
     bem.bem_set_allocator(None, None)
+
+
+def test_mesh_from_tree_checks_the_tree_options(bem):
+    """bem_mesh_create_from_tree refuses options whose tree or near-plan
+    fields differ from the host tree's, before any device work."""
+    nodes, tris = synth.icosphere(2)
+    t = bem.HostTree(nodes, tris, "tight", use_fmm=1, levels=2, leaf_size=16)
+    for key, val in (("levels", 3), ("leaf_size", 32), ("quad_eps", 1e-6), ("admissibility", 2.0)):
+        with pytest.raises(bem.BemError) as e:
+            bem.Mesh.from_tree(t, **{key: val})
+        assert e.value.status == bem.BEM_E_ARG
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_mesh_create_from_tree(None, bem.bem_options_default("tight"))
+    assert e.value.status == bem.BEM_E_ARG

@@ -159,3 +159,31 @@ def test_sweep_paper_policy():
         err = rel_l2(to_host(r["p"]), ref)
         announce(f"  f={r['f']:.0f} {r['method']} it={r['info']['iterations']} vs LU {err:.2e}")
         assert err < (1e-9 if r["method"][0] == "dense" else 1e-3)
+
+
+def test_mesh_from_tree_equals_a_new_mesh():
+    """A mesh made from a host tree (bem_mesh_create_from_tree: the tree's
+    geometry, cluster tree and near plan, shared by the sweep's method groups
+    of one depth) applies the same operator as a mesh built from the arrays,
+    bit for bit, for each far-field method and both precisions."""
+    from paper_2312_00005_amd import bemfmm
+    import torch
+    announce("mesh from a host tree vs a new mesh, ico3 depth 3")
+    nodes, tris = synth.icosphere(3)
+    t = bemfmm.HostTree(nodes, tris, "mixed", levels=3, leaf_size=16)
+    x = torch.from_numpy(synth.complex_normal(len(tris), seed=4)).to("cuda")
+    for far in (0, 1, 2):
+        a = bemfmm.Mesh.from_tree(t, far_direct=far)
+        b = bemfmm.Mesh(nodes, tris, "mixed", levels=3, leaf_size=16, far_direct=far)
+        assert a.stats() == b.stats()
+        for m in (a, b):
+            m.set_problem(3.5)
+        for prec in ("fp64", "mixed"):
+            for o in ("A", "AH"):
+                ya, yb = (to_host(m.apply(x, op=o, prec=prec)) for m in (a, b))
+                assert np.array_equal(ya, yb), (far, prec, o)
+        pa, _, ia = a.solve(a.rhs_plane_wave())
+        pb, _, ib = b.solve(b.rhs_plane_wave())
+        assert ia["iterations"] == ib["iterations"] and np.array_equal(to_host(pa), to_host(pb))
+        a.close()
+        b.close()
