@@ -575,7 +575,8 @@ def run_sweep(args, wl):
                    "n_elements": N, "frequencies": len(freqs)},
         "solve_s_per_frequency": tot["wall_s"] / len(freqs),
         "solve_s_per_frequency_excluding_plans": solve_time / len(freqs),
-        "sweep": {"wall_s": tot["wall_s"], "mesh_setup_s": tot["mesh_setup_s"],
+        "sweep": {"wall_s": tot["wall_s"], "mesh_setup_s": tot["mesh_setup_s"], "probe_s": tot["probe_s"],
+                  "probes": S.probes,
                   "plan_choice_s": tot["plan_choice_s"], "operator_applications": matvecs,
                   "direct_far_field_frequencies": n_direct,
                   "fp32_fmm_fp64_direct_frequencies": n_fmm32, "per_frequency": per},

@@ -78,11 +78,17 @@ class FrequencySweep:
 
     def __init__(self, nodes, tris, freqs, c=343.0, preset="mixed", depths=(4, 3, 2), leaf_size=32,
                  memory_budget=96e9, max_L=120, streams=1, steps=None, admittance=None, rho=1.21, batch=1,
-                 policy="stability", requested=bemfmm.BEM_METHOD_MLFMM, **overrides):
+                 policy="stability", requested=bemfmm.BEM_METHOD_MLFMM, probe=True, **overrides):
         """policy: "stability" (the deepest tree whose expansion the stability
         cap leaves intact, else the direct far field) or "paper" (the paper's
         automatic switches between the conventional method, the single-level
-        and the multilevel FMM, from the requested method)."""
+        and the multilevel FMM, from the requested method).
+        probe (mixed path, stability policy): before solving, the frequencies
+        given "fmm32" (FP64 lengths shortened by the stability cap, FP64
+        operator integrating the far field directly) are probed on the device:
+        where the capped FP64 FMM applies the same operator as the direct far
+        field to a tenth of the GMRES tolerance (relative l2 on a seeded
+        vector), the FP64 operator keeps the FMM ("fmm")."""
         """steps / admittance: the frequency step s of every frequency and a
         list of curves.AdmittanceGroup; each frequency is then solved with
         beta = rho c Y(s) per element (Y = 0, sound hard, outside the groups)."""
@@ -99,6 +105,9 @@ class FrequencySweep:
         self.overrides = overrides
         self.streams = max(1, int(streams))
         self.batch = max(1, int(batch))
+        self.probe = bool(probe)
+        self.probes = []
+        self._spare = {}  # method -> a mesh made for the probe, reused by that method's group
         if self.streams > 1:
             raise NotImplementedError("concurrent frequencies from several host threads are disabled "
                                       "(a host crash was seen in that mode and its cause is not known)")
@@ -134,6 +143,54 @@ class FrequencySweep:
         return bemfmm.Mesh(self.nodes, self.tris, self.preset, use_fmm=1, levels=d, leaf_size=self.leaf_size,
                            far_direct=far, **self.overrides)
 
+    def _probe_capped(self):
+        """Relabel "fmm32" frequencies as "fmm" where the capped FP64 FMM is
+        as good as the direct far field for this solve: relative l2 difference
+        of the two FP64 far fields on a seeded vector at most a tenth of the
+        GMRES tolerance.  The cap shortens the expansion less as k grows, so
+        within one depth the test is monotone in k: a binary search finds the
+        lowest frequency that passes and every higher one passes with it."""
+        import torch
+        opts = bemfmm.bem_options_default(self.preset)
+        for key, val in self.overrides.items():
+            setattr(opts, key, val)
+        tol = 0.1 * opts.gmres_tol
+        by_depth = {}
+        for i, (kind, d) in enumerate(self.methods):
+            if kind == "fmm32" and d in self.trees:
+                by_depth.setdefault(d, []).append(i)
+        for d, idx in by_depth.items():
+            idx = sorted(idx, key=lambda i: self.ks[i])
+            mf = bemfmm.Mesh.from_tree(self.trees[d], far_direct=0)
+            md = bemfmm.Mesh.from_tree(self.trees[d], far_direct=1)
+            gen = torch.Generator().manual_seed(20231200)
+            n = mf.n
+            x = torch.complex(torch.randn(n, generator=gen, dtype=torch.float64),
+                              torch.randn(n, generator=gen, dtype=torch.float64)).to("cuda")
+
+            def passes(i):
+                b = self.beta(i)
+                for m in (mf, md):
+                    m.set_problem(self.ks[i], b)
+                y0 = mf.apply_part(x, 2, prec="fp64")
+                y1 = md.apply_part(x, 2, prec="fp64")
+                err = float(torch.linalg.norm(y0 - y1) / torch.linalg.norm(mf.apply(x, prec="fp64")))
+                self.probes.append({"f": self.freqs[i], "depth": d, "rel_l2": err, "pass": err <= tol})
+                return err <= tol
+
+            lo, hi = 0, len(idx)
+            while lo < hi:
+                mid = (lo + hi) // 2
+                if passes(idx[mid]):
+                    hi = mid
+                else:
+                    lo = mid + 1
+            for i in idx[lo:]:
+                self.methods[i] = ("fmm", d)
+            md.close()
+            # the FMM mesh serves the "fmm" group of this depth
+            self._spare[("fmm", d)] = mf
+
     @classmethod
     def from_curve(cls, nodes, tris, n_steps, stepsize, s0, freq_curve, **kw):
         """Frequencies f_n = freq_curve(s0 + stepsize n), n = 1 .. n_steps."""
@@ -167,12 +224,17 @@ class FrequencySweep:
         set up (one per mesh) and solved together by bem_solve_batch; a
         frequency's seconds are then its share of the batch."""
         import torch
+        t0 = time.perf_counter()
+        t_probe = 0.0
+        if self.probe and any(m[0] == "fmm32" for m in self.methods):
+            self._probe_capped()
+            torch.cuda.synchronize()
+            t_probe = time.perf_counter() - t0
         groups = {}
         for i, m in enumerate(self.methods):
             groups.setdefault(m, []).append(i)
         results = [None] * len(self.ks)
-        t_setup = 0.0
-        t0 = time.perf_counter()
+        t_setup = t_probe
         for method, idx in groups.items():
             # the expansion tables grow with k and a buffer is only reallocated
             # when it grows: from the highest k down, every frequency of the
@@ -181,7 +243,8 @@ class FrequencySweep:
             # at ~40 GB, after earlier groups had freed theirs)
             idx = sorted(idx, key=lambda i: -self.ks[i])
             ts = time.perf_counter()
-            meshes = [self._mesh(method) for _ in range(min(self.batch, len(idx)))]
+            meshes = [self._spare.pop(method) if j == 0 and method in self._spare else self._mesh(method)
+                      for j in range(min(self.batch, len(idx)))]
             t_setup += time.perf_counter() - ts
             for c0 in range(0, len(idx), len(meshes)):
                 chunk = idx[c0:c0 + len(meshes)]
@@ -207,7 +270,10 @@ class FrequencySweep:
                                   "solve_seconds": (t3 - t2) / len(chunk), "p": p if keep_solutions else None}
             for mesh in meshes:
                 mesh.close()
+        for mesh in self._spare.values():
+            mesh.close()
+        self._spare = {}
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return results, {"wall_s": wall, "mesh_setup_s": t_setup, "plan_choice_s": self.plan_seconds,
-                         "solve_s_per_frequency": (wall - t_setup) / len(self.ks)}
+        return results, {"wall_s": wall, "mesh_setup_s": t_setup, "probe_s": t_probe,
+                         "plan_choice_s": self.plan_seconds, "solve_s_per_frequency": (wall - t_setup) / len(self.ks)}

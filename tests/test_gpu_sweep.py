@@ -187,3 +187,39 @@ def test_mesh_from_tree_equals_a_new_mesh():
         assert ia["iterations"] == ib["iterations"] and np.array_equal(to_host(pa), to_host(pb))
         a.close()
         b.close()
+
+
+def test_probe_relabels_capped_frequencies():
+    """Mixed path, GMRES tolerance 1e-6: the frequencies chosen as "fmm32"
+    are probed on the device (capped FP64 FMM against the direct far field,
+    relative l2 of A x); those at and above the lowest passing one take the
+    FMM for their FP64 operator too.  Every probe that decided a relabelling
+    passed at 1e-7, the relabelled set is the top of the group, and every
+    solution is within 2e-5 of the oracle's LU solution with the same rules."""
+    from paper_2312_00005_amd import sweep
+    announce("sweep probe ico3 leaf 16, tol 1e-6")
+    nodes, tris = synth.icosphere(3)
+    g = element_geometry(nodes, tris)
+    S = sweep.FrequencySweep(nodes, tris, FREQS, preset="mixed", depths=(3, 2), leaf_size=16, gmres_tol=1e-6)
+    before = list(S.methods)
+    results, tot = S.run()
+    announce(f"  before {before}")
+    announce(f"  after  {[r['method'] for r in results]}; probes {S.probes}; probe {tot['probe_s']:.2f} s")
+    capped = [i for i, m in enumerate(before) if m[0] == "fmm32"]
+    assert S.probes or not capped
+    moved = [i for i in capped if results[i]["method"][0] == "fmm"]
+    # the relabelled frequencies are the highest of the capped ones
+    assert moved == capped[len(capped) - len(moved):]
+    if moved:
+        fmin = min(FREQS[i] for i in moved)
+        assert any(p["pass"] and abs(p["f"] - fmin) < 1e-9 for p in S.probes)
+    assert all(p["pass"] == (p["rel_l2"] <= 1e-7) for p in S.probes)
+    p_mixed = preset("mixed")
+    for r in results:
+        k = r["k"]
+        b = op.rhs_plane_wave(g, k, (0.0, 0.0, 1.0), p=p_mixed)
+        ref = op.lu_solve(op.dense(g, k, p=p_mixed), b)
+        err = rel_l2(to_host(r["p"]), ref)
+        announce(f"  f={r['f']:.0f} {r['method']} it={r['info']['iterations']} vs LU {err:.2e}")
+        assert r["info"]["rel_residual"] < 1e-6
+        assert err < 2e-5
