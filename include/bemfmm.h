@@ -171,7 +171,9 @@ typedef struct bem_options {
                                the direct far field (far_direct = 1) in the
                                complex-FP32 operator, whose pair orders are
                                chosen on the fly; the FP64 operator and every
-                               near-field plan use quad_eps */
+                               near-field plan use quad_eps (tight / mixed:
+                               equal to quad_eps, so that the two operators
+                               differ by rounding only) */
   int32_t interior;         /* 0: exterior problem (tau = 1 in Eq. (SystemI));
                                1: interior problem (tau = -1: every integral
                                term negated, the jump term (phi - gamma v)/2

@@ -664,8 +664,11 @@ bem_status bem_options_default(bem_options* o, const char* preset) {
       o->edge_gauss = 6;
       o->gmres_tol = 1e-6;
       o->l_eps_mixed = 1e-4;
-      // complex-FP32 direct far field: rules for errors near FP32 rounding
-      o->quad_eps_mixed = 1e-6;
+      // complex-FP32 direct far field: the FP64 operator's rules, so that the
+      // two operators differ by rounding only and each refinement step gains
+      // the full inner reduction (the estimates do not see k: looser rules
+      // for the FP32 operator drifted from the FP64 one at large k h)
+      o->quad_eps_mixed = 1e-8;
       // the other sign of the imaginary coupling: the discrete spectrum lies
       // in the right half-plane, where block Jacobi also pays off
       o->gamma_im_k = -1.0;
