@@ -34,7 +34,8 @@ FLOPS_PER_POINT_BC = 61
 # implementation: 66 flops per point
 FLOPS_PER_POINT_DIRECT = 66
 # MI355X vector peaks: FP64 78.6 TFLOP/s; FP32 157.3 TFLOP/s with packed
-# FP32 instructions, which this build does not emit (78.6 without them)
+# FP32 instructions, which the library's kernels are compiled without (78.6
+# without them)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32_packed": 157.3, "fp32": 78.6}
 SOLVE_TOL = 1e-6
 
@@ -306,7 +307,7 @@ def main():
         summarize_translate(args.summarize_translate[0], args.summarize_translate[1], args.translate_out)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(frequency sharding across GPUs is a design note only).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
