@@ -187,9 +187,12 @@ class FrequencySweep:
                     lo = mid + 1
             for i in idx[lo:]:
                 self.methods[i] = ("fmm", d)
-            md.close()
-            # the FMM mesh serves the "fmm" group of this depth
-            self._spare[("fmm", d)] = mf
+            # the two meshes serve the "fmm" and "direct" groups of this depth
+            for key, mesh in ((("fmm", d), mf), (("direct", d), md)):
+                if key in self._spare:
+                    mesh.close()
+                else:
+                    self._spare[key] = mesh
 
     @classmethod
     def from_curve(cls, nodes, tris, n_steps, stepsize, s0, freq_curve, **kw):
