@@ -203,10 +203,10 @@ def measured_traffic(prec="mixed", workload="c2"):
     return rec["hbm_bytes_per_launch"]
 
 
-def summarize_translate(fetch_csv, write_csv, out):
-    """FETCH_SIZE / WRITE_SIZE per translation launch, grouped by grid (one
-    group per tree level), scaled by what the same counters read for the
-    calibration copy of known size."""
+def summarize_translate(fetch_csv, write_csv, out, prec="mixed"):
+    """FETCH_SIZE / WRITE_SIZE per translation launch of precision prec,
+    grouped by grid (one group per tree level), scaled by what the same
+    counters read for the calibration copy of known size."""
     import csv
 
     def per_dispatch(path, counter):
@@ -225,22 +225,26 @@ def summarize_translate(fetch_csv, write_csv, out):
     f_scale, w_scale = cal(fetch) / CAL_BYTES, cal(write) / CAL_BYTES
     avg = lambda v: sum(v) / len(v)
     groups = []
-    for key in sorted(k for k in fetch if "k_translate<float" in k[0]):
+    kname = "k_translate<double" if prec == "fp64" else "k_translate<float"
+    for key in sorted(k for k in fetch if kname in k[0]):
         fb = avg(fetch[key]) / f_scale
         wb = avg(write.get(key, [0.0])) / w_scale
         groups.append({"kernel": key[0].replace("bem::(anonymous namespace)::", "").split("(")[0],
                        "grid": key[1], "launches": len(fetch[key]),
                        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb})
     rel = lambda p: (lambda r: p if r.startswith("..") else r)(os.path.relpath(os.path.abspath(p), ROOT))
-    rec = {"workload": "c2: 20480-triangle sphere, 3-level FMM, tight preset, complex-FP32 far field",
+    pflag = " --profile-prec fp64" if prec == "fp64" else ""
+    rec = {"workload": "c2: 20480-triangle sphere, 3-level FMM, tight preset, "
+                       + ("FP64 far field" if prec == "fp64" else "complex-FP32 far field"),
            "calibration": {"known_bytes": CAL_BYTES, "fetch_scale": f_scale, "write_scale": w_scale},
            "groups": sorted(groups, key=lambda g: -g["fetch_bytes_per_launch"]),
            "commands": [
                f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {rel(os.path.dirname(fetch_csv) or '.')} -o f -- "
-               "python bench.py --profile-far-only --steps 3 --warmup 1",
+               f"python bench.py --profile-far-only --steps 3 --warmup 1{pflag}",
                f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {rel(os.path.dirname(write_csv) or '.')} -o w -- "
-               "python bench.py --profile-far-only --steps 3 --warmup 1",
-               f"python bench.py --summarize-translate {rel(fetch_csv)} {rel(write_csv)}"]}
+               f"python bench.py --profile-far-only --steps 3 --warmup 1{pflag}",
+               f"python bench.py --summarize-translate {rel(fetch_csv)} {rel(write_csv)}{pflag}"
+               + (f" --translate-out {rel(out)}" if prec == "fp64" else "")]}
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -304,7 +308,8 @@ def main():
         summarize_valu(args.summarize_valu[0], args.summarize_valu[1])
         return
     if args.summarize_translate:
-        summarize_translate(args.summarize_translate[0], args.summarize_translate[1], args.translate_out)
+        summarize_translate(args.summarize_translate[0], args.summarize_translate[1], args.translate_out,
+                            args.profile_prec)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
