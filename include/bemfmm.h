@@ -189,8 +189,10 @@ typedef struct bem_options {
                                block 64, 128 or 256 (0: 64), plus 4096 for the
                                XCD slab order of the blocks (each of the 8 XCDs
                                serving an eighth of a level's targets in tree
-                               order); a tuning choice, results are identical;
-                               bem_autotune replaces it */
+                               order) or 8192 for the node-range order (each
+                               XCD serving an eighth of the sphere nodes of
+                               every target); a tuning choice, results are
+                               identical; bem_autotune replaces it */
   int32_t near_split;       /* with near_waves_per_cu > 0: percent (1-99) of the
                                collocation points whose near field runs in the
                                resident grid beside the far field; the rest run

@@ -120,9 +120,11 @@ void check_options(const bem_options* o) {
   if (o->far_direct < 0 || o->far_direct > 2) throw Error(BEM_E_ARG, "far_direct must be 0, 1 or 2");
   if (o->interior != 0 && o->interior != 1) throw Error(BEM_E_ARG, "interior must be 0 or 1");
   {
-    const int t = o->translate_shape & ~kTranslateSlab;
-    if (o->translate_shape < 0 || (t != 0 && t != 64 && t != 128 && t != 256))
-      throw Error(BEM_E_ARG, "translate_shape must be 0, 64, 128 or 256, plus 4096 for the slab order");
+    const int t = o->translate_shape & ~kTranslateFlags;
+    if (o->translate_shape < 0 || (t != 0 && t != 64 && t != 128 && t != 256) ||
+        (o->translate_shape & kTranslateFlags) == kTranslateFlags)
+      throw Error(BEM_E_ARG, "translate_shape must be 0, 64, 128 or 256, plus 4096 for the slab order or 8192 "
+                             "for the node-range order");
   }
   if (o->near_split < 0 || o->near_split > 100) throw Error(BEM_E_ARG, "near_split must be in [0, 100]");
   if (o->far_rows != 0 && o->far_rows != 1 && o->far_rows != kFarRows)
@@ -717,8 +719,8 @@ bem_status create_mesh(int64_t n_nodes, const double* xyz, int64_t n_tri, const 
     m->N = n_tri;
     m->tune_nwaves[0] = m->tune_nwaves[1] = o->near_waves_per_cu;
     {
-      const int t = o->translate_shape & ~kTranslateSlab;
-      m->tune_tpb[0] = m->tune_tpb[1] = (t == 0 ? 64 : t) | (o->translate_shape & kTranslateSlab);
+      const int t = o->translate_shape & ~kTranslateFlags;
+      m->tune_tpb[0] = m->tune_tpb[1] = (t == 0 ? 64 : t) | (o->translate_shape & kTranslateFlags);
       m->tune_split[0] = m->tune_split[1] = o->near_split == 0 ? 100 : o->near_split;
       m->far_rows = o->far_rows;
     }
@@ -991,11 +993,18 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           m->tune_tpb[pi] = pick_tpb;
           m->tune_fork_late[pi] = pick_late;
           if (!direct) {
-            // the same shape with the translation blocks in XCD slab order
-            m->tune_tpb[pi] = pick_tpb | kTranslateSlab;
-            const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
-            if (!(t < best)) m->tune_tpb[pi] = pick_tpb;
-            else best = t;
+            // the same shape with the translation blocks in XCD slab order,
+            // then in XCD node-range order
+            int pick_order = 0;
+            for (int flag : {kTranslateSlab, kTranslateNodes}) {
+              m->tune_tpb[pi] = pick_tpb | flag;
+              const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
+              if (t < best) {
+                best = t;
+                pick_order = flag;
+              }
+            }
+            m->tune_tpb[pi] = pick_tpb | pick_order;
           }
           // a resident near-field grid: the share of targets it keeps beside
           // the far field (the rest run after it at full occupancy)

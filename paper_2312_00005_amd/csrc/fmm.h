@@ -48,10 +48,14 @@ void launch_fmm_aggregate(int64_t nclust, const int64_t* ebeg, const int64_t* ee
 template <typename T, typename V>
 void launch_fmm_disaggregate(int64_t N, const int64_t* elem_cluster, int nu, const V* Sm, const FactorArgs* F,
                              const V* loc, double2* y, bool conj_rows, hipStream_t st);
-// translation launch shape: threads per block (64, 128, 256), plus this flag
-// for the XCD slab order of the blocks (each XCD serves an eighth of the
-// targets in tree order)
+// translation launch shape: threads per block (64, 128, 256), plus one of
+// these flags: the XCD slab order of the blocks (each XCD serves an eighth of
+// the targets in tree order), or the node-range order (each XCD serves an
+// eighth of the nodes of every target, so the signatures it reads, one eighth
+// of each source's, stay in its L2)
 constexpr int kTranslateSlab = 0x1000;
+constexpr int kTranslateNodes = 0x2000;
+constexpr int kTranslateFlags = kTranslateSlab | kTranslateNodes;
 // code[q] = 2 slot + flip for interaction entry q = (m, n): D_mn is slot
 // `slot` of D at node nu (flip 0) or at the antipodal node (flip 1).
 // adjoint: loc_n = sum_m conj(D_mn) sig_m over the entries (n, m) of n.

@@ -308,33 +308,45 @@ __global__ __launch_bounds__(256) void k_disaggregate(int64_t N, const int64_t* 
 // slot code[q] >> 1 at node v or, if code[q] & 1, at the antipodal node
 // (t, j) -> (L-1-t, j+L mod 2L).  ADJ: loc_n = sum_q conj(D_(il[q], n)) sig_il[q]:
 // the same slot with the flip inverted.
-// SLAB: a one-dimensional grid whose blocks the hardware hands to the 8 XCDs
-// in turn (block b to XCD b mod 8) is mapped so that XCD j serves the
-// targets of the j-th eighth of the level in tree order: neighbouring
+// ORDER 1 (slab): a one-dimensional grid whose blocks the hardware hands to
+// the 8 XCDs in turn (block b to XCD b mod 8) is mapped so that XCD j serves
+// the targets of the j-th eighth of the level in tree order: neighbouring
 // targets share most of their interaction lists, so the source signatures
-// they read stay in that XCD's L2.
-template <typename T, typename V, bool ADJ, int TPB, bool SLAB>
+// they read stay in that XCD's L2.  ORDER 2 (node ranges): XCD j serves
+// nodes [j nu / 8, (j + 1) nu / 8) of every target, in chunks of TPB, so its
+// share of all the signatures (an eighth) fits its L2.
+template <typename T, typename V, bool ADJ, int TPB, int ORDER>
 __global__ __launch_bounds__(TPB) void k_translate(const int64_t* __restrict__ il_off,
                                                    const int64_t* __restrict__ il,
                                                    const int64_t* __restrict__ code, int L, int nu, int64_t nc,
                                                    const V* __restrict__ D, const V* __restrict__ sig,
                                                    V* __restrict__ loc) {
   int64_t m;
-  int vb;
-  if (SLAB) {
+  int v;
+  if (ORDER == 1) {
     const int nbx = (nu + TPB - 1) / TPB;
     const int64_t b = blockIdx.x;
     const int64_t xcd = b & 7, r = b >> 3;
     const int64_t m0 = nc * xcd / 8, m1 = nc * (xcd + 1) / 8;
     m = m0 + r / nbx;
-    vb = (int)(r % nbx);
     if (m >= m1) return;
+    v = (int)(r % nbx) * TPB + threadIdx.x;
+    if (v >= nu) return;
+  } else if (ORDER == 2) {
+    const int64_t b = blockIdx.x;
+    const int xcd = (int)(b & 7);
+    const int64_t r = b >> 3;
+    const int n0 = (int)((int64_t)nu * xcd / 8), n1 = (int)((int64_t)nu * (xcd + 1) / 8);
+    const int nch = ((nu + 7) / 8 + TPB - 1) / TPB;  // chunks per target and XCD (the widest range)
+    m = r / nch;
+    if (m >= nc) return;
+    v = n0 + (int)(r % nch) * TPB + threadIdx.x;
+    if (v >= n1) return;
   } else {
     m = blockIdx.y;
-    vb = blockIdx.x;
+    v = blockIdx.x * TPB + threadIdx.x;
+    if (v >= nu) return;
   }
-  const int v = vb * TPB + threadIdx.x;
-  if (v >= nu) return;
   const int twoL = 2 * L;
   const int t = v / twoL, j = v - t * twoL;
   const int va = (L - 1 - t) * twoL + (j < L ? j + L : j - L);
@@ -828,35 +840,39 @@ void launch_fmm_disaggregate(int64_t N, const int64_t* ec, int nu, const V* Sm, 
   }
 }
 
-template <typename T, typename V, int TPB, bool SLAB>
+template <typename T, typename V, int TPB, int ORDER>
 void translate_shape(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint, int L,
                      int nu, const V* D, const V* sig, V* loc, hipStream_t st) {
-  const dim3 grid = SLAB ? dim3((unsigned)(8 * ((nc + 7) / 8) * nblk(nu, TPB))) : dim3(nblk(nu, TPB), (unsigned)nc);
+  dim3 grid(nblk(nu, TPB), (unsigned)nc);
+  if (ORDER == 1) grid = dim3((unsigned)(8 * ((nc + 7) / 8) * nblk(nu, TPB)));
+  if (ORDER == 2) grid = dim3((unsigned)(8 * nc * nblk((nu + 7) / 8, TPB)));
   if (adjoint)
-    hipLaunchKernelGGL((k_translate<T, V, true, TPB, SLAB>), grid, dim3(TPB), 0, st, il_off, il, code, L, nu, nc, D,
+    hipLaunchKernelGGL((k_translate<T, V, true, TPB, ORDER>), grid, dim3(TPB), 0, st, il_off, il, code, L, nu, nc, D,
                        sig, loc);
   else
-    hipLaunchKernelGGL((k_translate<T, V, false, TPB, SLAB>), grid, dim3(TPB), 0, st, il_off, il, code, L, nu, nc, D,
-                       sig, loc);
+    hipLaunchKernelGGL((k_translate<T, V, false, TPB, ORDER>), grid, dim3(TPB), 0, st, il_off, il, code, L, nu, nc,
+                       D, sig, loc);
 }
 
 template <typename T, typename V, int TPB>
 void translate_tpb(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint, int L,
-                   int nu, const V* D, const V* sig, V* loc, bool slab, hipStream_t st) {
-  if (slab) translate_shape<T, V, TPB, true>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
-  else translate_shape<T, V, TPB, false>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
+                   int nu, const V* D, const V* sig, V* loc, int order, hipStream_t st) {
+  if (order == 1) translate_shape<T, V, TPB, 1>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
+  else if (order == 2) translate_shape<T, V, TPB, 2>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
+  else translate_shape<T, V, TPB, 0>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, st);
 }
 
-// tpb: 64, 128 or 256 threads per block; + kTranslateSlab: the XCD slab order
+// tpb: 64, 128 or 256 threads per block; + kTranslateSlab: the XCD slab
+// order, + kTranslateNodes: the XCD node-range order
 template <typename T, typename V>
 void launch_fmm_translate(int64_t nc, const int64_t* il_off, const int64_t* il, const int64_t* code, bool adjoint,
                           int L, int nu, const V* D, const V* sig, V* loc, int tpb, hipStream_t st) {
   if (nc <= 0) return;
-  const bool slab = (tpb & kTranslateSlab) != 0;
-  tpb &= ~kTranslateSlab;
-  if (tpb == 128) translate_tpb<T, V, 128>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, slab, st);
-  else if (tpb == 256) translate_tpb<T, V, 256>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, slab, st);
-  else translate_tpb<T, V, 64>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, slab, st);
+  const int order = (tpb & kTranslateSlab) ? 1 : (tpb & kTranslateNodes) ? 2 : 0;
+  tpb &= ~kTranslateFlags;
+  if (tpb == 128) translate_tpb<T, V, 128>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, order, st);
+  else if (tpb == 256) translate_tpb<T, V, 256>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, order, st);
+  else translate_tpb<T, V, 64>(nc, il_off, il, code, adjoint, L, nu, D, sig, loc, order, st);
 }
 
 template <typename T, typename V>

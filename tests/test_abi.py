@@ -89,6 +89,9 @@ def test_invalid_arguments(bem):
         with pytest.raises(bem.BemError) as e:
             bem.Mesh(nodes, tris, "paper", use_fmm=0, near_waves_per_cu=nw)
         assert e.value.status == bem.BEM_E_ARG
+    with pytest.raises(bem.BemError) as e:
+        bem.Mesh(nodes, tris, "paper", use_fmm=0, translate_shape=4096 + 8192 + 64)
+    assert e.value.status == bem.BEM_E_ARG
     for fr in (-1, 2, 8):
         with pytest.raises(bem.BemError) as e:
             bem.Mesh(nodes, tris, "paper", use_fmm=0, far_rows=fr)

@@ -59,7 +59,7 @@ def test_autotune_keeps_results(bem):
     picks = m.autotune()
     announce(f"  picks {picks}")
     assert set(picks["near_wpb"].values()) <= {1, 2, 4, 8}
-    assert {t & ~4096 for t in picks["translate_tpb"].values()} <= {64, 128, 256}
+    assert {t & ~(4096 | 8192) for t in picks["translate_tpb"].values()} <= {64, 128, 256}
     assert set(picks["near_waves_per_cu"].values()) <= {0, 8, 12, 16, 24}
     assert set(picks["near_split"].values()) <= {50, 60, 70, 80, 90, 100}
     for p in ("fp64", "mixed"):
@@ -77,8 +77,8 @@ def test_autotune_keeps_results(bem):
         for p in ("fp64", "mixed"):
             assert np.array_equal(to_host(ms.apply(x, prec=p)), before[p])
         ms.close()
-    # nor do the translation blocks in XCD slab order
-    for shape in (4096 + 64, 4096 + 256):
+    # nor do the translation blocks in XCD slab or node-range order
+    for shape in (4096 + 64, 4096 + 256, 8192 + 64, 8192 + 128, 8192 + 256):
         ms = bem.Mesh(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=32, translate_shape=shape)
         ms.set_problem(k)
         for p in ("fp64", "mixed"):
