@@ -430,14 +430,17 @@ bem_status bem_grad_admittance(bem_mesh* m, const bem_c128* p, const bem_c128* w
  * with the translation threads per workgroup (64, 128, 256; FMM only) and the
  * point where the leaf-level translation leaves the level chain for a stream
  * of its own (right after aggregation, or after the leaf level's transfer to
- * the level above) on whole applications, then the share of near-field
- * targets kept beside the far field (see near_split), then the translation
- * blocks in XCD slab order (each of the 8 XCDs serving an eighth of the targets in tree
+ * the level above) on whole applications, then the translation blocks in XCD
+ * slab order (each of the 8 XCDs serving an eighth of the targets in tree
  * order, so that the source signatures neighbouring targets share stay in
- * one L2), for the FP64 and the complex-FP32 operator.  Results are kept in the mesh and used by every later
- * application; near_wpb, translate_tpb (+ 4096 for the slab order) and near_waves (host int32[2]: FP64,
- * FP32) receive them and may be NULL.  Runs about 400 operator applications
- * or parts on the stream;
+ * one L2) and in XCD node-range order (each XCD serving an eighth of every
+ * target's sphere nodes), each at 64, 128 and 256 threads per workgroup,
+ * then the share of near-field targets kept beside the far field (see
+ * near_split), for the FP64 and the complex-FP32 operator.  Results are kept
+ * in the mesh and used by every later application; near_wpb, translate_tpb
+ * (threads per workgroup + 4096 for the slab order, + 8192 for the node-range
+ * order) and near_waves (host int32[2]: FP64, FP32) receive them and may be
+ * NULL.  Runs about 900 operator applications or parts on the stream;
  * results are unchanged by the choice (each output keeps its owner and
  * summation order). */
 bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb,

@@ -938,15 +938,21 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
     hipEvent_t e0, e1;
     BEM_HIP(hipEventCreate(&e0));
     BEM_HIP(hipEventCreate(&e1));
+    // the fastest of three batches of three runs after a warm-up: candidates
+    // differ by a few per cent, about what one batch varies by
     auto timed = [&](auto&& fn) {
-      fn();  // warm-up
-      BEM_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 5; ++r) fn();
-      BEM_HIP(hipEventRecord(e1, s));
-      BEM_HIP(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-      return ms;
+      fn();
+      float best_ms = -1.0f;
+      for (int batch = 0; batch < 3; ++batch) {
+        BEM_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) fn();
+        BEM_HIP(hipEventRecord(e1, s));
+        BEM_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (best_ms < 0.0f || ms < best_ms) best_ms = ms;
+      }
+      return best_ms;
     };
     try {
       BEM_HIP(hipMemsetAsync(m->d_x.p, 0, m->N * sizeof(double2), s));
@@ -993,18 +999,21 @@ bem_status bem_autotune(bem_mesh* m, int32_t* near_wpb, int32_t* translate_tpb, 
           m->tune_tpb[pi] = pick_tpb;
           m->tune_fork_late[pi] = pick_late;
           if (!direct) {
-            // the same shape with the translation blocks in XCD slab order,
-            // then in XCD node-range order
-            int pick_order = 0;
-            for (int flag : {kTranslateSlab, kTranslateNodes}) {
-              m->tune_tpb[pi] = pick_tpb | flag;
-              const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
-              if (t < best) {
-                best = t;
-                pick_order = flag;
+            // the translation blocks in XCD slab order, then in XCD
+            // node-range order, at each block size (a reordered grid can
+            // prefer another size than the plain one), keeping the
+            // near-field residency and fork point picked above
+            int pick_shape = pick_tpb;
+            for (int flag : {kTranslateSlab, kTranslateNodes})
+              for (int tpb : tpbs) {
+                m->tune_tpb[pi] = tpb | flag;
+                const float t = timed([&] { apply_tree_part(m, BEM_OP_A, prec, 0, m->d_x.p, m->d_y.p, s); });
+                if (t < best) {
+                  best = t;
+                  pick_shape = tpb | flag;
+                }
               }
-            }
-            m->tune_tpb[pi] = pick_tpb | pick_order;
+            m->tune_tpb[pi] = pick_shape;
           }
           // a resident near-field grid: the share of targets it keeps beside
           // the far field (the rest run after it at full occupancy)
