@@ -620,9 +620,12 @@ struct bem_tree {
   bem_options opt{};
   // the near plan is built on first use (bem_tree_plan_stats, or a mesh made
   // from the tree, which shares it): the tree alone serves
-  // bem_tree_fmm_lengths and the level queries
+  // bem_tree_fmm_lengths and the level queries.  The lock lets threads make
+  // meshes of one tree at the same time.
   mutable std::shared_ptr<NearPlan> plan;
+  mutable std::mutex plan_mu;
   const NearPlan& ensure_plan() const {
+    std::lock_guard<std::mutex> lock(plan_mu);
     if (!plan) {
       auto p = std::make_shared<NearPlan>();
       int64_t bad = -1;

@@ -139,3 +139,22 @@ def test_mesh_from_tree_checks_the_tree_options(bem):
     with pytest.raises(bem.BemError) as e:
         bem.bem_mesh_create_from_tree(None, bem.bem_options_default("tight"))
     assert e.value.status == bem.BEM_E_ARG
+
+
+def test_tree_plan_built_once_under_concurrent_calls(bem):
+    """A host tree builds its near plan on first use; threads asking for it at
+    the same time (ctypes releases the GIL during the call) all get the plan
+    of a tree that built it alone."""
+    import threading
+    nodes, tris = synth.icosphere(3)
+    ref = bem.HostTree(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=16).plan_stats()
+    t = bem.HostTree(nodes, tris, "tight", use_fmm=1, levels=3, leaf_size=16)
+    out = [None] * 4
+    def ask(i):
+        out[i] = t.plan_stats()
+    threads = [threading.Thread(target=ask, args=(i,)) for i in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert all(o == ref for o in out), (out, ref)
