@@ -61,3 +61,28 @@ def test_traffic_record_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     rec["source_sha256"] = "0" * 64
     json.dump(rec, open(out, "w"))
     assert bench.measured_traffic("fp64") is None
+
+
+def test_valu_share_from_counters(tmp_path):
+    """summarize_valu: clock = GRBM_GUI_ACTIVE / 8 XCDs / duration and VALU
+    share = 4 SQ_INSTS_VALU / (1024 SIMDs x clock x duration), from a dispatch
+    of 1 ms at 2 GHz whose counted instructions fill half the SIMD cycles."""
+    sys.path.insert(0, ROOT)
+    import bench
+    dur_ns, clk = 1_000_000, 2.0e9
+    gui = clk * 8 * dur_ns * 1e-9
+    insts = 0.5 * 1024 * clk * dur_ns * 1e-9 / 4
+    name = "void bem::(anonymous namespace)::k_near<double, false, false, 4>(bem::NearLaunch)"
+    p = tmp_path / "pmc.csv"
+    with open(p, "w") as fh:
+        fh.write("Dispatch_Id,Kernel_Name,Grid_Size,Counter_Name,Counter_Value,Start_Timestamp,End_Timestamp\n")
+        for c, v in (("SQ_INSTS_VALU", insts), ("SQ_ACTIVE_INST_VALU", 1.0), ("SQ_WAVES", 20480),
+                     ("GRBM_GUI_ACTIVE", gui)):
+            fh.write(f'7,"{name}",1310720,{c},{v},1000,{1000 + dur_ns}\n')
+    out = tmp_path / "valu.md"
+    bench.summarize_valu(str(p), str(out))
+    row = [l for l in open(out) if l.startswith("| `void k_near<double")][0]
+    cells = [c.strip() for c in row.strip().strip("|").split("|")]
+    assert cells[3] == "1000.0"      # average duration in microseconds
+    assert cells[7] == "2.00"        # clock in GHz
+    assert cells[8] == "0.50"        # VALU share
