@@ -86,3 +86,32 @@ def test_valu_share_from_counters(tmp_path):
     assert cells[3] == "1000.0"      # average duration in microseconds
     assert cells[7] == "2.00"        # clock in GHz
     assert cells[8] == "0.50"        # VALU share
+
+
+def test_translate_traffic_groups_by_launch_shape_and_grid(tmp_path):
+    """summarize_translate: one group per (kernel, grid), average bytes per
+    launch over its dispatches, scaled by the calibration copy's reading."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import json
+    k128 = "void bem::(anonymous namespace)::k_translate<double, HIP_vector_type<double, 2u>, false, 128, 2>(long)"
+    k256 = "void bem::(anonymous namespace)::k_translate<double, HIP_vector_type<double, 2u>, false, 256, 0>(long)"
+    copy = "void at::native::elementwise_kernel<128, 4, copy_kernel>(int)"
+    f, w, out = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "tr.json"
+    for path, counter, rows in ((f, "FETCH_SIZE", [(k128, 800, 4000), (k128, 800, 6000), (k256, 900, 2000),
+                                                   (k128, 100, 10), (copy, 1, 262144)]),
+                                (w, "WRITE_SIZE", [(k128, 800, 10), (k128, 800, 10), (k256, 900, 20),
+                                                   (k128, 100, 1), (copy, 1, 524288)])):
+        with open(path, "w") as fh:
+            fh.write("Dispatch_Id,Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+            for i, (name, grid, kib) in enumerate(rows):
+                fh.write(f'{i},"{name}",{grid},{counter},{kib}\n')
+    bench.summarize_translate(str(f), str(w), str(out), prec="fp64")
+    rec = json.load(open(out))
+    got = {(g["kernel"].split("false, ")[1], g["grid"]): (g["launches"], g["fetch_bytes_per_launch"],
+                                                          g["write_bytes_per_launch"]) for g in rec["groups"]}
+    assert got[("128, 2>", "800")] == (2, 5000 * 1024 / 0.5, 10 * 1024.0)
+    assert got[("256, 0>", "900")] == (1, 2000 * 1024 / 0.5, 20 * 1024.0)
+    assert got[("128, 2>", "100")] == (1, 10 * 1024 / 0.5, 1 * 1024.0)
+    assert [g["fetch_bytes_per_launch"] for g in rec["groups"]] == sorted(
+        (g["fetch_bytes_per_launch"] for g in rec["groups"]), reverse=True)
